@@ -1,0 +1,211 @@
+"""Serial FP64 oracle of the free-surface LBM step -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  It wraps ``liboracle.so`` (built from ``fslbm_oracle.cpp`` by
+``build()`` below) through ctypes and shares nothing with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["fslbm_oracle.cpp", "fslbm_oracle.hpp"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no FMA contraction, no fast-math)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", tmp, os.path.join(_HERE, "fslbm_oracle.cpp")]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _RefParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("px", ctypes.c_int), ("py", ctypes.c_int), ("pz", ctypes.c_int),
+                ("tau", ctypes.c_double), ("Lambda", ctypes.c_double),
+                ("incompressible", ctypes.c_int), ("stokes", ctypes.c_int),
+                ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
+                ("rho_gas", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        L.ref_create.restype = vp
+        L.ref_create.argtypes = [ctypes.POINTER(_RefParams), u8p, dp, dp, dp]
+        L.ref_create_state.restype = vp
+        L.ref_create_state.argtypes = [ctypes.POINTER(_RefParams), u8p, dp, dp, dp, ctypes.c_double]
+        L.ref_create_error.restype = ctypes.c_char_p
+        L.ref_destroy.argtypes = [vp]
+        L.ref_error.restype = ctypes.c_char_p
+        L.ref_error.argtypes = [vp]
+        L.ref_set_freeze.argtypes = [vp, ctypes.c_int]
+        L.ref_step.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.ref_step.restype = ctypes.c_int
+        for name in ("ref_get_populations", "ref_get_mass", "ref_get_phi"):
+            getattr(L, name).argtypes = [vp, dp]
+        L.ref_get_flags.argtypes = [vp, u8p]
+        L.ref_get_collision_moments.argtypes = [vp, dp, dp]
+        L.ref_get_macro.argtypes = [vp, dp, dp]
+        L.ref_total_mass.restype = ctypes.c_double
+        L.ref_total_mass.argtypes = [vp]
+        L.ref_reservoir.restype = ctypes.c_double
+        L.ref_reservoir.argtypes = [vp]
+        L.ref_list.restype = ctypes.c_int
+        L.ref_list.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int]
+        L.ref_constants.argtypes = [vp, dp]
+        L.ref_equilibrium_post.argtypes = [vp, ctypes.c_double, dp, dp]
+        L.ref_collide.argtypes = [vp, dp, dp, dp, dp]
+        L.ref_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _params(p) -> _RefParams:
+    return _RefParams(p.nx, p.ny, p.nz, int(p.periodic[0]), int(p.periodic[1]), int(p.periodic[2]),
+                      float(p.tau), float(p.Lambda), int(p.incompressible), int(p.stokes),
+                      float(p.g[0]), float(p.g[1]), float(p.g[2]), float(p.rho_gas), float(p.eps))
+
+
+FSK, FSL = 0, 1
+LISTS = {"F": 0, "E": 1, "E'": 2, "NI": 3, "NL": 4}
+
+
+class Oracle:
+    """One oracle simulation (FP64, serial)."""
+
+    def __init__(self, params, flags=None, rho=None, u=None, fill=None, state=None):
+        self.params = params
+        self.N = params.nx * params.ny * params.nz
+        L = lib()
+        self._p = _params(params)
+        N = self.N
+        if state is not None:
+            fl = np.ascontiguousarray(state["flags"], dtype=np.uint8)
+            ft = np.ascontiguousarray(state["f"], dtype=np.float64).reshape(-1)
+            m = np.ascontiguousarray(state["mass"], dtype=np.float64)
+            ph = np.ascontiguousarray(state["phi"], dtype=np.float64)
+            assert ft.size == 19 * N and fl.size == N and m.size == N and ph.size == N
+            h = L.ref_create_state(ctypes.byref(self._p), fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   _dptr(ft), _dptr(m), _dptr(ph), float(state.get("reservoir", 0.0)))
+        else:
+            fl = np.ascontiguousarray(flags, dtype=np.uint8)
+            r = np.ascontiguousarray(rho, dtype=np.float64)
+            uu = np.zeros((3, N)) if u is None else np.ascontiguousarray(u, dtype=np.float64)
+            fi = np.ascontiguousarray(fill, dtype=np.float64)
+            assert fl.size == N and r.size == N and uu.size == 3 * N and fi.size == N
+            h = L.ref_create(ctypes.byref(self._p), fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                             _dptr(r), _dptr(uu), _dptr(fi))
+        if not h:
+            raise ValueError("oracle rejected input: " + L.ref_create_error().decode())
+        self._h = ctypes.c_void_p(h)
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.params, w.flags, w.rho, w.u, w.fill)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ref_destroy(h)
+            self._h = None
+
+    def set_freeze(self, on: bool):
+        lib().ref_set_freeze(self._h, int(bool(on)))
+
+    def step(self, n: int = 1, rule: int = FSL):
+        if lib().ref_step(self._h, int(n), int(rule)) != 0:
+            raise RuntimeError("oracle step failed: " + lib().ref_error(self._h).decode())
+
+    def populations(self) -> np.ndarray:
+        out = np.empty(19 * self.N)
+        lib().ref_get_populations(self._h, _dptr(out))
+        return out.reshape(19, self.N)
+
+    def flags(self) -> np.ndarray:
+        out = np.empty(self.N, dtype=np.uint8)
+        lib().ref_get_flags(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        return out
+
+    def mass(self) -> np.ndarray:
+        out = np.empty(self.N)
+        lib().ref_get_mass(self._h, _dptr(out))
+        return out
+
+    def phi(self) -> np.ndarray:
+        out = np.empty(self.N)
+        lib().ref_get_phi(self._h, _dptr(out))
+        return out
+
+    def collision_moments(self):
+        rho = np.empty(self.N)
+        u = np.empty(3 * self.N)
+        lib().ref_get_collision_moments(self._h, _dptr(rho), _dptr(u))
+        return rho, u.reshape(3, self.N)
+
+    def macro(self):
+        rho = np.empty(self.N)
+        u = np.empty(3 * self.N)
+        lib().ref_get_macro(self._h, _dptr(rho), _dptr(u))
+        return rho, u.reshape(3, self.N)
+
+    def total_mass(self) -> float:
+        return lib().ref_total_mass(self._h)
+
+    def reservoir(self) -> float:
+        return lib().ref_reservoir(self._h)
+
+    def lists(self) -> dict:
+        out = {}
+        for name, which in LISTS.items():
+            n = lib().ref_list(self._h, which, None, 0)
+            buf = np.empty(max(n, 1), dtype=np.int32)
+            lib().ref_list(self._h, which, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n)
+            out[name] = buf[:n].copy()
+        return out
+
+    def constants(self) -> dict:
+        out = np.empty(4)
+        lib().ref_constants(self._h, _dptr(out))
+        return {"lambda_p": out[0], "lambda_m": out[1], "inv_1p_lambda_p": out[2], "thr_hi": out[3]}
+
+    def equilibrium_post(self, rho: float, u) -> np.ndarray:
+        uu = np.ascontiguousarray(u, dtype=np.float64)
+        out = np.empty(19)
+        lib().ref_equilibrium_post(self._h, float(rho), _dptr(uu), _dptr(out))
+        return out
+
+    def collide(self, f):
+        ff = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.empty(19)
+        rho = ctypes.c_double()
+        u = np.empty(3)
+        lib().ref_collide(self._h, _dptr(ff), _dptr(out), ctypes.byref(rho), _dptr(u))
+        return out, rho.value, u
+
+    def coeffs(self, rule: int, alpha_p: float = 1.0, delta: float = 0.0) -> np.ndarray:
+        out = np.empty(5)
+        lib().ref_coeffs(self._h, int(rule), float(alpha_p), float(delta), _dptr(out))
+        return out

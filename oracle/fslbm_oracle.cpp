@@ -1,0 +1,183 @@
+// C entry points of the serial FP64 oracle (test infrastructure only; see
+// fslbm_oracle.hpp).  Loaded by the tests through ctypes.
+#include <cstdio>
+#include <memory>
+
+#include "fslbm_oracle.hpp"
+
+using fsref::Oracle;
+using fsref::Params;
+
+namespace {
+struct Handle {
+  Oracle<double> sim;
+  std::string err;
+};
+thread_local std::string g_create_error;
+}  // namespace
+
+extern "C" {
+
+struct ref_params {
+  int nx, ny, nz;
+  int px, py, pz;
+  double tau, Lambda;
+  int incompressible, stokes;
+  double gx, gy, gz;
+  double rho_gas, eps;
+};
+
+static Params to_params(const ref_params* r) {
+  Params p{};
+  p.nx = r->nx;
+  p.ny = r->ny;
+  p.nz = r->nz;
+  p.periodic[0] = r->px;
+  p.periodic[1] = r->py;
+  p.periodic[2] = r->pz;
+  p.tau = r->tau;
+  p.Lambda = r->Lambda;
+  p.incompressible = r->incompressible;
+  p.stokes = r->stokes;
+  p.g[0] = r->gx;
+  p.g[1] = r->gy;
+  p.g[2] = r->gz;
+  p.rho_gas = r->rho_gas;
+  p.eps = r->eps;
+  return p;
+}
+
+// Create from macroscopic fields (flags, rho, u[3][N], fill).  Returns NULL on
+// invalid input; ref_create_error() then says why.
+void* ref_create(const ref_params* rp, const uint8_t* flags, const double* rho, const double* u,
+                 const double* fill) {
+  try {
+    auto h = std::make_unique<Handle>();
+    h->sim.set_params(to_params(rp));
+    h->sim.init_from_fields(flags, rho, u, fill);
+    return h.release();
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return nullptr;
+  }
+}
+
+// Create from a full state: flags, post-collision populations ft[19][N], mass,
+// fill, reservoir.
+void* ref_create_state(const ref_params* rp, const uint8_t* flags, const double* ft, const double* mass,
+                       const double* fill, double reservoir) {
+  try {
+    auto h = std::make_unique<Handle>();
+    h->sim.set_params(to_params(rp));
+    h->sim.init_from_state(flags, ft, mass, fill, reservoir);
+    return h.release();
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return nullptr;
+  }
+}
+
+const char* ref_create_error() { return g_create_error.c_str(); }
+
+void ref_destroy(void* hp) { delete static_cast<Handle*>(hp); }
+
+const char* ref_error(void* hp) { return static_cast<Handle*>(hp)->err.c_str(); }
+
+void ref_set_freeze(void* hp, int freeze) { static_cast<Handle*>(hp)->sim.freeze = freeze != 0; }
+
+// n steps with rule 0 = FSK, 1 = FSL.  Returns 0, or 1 with ref_error() set.
+int ref_step(void* hp, int n, int rule) {
+  auto* h = static_cast<Handle*>(hp);
+  try {
+    for (int i = 0; i < n; ++i) h->sim.step(rule);
+    return 0;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return 1;
+  }
+}
+
+void ref_get_populations(void* hp, double* out) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  std::memcpy(out, s.ft.data(), sizeof(double) * s.ft.size());
+}
+void ref_get_flags(void* hp, uint8_t* out) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  std::memcpy(out, s.type.data(), s.type.size());
+}
+void ref_get_mass(void* hp, double* out) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  std::memcpy(out, s.mass.data(), sizeof(double) * s.mass.size());
+}
+void ref_get_phi(void* hp, double* out) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  std::memcpy(out, s.phi.data(), sizeof(double) * s.phi.size());
+}
+// density and velocity of the last collision at interface cells
+void ref_get_collision_moments(void* hp, double* rho, double* u) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  std::memcpy(rho, s.rho_c.data(), sizeof(double) * s.rho_c.size());
+  std::memcpy(u, s.u_c.data(), sizeof(double) * s.u_c.size());
+}
+// rho and u at every non-gas cell recovered from the current post-collision
+// populations (gas cells get 0)
+void ref_get_macro(void* hp, double* rho, double* u) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  const int N = s.N;
+  for (int cell = 0; cell < N; ++cell) {
+    if (s.type[cell] == fsref::GAS) {
+      rho[cell] = 0.0;
+      u[cell] = u[N + cell] = u[2 * N + cell] = 0.0;
+      continue;
+    }
+    double f[fsref::Q], r, uu[3];
+    for (int q = 0; q < fsref::Q; ++q) f[q] = s.ft[(size_t)q * N + cell];
+    s.recover_moments(f, r, uu);
+    rho[cell] = r;
+    for (int a = 0; a < 3; ++a) u[(size_t)a * N + cell] = uu[a];
+  }
+}
+double ref_total_mass(void* hp) { return static_cast<Handle*>(hp)->sim.total_mass(); }
+double ref_reservoir(void* hp) { return static_cast<Handle*>(hp)->sim.reservoir; }
+
+// which: 0 = filled, 1 = emptied, 2 = emptied and converted, 3 = new interface
+// from gas, 4 = new interface from liquid.  Copies up to cap entries and
+// returns the list length.
+int ref_list(void* hp, int which, int* out, int cap) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  const std::vector<int>* L[5] = {&s.listF, &s.listE, &s.listEp, &s.listNI, &s.listNL};
+  if (which < 0 || which > 4) return -1;
+  const auto& v = *L[which];
+  int n = (int)v.size();
+  for (int i = 0; i < n && i < cap; ++i) out[i] = v[i];
+  return n;
+}
+
+// Relaxation constants as the oracle derives them (for tests).
+void ref_constants(void* hp, double* out4) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  out4[0] = s.lam_p;
+  out4[1] = s.lam_m;
+  out4[2] = s.inv_1p_lam_p;
+  out4[3] = s.thr_hi;
+}
+
+// Pointwise building blocks, exposed for the identity tests.
+void ref_equilibrium_post(void* hp, double rho, const double* u, double* out19) {
+  static_cast<Handle*>(hp)->sim.equilibrium_post(rho, u, out19);
+}
+void ref_collide(void* hp, const double* f19, double* out19, double* rho, double* u3) {
+  static_cast<Handle*>(hp)->sim.collide(f19, out19, *rho, u3);
+}
+// Closure coefficients: rule 0 = FSK row, rule 1 = Eq. (fsli) with alpha_+.
+void ref_coeffs(void* hp, int rule, double alpha_p, double delta, double* out5) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  auto k = rule == 0 ? s.coeffs_fsk() : s.coeffs_fsli(alpha_p, delta);
+  out5[0] = k.a0;
+  out5[1] = k.a0bar;
+  out5[2] = k.a1;
+  out5[3] = k.alpha_p;
+  out5[4] = k.C;
+}
+
+}  // extern "C"

@@ -1,0 +1,609 @@
+// Serial reference implementation of the free-surface lattice Boltzmann time
+// step (Bogner, Ammer, Ruede: "Boundary Conditions for Free Interfaces with the
+// Lattice Boltzmann Method").
+//
+// TEST INFRASTRUCTURE ONLY.  This oracle exists so that tests, the smoke check
+// and the CPU-baseline leg of the benchmark can check the GPU library against
+// a plain, slow, obviously correct implementation.  It shares no code, header,
+// table or constant with the GPU library and must never be called by it.
+//
+// Everything is serial, in ascending linear cell order idx = x + nx*(y + ny*z),
+// and templated on the scalar type T so that a dual-number scalar can give exact
+// directional derivatives (adjoint checks).  T = double is the FP64 oracle.
+//
+// Parity status per function is listed in the test files; every function here
+// is pinned by at least one closed form, invariant or special case.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace fsref {
+
+// ---------------------------------------------------------------------------
+// D3Q19 lattice (section 2.1; experiments use D3Q19, section 4).
+// Velocity order: rest, the six axis links, then the twelve diagonals; every
+// odd index q has its opposite at q+1.
+// ---------------------------------------------------------------------------
+static const int Q = 19;
+static const int CV[Q][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+// opposite direction: c_qbar = -c_q (section 2.1)
+inline int opposite(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+
+// Lattice weights of Qian et al. for D3Q19 (section 2.1 names them; the values
+// 1/3, 1/18, 1/36 are the textbook ones for c_s^2 = 1/3).
+inline double weight(int q) {
+  if (q == 0) return 1.0 / 3.0;
+  if (q <= 6) return 1.0 / 18.0;
+  return 1.0 / 36.0;
+}
+
+enum CellType : uint8_t { GAS = 0, INTERFACE = 1, LIQUID = 2 };
+enum Rule { FSK = 0, FSL = 1 };
+
+// Model parameters.  tau is the symmetric relaxation time (lambda_+ = -1/tau),
+// Lambda = Lambda_+ Lambda_- fixes lambda_- (section 3.1).  g is the body
+// acceleration; rho_gas the gas density with P_b = rho_gas / 3 (section 2.3).
+struct Params {
+  int nx, ny, nz;
+  int periodic[3];
+  double tau, Lambda;
+  int incompressible;  // rho_0 = 1 (He-Luo) if nonzero, else rho_0 = rho
+  int stokes;          // drop the quadratic part N_q of e+ (section 2.1)
+  double g[3];
+  double rho_gas;
+  double eps;          // conversion threshold margin
+};
+
+// ---------------------------------------------------------------------------
+// The simulation state and one time step.
+// ---------------------------------------------------------------------------
+template <class T>
+struct Oracle {
+  Params p{};
+  int N = 0;
+  // relaxation constants (section 2.1 and 3.1)
+  T lam_p, lam_m;       // lambda_+, lambda_-
+  T inv_1p_lam_p;       // 1/(1+lambda_+): recovers n+ from post-collision f
+  T gvec[3], half_g[3], g_over_lam_m[3];
+  T thr_hi, thr_lo;     // (1+eps), (-eps)
+
+  std::vector<uint8_t> type;  // cell classes
+  std::vector<T> ft;          // post-collision populations ft[q*N + cell]
+  std::vector<T> mass;        // interface mass m (FP64 bookkeeping)
+  std::vector<T> phi;         // fill level at interface cells
+  std::vector<T> rho_c;       // density of the last collision at I cells
+  std::vector<T> u_c;         // velocity of the last collision u_c[a*N+cell]
+  T reservoir = T(0.0);
+  bool freeze = false;        // frozen flag topology (no conversions)
+  long long steps_done = 0;
+
+  // conversion lists of the last step, ascending cell index
+  std::vector<int> listF, listE, listEp, listNI, listNL;
+
+  // ---------------------------------------------------------------- setup
+  void set_params(const Params& q) {
+    p = q;
+    if (p.nx <= 0 || p.ny <= 0 || p.nz <= 0) throw std::runtime_error("dims must be positive");
+    if (!(p.tau > 0.5)) throw std::runtime_error("tau must exceed 1/2");
+    if (!(p.Lambda > 0.0)) throw std::runtime_error("Lambda must be positive");
+    N = p.nx * p.ny * p.nz;
+    // lambda_+ = -1/tau; nu = -(1/3)(1/lambda_+ + 1/2) = (tau - 1/2)/3  (section 2.1)
+    // Lambda_+ = -(1/2 + 1/lambda_+) = tau - 1/2 ; Lambda_- = Lambda / Lambda_+ ;
+    // lambda_- = -1/(Lambda_- + 1/2)                                (section 3.1)
+    double lp = -1.0 / p.tau;
+    double Lp = p.tau - 0.5;
+    double Lm = p.Lambda / Lp;
+    double lm = -1.0 / (Lm + 0.5);
+    lam_p = T(lp);
+    lam_m = T(lm);
+    inv_1p_lam_p = T(1.0 / (1.0 + lp));
+    for (int a = 0; a < 3; ++a) {
+      gvec[a] = T(p.g[a]);
+      half_g[a] = T(0.5 * p.g[a]);
+      g_over_lam_m[a] = T(p.g[a] / lm);
+    }
+    thr_hi = T(1.0 + p.eps);
+    thr_lo = T(-p.eps);
+  }
+
+  // neighbour of cell (x,y,z) at offset d; -1 if it lies beyond a wall
+  int neighbor(int x, int y, int z, int dx, int dy, int dz) const {
+    int c[3] = {x + dx, y + dy, z + dz};
+    int n[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (c[a] < 0 || c[a] >= n[a]) {
+        if (!p.periodic[a]) return -1;
+        c[a] = (c[a] + n[a]) % n[a];
+      }
+    }
+    return c[0] + p.nx * (c[1] + p.ny * c[2]);
+  }
+  void coords(int cell, int& x, int& y, int& z) const {
+    x = cell % p.nx;
+    y = (cell / p.nx) % p.ny;
+    z = cell / (p.nx * p.ny);
+  }
+
+  // The invariant the free-surface model relies on: a liquid cell is never a
+  // direct neighbour of a gas cell (the interface layer separates them).
+  void check_layer_invariant() const {
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] > LIQUID) throw std::runtime_error("unknown cell type");
+      if (type[cell] != LIQUID) continue;
+      int x, y, z;
+      coords(cell, x, y, z);
+      for (int q = 1; q < Q; ++q) {
+        int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s >= 0 && type[s] == GAS)
+          throw std::runtime_error("liquid cell " + std::to_string(cell) + " has a gas neighbour");
+      }
+    }
+  }
+
+  // ----------------------------------------------------- equilibria (2.1)
+  T rho0_of(const T& rho) const { return p.incompressible ? T(1.0) : rho; }
+
+  // c_q . v: the sum of the (at most two) non-zero components
+  static T cdot(int q, const T v[3]) {
+    T s = T(0.0);
+    for (int a = 0; a < 3; ++a) {
+      if (CV[q][a] == 1) s = s + v[a];
+      if (CV[q][a] == -1) s = s - v[a];
+    }
+    return s;
+  }
+
+  // even equilibrium e+_q = (w_q/c_s^2)(P + N_q), P = rho/3,
+  // N_q = (rho_0/2) u_a u_b (3 c_a c_b - delta_ab)    (Eq. eqEven)
+  //     => e+_q = w_q (rho + rho_0 (4.5 (c.u)^2 - 1.5 u.u))
+  T e_plus(int q, const T& rho, const T& rho0, const T u[3]) const {
+    if (p.stokes) return T(weight(q)) * rho;
+    T cu = cdot(q, u);
+    T usq = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    return T(weight(q)) * (rho + rho0 * (T(4.5) * (cu * cu) - T(1.5) * usq));
+  }
+  // odd equilibrium e-_q = (w_q/c_s^2) rho_0 c_q.u_eq      (Eq. eqOdd)
+  T e_minus(int q, const T& rho0, const T ueq[3]) const {
+    T cu = cdot(q, ueq);
+    return T(3.0 * weight(q)) * (rho0 * cu);
+  }
+
+  // Zeroth and first moments (Eq. density, Eq. momentum).
+  static void moments(const T f[Q], T& rho, T j[3]) {
+    rho = f[0];
+    for (int q = 1; q < Q; ++q) rho = rho + f[q];
+    for (int a = 0; a < 3; ++a) {
+      j[a] = T(0.0);
+      for (int q = 0; q < Q; ++q) {
+        if (CV[q][a] == 1) j[a] = j[a] + f[q];
+        if (CV[q][a] == -1) j[a] = j[a] - f[q];
+      }
+    }
+  }
+
+  // TRT collision, Eq. (lbe2), with the force through
+  // u_eq = U - F/lambda_- and rho_0 U = rho_0 u - F/2 = sum c f (section 2.1);
+  // F = rho_0 g (g is an acceleration).  Returns rho and u of the pre-collision
+  // state.
+  void collide(const T f[Q], T out[Q], T& rho, T u[3]) const {
+    T j[3];
+    moments(f, rho, j);
+    T rho0 = rho0_of(rho);
+    T U[3], ueq[3];
+    for (int a = 0; a < 3; ++a) {
+      U[a] = j[a] / rho0;
+      u[a] = U[a] + half_g[a];
+      ueq[a] = U[a] - g_over_lam_m[a];
+    }
+    out[0] = f[0] + lam_p * (f[0] - e_plus(0, rho, rho0, u));
+    for (int q = 1; q < Q; q += 2) {
+      int qb = q + 1;
+      T fp = T(0.5) * (f[q] + f[qb]);  // f+_q
+      T fm = T(0.5) * (f[q] - f[qb]);  // f-_q
+      T np = fp - e_plus(q, rho, rho0, u);
+      T nm = fm - e_minus(q, rho0, ueq);
+      out[q] = (f[q] + lam_p * np) + lam_m * nm;
+      out[qb] = (f[qb] + lam_p * np) - lam_m * nm;
+    }
+  }
+
+  // Post-collision state of a pre-collision equilibrium with density rho and
+  // velocity u: even part e+(rho,u), odd part e-(rho_0, u + g/2) (the collision
+  // of such a state adds rho_0 g to its momentum).  Used for the initial state
+  // and for cells that newly join the interface.
+  void equilibrium_post(const T& rho, const T u[3], T out[Q]) const {
+    T rho0 = rho0_of(rho);
+    T v[3];
+    for (int a = 0; a < 3; ++a) v[a] = u[a] + half_g[a];
+    out[0] = e_plus(0, rho, rho0, u);
+    for (int q = 1; q < Q; q += 2) {
+      T ep = e_plus(q, rho, rho0, u);
+      T em = e_minus(q, rho0, v);
+      out[q] = ep + em;
+      out[q + 1] = ep - em;
+    }
+  }
+
+  // Moments at time t recovered from post-collision populations: rho is
+  // unchanged by the collision, the momentum grew by rho_0 g.
+  void recover_moments(const T ftl[Q], T& rho, T u[3]) const {
+    T j[3];
+    moments(ftl, rho, j);
+    T rho0 = rho0_of(rho);
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] / rho0 - gvec[a]) + half_g[a];
+  }
+
+  // ------------------------------------------- closure coefficients (3.3)
+  // General linear closure Eq. (closure) with f^{p.c.} = C n+ (Eq. correction)
+  // and f^b = alpha_+ e+(rho_b, u_b) (Eq. bterm with S^b = 0).
+  struct Coeffs { T a0, a0bar, a1, alpha_p, C; };
+  // FSK row of Table 1 (D = 0): the rule of Eq. (koerner).
+  Coeffs coeffs_fsk() const { return {T(-1.0), T(0.0), T(0.0), T(2.0), T(0.0)}; }
+  // FSL construction with free parameter alpha_+, Eq. (fsli1)-(fsli4).
+  Coeffs coeffs_fsli(const T& alpha_p, const T& delta) const {
+    Coeffs c;
+    c.a0 = T(1.0) - alpha_p * (T(0.5) + delta);
+    c.a0bar = T(1.0) - T(0.5) * alpha_p;
+    c.a1 = delta * alpha_p - T(1.0);
+    c.alpha_p = alpha_p;
+    c.C = (alpha_p * lam_p) * (T(0.5) + delta) - T(2.0) * lam_p;
+    return c;
+  }
+
+  // --------------------------------------------------------------- init
+  // flags: cell classes; rho, u (u[a*N+cell]): initial macroscopic state;
+  // fill: fill level (used at interface cells; m = fill * rho there).
+  void init_from_fields(const uint8_t* flags, const double* rho, const double* u, const double* fill) {
+    type.assign(flags, flags + N);
+    check_layer_invariant();
+    ft.assign((size_t)Q * N, T(0.0));
+    mass.assign(N, T(0.0));
+    phi.assign(N, T(0.0));
+    rho_c.assign(N, T(0.0));
+    u_c.assign((size_t)3 * N, T(0.0));
+    reservoir = T(0.0);
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] == GAS) continue;
+      T r = T(rho[cell]);
+      T uu[3] = {T(u[cell]), T(u[N + cell]), T(u[2 * N + cell])};
+      T out[Q];
+      equilibrium_post(r, uu, out);
+      for (int q = 0; q < Q; ++q) ft[(size_t)q * N + cell] = out[q];
+      if (type[cell] == INTERFACE) {
+        phi[cell] = T(fill[cell]);
+        mass[cell] = T(fill[cell]) * r;
+        rho_c[cell] = r;
+        for (int a = 0; a < 3; ++a) u_c[(size_t)a * N + cell] = uu[a];
+      }
+    }
+  }
+
+  // Restart / adjoint entry: the state given directly.
+  void init_from_state(const uint8_t* flags, const T* ftin, const T* m, const T* fill, const T& res) {
+    type.assign(flags, flags + N);
+    check_layer_invariant();
+    ft.assign(ftin, ftin + (size_t)Q * N);
+    mass.assign(m, m + N);
+    phi.assign(fill, fill + N);
+    rho_c.assign(N, T(0.0));
+    u_c.assign((size_t)3 * N, T(0.0));
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] != INTERFACE) continue;
+      T f[Q], r, uu[3];
+      for (int q = 0; q < Q; ++q) f[q] = ft[(size_t)q * N + cell];
+      recover_moments(f, r, uu);
+      rho_c[cell] = r;
+      for (int a = 0; a < 3; ++a) u_c[(size_t)a * N + cell] = uu[a];
+    }
+    reservoir = res;
+  }
+
+  // fill level seen by neighbours: liquid 1, gas 0, interface its own value
+  T phi_of(int s) const {
+    if (type[s] == LIQUID) return T(1.0);
+    if (type[s] == GAS) return T(0.0);
+    return phi[s];
+  }
+
+  // ------------------------------------------------------------ one step
+  std::vector<T> ftn;  // second population buffer (pull scheme ping-pong)
+
+  void step(int rule) {
+    ftn.resize((size_t)Q * N);
+    std::vector<T> massn = mass;
+    std::vector<T> phin = phi;
+
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] == GAS) continue;
+      int x, y, z;
+      coords(cell, x, y, z);
+      const bool iface = type[cell] == INTERFACE;
+
+      // own post-collision populations of time t
+      T own[Q];
+      for (int q = 0; q < Q; ++q) own[q] = ft[(size_t)q * N + cell];
+
+      // ---- S1 stream, Eq. (lbe1) in pull form: f_q(x) = ft_q(x - c_q).
+      // A source beyond a wall gives halfway bounce-back f_q(x) = ft_qbar(x).
+      T f[Q];
+      bool gaslink[Q] = {false};
+      int src[Q];
+      for (int q = 0; q < Q; ++q) {
+        int s = neighbor(x, y, z, -CV[q][0], -CV[q][1], -CV[q][2]);
+        src[q] = s;
+        if (s < 0) {
+          f[q] = own[opposite(q)];
+        } else if (type[s] == GAS) {
+          if (!iface) throw std::runtime_error("liquid cell with gas neighbour");
+          gaslink[q] = true;
+          f[q] = T(0.0);
+        } else {
+          f[q] = ft[(size_t)q * N + s];
+        }
+      }
+
+      T m_new = T(0.0);
+      if (iface) {
+        const T phix = phi[cell];
+
+        // ---- S4 mass exchange (interface tracking of the cited FSLBM):
+        // dm = sum_q w_xs (ft_q(x - c_q) - ft_qbar(x)), weight 1 to liquid,
+        // (phi_x + phi_s)/2 to interface, 0 to gas and walls.
+        T dm = T(0.0);
+        for (int q = 1; q < Q; ++q) {
+          int s = src[q];
+          if (s < 0 || type[s] == GAS) continue;
+          T diff = ft[(size_t)q * N + s] - own[opposite(q)];
+          if (type[s] == LIQUID) {
+            dm = dm + diff;
+          } else {
+            T wgt = T(0.5) * (phix + phi[s]);
+            dm = dm + wgt * diff;
+          }
+        }
+        m_new = mass[cell] + dm;
+
+        // ---- S2 interface geometry: normal from the fill-level gradient
+        // (central differences over the six axis neighbours), surface plane
+        // at signed distance phi - 1/2 from the node along the normal.
+        T grad[3];
+        for (int a = 0; a < 3; ++a) {
+          int d[3] = {0, 0, 0};
+          d[a] = 1;
+          int sp = neighbor(x, y, z, d[0], d[1], d[2]);
+          int sm = neighbor(x, y, z, -d[0], -d[1], -d[2]);
+          T vp = sp < 0 ? phix : phi_of(sp);
+          T vm = sm < 0 ? phix : phi_of(sm);
+          grad[a] = T(0.5) * (vp - vm);
+        }
+        T nrm2 = (grad[0] * grad[0] + grad[1] * grad[1]) + grad[2] * grad[2];
+        bool have_normal = nrm2 > T(0.0);
+        T nvec[3] = {T(0.0), T(0.0), T(0.0)};
+        if (have_normal) {
+          T nrm = sqrt(nrm2);
+          for (int a = 0; a < 3; ++a) nvec[a] = -grad[a] / nrm;
+        }
+        T dist = phix - T(0.5);
+
+        // ---- S3 reconstruction of every population streaming in from gas.
+        // In the paper's notation the link to gas is o (x + c_o is gas) and the
+        // unknown is f_{obar} = f_q.  Moments of time t from the own state:
+        T rho_t, u_t[3];
+        recover_moments(own, rho_t, u_t);
+        const T rho0_t = rho0_of(rho_t);
+        const T rho_b = T(p.rho_gas);
+        const T rho0_b = rho0_of(rho_b);
+        for (int q = 1; q < Q; ++q) {
+          if (!gaslink[q]) continue;
+          int o = opposite(q);
+          // n+_o(x,t): pre-collision even non-equilibrium recovered from
+          // ft+ = e+ + (1 + lambda_+) n+
+          T fplus = T(0.5) * (own[o] + own[q]);
+          T n_plus = (fplus - e_plus(o, rho_t, rho0_t, u_t)) * inv_1p_lam_p;
+          T e_b = e_plus(o, rho_b, rho0_b, u_t);  // boundary value, u_b = u(x,t)
+          Coeffs k = coeffs_fsk();
+          T f_o_next = T(0.0);
+          if (rule == FSL) {
+            // ft_o(x - c_o, t) = f_o(x, t+1): the value the pull delivers
+            // along o; unavailable when that source is gas too.
+            bool ok = have_normal && !gaslink[o];
+            T nc = cdot(o, nvec);
+            if (ok && nc > T(0.0)) {
+              T delta = dist / nc;
+              if (delta < T(0.0)) delta = T(0.0);
+              if (delta > T(1.0)) delta = T(1.0);
+              k = coeffs_fsli(T(1.0), delta);
+              f_o_next = f[o];
+            }
+          }
+          // Eq. (closure): f_{obar}(x,t+1) = a0 ft_o + a0bar ft_obar + a1 ft_o(x-c_o)
+          //                                  + C n+_o + alpha_+ e+_o(rho_b,u_b)
+          f[q] = (((k.a0 * own[o] + k.a0bar * own[q]) + k.a1 * f_o_next) + k.C * n_plus) +
+                 k.alpha_p * e_b;
+        }
+      }
+
+      // ---- S5 collide
+      T out[Q], rho, u[3];
+      collide(f, out, rho, u);
+      for (int q = 0; q < Q; ++q) ftn[(size_t)q * N + cell] = out[q];
+
+      if (iface) {
+        // ---- S6 fill level and classification
+        massn[cell] = m_new;
+        phin[cell] = m_new / rho;
+        rho_c[cell] = rho;
+        for (int a = 0; a < 3; ++a) u_c[(size_t)a * N + cell] = u[a];
+      }
+    }
+
+    ft.swap(ftn);
+    mass.swap(massn);
+    phi.swap(phin);
+
+    listF.clear(); listE.clear(); listEp.clear(); listNI.clear(); listNL.clear();
+    if (!freeze) convert();
+    ++steps_done;
+  }
+
+  // ---------------------------------------------- S6/S7 cell conversions
+  // Filled: m > (1+eps) rho; emptied: m < -eps rho (rho of the last collision).
+  void convert() {
+    std::vector<uint8_t> filled(N, 0), emptied(N, 0);
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] != INTERFACE) continue;
+      if (mass[cell] > thr_hi * rho_c[cell]) { filled[cell] = 1; listF.push_back(cell); }
+      if (mass[cell] < thr_lo * rho_c[cell]) { emptied[cell] = 1; listE.push_back(cell); }
+    }
+    auto near_filled = [&](int cell) {
+      int x, y, z;
+      coords(cell, x, y, z);
+      for (int q = 1; q < Q; ++q) {
+        int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s >= 0 && filled[s]) return true;
+      }
+      return false;
+    };
+    // E' = E minus the neighbourhood of F
+    std::vector<uint8_t> emptied2(N, 0);
+    for (int cell : listE)
+      if (!near_filled(cell)) { emptied2[cell] = 1; listEp.push_back(cell); }
+    // NI: gas next to a filled cell; NL: liquid next to an E' cell
+    std::vector<uint8_t> newI(N, 0), newL(N, 0);
+    for (int cell : listF) {
+      int x, y, z;
+      coords(cell, x, y, z);
+      for (int q = 1; q < Q; ++q) {
+        int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s >= 0 && type[s] == GAS) newI[s] = 1;
+      }
+    }
+    for (int cell : listEp) {
+      int x, y, z;
+      coords(cell, x, y, z);
+      for (int q = 1; q < Q; ++q) {
+        int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s >= 0 && type[s] == LIQUID) newL[s] = 1;
+      }
+    }
+    for (int cell = 0; cell < N; ++cell) {
+      if (newI[cell]) listNI.push_back(cell);
+      if (newL[cell]) listNL.push_back(cell);
+    }
+    // New interface cells from gas: post-collision equilibrium with the mean
+    // density and velocity of their interface neighbours (before conversion).
+    for (int cell : listNI) {
+      int x, y, z;
+      coords(cell, x, y, z);
+      T rs = T(0.0), us[3] = {T(0.0), T(0.0), T(0.0)};
+      int cnt = 0;
+      for (int q = 1; q < Q; ++q) {
+        int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s < 0 || type[s] == GAS) continue;
+        rs = rs + rho_c[s];
+        for (int a = 0; a < 3; ++a) us[a] = us[a] + u_c[(size_t)a * N + s];
+        ++cnt;
+      }
+      T rbar = rs / T((double)cnt);
+      T ubar[3];
+      for (int a = 0; a < 3; ++a) ubar[a] = us[a] / T((double)cnt);
+      T out[Q];
+      equilibrium_post(rbar, ubar, out);
+      for (int q = 0; q < Q; ++q) ft[(size_t)q * N + cell] = out[q];
+      mass[cell] = T(0.0);
+      rho_c[cell] = rbar;
+      for (int a = 0; a < 3; ++a) u_c[(size_t)a * N + cell] = ubar[a];
+    }
+    // New interface cells from liquid keep their populations; m = rho.
+    for (int cell : listNL) {
+      T r = ft[cell];
+      for (int q = 1; q < Q; ++q) r = r + ft[(size_t)q * N + cell];
+      mass[cell] = r;
+      rho_c[cell] = r;
+      T f[Q], rr, uu[3];
+      for (int q = 0; q < Q; ++q) f[q] = ft[(size_t)q * N + cell];
+      recover_moments(f, rr, uu);
+      for (int a = 0; a < 3; ++a) u_c[(size_t)a * N + cell] = uu[a];
+    }
+    // excess mass of converted cells
+    std::vector<T> excess(N, T(0.0));
+    for (int cell : listF) excess[cell] = mass[cell] - rho_c[cell];
+    for (int cell : listEp) excess[cell] = mass[cell];
+    // commit the new classes
+    for (int cell : listF) type[cell] = LIQUID;
+    for (int cell : listEp) type[cell] = GAS;
+    for (int cell : listNI) type[cell] = INTERFACE;
+    for (int cell : listNL) type[cell] = INTERFACE;
+    // share of each converted cell: split equally over its interface
+    // neighbours after conversion; none -> reservoir (ascending order).
+    std::vector<T> share(N, T(0.0));
+    std::vector<uint8_t> converted(N, 0);
+    std::vector<int> conv = listF;
+    conv.insert(conv.end(), listEp.begin(), listEp.end());
+    std::sort(conv.begin(), conv.end());
+    for (int cell : conv) {
+      converted[cell] = 1;
+      int x, y, z;
+      coords(cell, x, y, z);
+      int n_elig = 0;
+      for (int q = 1; q < Q; ++q) {
+        int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s >= 0 && type[s] == INTERFACE) ++n_elig;
+      }
+      if (n_elig == 0) {
+        reservoir = reservoir + excess[cell];
+        converted[cell] = 0;
+      } else {
+        share[cell] = excess[cell] / T((double)n_elig);
+      }
+    }
+    // every interface cell gathers the shares of its converted neighbours
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] != INTERFACE) continue;
+      int x, y, z;
+      coords(cell, x, y, z);
+      bool got = false;
+      T m = mass[cell];
+      for (int q = 1; q < Q; ++q) {
+        int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s >= 0 && converted[s]) { m = m + share[s]; got = true; }
+      }
+      if (got) {
+        mass[cell] = m;
+        phi[cell] = m / rho_c[cell];
+      }
+    }
+    for (int cell : listF) { mass[cell] = T(0.0); phi[cell] = T(0.0); }
+    for (int cell : listEp) { mass[cell] = T(0.0); phi[cell] = T(0.0); }
+  }
+
+  // ------------------------------------------------------- diagnostics
+  // M = sum over liquid of sum_q ft + sum over interface of m + reservoir
+  T total_mass() const {
+    T M = T(0.0);
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] == LIQUID) {
+        T r = ft[cell];
+        for (int q = 1; q < Q; ++q) r = r + ft[(size_t)q * N + cell];
+        M = M + r;
+      } else if (type[cell] == INTERFACE) {
+        M = M + mass[cell];
+      }
+    }
+    return M + reservoir;
+  }
+};
+
+}  // namespace fsref

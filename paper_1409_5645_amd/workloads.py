@@ -1,0 +1,182 @@
+"""Seeded synthetic inputs for the free-surface LBM step.
+
+This module produces initial *macroscopic* fields only -- cell classes, density,
+velocity and fill level -- plus the model parameters.  It contains none of the
+lattice Boltzmann arithmetic: the GPU library and the oracle each build their
+own populations from these fields.  Both the tests and the benchmark use it.
+
+Geometry conventions: cell (i, j, k) has linear index i + nx*(j + ny*k), its
+centre sits at y = j + 1/2, and a wall at a non-periodic face lies half a cell
+beyond the outermost cells (bounce-back, first node at distance 1/2; the
+steady film experiment of section 4.3 uses that placement).  A liquid column of
+height eta fills cell j with min(max(eta - j, 0), 1).  Fill 1 is liquid, fill 0
+is gas, anything in between is interface; a liquid cell touching gas on any
+D3Q19 link is turned into an interface cell with fill 1, so that a layer of
+interface cells always separates liquid from gas (section 2.3).
+
+Initial density: rho_gas plus the hydrostatic head 3|g_y| (eta - y) of the
+liquid above the cell centre (c_s^2 = 1/3, incompressible form); velocity 0.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+GAS, INTERFACE, LIQUID = 0, 1, 2
+
+# offsets of the 18 nearest neighbours on the cubic lattice (|d|^2 = 1 or 2)
+_NEIGHBOURS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+               if 1 <= dx * dx + dy * dy + dz * dz <= 2]
+
+
+@dataclasses.dataclass
+class Params:
+    nx: int
+    ny: int
+    nz: int
+    periodic: tuple = (0, 0, 0)
+    tau: float = 0.8
+    Lambda: float = 3.0 / 16.0
+    incompressible: int = 1
+    stokes: int = 0
+    g: tuple = (0.0, 0.0, 0.0)
+    rho_gas: float = 1.0
+    eps: float = 1e-3
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    params: Params
+    flags: np.ndarray            # uint8[N]
+    rho: np.ndarray              # float64[N]
+    u: np.ndarray | None         # float64[3, N] or None (= at rest)
+    fill: np.ndarray             # float64[N]
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    def velocity(self) -> np.ndarray:
+        if self.u is None:
+            return np.zeros((3, self.params.n_cells))
+        return self.u
+
+    def counts(self) -> dict:
+        b = np.bincount(self.flags, minlength=3)
+        return {"gas": int(b[GAS]), "interface": int(b[INTERFACE]), "liquid": int(b[LIQUID])}
+
+
+def _shift_any(mask3: np.ndarray, periodic) -> np.ndarray:
+    """True where any of the 18 neighbours (walls excluded) is set in mask3."""
+    out = np.zeros_like(mask3)
+    nz, ny, nx = mask3.shape
+    for dx, dy, dz in _NEIGHBOURS:
+        src = mask3
+        for axis, d, per in ((2, dx, periodic[0]), (1, dy, periodic[1]), (0, dz, periodic[2])):
+            if d == 0:
+                continue
+            if per:
+                src = np.roll(src, -d, axis=axis)
+            else:
+                # neighbour at +d; cells whose neighbour is beyond the wall get False
+                sl_dst = [slice(None)] * 3
+                sl_src = [slice(None)] * 3
+                n = src.shape[axis]
+                if d > 0:
+                    sl_dst[axis] = slice(0, n - d)
+                    sl_src[axis] = slice(d, n)
+                else:
+                    sl_dst[axis] = slice(-d, n)
+                    sl_src[axis] = slice(0, n + d)
+                tmp = np.zeros_like(src)
+                tmp[tuple(sl_dst)] = src[tuple(sl_src)]
+                src = tmp
+        out |= src
+    return out
+
+
+def _from_height(params: Params, eta_x: np.ndarray, name: str, meta: dict) -> Workload:
+    """Liquid below a surface height eta(x) (uniform in z)."""
+    nx, ny, nz = params.nx, params.ny, params.nz
+    j = np.arange(ny, dtype=np.float64)
+    fill2 = np.clip(eta_x[None, :] - j[:, None], 0.0, 1.0)          # [ny, nx]
+    types2 = np.where(fill2 >= 1.0, LIQUID, np.where(fill2 <= 0.0, GAS, INTERFACE)).astype(np.uint8)
+    types3 = np.broadcast_to(types2, (nz, ny, nx)).copy()
+    fill3 = np.broadcast_to(fill2, (nz, ny, nx)).copy()
+    gas_near = _shift_any(types3 == GAS, params.periodic)
+    promote = (types3 == LIQUID) & gas_near
+    types3[promote] = INTERFACE
+    fill3[promote] = 1.0
+    yc = j + 0.5
+    if params.g[1] == 0.0:
+        rho2 = np.full((ny, nx), params.rho_gas)
+    else:
+        rho2 = params.rho_gas + 3.0 * abs(params.g[1]) * (eta_x[None, :] - yc[:, None])
+    rho3 = np.broadcast_to(rho2, (nz, ny, nx)).copy()
+    rho3[types3 == GAS] = params.rho_gas
+    flags = types3.reshape(-1)
+    return Workload(name=name, params=params, flags=flags, rho=rho3.reshape(-1), u=None,
+                    fill=fill3.reshape(-1), meta=meta)
+
+
+def channel(h: float = 32.5, nx: int = 8, ny: int = 48, nz: int = 8, gx: float = 1e-6,
+            tau: float = 0.8, Lambda: float = 3.0 / 16.0, stokes: int = 0) -> Workload:
+    """Gravity-driven open-channel film: x, z periodic, wall at y = 0 (and at
+    the top, which only ever borders gas), flat surface at height h."""
+    p = Params(nx=nx, ny=ny, nz=nz, periodic=(1, 0, 1), tau=tau, Lambda=Lambda,
+               g=(gx, 0.0, 0.0), stokes=stokes)
+    eta = np.full(nx, float(h))
+    return _from_height(p, eta, "channel", {"h": h, "gx": gx})
+
+
+def channel_sweep(h: int, tau: float = 0.8, Lambda: float = 3.0 / 16.0, frac: float = 0.5,
+                  stokes: int = 0, nx: int = 4, nz: int = 4) -> Workload:
+    """Convergence-sweep member: film of height h + frac on a 4 x (h+16) x 4
+    grid, g_x = 1e-6 (32/h)^3 (diffusive scaling at fixed Reynolds number)."""
+    gx = 1e-6 * (32.0 / h) ** 3
+    w = channel(h=h + frac, nx=nx, ny=h + 16, nz=nz, gx=gx, tau=tau, Lambda=Lambda, stokes=stokes)
+    w.name = f"sweep_h{h}"
+    w.meta.update({"h_cells": h, "frac": frac})
+    return w
+
+
+def sloshing(nx: int = 256, ny: int = 160, nz: int = 256, depth: float = 96.0, amp: float = 6.0,
+             seed: int = 0, gy: float = -2e-5, tau: float = 0.55, Lambda: float = 3.0 / 16.0,
+             wavelength: float | None = None, periodic=(0, 0, 0)) -> Workload:
+    """Closed tank (walls on all faces) with a cosine surface
+    eta(i) = depth + amp cos(2 pi (i + 1/2)/wavelength + theta), theta drawn
+    from the seed, uniform in z, liquid initially at hydrostatic rest."""
+    rng = np.random.default_rng(seed)
+    theta = 2.0 * math.pi * float(rng.random())
+    lam = float(nx if wavelength is None else wavelength)
+    i = np.arange(nx, dtype=np.float64)
+    eta = depth + amp * np.cos(2.0 * math.pi * (i + 0.5) / lam + theta)
+    p = Params(nx=nx, ny=ny, nz=nz, periodic=tuple(periodic), tau=tau, Lambda=Lambda, g=(0.0, gy, 0.0))
+    return _from_height(p, eta, "sloshing",
+                        {"depth": depth, "amp": amp, "seed": seed, "theta": theta, "wavelength": lam})
+
+
+def pool(nx: int = 32, ny: int = 64, nz: int = 32, level: float = 40.5, gy: float = -1e-5,
+         tau: float = 0.8, Lambda: float = 3.0 / 16.0) -> Workload:
+    """Flat pool at hydrostatic rest in a closed tank."""
+    p = Params(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 0), tau=tau, Lambda=Lambda, g=(0.0, gy, 0.0))
+    return _from_height(p, np.full(nx, float(level)), "pool", {"level": level})
+
+
+# Named configurations (sizes of the measured workloads).
+def config(name: str, seed: int = 0) -> Workload:
+    if name == "channel":
+        return channel()
+    if name.startswith("sweep"):
+        return channel_sweep(int(name[len("sweep"):]))
+    if name == "slosh256":
+        return sloshing(256, 160, 256, depth=96.0, amp=6.0, seed=seed)
+    if name == "slosh512":
+        return sloshing(512, 320, 512, depth=192.0, amp=12.0, seed=seed)
+    if name == "slosh128":
+        return sloshing(128, 96, 128, depth=48.0, amp=3.0, seed=seed)
+    raise KeyError(name)
