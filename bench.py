@@ -1,0 +1,221 @@
+"""Benchmark of the free-surface LBM time step on one MI355X.
+
+Workload: the 512 x 320 x 512 sloshing tank (84 M cells, liquid depth 192 with a
+cosine surface of amplitude 12, walls on all faces, g_y = -2e-5, tau = 0.55,
+FSL rule), synthetic and seeded.  A step is one full time step: the fused
+stream/collide/interface sweep and the conversion kernels.  Each precision form
+(FP64, FP32 on shifted populations, FP16 storage of shifted populations) runs
+`warmup` untimed and `steps` timed steps from the same initial state; the
+velocity and fill errors of each form against the FP64 run are reported after
+the same number of steps (relative L2 / L-infinity norms over cells that are
+liquid or interface in both runs).
+
+Printed: one JSON line.  `value` is the MLUPS (million active-cell updates per
+second, active = liquid + interface) of the headline form (FP16 storage,
+FP32 compute).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32"}
+HEADLINE = "fp16s"
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fslbm_device.hpp", "fslbm_kernels.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1409_5645_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(form: str, n_act: float, n_cells: int):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != sweep_source_hash() or form not in d.get("forms", {}):
+        return None
+    return d["forms"][form].get("bytes_per_launch")
+
+
+def errors(ref: dict, other: dict) -> dict:
+    """Relative L2 and L-inf of u and phi (Eq. l2error, maxerror) over cells
+    active in both runs; flag mismatch count."""
+    import torch
+    act = (ref["flags"] != 0) & (other["flags"] != 0)
+    out = {"flag_mismatch": int((ref["flags"] != other["flags"]).sum().item())}
+    for name in ("u", "phi"):
+        a, b = other[name], ref[name]
+        if name == "u":
+            a, b = a[:, act], b[:, act]
+        else:
+            a, b = a[act], b[act]
+        d = (a - b).double()
+        out[f"{name}_l2"] = float(torch.sqrt((d * d).sum() / (b.double() * b.double()).sum()).item())
+        out[f"{name}_linf"] = float((d.abs().max() / b.abs().max()).item())
+    return out
+
+
+def run_form(w, form, steps, warmup, rule, log):
+    import torch
+    from paper_1409_5645_amd import fslbm
+    t0 = time.time()
+    s = fslbm.Sim.from_workload(w, precision=form)
+    st0 = s.stats()
+    log(f"[{form}] init {time.time() - t0:.1f}s, active {st0['liquid'] + st0['interface']}")
+    s.step(warmup, rule)
+    torch.cuda.synchronize()
+    stream = s.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.timing(True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(steps, rule)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    sweep_ms, nsweeps = s.timing(False)
+    st1 = s.stats()
+    n_act = 0.5 * ((st0["liquid"] + st0["interface"]) + (st1["liquid"] + st1["interface"]))
+    ms = ms_total / steps
+    sweep_avg = sweep_ms / max(nsweeps, 1)
+    alg_bytes = n_act * 38 * STORAGE_BYTES[form] + w.params.n_cells * 1
+    res = {
+        "mlups": n_act / (ms * 1e-3) / 1e6,
+        "mlups_all_cells": w.params.n_cells / (ms * 1e-3) / 1e6,
+        "ms_per_step": ms,
+        "sweep_ms": sweep_avg,
+        "sweep_share": sweep_ms / ms_total,
+        "active_cells": n_act,
+        "alg_bytes_per_sweep": alg_bytes,
+        "sweep_gbs": alg_bytes / (sweep_avg * 1e-3) / 1e9,
+        "mass_drift": (st1["total_mass"] - st0["total_mass"]) / st0["total_mass"],
+        "conversions_last_step": st1["filled"] + st1["emptied_converted"],
+    }
+    log(f"[{form}] {ms:.3f} ms/step, sweep {sweep_avg:.3f} ms, {res['mlups']:.0f} MLUPS, "
+        f"{res['sweep_gbs']:.0f} GB/s alg.")
+    f = s.fields(("u", "phi", "flags"), device=True)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return res, f
+
+
+def cpu_baseline(w_full, log, budget_s=12.0):
+    """The serial FP64 oracle on a z-slab of the same tank (same x-y profile,
+    walls on all faces), timed on one host core."""
+    import oracle
+    from paper_1409_5645_amd import workloads as W
+    p = w_full.params
+    nz = 16
+    m = w_full.meta
+    w = W.sloshing(p.nx, p.ny, nz, depth=m["depth"], amp=m["amp"], seed=m["seed"], gy=p.g[1], tau=p.tau,
+                   Lambda=p.Lambda, wavelength=m["wavelength"])
+    o = oracle.Oracle.from_workload(w)
+    n_act = int((w.flags != 0).sum())
+    t0 = time.time()
+    o.step(1, 1)
+    t1 = time.time() - t0
+    n = max(1, int(budget_s / max(t1, 1e-3)) - 1)
+    t0 = time.time()
+    o.step(n, 1)
+    dt = time.time() - t0
+    mlups = n_act * n / dt / 1e6
+    log(f"[cpu oracle] {n} steps of {p.nx}x{p.ny}x{nz}: {mlups:.2f} MLUPS")
+    return {"value": mlups, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n} FSL steps (after 1 untimed) of a {p.nx}x{p.ny}x{nz} z-slab of the same tank "
+                      f"({n_act} active cells), serial FP64 oracle, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--forms", default="fp64,fp32,fp16s")
+    ap.add_argument("--config", default="slosh512")
+    ap.add_argument("--rule", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    def log(msg):
+        if not args.quiet:
+            print(msg, file=sys.stderr, flush=True)
+
+    import torch
+    from paper_1409_5645_amd import fslbm, workloads as W
+    if not os.path.exists(fslbm.LIB_PATH):
+        from paper_1409_5645_amd import build
+        build.build()
+    t0 = time.time()
+    w = W.config(args.config, seed=0)
+    log(f"workload {w.name} {w.params.nx}x{w.params.ny}x{w.params.nz} generated in {time.time() - t0:.1f}s "
+        f"{w.counts()}")
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    results, fieldsets = {}, {}
+    for form in forms:
+        results[form], fieldsets[form] = run_form(w, form, args.steps, args.warmup, args.rule, log)
+    if "fp64" in fieldsets:
+        for form in forms:
+            if form != "fp64":
+                results[form]["err_vs_fp64"] = errors(fieldsets["fp64"], fieldsets[form])
+    fieldsets.clear()
+    torch.cuda.empty_cache()
+
+    head = HEADLINE if HEADLINE in results else forms[-1]
+    r = results[head]
+    traffic = traffic_for(head, r["active_cells"], w.params.n_cells)
+    roof = {"bound": "hbm", "achieved": r["sweep_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"k_sweep<{head}, FSL>",
+            "bytes_per_launch": r["alg_bytes_per_sweep"], "avg_launch_ms": r["sweep_ms"]}
+    for form in forms:
+        results[form]["roofline_frac"] = results[form]["sweep_gbs"] / HBM_PEAK_GBS
+    line = {
+        "metric": "MLUPS + % HBM roofline per form (FP64/FP32/FP16-store, FSL) at stated err vs FP64",
+        "value": r["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[head],
+        "storage": "f16" if head == "fp16s" else DTYPE[head],
+        "data": "synthetic",
+        "config": {"workload": f"sloshing tank {w.params.nx}x{w.params.ny}x{w.params.nz} "
+                               f"(depth {w.meta['depth']:g}, amplitude {w.meta['amp']:g}, seed 0), FSL rule, "
+                               f"tau {w.params.tau}, g_y {w.params.g[1]:g}",
+                   "cells": w.params.n_cells, "active_cells": r["active_cells"], "form": head},
+        "roofline": roof,
+        "forms": results,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, log)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

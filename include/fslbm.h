@@ -1,0 +1,175 @@
+/*
+ * fslbm.h -- C interface of the MI355X free-surface lattice Boltzmann library.
+ *
+ * One time step (Bogner, Ammer, Ruede, "Boundary Conditions for Free Interfaces
+ * with the Lattice Boltzmann Method"):
+ *   - D3Q19 two-relaxation-time stream/collide, Eq. (lbe1), (lbe2), with the
+ *     equilibria Eq. (eqEven), (eqOdd) and the body force through
+ *     u_eq = U - F/lambda_- (section 2.1);
+ *   - halfway bounce-back at every non-periodic domain face (section 4.3);
+ *   - reconstruction of every population that streams in from a gas cell by the
+ *     general linear closure Eq. (closure) with the FSK row of Table 1 (the rule
+ *     of Eq. (koerner)) or the FSL row (Eq. (fsli1)-(fsli4), alpha_+ = 1), with
+ *     S^b = 0 (section 3.4);
+ *   - mass exchange, fill-level update and interface <-> liquid / gas cell
+ *     conversion with excess-mass redistribution (the interface tracking of the
+ *     free-surface LBM that section 2.3 describes and section 4.4 cites).
+ *
+ * Memory: every device buffer is allocated by the caller (e.g. as torch
+ * tensors) and borrowed by the library until fslbm_destroy; the library never
+ * frees caller memory.  The library owns only its host-side context.
+ *
+ * Streams: fslbm_step enqueues work on the stream given at init and returns
+ * without synchronising.  Functions documented as "synchronises" wait for that
+ * stream.
+ *
+ * Errors: every entry point returns a status; no C++ exception crosses this
+ * interface.  fslbm_last_error gives a message for the last failure on a
+ * context.  HIP runtime failures map to FSLBM_E_DEVICE.
+ *
+ * Layout: a cell (x, y, z) has linear index idx = x + nx*(y + ny*z); population
+ * q of cell idx is element q*N + idx of a population buffer (N = nx*ny*nz).
+ * The population order is: q = 0 rest; 1..6 the axis links (+x, -x, +y, -y,
+ * +z, -z); 7..18 the diagonals (+x+y, -x-y, +x-y, -x+y, +x+z, -x-z, +x-z,
+ * -x+z, +y+z, -y-z, +y-z, -y+z); odd q has its opposite at q + 1.
+ */
+#ifndef FSLBM_H
+#define FSLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSLBM_ABI_VERSION 1
+
+typedef struct fslbm_ctx fslbm_ctx;
+
+typedef enum {
+  FSLBM_OK = 0,
+  FSLBM_E_INVALID = 1,      /* bad argument, size or cell-class pattern */
+  FSLBM_E_UNSUPPORTED = 2,  /* valid but not supported (e.g. FSL at tau = 1) */
+  FSLBM_E_DEVICE = 3,       /* HIP runtime error */
+  FSLBM_E_UNSTABLE = 4,     /* NaN or non-positive density found by fslbm_stats */
+  FSLBM_E_INVARIANT = 5,    /* a liquid cell touches a gas cell */
+  FSLBM_E_CAPACITY = 6      /* an output array is too small */
+} fslbm_status;
+
+/* Gas-side reconstruction rule (Table 1). */
+enum { FSLBM_RULE_FSK = 0, FSLBM_RULE_FSL = 1 };
+
+/* Precision forms.  FP64: populations f stored and computed in double.
+ * FP32: shifted populations f - w_q stored and computed in float.
+ * FP16S: shifted populations scaled by 2^fp16_scale_log2 stored as IEEE
+ * binary16 (round to nearest even), computed in float.  Mass, fill level and
+ * excess-mass redistribution are double in every form. */
+enum { FSLBM_FP64 = 0, FSLBM_FP32 = 1, FSLBM_FP16S = 2 };
+
+/* Cell classes stored in the flags array. */
+enum { FSLBM_GAS = 0, FSLBM_INTERFACE = 1, FSLBM_LIQUID = 2 };
+
+typedef struct {
+  int32_t abi_version;      /* FSLBM_ABI_VERSION */
+  int32_t nx, ny, nz;       /* lattice size, each >= 1, nx*ny*nz < 2^31 / 19 */
+  int32_t periodic[3];      /* nonzero: periodic axis; zero: bounce-back walls */
+  int32_t precision;        /* FSLBM_FP64, FSLBM_FP32 or FSLBM_FP16S */
+  double tau;               /* symmetric relaxation time, lambda_+ = -1/tau; > 1/2 */
+  double magic;             /* Lambda = Lambda_+ Lambda_- (section 3.1); > 0 */
+  int32_t incompressible;   /* nonzero: rho_0 = 1; zero: rho_0 = rho (section 2.1) */
+  int32_t stokes;           /* nonzero: drop the quadratic term N_q of e+ */
+  double g[3];              /* body acceleration (force F = rho_0 g) */
+  double rho_gas;           /* gas density rho_b, pressure P_b = rho_b / 3 */
+  double conv_eps;          /* conversion margin: filled m > (1+eps) rho, emptied m < -eps rho */
+  int32_t fp16_scale_log2;  /* FP16S scale exponent k (storage 2^k (f - w)); 0..24 */
+  int32_t freeze;           /* nonzero: frozen flag topology, no conversions */
+} fslbm_params;
+
+typedef struct {
+  void* f[2];               /* 2 buffers of 19*N elements of the storage type
+                               (double, float or binary16) */
+  uint8_t* flags;           /* N cell classes; filled by the caller before init */
+  double* mass;             /* N interface mass values */
+  double* phi[2];           /* 2 buffers of N fill levels */
+  void* workspace;          /* fslbm_workspace_size bytes, 256-byte aligned */
+  size_t workspace_bytes;
+  void* stream;             /* hipStream_t, or NULL for the null stream */
+} fslbm_buffers;
+
+/* Bytes of workspace a context with these parameters needs. */
+fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes);
+
+/* Validate parameters and buffers, check the cell classes on the device (every
+ * class in {GAS, INTERFACE, LIQUID}; no liquid cell has a gas cell among its 18
+ * neighbours, walls excluded) and create a context.  Rejects: dims < 1, too
+ * many cells, tau <= 1/2, magic <= 0, an unknown precision, NULL buffers, a
+ * short workspace.  Synchronises.  Populations are undefined until
+ * fslbm_set_equilibrium or fslbm_set_state. */
+fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out);
+
+/* Initial state from macroscopic fields (device pointers, double): rho[N],
+ * u[3*N] (u[a*N + idx]) and fill[N].  Every non-gas cell gets the
+ * post-collision state of a resting-frame equilibrium, e+(rho,u) +
+ * e-(rho_0, u + g/2); interface cells get m = fill * rho.  Synchronises. */
+fslbm_status fslbm_set_equilibrium(fslbm_ctx* c, const double* rho, const double* u, const double* fill);
+
+/* Initial state given directly (device pointers, double): post-collision
+ * populations f[19*N] (unshifted), mass[N] and fill[N] (read at interface
+ * cells), and the reservoir value.  Synchronises. */
+fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, const double* fill,
+                             double reservoir);
+
+/* Enqueue n time steps with rule FSLBM_RULE_FSK or FSLBM_RULE_FSL.  FSL with
+ * tau = 1 is FSLBM_E_UNSUPPORTED (n+ cannot be recovered from the
+ * post-collision state).  Asynchronous. */
+fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule);
+
+/* Field export into caller device buffers.  mask selects fields by bit; dst[i]
+ * is the destination of bit i (unused entries may be NULL):
+ *   bit 0 rho     double[N]   density from the current populations (gas: 0)
+ *   bit 1 u       double[3N]  velocity u = U + g/2 of time t (gas: 0)
+ *   bit 2 phi     double[N]   fill level: liquid 1, gas 0, interface m/rho
+ *   bit 3 flags   uint8[N]    cell classes
+ *   bit 4 f       double[19N] post-collision populations, unshifted
+ *   bit 5 mass    double[N]   interface mass (meaningful at interface cells)
+ *   bit 6 rho_c   double[N]   density of the last collision (interface cells)
+ *   bit 7 u_c     double[3N]  velocity of the last collision (interface cells)
+ * Synchronises. */
+fslbm_status fslbm_fields(fslbm_ctx* c, uint32_t mask, void* const* dst);
+
+/* Diagnostics (host outputs).  total_mass = sum over liquid cells of sum_q f +
+ * sum over interface cells of m + reservoir (double).  counts: [0] filled,
+ * [1] emptied, [2] emptied and converted, [3] new interface from gas, [4] new
+ * interface from liquid (all of the last step), [5] interface cells now,
+ * [6] liquid cells now, [7] steps done.  Returns FSLBM_E_UNSTABLE if a
+ * non-gas cell has a NaN or non-positive density.  Synchronises. */
+fslbm_status fslbm_stats(fslbm_ctx* c, double* total_mass, double* reservoir, int64_t counts[8]);
+
+/* Conversion lists of the last step into host arrays, ascending cell index:
+ * out[0] filled, out[1] emptied, out[2] emptied and converted, out[3] new
+ * interface from gas, out[4] new interface from liquid.  n_out[i] receives each
+ * length; FSLBM_E_CAPACITY if a length exceeds cap (the first cap entries are
+ * still written).  Synchronises. */
+fslbm_status fslbm_conversions(fslbm_ctx* c, int32_t* const* out, int32_t cap, int32_t n_out[5]);
+
+/* Kernel timing of the stream/collide sweep (the kernel that moves the
+ * populations).  enable = 1 clears the record and starts bracketing every
+ * sweep launch of fslbm_step with a pair of HIP events on the context's
+ * stream; enable = 0 stops recording.  In both cases, when sweep_ms / sweeps
+ * are non-NULL, they receive the summed event-to-event time (milliseconds) and
+ * the number of sweeps recorded so far (synchronises). */
+fslbm_status fslbm_timing(fslbm_ctx* c, int32_t enable, double* sweep_ms, int64_t* sweeps);
+
+/* Release the context (not the caller's buffers).  Synchronises. */
+fslbm_status fslbm_destroy(fslbm_ctx* c);
+
+/* Message of the last failure on c, or of the last failed fslbm_init when c is
+ * NULL.  Valid until the next call on the same context. */
+const char* fslbm_last_error(const fslbm_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSLBM_H */

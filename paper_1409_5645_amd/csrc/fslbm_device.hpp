@@ -1,0 +1,244 @@
+// Device-side building blocks of the free-surface LBM step on gfx950:
+// D3Q19 lattice tables, precision forms, equilibria and the TRT collision.
+//
+// Floating-point expression order is fixed (ascending-q sums, no FMA
+// contraction: the library is compiled with -ffp-contract=off) so that the FP64
+// form is reproducible bit for bit on any IEEE machine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fslbm {
+
+constexpr int Q = 19;
+
+// D3Q19 velocities: rest, axis links, diagonals; odd q has its opposite at q+1.
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+// Lattice weights w_q (Qian et al.; c_s^2 = 1/3) and 3 w_q = w_q / c_s^2.
+constexpr double WD[Q] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+constexpr double W3D[Q] = {3.0 * (1.0 / 3.0),  3.0 * (1.0 / 18.0), 3.0 * (1.0 / 18.0), 3.0 * (1.0 / 18.0),
+                           3.0 * (1.0 / 18.0), 3.0 * (1.0 / 18.0), 3.0 * (1.0 / 18.0), 3.0 * (1.0 / 36.0),
+                           3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0),
+                           3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0),
+                           3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0)};
+
+enum : uint8_t { GAS = 0, IFACE = 1, LIQ = 2 };
+
+// ---------------------------------------------------------------- forms
+// R: compute type; S: storage type.  Shifted forms store g_q = f_q - w_q, so
+// that "density" in storage convention is delta rho = rho - 1.
+struct FormF64 {
+  using R = double;
+  using S = double;
+  static constexpr bool shifted = false;
+  __device__ static R load(const S* p, float) { return *p; }
+  __device__ static void store(S* p, R v, float) { *p = v; }
+};
+struct FormF32 {
+  using R = float;
+  using S = float;
+  static constexpr bool shifted = true;
+  __device__ static R load(const S* p, float) { return *p; }
+  __device__ static void store(S* p, R v, float) { *p = v; }
+};
+struct FormF16 {
+  using R = float;
+  using S = _Float16;
+  static constexpr bool shifted = true;
+  // stored value = 2^k g in binary16 (round to nearest even); scale factors
+  // are exact powers of two
+  __device__ static R load(const S* p, float inv_scale) { return (float)(*p) * inv_scale; }
+  __device__ static void store(S* p, R v, float scale) { *p = (_Float16)(v * scale); }
+};
+
+// Per-form constants (all derived on the host in double, then rounded once).
+template <class R>
+struct Consts {
+  R lp, lm, inv1p;        // lambda_+, lambda_-, 1/(1+lambda_+)
+  R g[3], hg[3], glm[3];  // g, g/2, g/lambda_-
+  R rhob_s;               // gas density in storage convention
+  R rho0b;                // rho_0 used with the gas density
+};
+
+// c_q . v with the non-zero components only, in axis order
+template <int q, class R>
+__device__ __forceinline__ R cdot(const R v[3]) {
+  R s = R(0.0);
+  if (CX[q] == 1) s = s + v[0];
+  if (CX[q] == -1) s = s - v[0];
+  if (CY[q] == 1) s = s + v[1];
+  if (CY[q] == -1) s = s - v[1];
+  if (CZ[q] == 1) s = s + v[2];
+  if (CZ[q] == -1) s = s - v[2];
+  return s;
+}
+
+template <class R>
+__device__ __forceinline__ R usq_of(const R u[3]) {
+  return (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+}
+
+// even equilibrium e+_q (Eq. eqEven) in storage convention:
+// w_q (rho_s + rho_0 (4.5 (c.u)^2 - 1.5 u.u)); rho_s is rho or rho - 1
+template <int q, class R>
+__device__ __forceinline__ R e_plus(R rho_s, R rho0, bool incomp, bool stokes, const R u[3], R usq) {
+  if (stokes) return R(WD[q]) * rho_s;
+  R cu = cdot<q>(u);
+  R nl = R(4.5) * (cu * cu) - R(1.5) * usq;
+  if (!incomp) nl = rho0 * nl;
+  return R(WD[q]) * (rho_s + nl);
+}
+
+// odd equilibrium e-_q (Eq. eqOdd): 3 w_q rho_0 c_q.u_eq
+template <int q, class R>
+__device__ __forceinline__ R e_minus(R rho0, bool incomp, const R ueq[3]) {
+  R cu = cdot<q>(ueq);
+  if (!incomp) cu = rho0 * cu;
+  return R(W3D[q]) * cu;
+}
+
+// zeroth moment (storage convention) and first moment, ascending q
+template <class R>
+__device__ __forceinline__ void moments(const R f[Q], R& rho_s, R j[3]) {
+  R r = f[0];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) r = r + f[q];
+  rho_s = r;
+  R jx = R(0.0), jy = R(0.0), jz = R(0.0);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (CX[q] == 1) jx = jx + f[q];
+    if (CX[q] == -1) jx = jx - f[q];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (CY[q] == 1) jy = jy + f[q];
+    if (CY[q] == -1) jy = jy - f[q];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (CZ[q] == 1) jz = jz + f[q];
+    if (CZ[q] == -1) jz = jz - f[q];
+  }
+  j[0] = jx;
+  j[1] = jy;
+  j[2] = jz;
+}
+
+template <class R, bool SHIFTED>
+__device__ __forceinline__ R rho0_of(R rho_s, bool incomp) {
+  if (incomp) return R(1.0);
+  return SHIFTED ? R(1.0) + rho_s : rho_s;
+}
+
+// TRT collision, Eq. (lbe2), force through u_eq = U - g/lambda_- (F = rho_0 g).
+// Overwrites f with the post-collision populations; returns rho_s and u.
+template <class R, bool SHIFTED>
+__device__ __forceinline__ void collide(R f[Q], const Consts<R>& k, bool incomp, bool stokes, R& rho_s,
+                                        R u[3]) {
+  R j[3];
+  moments(f, rho_s, j);
+  const R rho0 = rho0_of<R, SHIFTED>(rho_s, incomp);
+  R ueq[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R U = incomp ? j[a] : j[a] / rho0;
+    u[a] = U + k.hg[a];
+    ueq[a] = U - k.glm[a];
+  }
+  const R usq = usq_of(u);
+  {
+    R ep = e_plus<0>(rho_s, rho0, incomp, stokes, u, usq);
+    f[0] = f[0] + k.lp * (f[0] - ep);
+  }
+#define FSLBM_PAIR(q)                                            \
+  {                                                              \
+    R fp = R(0.5) * (f[q] + f[q + 1]);                           \
+    R fm = R(0.5) * (f[q] - f[q + 1]);                           \
+    R np = fp - e_plus<q>(rho_s, rho0, incomp, stokes, u, usq);  \
+    R nm = fm - e_minus<q>(rho0, incomp, ueq);                   \
+    R a = f[q], b = f[q + 1];                                    \
+    f[q] = (a + k.lp * np) + k.lm * nm;                          \
+    f[q + 1] = (b + k.lp * np) - k.lm * nm;                      \
+  }
+  FSLBM_PAIR(1) FSLBM_PAIR(3) FSLBM_PAIR(5) FSLBM_PAIR(7) FSLBM_PAIR(9) FSLBM_PAIR(11) FSLBM_PAIR(13)
+  FSLBM_PAIR(15) FSLBM_PAIR(17)
+#undef FSLBM_PAIR
+}
+
+// Post-collision state of a resting-frame equilibrium (rho, u):
+// e+(rho, u) + e-(rho_0, u + g/2).  rho_s in storage convention.
+template <class R, bool SHIFTED>
+__device__ __forceinline__ void equilibrium_post(R rho_s, const R u[3], const Consts<R>& k, bool incomp,
+                                                 bool stokes, R out[Q]) {
+  const R rho0 = rho0_of<R, SHIFTED>(rho_s, incomp);
+  R v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v[a] = u[a] + k.hg[a];
+  const R usq = usq_of(u);
+  out[0] = e_plus<0>(rho_s, rho0, incomp, stokes, u, usq);
+#define FSLBM_EQ(q)                                             \
+  {                                                             \
+    R ep = e_plus<q>(rho_s, rho0, incomp, stokes, u, usq);      \
+    R em = e_minus<q>(rho0, incomp, v);                         \
+    out[q] = ep + em;                                           \
+    out[q + 1] = ep - em;                                       \
+  }
+  FSLBM_EQ(1) FSLBM_EQ(3) FSLBM_EQ(5) FSLBM_EQ(7) FSLBM_EQ(9) FSLBM_EQ(11) FSLBM_EQ(13) FSLBM_EQ(15)
+  FSLBM_EQ(17)
+#undef FSLBM_EQ
+}
+
+// Moments of time t recovered from post-collision populations (the collision
+// keeps rho and adds rho_0 g to the momentum): u = (j/rho_0 - g) + g/2.
+template <class R, bool SHIFTED>
+__device__ __forceinline__ void recover_moments(const R f[Q], const Consts<R>& k, bool incomp, R& rho_s,
+                                                R u[3]) {
+  R j[3];
+  moments(f, rho_s, j);
+  const R rho0 = rho0_of<R, SHIFTED>(rho_s, incomp);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R U = incomp ? j[a] : j[a] / rho0;
+    u[a] = (U - k.g[a]) + k.hg[a];
+  }
+}
+
+// ------------------------------------------------------------- geometry
+struct Grid {
+  int nx, ny, nz, N;
+  int px, py, pz;
+};
+
+// coordinate one step along an axis; -1 if beyond a wall
+__device__ __forceinline__ int step_axis(int c, int d, int n, int per) {
+  int s = c + d;
+  if (s < 0) return per ? n - 1 : -1;
+  if (s >= n) return per ? 0 : -1;
+  return s;
+}
+
+// neighbour index of (x,y,z) at offset (dx,dy,dz); -1 beyond a wall
+__device__ __forceinline__ int neighbor(const Grid& g, int x, int y, int z, int dx, int dy, int dz) {
+  int sx = dx ? step_axis(x, dx, g.nx, g.px) : x;
+  int sy = dy ? step_axis(y, dy, g.ny, g.py) : y;
+  int sz = dz ? step_axis(z, dz, g.nz, g.pz) : z;
+  if ((sx | sy | sz) < 0) return -1;
+  return sx + g.nx * (sy + g.ny * sz);
+}
+
+__device__ __forceinline__ void coords(const Grid& g, int idx, int& x, int& y, int& z) {
+  x = idx % g.nx;
+  int r = idx / g.nx;
+  y = r % g.ny;
+  z = r / g.ny;
+}
+
+}  // namespace fslbm

@@ -1,0 +1,127 @@
+// Internal interface between the C-ABI host code and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fslbm_device.hpp"
+
+namespace fslbm {
+
+// list counters of one step (two sets, selected by step parity)
+enum { C_F = 0, C_E = 1, C_EP = 2, C_NI = 3, C_NL = 4, C_I = 5, C_R = 6, NCOUNT = 8 };
+
+struct Common {
+  Grid grid;
+  Consts<double> kd;
+  Consts<float> kf;
+  int incomp, stokes;
+  float scale, inv_scale;  // FP16 storage scaling (powers of two)
+};
+
+template <class R>
+__device__ __forceinline__ const Consts<R>& pick_consts(const Common& c);
+template <>
+__device__ __forceinline__ const Consts<double>& pick_consts<double>(const Common& c) {
+  return c.kd;
+}
+template <>
+__device__ __forceinline__ const Consts<float>& pick_consts<float>(const Common& c) {
+  return c.kf;
+}
+
+struct SweepArgs {
+  Common c;
+  const void* fin;
+  void* fout;
+  const uint8_t* flags;
+  double* mass;
+  const double* phi_in;
+  double* phi_out;
+  double* aux_rho;
+  double* aux_u;
+  int32_t* f_epoch;
+  int32_t* listF;
+  int32_t* listE;
+  int32_t* counters;
+  int32_t* counters_next;
+  double thr_hi, thr_lo;
+  int step;
+  int freeze;
+};
+
+struct ConvArgs {
+  Common c;
+  void* fout;  // populations of time t+1
+  uint8_t* flags;
+  double* mass;
+  double* phi_out;
+  double* aux_rho;
+  const double* aux_u;
+  int32_t* f_epoch;
+  int32_t* new_epoch;
+  int32_t* recv_epoch;
+  int32_t* conv_epoch;
+  int32_t *listF, *listE, *listEP, *listNI, *listNL, *listR;
+  int32_t* counters;
+  double* reservoir;
+  int step;
+};
+
+struct StepLaunch {
+  SweepArgs sweep;
+  ConvArgs conv;
+  void* stream;
+};
+
+struct InitArgs {
+  Common c;
+  void* f;
+  const uint8_t* flags;
+  double* mass;
+  double* phi;
+  double* aux_rho;
+  double* aux_u;
+};
+
+struct FieldArgs {
+  Common c;
+  const void* f;
+  const uint8_t* flags;
+  const double* mass;
+  const double* phi;
+  const double* aux_rho;
+  const double* aux_u;
+  double* rho_out;
+  double* u_out;
+  double* phi_out;
+  uint8_t* flags_out;
+  double* f_out;
+  double* mass_out;
+  double* rhoc_out;
+  double* uc_out;
+};
+
+struct StatArgs {
+  Common c;
+  const void* f;
+  const uint8_t* flags;
+  const double* mass;
+  double* acc;    // [0] mass sum
+  int32_t* cnt;   // [0] liquid cells, [1] bad cells, [2] interface cells
+};
+
+hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
+hipError_t launch_convert(const StepLaunch& L, int precision);
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, void* stream);
+hipError_t launch_fill_f64(double* p, size_t n, double v, void* stream);
+hipError_t launch_check_flags(const uint8_t* flags, const Grid& g, int32_t* err, void* stream);
+hipError_t launch_set_equilibrium(const InitArgs& a, int precision, const double* rho, const double* u,
+                                  const double* fill, void* stream);
+hipError_t launch_set_state(const InitArgs& a, int precision, const double* f, const double* mass,
+                            const double* fill, void* stream);
+hipError_t launch_fields(const FieldArgs& a, int precision, void* stream);
+hipError_t launch_stats(const StatArgs& a, int precision, void* stream);
+
+}  // namespace fslbm

@@ -1,0 +1,211 @@
+"""ctypes binding of libfslbm.so (the C interface of include/fslbm.h).
+
+Argument marshalling only: torch allocates the device buffers and supplies the
+stream; every step of the method runs in the library's HIP kernels.  There is
+no CPU fallback: if the library is missing or no GPU is present, construction
+fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfslbm.so")
+
+FSK, FSL = 0, 1
+FP64, FP32, FP16S = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
+GAS, INTERFACE, LIQUID = 0, 1, 2
+STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "DEVICE", 4: "UNSTABLE", 5: "INVARIANT", 6: "CAPACITY"}
+FIELDS = ("rho", "u", "phi", "flags", "f", "mass", "rho_c", "u_c")
+ABI_VERSION = 1
+
+
+class FslbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fslbm {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("periodic", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("magic", ctypes.c_double), ("incompressible", ctypes.c_int32),
+                ("stokes", ctypes.c_int32), ("g", ctypes.c_double * 3), ("rho_gas", ctypes.c_double),
+                ("conv_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32), ("freeze", ctypes.c_int32)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p * 2), ("flags", ctypes.c_void_p), ("mass", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p * 2), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+
+
+EXPORTS = ("fslbm_workspace_size", "fslbm_init", "fslbm_set_equilibrium", "fslbm_set_state", "fslbm_step",
+           "fslbm_fields", "fslbm_stats", "fslbm_conversions", "fslbm_timing", "fslbm_destroy",
+           "fslbm_last_error")
+
+_lib = None
+
+
+def lib():
+    """Load libfslbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1409_5645_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.fslbm_workspace_size.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
+        L.fslbm_init.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Buffers), ctypes.POINTER(vp)]
+        L.fslbm_set_equilibrium.argtypes = [vp, vp, vp, vp]
+        L.fslbm_set_state.argtypes = [vp, vp, vp, vp, ctypes.c_double]
+        L.fslbm_step.argtypes = [vp, i32, i32]
+        L.fslbm_fields.argtypes = [vp, u32, ctypes.POINTER(vp)]
+        L.fslbm_stats.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.fslbm_conversions.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(i32)), i32, ctypes.POINTER(i32)]
+        L.fslbm_timing.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.fslbm_destroy.argtypes = [vp]
+        L.fslbm_last_error.argtypes = [vp]
+        L.fslbm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "fslbm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13) -> Params:
+    """C parameter block from a workloads.Params."""
+    return Params(ABI_VERSION, p.nx, p.ny, p.nz, (ctypes.c_int32 * 3)(*[int(v) for v in p.periodic]),
+                  int(precision), float(p.tau), float(p.Lambda), int(p.incompressible), int(p.stokes),
+                  (ctypes.c_double * 3)(*[float(v) for v in p.g]), float(p.rho_gas), float(p.eps),
+                  int(fp16_scale_log2), int(bool(freeze)))
+
+
+class Sim:
+    """One simulation on a GPU.  Buffers are torch tensors on `device`."""
+
+    def __init__(self, params, flags, precision="fp64", device="cuda:0", stream=None, freeze=False,
+                 fp16_scale_log2=13):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("fslbm needs a GPU (torch.cuda.is_available() is False)")
+        L = lib()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = params
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.N = N = params.nx * params.ny * params.nz
+        self.cp = make_params(params, self.precision, freeze, fp16_scale_log2)
+        ws = ctypes.c_size_t()
+        self._check(L.fslbm_workspace_size(ctypes.byref(self.cp), ctypes.byref(ws)), None)
+        dt = {FP64: torch.float64, FP32: torch.float32, FP16S: torch.float16}[self.precision]
+        with torch.cuda.device(self.device):
+            self.stream = stream or torch.cuda.current_stream(self.device)
+            self.f = [torch.empty(19 * N, dtype=dt, device=self.device) for _ in range(2)]
+            self.flags_t = torch.as_tensor(np.ascontiguousarray(flags, dtype=np.uint8)).to(self.device)
+            self.mass_t = torch.zeros(N, dtype=torch.float64, device=self.device)
+            self.phi_t = [torch.zeros(N, dtype=torch.float64, device=self.device) for _ in range(2)]
+            self.ws = torch.empty(ws.value, dtype=torch.uint8, device=self.device)
+        assert self.ws.data_ptr() % 256 == 0
+        b = Buffers((ctypes.c_void_p * 2)(self.f[0].data_ptr(), self.f[1].data_ptr()), self.flags_t.data_ptr(),
+                    self.mass_t.data_ptr(), (ctypes.c_void_p * 2)(self.phi_t[0].data_ptr(), self.phi_t[1].data_ptr()),
+                    self.ws.data_ptr(), ws.value, self.stream.cuda_stream)
+        torch.cuda.synchronize(self.device)
+        h = ctypes.c_void_p()
+        self._check(L.fslbm_init(ctypes.byref(self.cp), ctypes.byref(b), ctypes.byref(h)), None)
+        self.ctx = h
+
+    # ------------------------------------------------------------- helpers
+    def _check(self, st, ctx):
+        if st != 0:
+            msg = lib().fslbm_last_error(ctx).decode()
+            raise FslbmError(st, msg)
+
+    def _dev(self, a, dtype=None):
+        t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=dtype or np.float64))
+        return t.to(self.device)
+
+    @classmethod
+    def from_workload(cls, w, precision="fp64", **kw):
+        s = cls(w.params, w.flags, precision=precision, **kw)
+        s.set_equilibrium(w.rho, w.velocity(), w.fill)
+        return s
+
+    # ---------------------------------------------------------------- API
+    def set_equilibrium(self, rho, u, fill):
+        r, uu, fi = self._dev(rho), self._dev(u), self._dev(fill)
+        self.torch.cuda.synchronize(self.device)
+        self._check(lib().fslbm_set_equilibrium(self.ctx, r.data_ptr(), uu.data_ptr(), fi.data_ptr()), self.ctx)
+
+    def set_state(self, f, mass, fill, reservoir=0.0):
+        ff, m, fi = self._dev(f), self._dev(mass), self._dev(fill)
+        self.torch.cuda.synchronize(self.device)
+        self._check(lib().fslbm_set_state(self.ctx, ff.data_ptr(), m.data_ptr(), fi.data_ptr(), float(reservoir)),
+                    self.ctx)
+
+    def step(self, n=1, rule=FSL):
+        self._check(lib().fslbm_step(self.ctx, int(n), int(rule)), self.ctx)
+
+    def fields(self, names=FIELDS, device=False) -> dict:
+        """Requested fields as numpy arrays, or torch device tensors when
+        device=True (synchronises)."""
+        torch = self.torch
+        N = self.N
+        shapes = {"rho": (N,), "u": (3, N), "phi": (N,), "flags": (N,), "f": (19, N), "mass": (N,),
+                  "rho_c": (N,), "u_c": (3, N)}
+        out = {}
+        ptrs = (ctypes.c_void_p * 8)()
+        mask = 0
+        for name in names:
+            i = FIELDS.index(name)
+            dt = torch.uint8 if name == "flags" else torch.float64
+            out[name] = torch.empty(shapes[name], dtype=dt, device=self.device)
+            ptrs[i] = out[name].data_ptr()
+            mask |= 1 << i
+        self._check(lib().fslbm_fields(self.ctx, mask, ptrs), self.ctx)
+        if device:
+            return out
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
+    def stats(self) -> dict:
+        M, R = ctypes.c_double(), ctypes.c_double()
+        c = (ctypes.c_int64 * 8)()
+        self._check(lib().fslbm_stats(self.ctx, ctypes.byref(M), ctypes.byref(R), c), self.ctx)
+        keys = ("filled", "emptied", "emptied_converted", "new_from_gas", "new_from_liquid", "interface",
+                "liquid", "steps")
+        d = {k: int(v) for k, v in zip(keys, c)}
+        d.update(total_mass=M.value, reservoir=R.value)
+        return d
+
+    def conversions(self, cap=None) -> dict:
+        """Lists of the last step, ascending: F, E, E', NI, NL."""
+        cap = self.N if cap is None else cap
+        bufs = [np.empty(max(cap, 1), dtype=np.int32) for _ in range(5)]
+        arr = (ctypes.POINTER(ctypes.c_int32) * 5)(*[b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for b in bufs])
+        n = (ctypes.c_int32 * 5)()
+        self._check(lib().fslbm_conversions(self.ctx, arr, int(cap), n), self.ctx)
+        return {k: bufs[i][:n[i]].copy() for i, k in enumerate(("F", "E", "E'", "NI", "NL"))}
+
+    def timing(self, enable: bool):
+        """Start (True) or stop (False) sweep-kernel event timing; returns the
+        summed sweep milliseconds and the number of sweeps recorded."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(lib().fslbm_timing(self.ctx, int(bool(enable)), ctypes.byref(ms), ctypes.byref(n)), self.ctx)
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().fslbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

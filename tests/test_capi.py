@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every symbol include/fslbm.h declares
+(no compute: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fslbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fslbm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    from paper_1409_5645_amd import build, fslbm
+    if not os.path.exists(fslbm.LIB_PATH):
+        build.build()
+    return fslbm.LIB_PATH
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("fslbm_init", "fslbm_step", "fslbm_fields", "fslbm_stats", "fslbm_conversions",
+              "fslbm_set_equilibrium", "fslbm_set_state", "fslbm_destroy", "fslbm_last_error",
+              "fslbm_workspace_size"):
+        assert n in names
+
+
+def test_library_exports_all_declared(libpath):
+    lib = ctypes.CDLL(libpath)
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_workspace_size_and_param_validation(libpath):
+    from paper_1409_5645_amd import fslbm, workloads as W
+    L = fslbm.lib()
+    p = W.Params(nx=10, ny=12, nz=14)
+    cp = fslbm.make_params(p)
+    ws = ctypes.c_size_t()
+    assert L.fslbm_workspace_size(ctypes.byref(cp), ctypes.byref(ws)) == 0
+    assert ws.value >= 72 * 10 * 12 * 14
+    for field, bad in (("tau", 0.5), ("magic", 0.0), ("precision", 7), ("nx", 0), ("abi_version", 99),
+                       ("fp16_scale_log2", 40), ("rho_gas", -1.0)):
+        cp2 = fslbm.make_params(p)
+        setattr(cp2, field, bad)
+        assert L.fslbm_workspace_size(ctypes.byref(cp2), ctypes.byref(ws)) == 1, field
+        assert L.fslbm_last_error(None)
+    # init with NULL buffers is rejected before any device work
+    b = fslbm.Buffers()
+    h = ctypes.c_void_p()
+    assert L.fslbm_init(ctypes.byref(cp), ctypes.byref(b), ctypes.byref(h)) == 1
+    assert b"NULL" in L.fslbm_last_error(None)
+
+
+def test_binding_fails_loudly_without_gpu(libpath):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1409_5645_amd import fslbm, workloads as W
+    w = W.channel(nx=2, nz=2)
+    with pytest.raises(RuntimeError):
+        fslbm.Sim.from_workload(w)

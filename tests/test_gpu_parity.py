@@ -1,0 +1,201 @@
+"""GPU library (through the C-ABI) against the serial FP64 oracle.
+
+FP64 form: cell classes and conversion lists bit-exact, populations within
+1e-12 relative (the expression order is the same on both sides, so they are in
+fact expected to agree bit for bit).  FP32 / FP16-storage forms: stated
+tolerances against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_1409_5645_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def fs():
+    from paper_1409_5645_amd import fslbm
+    return fslbm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _compare(o, s, tag, rel=REL, exact_flags=True, lists=True):
+    """Compare a GPU Sim with an oracle at the same step."""
+    fo = o.populations()
+    flo = o.flags()
+    g = s.fields(("f", "flags", "mass", "phi"))
+    if exact_flags:
+        bad = np.nonzero(g["flags"] != flo)[0]
+        assert bad.size == 0, f"{tag}: {bad.size} cell classes differ, first {bad[:10]}"
+    act = flo != W.GAS
+    a, b = g["f"][:, act], fo[:, act]
+    err = np.abs(a - b).max() / np.abs(b).max()
+    assert err <= rel, f"{tag}: population rel err {err:.3e}"
+    it = flo == W.INTERFACE
+    if it.any():
+        merr = np.abs(g["mass"][it] - o.mass()[it]).max()
+        assert merr <= rel * 10, f"{tag}: interface mass err {merr:.3e}"
+        perr = np.abs(g["phi"][it] - o.phi()[it]).max()
+        assert perr <= rel * 10, f"{tag}: fill err {perr:.3e}"
+    if lists:
+        lo, lg = o.lists(), s.conversions()
+        for k in lo:
+            np.testing.assert_array_equal(lg[k], lo[k], err_msg=f"{tag}: list {k}")
+    return err
+
+
+def _run_pair(fs, oracle_mod, w, rule, steps, every, precision="fp64", rel=REL):
+    _say(f"case {w.name} {w.params.nx}x{w.params.ny}x{w.params.nz} rule={rule} {precision} steps={steps}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    errs = []
+    done = 0
+    while done < steps:
+        n = min(every, steps - done)
+        o.step(n, rule)
+        s.step(n, rule)
+        done += n
+        errs.append(_compare(o, s, f"{w.name} step {done}", rel=rel))
+    return o, s, errs
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_channel_fp64_parity(fs, oracle_mod, rule):
+    """Channel film 8 x 48 x 8 (frozen topology in practice)."""
+    w = W.channel()
+    o, s, errs = _run_pair(fs, oracle_mod, w, rule, 600, 200)
+    _say("channel max rel err", max(errs))
+    st = s.stats()
+    assert st["total_mass"] == pytest.approx(o.total_mass(), rel=1e-12)
+
+
+@pytest.mark.parametrize("rule", [1, 0])
+def test_sloshing_fp64_parity_with_conversions(fs, oracle_mod, rule):
+    """Small tank with a ragged x extent (37 cells: several wavefronts and a
+    partial one per row) and strong gravity so that cells convert every few
+    steps: classes and lists bit-exact after every step."""
+    w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    _say(f"case sloshing 37x24x10 rule={rule}")
+    nconv = 0
+    for it in range(150):
+        o.step(1, rule)
+        s.step(1, rule)
+        if it % 10 == 9 or it < 5:
+            _compare(o, s, f"step {it + 1}")
+        else:
+            lo, lg = o.lists(), s.conversions()
+            for k in lo:
+                np.testing.assert_array_equal(lg[k], lo[k], err_msg=f"step {it + 1} list {k}")
+        nconv += len(o.lists()["F"]) + len(o.lists()["E'"])
+    assert nconv > 20
+    st = s.stats()
+    assert st["total_mass"] == pytest.approx(o.total_mass(), rel=1e-12)
+    assert st["reservoir"] == pytest.approx(o.reservoir(), abs=1e-12)
+
+
+def test_periodic_and_degenerate_extents(fs, oracle_mod):
+    """nx = 1 periodic (a row wraps onto itself) and nz = 1 periodic."""
+    w = W.channel(h=10.83, nx=1, ny=16, nz=1, gx=5e-6)
+    _run_pair(fs, oracle_mod, w, 1, 200, 100)
+    w = W.sloshing(19, 14, 1, depth=7.0, amp=2.0, seed=3, gy=-3e-4, tau=0.6, periodic=(1, 0, 1))
+    _run_pair(fs, oracle_mod, w, 1, 120, 40)
+
+
+def test_all_liquid_and_orphan(fs, oracle_mod):
+    """No interface cells at all; then one isolated interface cell that fills
+    with no interface neighbour (its excess goes to the reservoir)."""
+    n = 9
+    p = W.Params(nx=n, ny=n, nz=n, periodic=(1, 1, 1), tau=0.7, g=(1e-5, 0, 0))
+    flags = np.full(n ** 3, W.LIQUID, np.uint8)
+    rng = np.random.default_rng(0)
+    rho = 1.0 + 1e-3 * rng.standard_normal(n ** 3)
+    u = 1e-3 * rng.standard_normal((3, n ** 3))
+    o = oracle_mod.Oracle(p, flags, rho, u, np.ones(n ** 3))
+    s = fs.Sim(p, flags)
+    s.set_equilibrium(rho, u, np.ones(n ** 3))
+    o.step(50, 1)
+    s.step(50, 1)
+    _compare(o, s, "all liquid")
+    c = 4 + n * (4 + n * 4)
+    flags[c] = W.INTERFACE
+    fill = np.ones(n ** 3)
+    fill[c] = 1.3
+    o = oracle_mod.Oracle(p, flags, np.ones(n ** 3), None, fill)
+    s = fs.Sim(p, flags)
+    s.set_equilibrium(np.ones(n ** 3), np.zeros((3, n ** 3)), fill)
+    o.step(1, 1)
+    s.step(1, 1)
+    _compare(o, s, "orphan")
+    assert s.stats()["reservoir"] == pytest.approx(o.reservoir(), abs=1e-15)
+    assert s.stats()["reservoir"] == pytest.approx(0.3, abs=1e-6)
+
+
+def test_invalid_flags_rejected(fs):
+    p = W.Params(nx=6, ny=6, nz=6, periodic=(1, 1, 1))
+    flags = np.full(216, W.LIQUID, np.uint8)
+    flags[10] = W.GAS
+    with pytest.raises(fs.FslbmError) as e:
+        fs.Sim(p, flags)
+    assert e.value.status == 1
+    flags[10] = 7
+    with pytest.raises(fs.FslbmError):
+        fs.Sim(p, flags)
+
+
+def test_fsl_rejected_at_tau_one(fs):
+    w = W.channel(nx=2, nz=2, tau=1.0)
+    s = fs.Sim.from_workload(w)
+    with pytest.raises(fs.FslbmError) as e:
+        s.step(1, 1)
+    assert e.value.status == 2
+    s.step(1, 0)
+
+
+def test_restart_and_determinism(fs, oracle_mod):
+    """Export the state, re-initialise a new context from it, continue: the
+    result is bit-identical to an uninterrupted run, and two runs agree bit for
+    bit (no order-dependent arithmetic outside the reservoir)."""
+    w = W.sloshing(40, 28, 12, depth=13.0, amp=3.0, seed=5, gy=-4e-4, tau=0.6)
+    a = fs.Sim.from_workload(w)
+    a.step(60, 1)
+    st = a.fields(("f", "mass", "phi", "flags"))
+    res = a.stats()["reservoir"]
+    b = fs.Sim(w.params, st["flags"])
+    b.set_state(st["f"], st["mass"], st["phi"], res)
+    a.step(60, 1)
+    b.step(60, 1)
+    fa, fb = a.fields(("f", "flags", "mass")), b.fields(("f", "flags", "mass"))
+    np.testing.assert_array_equal(fa["flags"], fb["flags"])
+    np.testing.assert_array_equal(fa["f"], fb["f"])
+    np.testing.assert_array_equal(fa["mass"], fb["mass"])
+    c = fs.Sim.from_workload(w)
+    c.step(120, 1)
+    fc = c.fields(("f", "flags"))
+    np.testing.assert_array_equal(fa["f"], fc["f"])
+    np.testing.assert_array_equal(fa["flags"], fc["flags"])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp16s", 2e-3)])
+def test_reduced_precision_channel(fs, oracle_mod, precision, tol):
+    """FP32 on shifted populations and FP16 storage against the FP64 oracle on
+    the channel film (velocity error relative to the maximum velocity)."""
+    w = W.channel()
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    o.step(1000, 1)
+    s.step(1000, 1)
+    _, uo = o.macro()
+    ug = s.fields(("u",))["u"]
+    act = w.flags != W.GAS
+    err = np.abs(ug[0, act] - uo[0, act]).max() / np.abs(uo[0, act]).max()
+    _say(precision, "channel u rel err", err)
+    assert err < tol
+    np.testing.assert_array_equal(s.fields(("flags",))["flags"], o.flags())
