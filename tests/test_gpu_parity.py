@@ -183,7 +183,13 @@ def test_restart_and_determinism(fs, oracle_mod):
     np.testing.assert_array_equal(fa["flags"], fc["flags"])
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp16s", 2e-3)])
+# Tolerances.  FP32: the film velocity u ~ g t grows by g = 1e-6 per step while
+# u reaches 1e-3, so each FP32 update u + g is rounded to ulp(u)/2 ~ 2^-24 u,
+# i.e. a relative error of up to 2^-24 per step on u: n = 1000 steps give at
+# most ~6e-5.  FP16 storage: every stored population carries a relative error
+# of 2^-11 of its shifted value w (delta rho + 3 c.u) ~ w u, i.e. ~5e-4 of u per
+# step, damped by the collision; 3e-2 bounds the accumulated error.
+@pytest.mark.parametrize("precision,tol", [("fp32", 6e-5), ("fp16s", 3e-2)])
 def test_reduced_precision_channel(fs, oracle_mod, precision, tol):
     """FP32 on shifted populations and FP16 storage against the FP64 oracle on
     the channel film (velocity error relative to the maximum velocity)."""
