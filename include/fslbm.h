@@ -72,7 +72,7 @@ enum { FSLBM_GAS = 0, FSLBM_INTERFACE = 1, FSLBM_LIQUID = 2 };
 
 typedef struct {
   int32_t abi_version;      /* FSLBM_ABI_VERSION */
-  int32_t nx, ny, nz;       /* lattice size, each >= 1, nx*ny*nz < 2^31 / 19 */
+  int32_t nx, ny, nz;       /* lattice size, each >= 1, 19*nx*ny*nz < 2^32 */
   int32_t periodic[3];      /* nonzero: periodic axis; zero: bounce-back walls */
   int32_t precision;        /* FSLBM_FP64, FSLBM_FP32 or FSLBM_FP16S */
   double tau;               /* symmetric relaxation time, lambda_+ = -1/tau; > 1/2 */

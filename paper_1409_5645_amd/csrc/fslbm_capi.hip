@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -27,7 +28,7 @@ struct fslbm_ctx {
   double* aux_rho;
   double* aux_u;
   int32_t *f_epoch, *new_epoch, *recv_epoch, *conv_epoch;
-  int32_t *listF, *listE, *listEP, *listNI, *listNL, *listR;
+  int32_t *listF, *listE, *listEP, *listNI, *listNL, *listR, *listI;
   int32_t* counters;    // 2 sets of NCOUNT
   double* reservoir;
   double* acc;
@@ -38,6 +39,7 @@ struct fslbm_ctx {
   bool timing = false;
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
+  int pairs = 1;  // FP16 sweep with two cells per lane (FSLBM_FP16_PAIRS=0 disables)
 };
 
 namespace {
@@ -48,7 +50,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t aux_rho, aux_u, epochs[4], lists[6], counters, scalars, total;
+  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, total;
 };
 
 Layout layout(size_t N) {
@@ -62,7 +64,7 @@ Layout layout(size_t N) {
     L.epochs[i] = o;
     o = align_up(o + 4 * N);
   }
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < 7; ++i) {
     L.lists[i] = o;
     o = align_up(o + 4 * N);
   }
@@ -79,7 +81,8 @@ fslbm_status check_params(const fslbm_params* p, std::string& why) {
   if (p->abi_version != FSLBM_ABI_VERSION) { why = "abi_version mismatch"; return FSLBM_E_INVALID; }
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "dimensions must be >= 1"; return FSLBM_E_INVALID; }
   const double n = (double)p->nx * (double)p->ny * (double)p->nz;
-  if (n > 2147483647.0) { why = "too many cells (N must be < 2^31)"; return FSLBM_E_INVALID; }
+  // 32-bit element offsets address the 19 population planes of a buffer
+  if (19.0 * n > 4294967295.0) { why = "too many cells (19 N must be < 2^32)"; return FSLBM_E_INVALID; }
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { why = "tau must exceed 1/2"; return FSLBM_E_INVALID; }
   if (!(p->magic > 0.0) || !std::isfinite(p->magic)) { why = "magic (Lambda) must be positive"; return FSLBM_E_INVALID; }
   if (p->precision < FSLBM_FP64 || p->precision > FSLBM_FP16S) { why = "unknown precision"; return FSLBM_E_INVALID; }
@@ -187,13 +190,14 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   c->phi[0] = b->phi[0];
   c->phi[1] = b->phi[1];
   c->stream = (hipStream_t)b->stream;
+  if (const char* e = std::getenv("FSLBM_FP16_PAIRS")) c->pairs = std::atoi(e) != 0;
   char* w = (char*)b->workspace;
   c->aux_rho = (double*)(w + L.aux_rho);
   c->aux_u = (double*)(w + L.aux_u);
   int32_t** ep[4] = {&c->f_epoch, &c->new_epoch, &c->recv_epoch, &c->conv_epoch};
   for (int i = 0; i < 4; ++i) *ep[i] = (int32_t*)(w + L.epochs[i]);
-  int32_t** ls[6] = {&c->listF, &c->listE, &c->listEP, &c->listNI, &c->listNL, &c->listR};
-  for (int i = 0; i < 6; ++i) *ls[i] = (int32_t*)(w + L.lists[i]);
+  int32_t** ls[7] = {&c->listF, &c->listE, &c->listEP, &c->listNI, &c->listNL, &c->listR, &c->listI};
+  for (int i = 0; i < 7; ++i) *ls[i] = (int32_t*)(w + L.lists[i]);
   c->counters = (int32_t*)(w + L.counters);
   c->reservoir = (double*)(w + L.scalars);
   c->acc = c->reservoir + 1;
@@ -277,12 +281,15 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.f_epoch = c->f_epoch;
     s.listF = c->listF;
     s.listE = c->listE;
+    s.listI = c->listI;
     s.counters = c->counters + (c->step & 1) * NCOUNT;
     s.counters_next = c->counters + ((c->step + 1) & 1) * NCOUNT;
     s.thr_hi = c->thr_hi;
     s.thr_lo = c->thr_lo;
     s.step = c->step;
     s.freeze = c->p.freeze ? 1 : 0;
+    s.cpr = 0;
+    s.pairs = c->pairs;
     ConvArgs& v = L.conv;
     v.c = c->com;
     v.fout = c->f[b];
@@ -318,6 +325,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
       HIPCHK(c, hipEventRecord(c->events[c->events_used + 1], c->stream), "event record");
       c->events_used += 2;
     }
+    HIPCHK(c, launch_iface(L, c->p.precision, rule), "interface launch");
     if (!c->p.freeze) HIPCHK(c, launch_convert(L, c->p.precision), "conversion launch");
     c->cur = b;
     c->step += 1;

@@ -38,15 +38,21 @@ struct FormF64 {
   using R = double;
   using S = double;
   static constexpr bool shifted = false;
+  static constexpr bool scaled = false;
   __device__ static R load(const S* p, float) { return *p; }
   __device__ static void store(S* p, R v, float) { *p = v; }
+  __device__ static R load_raw(const S* p) { return *p; }
+  __device__ static void store_raw(S* p, R v) { *p = v; }
 };
 struct FormF32 {
   using R = float;
   using S = float;
   static constexpr bool shifted = true;
+  static constexpr bool scaled = false;
   __device__ static R load(const S* p, float) { return *p; }
   __device__ static void store(S* p, R v, float) { *p = v; }
+  __device__ static R load_raw(const S* p) { return *p; }
+  __device__ static void store_raw(S* p, R v) { *p = v; }
 };
 struct FormF16 {
   using R = float;
@@ -54,8 +60,12 @@ struct FormF16 {
   static constexpr bool shifted = true;
   // stored value = 2^k g in binary16 (round to nearest even); scale factors
   // are exact powers of two
+  static constexpr bool scaled = true;
   __device__ static R load(const S* p, float inv_scale) { return (float)(*p) * inv_scale; }
   __device__ static void store(S* p, R v, float scale) { *p = (_Float16)(v * scale); }
+  // scaled units: the stored value 2^k g itself (the sweep collides in these units)
+  __device__ static R load_raw(const S* p) { return (float)(*p); }
+  __device__ static void store_raw(S* p, R v) { *p = (_Float16)v; }
 };
 
 // Per-form constants (all derived on the host in double, then rounded once).
@@ -171,6 +181,68 @@ __device__ __forceinline__ void collide(R f[Q], const Consts<R>& k, bool incomp,
   FSLBM_PAIR(1) FSLBM_PAIR(3) FSLBM_PAIR(5) FSLBM_PAIR(7) FSLBM_PAIR(9) FSLBM_PAIR(11) FSLBM_PAIR(13)
   FSLBM_PAIR(15) FSLBM_PAIR(17)
 #undef FSLBM_PAIR
+}
+
+// The same collision for the FP32 forms, written with fused multiply-adds (the
+// reduced-precision forms are not reproduced bit for bit, so the contraction
+// that saves issue slots is taken here and only here).
+// The same collision for the FP32 forms, written with fused multiply-adds (the
+// reduced-precision forms are not reproduced bit for bit, so the contraction
+// that saves issue slots is taken here and only here).  With SCALED, f holds
+// populations in units of 1/sc (the FP16 storage scale), which the collision is
+// linear in except for the quadratic equilibrium term and the velocity; sc is
+// folded into those constants instead of rescaling all 19 values.
+template <bool SHIFTED, bool SCALED>
+__device__ __forceinline__ void collide_f32_scaled(float f[Q], const Consts<float>& k, bool incomp, bool stokes,
+                                                   float sc, float isc, float& rho_s, float u[3]) {
+  float j[3];
+  moments(f, rho_s, j);  // rho_s, j in units of 1/sc
+  const float rho0 = incomp ? 1.0f : (SHIFTED ? (SCALED ? __builtin_fmaf(rho_s, isc, 1.0f) : 1.0f + rho_s)
+                                              : rho_s);
+  float ueq[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float Js = SCALED ? j[a] * isc : j[a];
+    const float U = incomp ? Js : Js / rho0;
+    u[a] = U + k.hg[a];
+    ueq[a] = U - k.glm[a];
+  }
+  const float c45 = SCALED ? 4.5f * sc : 4.5f;
+  const float m15usq = (SCALED ? -1.5f * sc : -1.5f) * usq_of(u);
+  const float wr[3] = {float(WD[0]) * rho_s, float(WD[1]) * rho_s, float(WD[7]) * rho_s};
+  const float r0s = SCALED ? rho0 * sc : rho0;  // rho_0 in units of 1/sc
+  auto ep_of = [&](float cu, int q, int cls) -> float {
+    if (stokes) return wr[cls];
+    float nl = __builtin_fmaf(c45 * cu, cu, m15usq);
+    if (!incomp) nl = rho0 * nl;
+    return __builtin_fmaf(float(WD[q]), nl, wr[cls]);
+  };
+  {
+    const float ep = ep_of(0.0f, 0, 0);
+    f[0] = __builtin_fmaf(k.lp, f[0] - ep, f[0]);
+  }
+#define FSLBM_PAIR32(q)                                                   \
+  {                                                                       \
+    const float cu = cdot<q>(u);                                          \
+    const float cue = cdot<q>(ueq);                                       \
+    const float em = float(W3D[q]) * (incomp && !SCALED ? cue : r0s * cue); \
+    const float ep = ep_of(cu, q, q <= 6 ? 1 : 2);                        \
+    const float a = f[q], b = f[q + 1];                                   \
+    const float np = 0.5f * (a + b) - ep;                                 \
+    const float nm = 0.5f * (a - b) - em;                                 \
+    const float lpn = k.lp * np;                                          \
+    f[q] = __builtin_fmaf(k.lm, nm, a + lpn);                             \
+    f[q + 1] = __builtin_fmaf(-k.lm, nm, b + lpn);                        \
+  }
+  FSLBM_PAIR32(1) FSLBM_PAIR32(3) FSLBM_PAIR32(5) FSLBM_PAIR32(7) FSLBM_PAIR32(9) FSLBM_PAIR32(11)
+  FSLBM_PAIR32(13) FSLBM_PAIR32(15) FSLBM_PAIR32(17)
+#undef FSLBM_PAIR32
+}
+
+template <bool SHIFTED>
+__device__ __forceinline__ void collide_f32(float f[Q], const Consts<float>& k, bool incomp, bool stokes,
+                                            float& rho_s, float u[3]) {
+  collide_f32_scaled<SHIFTED, false>(f, k, incomp, stokes, 1.0f, 1.0f, rho_s, u);
 }
 
 // Post-collision state of a resting-frame equilibrium (rho, u):

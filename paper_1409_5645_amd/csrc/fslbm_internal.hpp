@@ -44,11 +44,14 @@ struct SweepArgs {
   int32_t* f_epoch;
   int32_t* listF;
   int32_t* listE;
+  int32_t* listI;  // interface cells of time t (built by the sweep)
   int32_t* counters;
   int32_t* counters_next;
   double thr_hi, thr_lo;
   int step;
   int freeze;
+  int cpr;   // blocks per lattice row (set by the launcher)
+  int pairs; // FP16 form: two cells per lane when rows have even length
 };
 
 struct ConvArgs {
@@ -113,6 +116,7 @@ struct StatArgs {
 };
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
+hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
 hipError_t launch_convert(const StepLaunch& L, int precision);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, void* stream);
 hipError_t launch_fill_f64(double* p, size_t n, double v, void* stream);

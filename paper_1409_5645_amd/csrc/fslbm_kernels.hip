@@ -16,6 +16,9 @@
 #include "fslbm_device.hpp"
 #include "fslbm_internal.hpp"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace fslbm {
 
 constexpr int BLOCK = 256;
@@ -35,44 +38,25 @@ __device__ __forceinline__ int pull_source(const Grid& g, const Nbr& n) {
   return ((sx | sy | sz) < 0) ? -1 : sx + g.nx * (sy + g.ny * sz);
 }
 
+constexpr uint8_t WALL_CLASS = 3;  // class recorded for a pull source beyond a wall
+
+// Neighbourhood of one interface cell, loaded in a single pass (all loads
+// independent, so the cell costs one memory round trip, not a chain of them).
 template <class F>
-struct IfaceCtx {
+struct IfaceData {
   using R = typename F::R;
-  using S = typename F::S;
-  const S* fin;
-  size_t N;
-  int idx;
-  float isc;
-  uint32_t gasmask;
-  bool have_n;
-  double nv[3];
-  double dist;
-  R rho_t, rho0_t, u_t[3], usq_t;
-  const Consts<R>* k;
-  bool incomp, stokes;
+  R f[Q];         // pulled populations f_q(x, t+1) (gas links: placeholder)
+  R own[Q];       // own post-collision populations of time t
+  uint8_t ty[Q];  // class of the pull source x - c_q (WALL_CLASS beyond a wall)
+  double ph[Q];   // fill of the pull source (own fill beyond a wall)
+  double m, phix;
 };
 
-// Mass exchange over link q (FP64): weight 1 to liquid, (phi_x+phi_s)/2 to
-// interface, nothing from gas or walls.
-template <class F, int q>
-__device__ __forceinline__ void exchange(double& dm, const typename F::R (&f)[Q], const Grid& g, const Nbr& n,
-                                         const uint8_t* flags, const double* phi, double phix,
-                                         const typename F::S* fin, int idx, float isc, uint32_t& gasmask) {
-  const int s = pull_source<q>(g, n);
-  if (s < 0) return;
-  const uint8_t ts = flags[s];
-  if (ts == GAS) {
-    gasmask |= 1u << q;
-    return;
-  }
-  const double own_qb = (double)F::load(fin + (size_t)OPP[q] * g.N + idx, isc);
-  const double diff = (double)f[q] - own_qb;
-  if (ts == LIQ) {
-    dm = dm + diff;
-  } else {
-    const double wgt = 0.5 * (phix + phi[s]);
-    dm = dm + wgt * diff;
-  }
+template <class F>
+__device__ __forceinline__ double phi_seen(const IfaceData<F>& d, int q) {
+  // fill level seen from the cell: liquid 1, gas 0, interface its fill,
+  // beyond a wall the cell's own fill
+  return d.ty[q] == LIQ ? 1.0 : (d.ty[q] == GAS ? 0.0 : d.ph[q]);
 }
 
 // Reconstruction of the population f_q that would stream in from a gas cell.
@@ -80,152 +64,396 @@ __device__ __forceinline__ void exchange(double& dm, const typename F::R (&f)[Q]
 //   f_q = a0 ft_o(x) + a0bar ft_q(x) + a1 f_o(x,t+1) + C n+_o(x,t) + alpha_+ e+_o(rho_b,u_b)
 // with the FSK row of Table 1 (Eq. koerner) or Eq. (fsli1)-(fsli4) at alpha_+ = 1.
 template <class F, int RULE, int q>
-__device__ __forceinline__ void rebuild(typename F::R (&f)[Q], const IfaceCtx<F>& c) {
+__device__ __forceinline__ void rebuild(IfaceData<F>& d, uint32_t gasmask, bool have_n, const double (&nv)[3],
+                                        double dist, typename F::R rho_t, typename F::R rho0_t,
+                                        const typename F::R (&u_t)[3], typename F::R usq_t,
+                                        const Consts<typename F::R>& k, bool incomp, bool stokes) {
   using R = typename F::R;
-  if (!((c.gasmask >> q) & 1u)) return;
+  if (!((gasmask >> q) & 1u)) return;
   constexpr int o = OPP[q];
-  const R own_o = F::load(c.fin + (size_t)o * c.N + c.idx, c.isc);
-  const R e_b = e_plus<o>(c.k->rhob_s, c.k->rho0b, c.incomp, c.stokes, c.u_t, c.usq_t);
-  if (RULE == 1 && c.have_n && !((c.gasmask >> o) & 1u)) {
+  const R own_o = d.own[o];
+  const R e_b = e_plus<o>(k.rhob_s, k.rho0b, incomp, stokes, u_t, usq_t);
+  if (RULE == 1 && have_n && !((gasmask >> o) & 1u)) {
     // link distance delta: plane with normal n at offset phi - 1/2
     double nc = 0.0;
-    if (CX[o] == 1) nc = nc + c.nv[0];
-    if (CX[o] == -1) nc = nc - c.nv[0];
-    if (CY[o] == 1) nc = nc + c.nv[1];
-    if (CY[o] == -1) nc = nc - c.nv[1];
-    if (CZ[o] == 1) nc = nc + c.nv[2];
-    if (CZ[o] == -1) nc = nc - c.nv[2];
+    if (CX[o] == 1) nc = nc + nv[0];
+    if (CX[o] == -1) nc = nc - nv[0];
+    if (CY[o] == 1) nc = nc + nv[1];
+    if (CY[o] == -1) nc = nc - nv[1];
+    if (CZ[o] == 1) nc = nc + nv[2];
+    if (CZ[o] == -1) nc = nc - nv[2];
     if (nc > 0.0) {
-      double d = c.dist / nc;
-      if (d < 0.0) d = 0.0;
-      if (d > 1.0) d = 1.0;
-      const R delta = (R)d;
-      const R own_q = F::load(c.fin + (size_t)q * c.N + c.idx, c.isc);
+      double dl = dist / nc;
+      if (dl < 0.0) dl = 0.0;
+      if (dl > 1.0) dl = 1.0;
+      const R delta = (R)dl;
+      const R own_q = d.own[q];
       // n+_o(x,t) from ft+ = e+ + (1 + lambda_+) n+
-      const R e_o_t = e_plus<o>(c.rho_t, c.rho0_t, c.incomp, c.stokes, c.u_t, c.usq_t);
-      const R n_plus = (R(0.5) * (own_o + own_q) - e_o_t) * c.k->inv1p;
+      const R e_o_t = e_plus<o>(rho_t, rho0_t, incomp, stokes, u_t, usq_t);
+      const R n_plus = (R(0.5) * (own_o + own_q) - e_o_t) * k.inv1p;
       const R a0 = R(1.0) - (R(0.5) + delta);
       const R a1 = delta - R(1.0);
-      const R Cc = c.k->lp * (R(0.5) + delta) - R(2.0) * c.k->lp;
-      f[q] = (((a0 * own_o + R(0.5) * own_q) + a1 * f[o]) + Cc * n_plus) + e_b;
+      const R Cc = k.lp * (R(0.5) + delta) - R(2.0) * k.lp;
+      d.f[q] = (((a0 * own_o + R(0.5) * own_q) + a1 * d.f[o]) + Cc * n_plus) + e_b;
       return;
     }
   }
-  f[q] = R(2.0) * e_b - own_o;  // FSK: -ft_o + 2 e+_o(rho_b, u_b)
+  d.f[q] = R(2.0) * e_b - own_o;  // FSK: -ft_o + 2 e+_o(rho_b, u_b)
 }
 
 #define FSLBM_LINKS(M) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16) M(17) M(18)
 
+// Update of one interface cell from its loaded neighbourhood: mass exchange,
+// geometry, reconstruction of the gas-side populations, TRT collision.  On exit
+// d.f holds the post-collision populations; returns the new mass, the density
+// (storage convention) and the velocity of the collision.
 template <class F, int RULE>
+__device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& cm, typename F::R& rho_s,
+                                                typename F::R (&u)[3]) {
+  using R = typename F::R;
+  constexpr bool SH = F::shifted;
+  const Consts<R>& k = pick_consts<R>(cm);
+  const bool incomp = cm.incomp, stokes = cm.stokes;
+
+  // ---- mass exchange (FP64): dm = sum_q w (ft_q(x-c_q) - ft_qbar(x)); weight 1
+  // to liquid, (phi_x + phi_s)/2 to interface, nothing from gas or walls
+  uint32_t gasmask = 0;
+  double dm = 0.0;
+#define FSLBM_EXCH(q)                                              \
+  {                                                                \
+    const uint8_t ts = d.ty[q];                                    \
+    if (ts == GAS) gasmask |= 1u << q;                             \
+    if (ts == LIQ || ts == IFACE) {                                \
+      const double diff = (double)d.f[q] - (double)d.own[OPP[q]];  \
+      if (ts == LIQ) {                                             \
+        dm = dm + diff;                                            \
+      } else {                                                     \
+        const double wgt = 0.5 * (d.phix + d.ph[q]);               \
+        dm = dm + wgt * diff;                                      \
+      }                                                            \
+    }                                                              \
+  }
+  FSLBM_LINKS(FSLBM_EXCH)
+#undef FSLBM_EXCH
+  const double m_new = d.m + dm;
+
+  if (gasmask) {
+    // ---- interface geometry: n = -grad(phi)/|grad(phi)| by central
+    // differences over the six axis neighbours (pull sources of links 1..6 are
+    // x-1, x+1, y-1, y+1, z-1, z+1)
+    const double gx = 0.5 * (phi_seen(d, 2) - phi_seen(d, 1));
+    const double gy = 0.5 * (phi_seen(d, 4) - phi_seen(d, 3));
+    const double gz = 0.5 * (phi_seen(d, 6) - phi_seen(d, 5));
+    const double nrm2 = (gx * gx + gy * gy) + gz * gz;
+    const bool have_n = nrm2 > 0.0;
+    double nv[3] = {0.0, 0.0, 0.0};
+    if (have_n) {
+      const double nrm = sqrt(nrm2);
+      nv[0] = -gx / nrm;
+      nv[1] = -gy / nrm;
+      nv[2] = -gz / nrm;
+    }
+    const double dist = d.phix - 0.5;
+    // ---- moments of time t from the own post-collision populations
+    R rho_t, u_t[3];
+    recover_moments<R, SH>(d.own, k, incomp, rho_t, u_t);
+    const R rho0_t = rho0_of<R, SH>(rho_t, incomp);
+    const R usq_t = usq_of(u_t);
+#define FSLBM_REBUILD(q) rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, rho0_t, u_t, usq_t, k, incomp, stokes);
+    FSLBM_LINKS(FSLBM_REBUILD)
+#undef FSLBM_REBUILD
+  }
+
+  // ---- TRT collision, Eq. (lbe2)
+  if constexpr (sizeof(R) == 4)
+    collide_f32<SH>(d.f, k, incomp, stokes, rho_s, u);
+  else
+    collide<R, SH>(d.f, k, incomp, stokes, rho_s, u);
+  return m_new;
+}
+
+// Stream/collide sweep over liquid cells, one cell per lane; a block covers a
+// chunk of one lattice row, so the row, its y and z and the source rows of
+// every link are uniform (scalar) values.  Interface cells are appended to the
+// interface list (one atomic per wavefront) and updated by k_iface; gas cells
+// are skipped.
+//
+// Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q).  A source beyond a wall gives
+// halfway bounce-back f_q(x) = ft_qbar(x).  Every load is unconditional with a
+// 32-bit element offset from the buffer start (selected per lane), so all 19
+// loads of a cell are in flight together.  MODEL 1 fixes the incompressible
+// non-Stokes equilibrium at compile time; MODEL 0 reads both switches.
+constexpr unsigned WALL_ROW = 0xffffffffu;
+
+template <class F, int MODEL>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
   constexpr bool SH = F::shifted;
   const Grid g = a.c.grid;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
   }
-  if (idx >= g.N) return;
-  const uint8_t t = a.flags[idx];
-  if (t == GAS) return;
-
-  Nbr n;
-  coords(g, idx, n.x, n.y, n.z);
-  n.xm = step_axis(n.x, -1, g.nx, g.px);
-  n.xp = step_axis(n.x, 1, g.nx, g.px);
-  n.ym = step_axis(n.y, -1, g.ny, g.py);
-  n.yp = step_axis(n.y, 1, g.ny, g.py);
-  n.zm = step_axis(n.z, -1, g.nz, g.pz);
-  n.zp = step_axis(n.z, 1, g.nz, g.pz);
-  const S* __restrict__ fin = reinterpret_cast<const S*>(a.fin);
-  S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
-  const size_t N = (size_t)g.N;
-  const Consts<R>& k = pick_consts<R>(a.c);
-  const float isc = a.c.inv_scale;
-  const bool incomp = a.c.incomp, stokes = a.c.stokes;
-
-  // ---- pull stream, Eq. (lbe1): f_q(x) = ft_q(x - c_q); a source beyond a
-  // wall gives halfway bounce-back f_q(x) = ft_qbar(x).
-  R f[Q];
-#define FSLBM_PULL(q)                                                                       \
-  {                                                                                         \
-    const int s = pull_source<q>(g, n);                                                     \
-    const size_t off = s >= 0 ? (size_t)q * N + (size_t)s : (size_t)OPP[q] * N + idx;       \
-    f[q] = F::load(fin + off, isc);                                                         \
+  const int row = (int)blockIdx.x / a.cpr;
+  const int chunk = (int)blockIdx.x - row * a.cpr;
+  const int y = row % g.ny, z = row / g.ny;
+  const int x = chunk * BLOCK + (int)threadIdx.x;
+  const unsigned rbase = (unsigned)row * (unsigned)g.nx;
+  const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
+  const int lane = (int)threadIdx.x & 63;
+  {
+    // interface cells -> list (wavefront-aggregated append)
+    const unsigned long long b = __ballot(t == IFACE);
+    if (b) {
+      const int leader = __ffsll((long long)b) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
+      base = __shfl(base, leader);
+      if (t == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)(rbase + x);
+    }
   }
-  f[0] = F::load(fin + idx, isc);
+  if (t != LIQ) return;
+
+  // source rows (element offsets) of the nine (c_y, c_z) combinations
+  const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
+  const int zm = step_axis(z, -1, g.nz, g.pz), zp = step_axis(z, 1, g.nz, g.pz);
+  auto row_of = [&](int sy, int sz) -> unsigned {
+    return (sy < 0 || sz < 0) ? WALL_ROW : (unsigned)(sy + g.ny * sz) * (unsigned)g.nx;
+  };
+  // index: (c_y + 1) + 3 (c_z + 1); source row is (y - c_y, z - c_z)
+  const unsigned srow[9] = {row_of(yp, zp), row_of(y, zp), row_of(ym, zp),
+                            row_of(yp, z),  rbase,         row_of(ym, z),
+                            row_of(yp, zm), row_of(y, zm), row_of(ym, zm)};
+  // source columns (-1 beyond a wall at a row end: bounce-back)
+  const int xm = step_axis(x, -1, g.nx, g.px), xp = step_axis(x, 1, g.nx, g.px);
+  const unsigned N = (unsigned)g.N;  // 19 N < 2^32 is checked at init
+  const S* __restrict__ fin = reinterpret_cast<const S*>(a.fin);
+
+  // Every load is unconditional with a 32-bit element offset (selected per
+  // lane), so all 19 loads of a cell are in flight together.  F::load_raw
+  // keeps the FP16 form in its storage units (the collision absorbs the scale).
+  R f[Q];
+#define FSLBM_PULL(q)                                                                               \
+  {                                                                                                 \
+    const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                        \
+    const int sx = CX[q] == 1 ? xm : (CX[q] == -1 ? xp : x);                                        \
+    const unsigned off = (ro == WALL_ROW || sx < 0) ? (unsigned)OPP[q] * N + rbase + (unsigned)x     \
+                                                    : (unsigned)q * N + ro + (unsigned)sx;          \
+    f[q] = F::load_raw(fin + off);                                                                  \
+  }
+  FSLBM_PULL(0)
   FSLBM_LINKS(FSLBM_PULL)
 #undef FSLBM_PULL
 
-  double m_new = 0.0;
-  if (t == IFACE) {
-    const double phix = a.phi_in[idx];
-    IfaceCtx<F> c;
-    c.gasmask = 0;
-    // ---- mass exchange (FP64), fills the gas-link mask on the way
-    double dm = 0.0;
-#define FSLBM_EXCH(q) exchange<F, q>(dm, f, g, n, a.flags, a.phi_in, phix, fin, idx, isc, c.gasmask);
-    FSLBM_LINKS(FSLBM_EXCH)
-#undef FSLBM_EXCH
-    m_new = a.mass[idx] + dm;
-
-    if (c.gasmask) {
-      // ---- interface geometry: n = -grad(phi)/|grad(phi)| by central
-      // differences; liquid 1, gas 0, beyond a wall phi(x)
-      auto phi_at = [&](int s) -> double {
-        if (s < 0) return phix;
-        const uint8_t ts = a.flags[s];
-        if (ts == LIQ) return 1.0;
-        if (ts == GAS) return 0.0;
-        return a.phi_in[s];
-      };
-      // pull sources of links 1..6 are x-1, x+1, y-1, y+1, z-1, z+1
-      const double gx = 0.5 * (phi_at(pull_source<2>(g, n)) - phi_at(pull_source<1>(g, n)));
-      const double gy = 0.5 * (phi_at(pull_source<4>(g, n)) - phi_at(pull_source<3>(g, n)));
-      const double gz = 0.5 * (phi_at(pull_source<6>(g, n)) - phi_at(pull_source<5>(g, n)));
-      const double nrm2 = (gx * gx + gy * gy) + gz * gz;
-      c.have_n = nrm2 > 0.0;
-      c.nv[0] = c.nv[1] = c.nv[2] = 0.0;
-      if (c.have_n) {
-        const double nrm = sqrt(nrm2);
-        c.nv[0] = -gx / nrm;
-        c.nv[1] = -gy / nrm;
-        c.nv[2] = -gz / nrm;
-      }
-      c.dist = phix - 0.5;
-      // ---- moments of time t from the own post-collision populations
-      {
-        R own[Q];
+  // ---- TRT collision, Eq. (lbe2)
+  const Consts<R>& k = pick_consts<R>(a.c);
+  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+  R rho_s, u[3];
+  if constexpr (sizeof(R) == 4)
+    collide_f32_scaled<SH, F::scaled>(f, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  else
+    collide<R, SH>(f, k, incomp, stokes, rho_s, u);
+  S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) own[q] = F::load(fin + (size_t)q * N + idx, isc);
-        recover_moments<R, SH>(own, k, incomp, c.rho_t, c.u_t);
-      }
-      c.rho0_t = rho0_of<R, SH>(c.rho_t, incomp);
-      c.usq_t = usq_of(c.u_t);
-      c.fin = fin;
-      c.N = N;
-      c.idx = idx;
-      c.isc = isc;
-      c.k = &k;
-      c.incomp = incomp;
-      c.stokes = stokes;
-#define FSLBM_REBUILD(q) rebuild<F, RULE, q>(f, c);
-      FSLBM_LINKS(FSLBM_REBUILD)
-#undef FSLBM_REBUILD
+  for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+}
+
+// FP16-storage sweep with two cells per lane (rows of even length): the 19
+// populations of a pair are 4-byte aligned loads; the x-shifted neighbour comes
+// from the adjacent lane by a wavefront shift (DPP), and the one element beyond
+// the wavefront (or the row end: periodic wrap, or bounce-back at a wall) is a
+// broadcast load from a wavefront-uniform address.  Liquid cells only; a pair
+// store also covers an interface or gas partner (k_iface, which runs after this
+// kernel, writes interface cells; gas slots are never read).
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i receives lane i-1
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i receives lane i+1
+
+__device__ __forceinline__ float h_lo(uint32_t p) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(p & 0xffffu));
+}
+__device__ __forceinline__ float h_hi(uint32_t p) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(p >> 16)); }
+__device__ __forceinline__ float h_one(uint16_t v) { return (float)__builtin_bit_cast(_Float16, v); }
+__device__ __forceinline__ uint32_t h_pack(float a, float b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+}
+
+// Pull of the 19 populations of a lane's cell pair (see k_sweep_h2).  Phase 1
+// issues all loads (19 pairs, 10 wavefront-edge elements); phase 2 shifts and
+// selects, so no load waits on another link's data movement.
+template <bool WALLS>
+__device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const uint16_t* __restrict__ fin,
+                                          const Grid& g, size_t N, const unsigned (&srow)[9], unsigned rbase,
+                                          int xl, int wx0, int wend, bool row_end) {
+  uint32_t p[Q], e[Q];
+#define FSLBM_LOAD2(q)                                                                            \
+  {                                                                                               \
+    const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                      \
+    const bool wall = WALLS && ro == WALL_ROW;                                                    \
+    const uint16_t* own_qb = fin + (size_t)OPP[q] * N + rbase;                                    \
+    const uint16_t* src = wall ? own_qb : fin + (size_t)q * N + ro;                               \
+    p[q] = *reinterpret_cast<const uint32_t*>(src + xl);                                          \
+    if (CX[q] == 1) {                                                                             \
+      const uint16_t* ep = wx0 > 0 ? src + (wx0 - 1) : (g.px ? src + (g.nx - 1) : own_qb);        \
+      e[q] = (uint32_t)*ep << 16;                                                                 \
+    } else if (CX[q] == -1) {                                                                     \
+      const uint16_t* ep = wend < g.nx ? src + wend : (g.px ? src : own_qb + (g.nx - 1));         \
+      e[q] = (uint32_t)*ep;                                                                       \
+    }                                                                                             \
+  }
+  FSLBM_LOAD2(0)
+  FSLBM_LINKS(FSLBM_LOAD2)
+#undef FSLBM_LOAD2
+#define FSLBM_SHIFT2(q)                                                                           \
+  {                                                                                               \
+    const bool wall = WALLS && srow[(CY[q] + 1) + 3 * (CZ[q] + 1)] == WALL_ROW;                   \
+    uint32_t lo = p[q], hi = p[q];                                                                \
+    if (CX[q] == 1) {                                                                             \
+      /* cell x0 <- x0-1 (lane 0: the edge element as the shift's fill), cell x0+1 <- x0 */       \
+      const uint32_t nb = (uint32_t)__builtin_amdgcn_update_dpp((int)e[q], (int)p[q], DPP_WAVE_SHR1, 0xf, 0xf, false); \
+      lo = wall ? p[q] : (nb >> 16);                                                              \
+      hi = wall ? p[q] : (p[q] << 16);                                                            \
+    } else if (CX[q] == -1) {                                                                     \
+      /* cell x0 <- x0+1, cell x0+1 <- x0+2 (lane 63 and the row's last pair: the edge element) */ \
+      const uint32_t nb = (uint32_t)__builtin_amdgcn_update_dpp((int)e[q], (int)p[q], DPP_WAVE_SHL1, 0xf, 0xf, false); \
+      const uint32_t nx2 = row_end ? e[q] : nb;                                                   \
+      lo = wall ? p[q] : (p[q] >> 16);                                                            \
+      hi = wall ? p[q] : (nx2 << 16);                                                             \
+    }                                                                                             \
+    f0[q] = h_lo(lo);                                                                             \
+    f1[q] = h_hi(hi);                                                                             \
+  }
+  FSLBM_SHIFT2(0)
+  FSLBM_LINKS(FSLBM_SHIFT2)
+#undef FSLBM_SHIFT2
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
+  const Grid g = a.c.grid;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
+  }
+  const int row = (int)blockIdx.x / a.cpr;
+  const int chunk = (int)blockIdx.x - row * a.cpr;
+  const int y = row % g.ny, z = row / g.ny;
+  const int x0 = (chunk * BLOCK + (int)threadIdx.x) * 2;
+  const bool valid = x0 < g.nx;
+  const int xl = valid ? x0 : 0;  // in-bounds pair for lanes past the row end
+  const unsigned rbase = (unsigned)row * (unsigned)g.nx;
+  const uint16_t fl2 = valid ? *reinterpret_cast<const uint16_t*>(a.flags + rbase + xl) : (uint16_t)0;
+  const uint8_t tt[2] = {(uint8_t)(fl2 & 0xffu), (uint8_t)(fl2 >> 8)};
+  const int lane = (int)threadIdx.x & 63;
+  // interface cells -> list (wavefront-aggregated append, one cell of the pair at a time)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const unsigned long long b = __ballot(tt[j] == IFACE);
+    if (b) {
+      const int leader = __ffsll((long long)b) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
+      base = __shfl(base, leader);
+      if (tt[j] == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)rbase + x0 + j;
     }
   }
+  const bool liq = tt[0] == LIQ || tt[1] == LIQ;
+  if (__ballot(liq) == 0) return;  // lanes exchange data below: whole wavefronts only
 
-  // ---- TRT collision, Eq. (lbe2)
-  R rho_s, u[3];
-  collide<R, SH>(f, k, incomp, stokes, rho_s, u);
+  const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
+  const int zm = step_axis(z, -1, g.nz, g.pz), zp = step_axis(z, 1, g.nz, g.pz);
+  auto row_of = [&](int sy, int sz) -> unsigned {
+    return (sy < 0 || sz < 0) ? WALL_ROW : (unsigned)(sy + g.ny * sz) * (unsigned)g.nx;
+  };
+  const unsigned srow[9] = {row_of(yp, zp), row_of(y, zp), row_of(ym, zp),
+                            row_of(yp, z),  rbase,         row_of(ym, z),
+                            row_of(yp, zm), row_of(y, zm), row_of(ym, zm)};
+  // first column of the wavefront (uniform over it; readfirstlane says so) and after it
+  const int wx0 = __builtin_amdgcn_readfirstlane((chunk * BLOCK + ((int)threadIdx.x & ~63)) * 2);
+  const int wend = wx0 + 128;
+  const bool row_end = xl + 2 == g.nx;  // last pair of the row (its right neighbour is past the row)
+  const size_t N = (size_t)g.N;
+  const uint16_t* __restrict__ fin = reinterpret_cast<const uint16_t*>(a.fin);
+
+  float f0[Q], f1[Q];
+  // interior blocks (no source row beyond a y/z wall) take a select-only pull;
+  // the few blocks on the y/z faces take the general one
+  bool wall_rows = false;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, f[q], a.c.scale);
+  for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
+  if (!wall_rows)
+    pull_pair<false>(f0, f1, fin, g, N, srow, rbase, xl, wx0, wend, row_end);
+  else
+    pull_pair<true>(f0, f1, fin, g, N, srow, rbase, xl, wx0, wend, row_end);
 
-  const bool iface = t == IFACE;
-  if (iface) {
-    // ---- fill level and classification (FP64 bookkeeping)
+  // ---- TRT collision, Eq. (lbe2), in storage units
+  const Consts<float>& k = a.c.kf;
+  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+  float rho_s, u[3];
+  collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  if (liq) {
+    uint16_t* __restrict__ fout = reinterpret_cast<uint16_t*>(a.fout) + rbase + x0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fout + (size_t)q * N) = h_pack(f0[q], f1[q]);
+  }
+}
+
+// Interface cells of the list built by the sweep: one cell per thread, in
+// three phases -- load the whole neighbourhood (independent loads), compute in
+// registers, store.
+template <class F, int RULE>
+__global__ __launch_bounds__(BLOCK) void k_iface(SweepArgs a) {
+  using R = typename F::R;
+  using S = typename F::S;
+  constexpr bool SH = F::shifted;
+  const Grid g = a.c.grid;
+  const int n_i = a.counters[C_I];
+  const S* __restrict__ fin = reinterpret_cast<const S*>(a.fin);
+  S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
+  const size_t N = (size_t)g.N;
+  const float isc = a.c.inv_scale;
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n_i; i += gridDim.x * BLOCK) {
+    const int idx = a.listI[i];
+    Nbr n;
+    coords(g, idx, n.x, n.y, n.z);
+    n.xm = step_axis(n.x, -1, g.nx, g.px);
+    n.xp = step_axis(n.x, 1, g.nx, g.px);
+    n.ym = step_axis(n.y, -1, g.ny, g.py);
+    n.yp = step_axis(n.y, 1, g.ny, g.py);
+    n.zm = step_axis(n.z, -1, g.nz, g.pz);
+    n.zp = step_axis(n.z, 1, g.nz, g.pz);
+    // ---- phase 1: loads.  Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q); beyond a
+    // wall halfway bounce-back f_q(x) = ft_qbar(x).
+    IfaceData<F> d;
+    d.f[0] = F::load(fin + idx, isc);
+    d.own[0] = d.f[0];
+    d.ty[0] = IFACE;
+    d.ph[0] = 0.0;
+#define FSLBM_ILOAD(q)                                                                     \
+  {                                                                                        \
+    const int s = pull_source<q>(g, n);                                                    \
+    const int sc = s >= 0 ? s : idx;                                                       \
+    const size_t off = s >= 0 ? (size_t)q * N + (size_t)s : (size_t)OPP[q] * N + idx;      \
+    d.f[q] = F::load(fin + off, isc);                                                      \
+    d.own[q] = F::load(fin + (size_t)q * N + idx, isc);                                    \
+    const uint8_t ts = a.flags[sc];                                                        \
+    d.ty[q] = s >= 0 ? ts : WALL_CLASS;                                                    \
+    d.ph[q] = a.phi_in[sc];                                                                \
+  }
+    FSLBM_LINKS(FSLBM_ILOAD)
+#undef FSLBM_ILOAD
+    d.m = a.mass[idx];
+    d.phix = a.phi_in[idx];
+    // ---- phase 2: interface treatment and collision
+    R rho_s, u[3];
+    const double m_new = iface_compute<F, RULE>(d, a.c, rho_s, u);
+    // ---- phase 3: populations, fill level and classification (FP64 bookkeeping)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, d.f[q], a.c.scale);
     const double rho = SH ? 1.0 + (double)rho_s : (double)rho_s;
     a.mass[idx] = m_new;
     a.phi_out[idx] = m_new / rho;
@@ -241,9 +469,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
       if (m_new < a.thr_lo * rho) a.listE[atomicAdd(&a.counters[C_E], 1)] = idx;
     }
   }
-  // count interface cells (one atomic per wavefront)
-  const unsigned long long b = __ballot(iface);
-  if (b && (int)(threadIdx.x & 63) == __ffsll((long long)b) - 1) atomicAdd(&a.counters[C_I], __popcll(b));
 }
 
 // ------------------------------------------------------------ conversions
@@ -527,24 +752,22 @@ __global__ __launch_bounds__(BLOCK) void k_stats(StatArgs a) {
   __shared__ double sm[BLOCK / 64];
   __shared__ int sl[BLOCK / 64];
   __shared__ int si[BLOCK / 64];
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
   double v = 0.0;
   int nl = 0, ni = 0;
-  if (idx < a.c.grid.N) {
+  const S* fi = reinterpret_cast<const S*>(a.f);
+  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < a.c.grid.N; idx += gridDim.x * BLOCK) {
     const uint8_t t = a.flags[idx];
-    const S* fi = reinterpret_cast<const S*>(a.f);
-    if (t != GAS) {
-      double r = 0.0;
-      for (int q = 0; q < Q; ++q) r = r + (double)F::load(fi + (size_t)q * a.c.grid.N + idx, a.c.inv_scale);
-      if (F::shifted) r = 1.0 + r;
-      if (!(r > 0.0) || !isfinite(r)) atomicAdd(&a.cnt[1], 1);
-      if (t == LIQ) {
-        v = r;
-        nl = 1;
-      } else {
-        v = a.mass[idx];
-        ni = 1;
-      }
+    if (t == GAS) continue;
+    double r = 0.0;
+    for (int q = 0; q < Q; ++q) r = r + (double)F::load(fi + (size_t)q * a.c.grid.N + idx, a.c.inv_scale);
+    if (F::shifted) r = 1.0 + r;
+    if (!(r > 0.0) || !isfinite(r)) atomicAdd(&a.cnt[1], 1);
+    if (t == LIQ) {
+      v += r;
+      nl += 1;
+    } else {
+      v += a.mass[idx];
+      ni += 1;
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -575,15 +798,29 @@ __global__ __launch_bounds__(BLOCK) void k_stats(StatArgs a) {
 // ------------------------------------------------------------ launchers
 static inline unsigned blocks_for(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 static constexpr unsigned LIST_GRID = 512;
+static constexpr unsigned IFACE_GRID = 2048;
 
 template <class F>
-static void sweep_form(const StepLaunch& L, int rule) {
+static void sweep_form(const StepLaunch& L) {
   hipStream_t st = (hipStream_t)L.stream;
-  const unsigned nb = blocks_for(L.sweep.c.grid.N);
-  if (rule == 0)
-    k_sweep<F, 0><<<nb, BLOCK, 0, st>>>(L.sweep);
+  SweepArgs a = L.sweep;
+  const Grid& g = a.c.grid;
+  a.cpr = (g.nx + BLOCK - 1) / BLOCK;
+  const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
+  if (a.c.incomp && !a.c.stokes)
+    k_sweep<F, 1><<<nb, BLOCK, 0, st>>>(a);
   else
-    k_sweep<F, 1><<<nb, BLOCK, 0, st>>>(L.sweep);
+    k_sweep<F, 0><<<nb, BLOCK, 0, st>>>(a);
+}
+
+template <class F>
+static void iface_form(const StepLaunch& L, int rule) {
+  hipStream_t st = (hipStream_t)L.stream;
+  const unsigned nb = std::min<unsigned>(IFACE_GRID, blocks_for(L.sweep.c.grid.N));
+  if (rule == 0)
+    k_iface<F, 0><<<nb, BLOCK, 0, st>>>(L.sweep);
+  else
+    k_iface<F, 1><<<nb, BLOCK, 0, st>>>(L.sweep);
 }
 
 template <class F>
@@ -595,10 +832,31 @@ static void convert_form(const StepLaunch& L) {
   k_gather<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
 }
 
+static void sweep_h2(const StepLaunch& L) {
+  hipStream_t st = (hipStream_t)L.stream;
+  SweepArgs a = L.sweep;
+  const Grid& g = a.c.grid;
+  a.cpr = (g.nx + 2 * BLOCK - 1) / (2 * BLOCK);
+  const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
+  if (a.c.incomp && !a.c.stokes)
+    k_sweep_h2<1><<<nb, BLOCK, 0, st>>>(a);
+  else
+    k_sweep_h2<0><<<nb, BLOCK, 0, st>>>(a);
+}
+
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule) {
-  if (precision == 0) sweep_form<FormF64>(L, rule);
-  else if (precision == 1) sweep_form<FormF32>(L, rule);
-  else sweep_form<FormF16>(L, rule);
+  (void)rule;  // the sweep covers liquid cells only; the rule acts in k_iface
+  if (precision == 0) sweep_form<FormF64>(L);
+  else if (precision == 1) sweep_form<FormF32>(L);
+  else if (L.sweep.c.grid.nx % 2 == 0 && L.sweep.pairs) sweep_h2(L);
+  else sweep_form<FormF16>(L);
+  return hipGetLastError();
+}
+
+hipError_t launch_iface(const StepLaunch& L, int precision, int rule) {
+  if (precision == 0) iface_form<FormF64>(L, rule);
+  else if (precision == 1) iface_form<FormF32>(L, rule);
+  else iface_form<FormF16>(L, rule);
   return hipGetLastError();
 }
 
@@ -658,7 +916,7 @@ hipError_t launch_fields(const FieldArgs& a, int precision, void* stream) {
 }
 
 hipError_t launch_stats(const StatArgs& a, int precision, void* stream) {
-  const unsigned nb = blocks_for(a.c.grid.N);
+  const unsigned nb = std::min<unsigned>(2048u, blocks_for(a.c.grid.N));
   hipStream_t s = (hipStream_t)stream;
   if (precision == 0) k_stats<FormF64><<<nb, BLOCK, 0, s>>>(a);
   else if (precision == 1) k_stats<FormF32><<<nb, BLOCK, 0, s>>>(a);

@@ -205,3 +205,27 @@ def test_reduced_precision_channel(fs, oracle_mod, precision, tol):
     _say(precision, "channel u rel err", err)
     assert err < tol
     np.testing.assert_array_equal(s.fields(("flags",))["flags"], o.flags())
+
+
+@pytest.mark.parametrize("nx,periodic", [(200, (0, 0, 0)), (600, (1, 0, 1)), (64, (1, 0, 0))])
+def test_fp16_pair_sweep_matches_single(fs, monkeypatch, nx, periodic):
+    """The FP16 sweep with two cells per lane (wavefront shifts for the x
+    neighbours, broadcast loads at wavefront and row ends) gives exactly the
+    populations of the one-cell-per-lane sweep, with conversions running: rows
+    ending inside a wavefront (200), rows longer than one block (600), walls and
+    periodic x."""
+    w = W.sloshing(nx, 22, 6, depth=10.0, amp=3.0, seed=8, gy=-4e-4, tau=0.6, periodic=periodic)
+    _say(f"case fp16 pairs nx={nx} periodic={periodic}")
+    monkeypatch.setenv("FSLBM_FP16_PAIRS", "1")
+    a = fs.Sim.from_workload(w, precision="fp16s")
+    monkeypatch.setenv("FSLBM_FP16_PAIRS", "0")
+    b = fs.Sim.from_workload(w, precision="fp16s")
+    for _ in range(3):
+        a.step(20, 1)
+        b.step(20, 1)
+        fa, fb = a.fields(("f", "flags", "mass")), b.fields(("f", "flags", "mass"))
+        np.testing.assert_array_equal(fa["flags"], fb["flags"])
+        act = fa["flags"] != W.GAS
+        np.testing.assert_array_equal(fa["f"][:, act], fb["f"][:, act])
+        np.testing.assert_array_equal(fa["mass"], fb["mass"])
+    assert a.stats()["interface"] > 0
