@@ -1,0 +1,149 @@
+"""GPU library at the full sizes of the measured workloads, in the launch
+configuration bench.py times.
+
+- 256 x 160 x 256 tank (FP64): after a GPU run, one more step on the GPU and one
+  step of the oracle from the same state over the whole lattice: cell classes
+  and conversion lists bit-exact, populations within 1e-12.
+- 512 x 320 x 512 tank (FP64): the same on a sub-box of the lattice around the
+  free surface; the oracle runs on the sub-box (its cut faces act as walls), and
+  cells at least MARGIN cells from a cut face are compared -- one step, including
+  conversions, reads at most five cells away.
+- 512 x 320 x 512 tank, FP32 and FP16 storage: properties that hold at any size
+  (no liquid cell next to gas, mass conserved to the precision of the form, no
+  NaN or non-positive density).
+"""
+import numpy as np
+import pytest
+
+from paper_1409_5645_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+MARGIN = 6
+
+
+@pytest.fixture(scope="module")
+def fs():
+    from paper_1409_5645_amd import fslbm
+    return fslbm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _state(s):
+    g = s.fields(("f", "mass", "phi", "flags"))
+    st = s.stats()
+    return {"f": g["f"], "mass": g["mass"], "phi": g["phi"], "flags": g["flags"], "reservoir": st["reservoir"]}
+
+
+def test_slosh256_fp64_full_lattice_step(fs, oracle_mod):
+    w = W.config("slosh256", seed=1)
+    _say("case slosh256 fp64: 30 GPU steps, then one step GPU vs oracle")
+    s = fs.Sim.from_workload(w)
+    s.step(30, fs.FSL)
+    st = _state(s)
+    o = oracle_mod.Oracle(w.params, state=st)
+    del st
+    s.step(1, fs.FSL)
+    o.step(1, oracle_mod.FSL)
+    g = s.fields(("f", "flags", "mass"))
+    flo = o.flags()
+    np.testing.assert_array_equal(g["flags"], flo)
+    act = flo != W.GAS
+    fo = o.populations()
+    err = np.abs(g["f"][:, act] - fo[:, act]).max() / np.abs(fo[:, act]).max()
+    _say("slosh256 population rel err", err)
+    assert err <= 1e-12
+    it = flo == W.INTERFACE
+    assert np.abs(g["mass"][it] - o.mass()[it]).max() <= 1e-11
+    lo, lg = o.lists(), s.conversions()
+    for k in lo:
+        np.testing.assert_array_equal(lg[k], lo[k], err_msg=k)
+
+
+def _subbox(t3, box):
+    """Sub-box [x0,x1) x [y0,y1) x [z0,z1) of a device tensor shaped [..., nz, ny, nx]."""
+    (x0, x1), (y0, y1), (z0, z1) = box
+    return t3[..., z0:z1, y0:y1, x0:x1].contiguous()
+
+
+def test_slosh512_fp64_subbox_step(fs, oracle_mod):
+    w = W.config("slosh512", seed=0)
+    p = w.params
+    nx, ny, nz = p.nx, p.ny, p.nz
+    _say("case slosh512 fp64: 20 GPU steps, then one step on a sub-box vs the oracle")
+    s = fs.Sim.from_workload(w)
+    s.step(20, fs.FSL)
+    g0 = s.fields(("f", "mass", "phi", "flags"), device=True)
+    # sub-box around the surface, touching the x = 0 wall (a real wall) and cut elsewhere
+    box = ((0, 72), (170, 220), (200, 240))
+    f3 = g0["f"].reshape(19, nz, ny, nx)
+    sub = {
+        "f": _subbox(f3, box).reshape(19, -1).cpu().numpy(),
+        "mass": _subbox(g0["mass"].reshape(nz, ny, nx), box).reshape(-1).cpu().numpy(),
+        "phi": _subbox(g0["phi"].reshape(nz, ny, nx), box).reshape(-1).cpu().numpy(),
+        "flags": _subbox(g0["flags"].reshape(nz, ny, nx), box).reshape(-1).cpu().numpy(),
+    }
+    del g0, f3
+    (x0, x1), (y0, y1), (z0, z1) = box
+    ps = W.Params(nx=x1 - x0, ny=y1 - y0, nz=z1 - z0, periodic=(0, 0, 0), tau=p.tau, Lambda=p.Lambda,
+                  g=p.g, rho_gas=p.rho_gas, eps=p.eps)
+    o = oracle_mod.Oracle(ps, state=sub)
+    assert (sub["flags"] == W.INTERFACE).sum() > 1000
+    s.step(1, fs.FSL)
+    o.step(1, oracle_mod.FSL)
+    g1 = s.fields(("f", "flags", "mass"), device=True)
+    gf = _subbox(g1["f"].reshape(19, nz, ny, nx), box).cpu().numpy()
+    gfl = _subbox(g1["flags"].reshape(nz, ny, nx), box).cpu().numpy()
+    gm = _subbox(g1["mass"].reshape(nz, ny, nx), box).cpu().numpy()
+    del g1
+    shp = (ps.nz, ps.ny, ps.nx)
+    # interior of the sub-box: MARGIN from every cut face (x = 0 is a real wall)
+    inner = (slice(MARGIN, shp[0] - MARGIN), slice(MARGIN, shp[1] - MARGIN), slice(0, shp[2] - MARGIN))
+    flo = o.flags().reshape(shp)
+    np.testing.assert_array_equal(gfl[inner], flo[inner])
+    fo = o.populations().reshape((19,) + shp)
+    act = flo[inner] != W.GAS
+    a, b = gf[(slice(None),) + inner][:, act], fo[(slice(None),) + inner][:, act]
+    err = np.abs(a - b).max() / np.abs(b).max()
+    _say("slosh512 sub-box population rel err", err, "active compared", int(act.sum()))
+    assert err <= 1e-12
+    it = flo[inner] == W.INTERFACE
+    assert np.abs(gm[inner][it] - o.mass().reshape(shp)[inner][it]).max() <= 1e-11
+
+
+def _layer_ok(flags, shape):
+    """No liquid cell with a gas cell among its 18 neighbours (walls excluded)."""
+    import torch
+    fl = flags.reshape(shape)
+    L = fl == W.LIQUID
+    G = fl == W.GAS
+    nz, ny, nx = shape
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if not 1 <= dx * dx + dy * dy + dz * dz <= 2:
+                    continue
+                a = L[max(0, -dz):nz - max(0, dz), max(0, -dy):ny - max(0, dy), max(0, -dx):nx - max(0, dx)]
+                b = G[max(0, dz):nz - max(0, -dz) or None, max(0, dy):ny - max(0, -dy) or None,
+                      max(0, dx):nx - max(0, -dx) or None]
+                if bool(torch.any(a & b)):
+                    return False
+    return True
+
+
+@pytest.mark.parametrize("precision,drift", [("fp32", 1e-6), ("fp16s", 1e-4)])
+def test_slosh512_reduced_precision_properties(fs, precision, drift):
+    w = W.config("slosh512", seed=0)
+    p = w.params
+    _say(f"case slosh512 {precision}: 200 steps, invariants")
+    s = fs.Sim.from_workload(w, precision=precision)
+    st0 = s.stats()
+    s.step(200, fs.FSL)
+    st1 = s.stats()  # raises on NaN / non-positive density
+    rel = abs(st1["total_mass"] - st0["total_mass"]) / st0["total_mass"]
+    _say(precision, "mass drift", rel, "interface", st1["interface"])
+    assert rel < drift
+    fl = s.fields(("flags",), device=True)["flags"]
+    assert _layer_ok(fl, (p.nz, p.ny, p.nx))

@@ -1,0 +1,126 @@
+"""The GPU library against what the paper and the mathematics fix, at the
+configurations of the measured workloads (FP64 unless stated)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1409_5645_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fs():
+    from paper_1409_5645_amd import fslbm
+    return fslbm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _l2(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def _startup_series(y, t, g, nu, H, K=400):
+    us = g / nu * (H * y - y * y / 2)
+    for k in range(K):
+        m = 2 * k + 1
+        us = us - 16 * g * H * H / (nu * math.pi ** 3 * m ** 3) * np.sin(m * math.pi * y / (2 * H)) \
+            * np.exp(-nu * m * m * math.pi ** 2 * t / (4 * H * H))
+    return us
+
+
+def test_channel_startup_series(fs):
+    """Channel 8 x 48 x 8, 3000 steps: FSL tracks the start-up series of the
+    film of height 32.5 (as the oracle does, section 4.3)."""
+    w = W.channel()
+    s = fs.Sim.from_workload(w)
+    s.step(3000, fs.FSL)
+    u = s.fields(("u",))["u"][0].reshape(8, 48, 8)
+    assert np.ptp(u[:, :33, :], axis=(0, 2)).max() < 1e-18
+    y = np.arange(48) + 0.5
+    act = w.flags.reshape(8, 48, 8)[0, :, 0] != W.GAS
+    err = _l2(u[0, :, 0][act], _startup_series(y, 3000, 1e-6, 0.1, 32.5)[act])
+    _say("channel startup L2", err)
+    assert err < 5e-5
+
+
+@pytest.mark.parametrize("rule,Lambda,expect", [(0, 3 / 16, (0.85, 1.15)), (1, 1 / 4, (1.75, 2.25))])
+def test_convergence_sweep_orders(fs, rule, Lambda, expect):
+    """Convergence sweep (grid 4 x (h+16) x 4, g ~ h^-3) run to the steady
+    state: FSK first order, FSL second order once the bounce-back wall is not
+    exact (Lambda = 1/4)."""
+    errs = []
+    for h in (16, 32):
+        w = W.channel_sweep(h, Lambda=Lambda)
+        s = fs.Sim.from_workload(w)
+        nu = (0.8 - 0.5) / 3
+        H = h + 0.5
+        s.step(int(30 * 4 * H * H / (math.pi ** 2 * nu)), rule)
+        u = s.fields(("u",))["u"][0].reshape(4, h + 16, 4)[0, :, 0]
+        y = np.arange(h + 16) + 0.5
+        act = w.flags.reshape(4, h + 16, 4)[0, :, 0] != W.GAS
+        errs.append(_l2(u[act], (w.params.g[0] / nu * (H * y - y * y / 2))[act]))
+    order = math.log2(errs[0] / errs[1])
+    _say("rule", rule, "errors", errs, "order", order)
+    assert expect[0] < order < expect[1]
+
+
+def test_convergence_sweep_fsl_exact(fs):
+    """At Lambda = 3/16 the FSL steady film is exact for every member of the
+    sweep (section 4.3)."""
+    for h in (16, 64):
+        w = W.channel_sweep(h)
+        s = fs.Sim.from_workload(w)
+        nu = 0.1
+        H = h + 0.5
+        s.step(int(32 * 4 * H * H / (math.pi ** 2 * nu)), fs.FSL)
+        u = s.fields(("u",))["u"][0].reshape(4, h + 16, 4)[0, :, 0]
+        y = np.arange(h + 16) + 0.5
+        act = w.flags.reshape(4, h + 16, 4)[0, :, 0] != W.GAS
+        err = _l2(u[act], (w.params.g[0] / nu * (H * y - y * y / 2))[act])
+        _say("FSL film h", h, "L2", err)
+        assert err < 1e-10
+
+
+def test_hydrostatic_pool_large(fs):
+    """A 128 x 96 x 128 hydrostatic pool stays at rest under FSL."""
+    w = W.pool(nx=128, ny=96, nz=128, level=60.5, gy=-2e-5, tau=0.55)
+    s = fs.Sim.from_workload(w)
+    m0 = s.stats()["total_mass"]
+    s.step(500, fs.FSL)
+    g = s.fields(("u", "flags"))
+    act = w.flags != W.GAS
+    assert np.abs(g["u"][:, act]).max() < 1e-12
+    np.testing.assert_array_equal(g["flags"], w.flags)
+    assert abs(s.stats()["total_mass"] - m0) / m0 < 1e-13
+
+
+def test_sloshing_period_linear_theory(fs):
+    """Standing wave in the 256 x 160 x 256 tank (depth 96, g = 2e-5, FP32).
+    The surface height is projected on the closed-tank eigenmode cos(2 pi x/L)
+    (the wavelength of the initial cosine); that amplitude oscillates with the
+    linear-theory period 2 pi / omega, omega^2 = g k tanh(k h), within 5 %."""
+    w = W.config("slosh256", seed=0)
+    s = fs.Sim.from_workload(w, precision="fp32")
+    nx, ny, nz = 256, 160, 256
+    basis = np.cos(2 * math.pi * (np.arange(nx) + 0.5) / nx)
+    times, amp = [], []
+    for it in range(95):
+        s.step(200, fs.FSL)
+        phi = s.fields(("phi",), device=True)["phi"].reshape(nz, ny, nx)
+        h = phi[nz // 2].sum(dim=0).cpu().numpy()  # liquid column height h(x)
+        amp.append(float(np.dot(h - h.mean(), basis)))
+        times.append((it + 1) * 200)
+    amp = np.array(amp)
+    zc = [times[i] + (times[i + 1] - times[i]) * amp[i] / (amp[i] - amp[i + 1])
+          for i in range(len(amp) - 1) if amp[i] * amp[i + 1] < 0]
+    assert len(zc) >= 3, zc
+    period = 2 * float(np.mean(np.diff(zc)))
+    k = 2 * math.pi / nx
+    theory = 2 * math.pi / math.sqrt(2e-5 * k * math.tanh(k * 96))
+    _say("mode-2 period", period, "linear theory", theory, "crossings", zc)
+    assert abs(period - theory) / theory < 0.05
