@@ -14,7 +14,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["fslbm_oracle.cpp", "fslbm_oracle.hpp"]
+_SOURCES = ["fslbm_oracle.cpp", "fslbm_oracle.hpp", "dual.hpp"]
 
 
 def build(force: bool = True) -> str:
@@ -75,6 +75,9 @@ def lib():
         L.ref_equilibrium_post.argtypes = [vp, ctypes.c_double, dp, dp]
         L.ref_collide.argtypes = [vp, dp, dp, dp, dp]
         L.ref_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        L.ref_window_dual.restype = ctypes.c_int
+        L.ref_window_dual.argtypes = [ctypes.POINTER(_RefParams), u8p, dp, dp, dp, dp, dp, dp, ctypes.c_double,
+                                      dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -209,3 +212,37 @@ class Oracle:
         out = np.empty(5)
         lib().ref_coeffs(self._h, int(rule), float(alpha_p), float(delta), _dptr(out))
         return out
+
+
+def window_dual(params, flags, f0, m0, phi0, u_target, phi_target, T: int, rule: int = FSL,
+                df0=None, dm0=None, dphi0=None, drho_b: float = 0.0, dg=None, want_state: bool = False):
+    """Frozen-topology window of T steps and the loss
+    L = sum over interface cells of |u_T - u*|^2 + (phi_T - phi*)^2,
+    with its exact directional derivative along (df0, dm0, dphi0, drho_b, dg)
+    from a dual-number run of the oracle.  Returns (L, dL) or, with want_state,
+    (L, dL, {"f", "mass", "phi"}) of time T."""
+    N = params.nx * params.ny * params.nz
+
+    def arr(a, n):
+        return None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+
+    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+    f0, m0, phi0 = arr(f0, 19 * N), arr(m0, N), arr(phi0, N)
+    ut, pt = arr(u_target, 3 * N), arr(phi_target, N)
+    d = [arr(df0, 19 * N), arr(dm0, N), arr(dphi0, N), arr(dg, 3)]
+    assert f0.size == 19 * N and m0.size == N and phi0.size == N and ut.size == 3 * N and pt.size == N
+    out2 = np.zeros(2)
+    fT = np.empty(19 * N) if want_state else None
+    mT = np.empty(N) if want_state else None
+    pT = np.empty(N) if want_state else None
+    opt = lambda a: None if a is None else _dptr(a)  # noqa: E731
+    p = _params(params)
+    rc = lib().ref_window_dual(ctypes.byref(p), fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                               _dptr(f0), _dptr(m0), _dptr(phi0), opt(d[0]), opt(d[1]), opt(d[2]),
+                               float(drho_b), opt(d[3]), int(T), int(rule), _dptr(ut), _dptr(pt), _dptr(out2),
+                               opt(fT), opt(mT), opt(pT))
+    if rc != 0:
+        raise ValueError("oracle window failed: " + lib().ref_create_error().decode())
+    if want_state:
+        return out2[0], out2[1], {"f": fT.reshape(19, N), "mass": mT, "phi": pT}
+    return out2[0], out2[1]

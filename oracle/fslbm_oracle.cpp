@@ -3,8 +3,10 @@
 #include <cstdio>
 #include <memory>
 
+#include "dual.hpp"
 #include "fslbm_oracle.hpp"
 
+using fsref::Dual;
 using fsref::Oracle;
 using fsref::Params;
 
@@ -178,6 +180,71 @@ void ref_coeffs(void* hp, int rule, double alpha_p, double delta, double* out5) 
   out5[2] = k.a1;
   out5[3] = k.alpha_p;
   out5[4] = k.C;
+}
+
+// Frozen-topology window with a loss and its exact directional derivative.
+//
+// From the state (flags, ft0, m0, phi0), T steps with conversions disabled;
+// then L = sum over interface cells of |u_T - u*|^2 + (phi_T - phi*)^2, where
+// u_T is recovered from the post-collision populations of time T.  The run is
+// made on dual numbers, so next to L it yields dL along the input direction
+// (dft0, dm0, dphi0, drho_b, dg): the exact derivative of the same arithmetic.
+// Any direction pointer may be NULL (no change).  out2 = {L, dL}; fT, mT, phiT
+// (optional) receive the value part of the final state.  Returns 0, or 1 with
+// the message in ref_create_error().
+int ref_window_dual(const ref_params* rp, const uint8_t* flags, const double* ft0, const double* m0,
+                    const double* phi0, const double* dft0, const double* dm0, const double* dphi0,
+                    double drho_b, const double* dg, int T, int rule, const double* u_target,
+                    const double* phi_target, double* out2, double* fT, double* mT, double* phiT) {
+  try {
+    auto s = std::make_unique<Oracle<Dual>>();
+    s->set_params(to_params(rp));
+    const int N = s->N;
+    // seed the parameter directions: rho_b, g and the constants derived from g
+    s->rho_b.d = drho_b;
+    if (dg) {
+      const double lm = s->lam_m.v;
+      for (int a = 0; a < 3; ++a) {
+        s->gvec[a].d = dg[a];
+        s->half_g[a].d = 0.5 * dg[a];
+        s->g_over_lam_m[a].d = dg[a] / lm;
+      }
+    }
+    std::vector<Dual> F((size_t)fsref::Q * N), M(N), P(N);
+    for (size_t i = 0; i < F.size(); ++i) F[i] = Dual(ft0[i], dft0 ? dft0[i] : 0.0);
+    for (int i = 0; i < N; ++i) {
+      M[i] = Dual(m0[i], dm0 ? dm0[i] : 0.0);
+      P[i] = Dual(phi0[i], dphi0 ? dphi0[i] : 0.0);
+    }
+    s->init_from_state(flags, F.data(), M.data(), P.data(), Dual(0.0));
+    s->freeze = true;
+    for (int t = 0; t < T; ++t) s->step(rule);
+    Dual L(0.0);
+    for (int cell = 0; cell < N; ++cell) {
+      if (s->type[cell] != fsref::INTERFACE) continue;
+      Dual f[fsref::Q], r, u[3];
+      for (int q = 0; q < fsref::Q; ++q) f[q] = s->ft[(size_t)q * N + cell];
+      s->recover_moments(f, r, u);
+      for (int a = 0; a < 3; ++a) {
+        const Dual e = u[a] - Dual(u_target[(size_t)a * N + cell]);
+        L = L + e * e;
+      }
+      const Dual e = s->phi[cell] - Dual(phi_target[cell]);
+      L = L + e * e;
+    }
+    out2[0] = L.v;
+    out2[1] = L.d;
+    if (fT)
+      for (size_t i = 0; i < F.size(); ++i) fT[i] = s->ft[i].v;
+    for (int i = 0; i < N; ++i) {
+      if (mT) mT[i] = s->mass[i].v;
+      if (phiT) phiT[i] = s->phi[i].v;
+    }
+    return 0;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return 1;
+  }
 }
 
 }  // extern "C"

@@ -78,6 +78,7 @@ struct Oracle {
   T inv_1p_lam_p;       // 1/(1+lambda_+): recovers n+ from post-collision f
   T gvec[3], half_g[3], g_over_lam_m[3];
   T thr_hi, thr_lo;     // (1+eps), (-eps)
+  T rho_b;              // gas density rho_b = 3 P_b of the boundary term
 
   std::vector<uint8_t> type;  // cell classes
   std::vector<T> ft;          // post-collision populations ft[q*N + cell]
@@ -116,6 +117,7 @@ struct Oracle {
     }
     thr_hi = T(1.0 + p.eps);
     thr_lo = T(-p.eps);
+    rho_b = T(p.rho_gas);
   }
 
   // neighbour of cell (x,y,z) at offset d; -1 if it lies beyond a wall
@@ -392,6 +394,7 @@ struct Oracle {
         bool have_normal = nrm2 > T(0.0);
         T nvec[3] = {T(0.0), T(0.0), T(0.0)};
         if (have_normal) {
+          using std::sqrt;  // the dual-number sqrt is found by argument lookup
           T nrm = sqrt(nrm2);
           for (int a = 0; a < 3; ++a) nvec[a] = -grad[a] / nrm;
         }
@@ -403,7 +406,6 @@ struct Oracle {
         T rho_t, u_t[3];
         recover_moments(own, rho_t, u_t);
         const T rho0_t = rho0_of(rho_t);
-        const T rho_b = T(p.rho_gas);
         const T rho0_b = rho0_of(rho_b);
         for (int q = 1; q < Q; ++q) {
           if (!gaslink[q]) continue;

@@ -99,24 +99,22 @@ def _shift_any(mask3: np.ndarray, periodic) -> np.ndarray:
     return out
 
 
-def _from_height(params: Params, eta_x: np.ndarray, name: str, meta: dict) -> Workload:
-    """Liquid below a surface height eta(x) (uniform in z)."""
+def _from_height(params: Params, eta: np.ndarray, name: str, meta: dict) -> Workload:
+    """Liquid below a surface height eta(x) (uniform in z) or eta(z, x)."""
     nx, ny, nz = params.nx, params.ny, params.nz
+    eta3 = np.broadcast_to(np.asarray(eta, dtype=np.float64).reshape(-1, nx), (nz, nx))  # [nz, nx]
     j = np.arange(ny, dtype=np.float64)
-    fill2 = np.clip(eta_x[None, :] - j[:, None], 0.0, 1.0)          # [ny, nx]
-    types2 = np.where(fill2 >= 1.0, LIQUID, np.where(fill2 <= 0.0, GAS, INTERFACE)).astype(np.uint8)
-    types3 = np.broadcast_to(types2, (nz, ny, nx)).copy()
-    fill3 = np.broadcast_to(fill2, (nz, ny, nx)).copy()
+    fill3 = np.clip(eta3[:, None, :] - j[None, :, None], 0.0, 1.0)  # [nz, ny, nx]
+    types3 = np.where(fill3 >= 1.0, LIQUID, np.where(fill3 <= 0.0, GAS, INTERFACE)).astype(np.uint8)
     gas_near = _shift_any(types3 == GAS, params.periodic)
     promote = (types3 == LIQUID) & gas_near
     types3[promote] = INTERFACE
     fill3[promote] = 1.0
     yc = j + 0.5
     if params.g[1] == 0.0:
-        rho2 = np.full((ny, nx), params.rho_gas)
+        rho3 = np.full((nz, ny, nx), params.rho_gas)
     else:
-        rho2 = params.rho_gas + 3.0 * abs(params.g[1]) * (eta_x[None, :] - yc[:, None])
-    rho3 = np.broadcast_to(rho2, (nz, ny, nx)).copy()
+        rho3 = params.rho_gas + 3.0 * abs(params.g[1]) * (eta3[:, None, :] - yc[None, :, None])
     rho3[types3 == GAS] = params.rho_gas
     flags = types3.reshape(-1)
     return Workload(name=name, params=params, flags=flags, rho=rho3.reshape(-1), u=None,
@@ -146,18 +144,25 @@ def channel_sweep(h: int, tau: float = 0.8, Lambda: float = 3.0 / 16.0, frac: fl
 
 def sloshing(nx: int = 256, ny: int = 160, nz: int = 256, depth: float = 96.0, amp: float = 6.0,
              seed: int = 0, gy: float = -2e-5, tau: float = 0.55, Lambda: float = 3.0 / 16.0,
-             wavelength: float | None = None, periodic=(0, 0, 0)) -> Workload:
+             wavelength: float | None = None, periodic=(0, 0, 0), amp_z: float = 0.0) -> Workload:
     """Closed tank (walls on all faces) with a cosine surface
-    eta(i) = depth + amp cos(2 pi (i + 1/2)/wavelength + theta), theta drawn
-    from the seed, uniform in z, liquid initially at hydrostatic rest."""
+    eta(i, k) = depth + amp cos(2 pi (i + 1/2)/wavelength + theta)
+                      + amp_z cos(2 pi (k + 1/2)/nz + theta_z),
+    theta and theta_z drawn from the seed (in that order), liquid initially at
+    hydrostatic rest.  amp_z = 0 gives a surface uniform in z."""
     rng = np.random.default_rng(seed)
     theta = 2.0 * math.pi * float(rng.random())
+    theta_z = 2.0 * math.pi * float(rng.random())
     lam = float(nx if wavelength is None else wavelength)
     i = np.arange(nx, dtype=np.float64)
+    k = np.arange(nz, dtype=np.float64)
     eta = depth + amp * np.cos(2.0 * math.pi * (i + 0.5) / lam + theta)
+    if amp_z != 0.0:
+        eta = eta[None, :] + amp_z * np.cos(2.0 * math.pi * (k[:, None] + 0.5) / nz + theta_z)
     p = Params(nx=nx, ny=ny, nz=nz, periodic=tuple(periodic), tau=tau, Lambda=Lambda, g=(0.0, gy, 0.0))
     return _from_height(p, eta, "sloshing",
-                        {"depth": depth, "amp": amp, "seed": seed, "theta": theta, "wavelength": lam})
+                        {"depth": depth, "amp": amp, "amp_z": amp_z, "seed": seed, "theta": theta,
+                         "theta_z": theta_z, "wavelength": lam})
 
 
 def pool(nx: int = 32, ny: int = 64, nz: int = 32, level: float = 40.5, gy: float = -1e-5,
