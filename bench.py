@@ -116,6 +116,90 @@ def run_form(w, form, steps, warmup, rule, log):
     return res, f
 
 
+def adjoint_leg(log, T=400, config="slosh128"):
+    """Adjoint window of T steps with frozen cell classes on the 128 x 96 x 128
+    sloshing tank: FP32 (headline) and FP64 gradients of
+    L = sum over interface cells of |u_T - u*|^2 + (phi_T - phi*)^2 with respect
+    to f0, P_b and g; u*, phi* from a seed-generated target run (P_b and g scaled
+    by 1 + 0.01 xi, f0 + 1e-4 w xi).  Cost = (window forward with checkpoints +
+    backward) / (T plain frozen steps)."""
+    import torch
+    from paper_1409_5645_amd import fslbm, workloads as W
+    w = W.config(config, seed=0)
+    p = w.params
+    rng = np.random.default_rng(11)
+    xi1, xi2 = rng.normal(size=2)
+    base_sim = fslbm.Sim.from_workload(w)
+    base = base_sim.fields(("f", "mass", "phi", "flags"), device=True)
+    base_sim.close()
+    dev = base["f"].device
+    iface = base["flags"] == 1
+    act = (base["flags"] != 0).to(torch.float64)
+    wq = torch.tensor([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(11)
+    f_t = base["f"] + 1e-4 * wq[:, None] * torch.randn(base["f"].shape, dtype=torch.float64, device=dev,
+                                                       generator=gen) * act
+    tgt = fslbm.Sim(p, w.flags)
+    tgt.set_state(f_t, base["mass"], base["phi"])
+    tgt.set_forcing([v * (1 + 0.01 * xi2) for v in p.g], p.rho_gas * (1 + 0.01 * xi1))
+    tgt.window(T, 1)
+    tg = tgt.fields(("u", "phi"), device=True)
+    tgt.close()
+    C = torch.tensor([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1), (1, 1, 0),
+                      (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1), (0, 1, 1),
+                      (0, -1, -1), (0, 1, -1), (0, -1, 1)], dtype=torch.float64, device=dev)
+
+    def loss(fT, phiT, g):
+        u = (C.T @ fT - g[:, None]) + 0.5 * g[:, None]
+        return ((u - tg["u"]) ** 2).sum(0)[iface].sum() + ((phiT - tg["phi"]) ** 2)[iface].sum()
+
+    out = {}
+    for form in ("fp64", "fp32"):
+        sim = fslbm.Sim(p, w.flags, precision=form, freeze=True)
+        # T plain frozen steps
+        sim.set_state(base["f"], base["mass"], base["phi"])
+        sim.step(20, 1)
+        sim.set_state(base["f"], base["mass"], base["phi"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(T, 1)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        res = None
+        for rep in range(2):  # the first repetition warms the allocator
+            f0 = base["f"].clone().requires_grad_(True)
+            P_b = torch.tensor(p.rho_gas / 3.0, dtype=torch.float64, device=dev, requires_grad=True)
+            g = torch.tensor(p.g, dtype=torch.float64, device=dev, requires_grad=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fT, mT, phiT = fslbm.window_apply(sim, T, 1, f0, base["mass"], base["phi"], P_b, g)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L = loss(fT, phiT, g)
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            res = {"L": float(L.detach()), "dL_dPb": float(P_b.grad), "dL_dg": g.grad.cpu().tolist(),
+                   "f0_grad": f0.grad, "t_plain_ms": t_plain * 1e3, "t_window_fwd_ms": (t1 - t0) * 1e3,
+                   "t_backward_ms": (t2 - t1) * 1e3}
+            del fT, mT, phiT, L
+        res["cost_ratio"] = (res["t_window_fwd_ms"] + res["t_backward_ms"]) / res["t_plain_ms"]
+        out[form] = res
+        sim.close()
+        log(f"[adjoint {form}] plain {res['t_plain_ms']:.1f} ms, window fwd {res['t_window_fwd_ms']:.1f} ms, "
+            f"bwd {res['t_backward_ms']:.1f} ms, cost x{res['cost_ratio']:.2f}, dL/dP_b {res['dL_dPb']:.6e}")
+    a, b = out["fp32"], out["fp64"]
+    err = {"f0": float(torch.linalg.norm(a["f0_grad"] - b["f0_grad"]) / torch.linalg.norm(b["f0_grad"])),
+           "P_b": abs(a["dL_dPb"] - b["dL_dPb"]) / abs(b["dL_dPb"]),
+           "g": float(np.linalg.norm(np.subtract(a["dL_dg"], b["dL_dg"])) / np.linalg.norm(b["dL_dg"]))}
+    for r in out.values():
+        del r["f0_grad"]
+    torch.cuda.empty_cache()
+    return {"workload": f"sloshing tank {p.nx}x{p.ny}x{p.nz}, T = {T} steps with frozen cell classes, FSL, "
+                        f"checkpoint spacing ceil(sqrt T)",
+            "cost_ratio": out["fp32"]["cost_ratio"], "fp32_grad_err_vs_fp64": err, "forms": out}
+
+
 def cpu_baseline(w_full, log, budget_s=12.0):
     """The serial FP64 oracle on a z-slab of the same tank (same x-y profile,
     walls on all faces), timed on one host core."""
@@ -151,6 +235,7 @@ def main():
     ap.add_argument("--config", default="slosh512")
     ap.add_argument("--rule", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -212,6 +297,8 @@ def main():
         "roofline": roof,
         "forms": results,
     }
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_leg(log)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, log)
     print(json.dumps(line), flush=True)

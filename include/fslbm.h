@@ -161,6 +161,62 @@ fslbm_status fslbm_conversions(fslbm_ctx* c, int32_t* const* out, int32_t cap, i
  * the number of sweeps recorded so far (synchronises). */
 fslbm_status fslbm_timing(fslbm_ctx* c, int32_t enable, double* sweep_ms, int64_t* sweeps);
 
+/* Set the body acceleration g and the gas density rho_b (P_b = rho_b / 3) used
+ * by the steps enqueued from now on (the parameters of the boundary term of
+ * Eq. (bterm) and of the force of section 2.1).  Host arguments; no device
+ * work. */
+fslbm_status fslbm_set_forcing(fslbm_ctx* c, const double g[3], double rho_gas);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint window: gradients through T steps with frozen cell classes.
+ *
+ * Over a window the cell classes stay fixed (no conversions), so a step is a
+ * piecewise-smooth map of the state (ft, m, phi): pull (Eq. lbe1), mass
+ * exchange, the normal from the fill gradient and the link distance delta
+ * (section 3.3), FSK / FSL reconstruction (Eq. closure; Table 1 or Eq.
+ * fsli1-fsli4), TRT collision (Eq. lbe2), phi = m / rho.  The window's
+ * backward pass is the exact reverse-mode derivative of that map (the branches
+ * of the forward run: delta clamps, the FSK fallback), written by hand; states
+ * are kept by sqrt(T) checkpointing: every K-th state (K = ceil(sqrt T) by
+ * default) is stored during the forward pass, and each segment's states are
+ * recomputed from its checkpoint during the backward pass (the last segment's
+ * are kept from the forward pass).  Supported: FP64 and FP32 forms, the
+ * incompressible equilibrium with its quadratic term (otherwise
+ * FSLBM_E_UNSUPPORTED).  The caller owns the window workspace; it must stay
+ * allocated, and the context alive, until fslbm_window_destroy. */
+typedef struct fslbm_window fslbm_window;
+
+/* Bytes of window workspace for T steps with checkpoint spacing K (0: the
+ * default) for the current cell classes of c.  Synchronises. */
+fslbm_status fslbm_window_workspace_size(fslbm_ctx* c, int32_t T, int32_t K, size_t* bytes);
+
+/* Forward pass: T steps with rule FSK or FSL from the current state of c,
+ * conversions disabled, storing checkpoints in the workspace (device memory,
+ * 256-byte aligned, at least fslbm_window_workspace_size bytes).  On return the
+ * state of c is that of time T (read it with fslbm_fields) and *out is the
+ * window.  Synchronises once (to size the interface-cell list), then enqueues
+ * the steps. */
+fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t rule, void* workspace,
+                                  size_t workspace_bytes, fslbm_window** out);
+
+/* Backward pass.  Inputs (device, double; any may be NULL = zero): dL_df[19N]
+ * = dL/d(post-collision populations of time T, unshifted; read at non-gas
+ * cells), dL_dm[N] and dL_dphi[N] = dL/d(mass, fill of time T; read at
+ * interface cells).  Outputs (device, double; any may be NULL = not written):
+ * dL_df0[19N] (zero at gas cells), dL_dm0[N] and dL_dphi0[N] (zero outside
+ * interface cells) for the state of time 0; host grads[4] = {dL/drho_b,
+ * dL/dg_x, dL/dg_y, dL/dg_z} with dL/dP_b = 3 dL/drho_b.  Parameter gradients
+ * are summed in FP64 in a fixed order.  May be called more than once.
+ * Synchronises. */
+fslbm_status fslbm_window_backward(fslbm_window* w, const double* dL_df, const double* dL_dm, const double* dL_dphi,
+                                   double* dL_df0, double* dL_dm0, double* dL_dphi0, double grads[4]);
+
+/* info = {T, K, number of checkpoints, interface cells}. */
+fslbm_status fslbm_window_info(const fslbm_window* w, int32_t info[4]);
+
+/* Release the window's host state (not the workspace). */
+fslbm_status fslbm_window_destroy(fslbm_window* w);
+
 /* Release the context (not the caller's buffers).  Synchronises. */
 fslbm_status fslbm_destroy(fslbm_ctx* c);
 

@@ -186,7 +186,9 @@ void ref_coeffs(void* hp, int rule, double alpha_p, double delta, double* out5) 
 //
 // From the state (flags, ft0, m0, phi0), T steps with conversions disabled;
 // then L = sum over interface cells of |u_T - u*|^2 + (phi_T - phi*)^2, where
-// u_T is recovered from the post-collision populations of time T.  The run is
+// u_T is recovered from the post-collision populations of time T, plus
+// sum over non-gas cells and q of a_q ft_q(T) when the weights a (f_weight,
+// 19 N values) are given.  The run is
 // made on dual numbers, so next to L it yields dL along the input direction
 // (dft0, dm0, dphi0, drho_b, dg): the exact derivative of the same arithmetic.
 // Any direction pointer may be NULL (no change).  out2 = {L, dL}; fT, mT, phiT
@@ -195,7 +197,8 @@ void ref_coeffs(void* hp, int rule, double alpha_p, double delta, double* out5) 
 int ref_window_dual(const ref_params* rp, const uint8_t* flags, const double* ft0, const double* m0,
                     const double* phi0, const double* dft0, const double* dm0, const double* dphi0,
                     double drho_b, const double* dg, int T, int rule, const double* u_target,
-                    const double* phi_target, double* out2, double* fT, double* mT, double* phiT) {
+                    const double* phi_target, const double* f_weight, double* out2, double* fT, double* mT,
+                    double* phiT) {
   try {
     auto s = std::make_unique<Oracle<Dual>>();
     s->set_params(to_params(rp));
@@ -231,6 +234,15 @@ int ref_window_dual(const ref_params* rp, const uint8_t* flags, const double* ft
       }
       const Dual e = s->phi[cell] - Dual(phi_target[cell]);
       L = L + e * e;
+    }
+    if (f_weight) {
+      for (int cell = 0; cell < N; ++cell) {
+        if (s->type[cell] == fsref::GAS) continue;
+        for (int q = 0; q < fsref::Q; ++q) {
+          const size_t i = (size_t)q * N + cell;
+          L = L + Dual(f_weight[i]) * s->ft[i];
+        }
+      }
     }
     out2[0] = L.v;
     out2[1] = L.d;

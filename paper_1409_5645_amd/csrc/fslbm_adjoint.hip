@@ -1,0 +1,687 @@
+// Reverse-mode (adjoint) kernels of the free-surface LBM step over a window of
+// steps with frozen cell classes (no conversions), for the incompressible
+// equilibrium with its quadratic term.
+//
+// A forward step maps the state (ft, m, phi) of time t to time t+1:
+//   pull (Eq. lbe1) -> [interface cells: mass exchange; normal from the fill
+//   gradient; FSK / FSL reconstruction of the gas-side populations, Eq.
+//   (closure) with Table 1 or Eq. (fsli1)-(fsli4)] -> TRT collision (Eq. lbe2)
+//   -> [interface cells: phi = m / rho].
+// The adjoint maps lambda = dL/d(state) of time t+1 to time t.  The adjoint of
+// the pull is a push: the adjoint of a pulled value is written to the very
+// element the pull read (the source population, or the cell's own opposite
+// population at a wall).  Every element is read by exactly one pull, so the
+// push needs no atomics.
+//
+//   k_adj_sweep    liquid cells: pull of time t (for the collision velocity),
+//                  collision adjoint, push.
+//   k_adj_iface    interface cells: forward recompute keeping intermediates;
+//                  adjoint of phi = m/rho, of the collision, reconstruction,
+//                  normal and mass exchange; push; own-population and fill
+//                  terms to per-cell scratch.
+//   k_adj_iface2   interface cells: add the own-population terms (set them where
+//                  the pull that reads the element comes from gas) and gather the
+//                  fill adjoint from the cell and its interface neighbours.
+// Parameter gradients (dL/drho_b, dL/dg) are summed per block in FP64 into
+// fixed slots and reduced at the end in a fixed order: a run is reproducible
+// bit for bit.
+#include "fslbm_device.hpp"
+#include "fslbm_internal.hpp"
+#include "fslbm_stencil.hpp"
+
+#include <algorithm>
+
+namespace fslbm {
+
+constexpr int ABLOCK = 256;
+static constexpr unsigned ADJ_IFACE_GRID = 2048;
+
+// v += c_q t
+template <int q, class R>
+__device__ __forceinline__ void cadd(R (&v)[3], R t) {
+  if (CX[q] == 1) v[0] = v[0] + t;
+  if (CX[q] == -1) v[0] = v[0] - t;
+  if (CY[q] == 1) v[1] = v[1] + t;
+  if (CY[q] == -1) v[1] = v[1] - t;
+  if (CZ[q] == 1) v[2] = v[2] + t;
+  if (CZ[q] == -1) v[2] = v[2] - t;
+}
+
+// Adjoint of e+_q(rho, u) = w_q (rho + 4.5 (c_q.u)^2 - 1.5 u.u) for a given
+// eb = dL/de+_q: rb += w_q eb, ub += w_q eb (9 (c_q.u) c_q - 3 u).
+template <int q, class R>
+__device__ __forceinline__ void eplus_adj(R eb, const R (&u)[3], R& rb, R (&ub)[3]) {
+  const R we = R(WD[q]) * eb;
+  rb = rb + we;
+  const R t = R(9.0) * (we * cdot<q>(u));
+  cadd<q>(ub, t);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ub[a] = ub[a] - R(3.0) * (we * u[a]);
+}
+
+// Adjoint of the TRT collision, Eq. (lbe2), with the force in
+// u = U + g/2, u_eq = U - g/lambda_- (incompressible: U = sum_q c_q f_q).
+// ob = dL/d(post-collision f), u = collision velocity, rho_extra = dL/drho
+// from elsewhere.  Returns fb = dL/d(pre-collision f) and gb = dL/dg.
+//   out_q    = f_q    + lambda_+ n+ + lambda_- n-
+//   out_qbar = f_qbar + lambda_+ n+ - lambda_- n-,  n+- = (f_q +- f_qbar)/2 - e+-_q
+template <class R>
+__device__ __forceinline__ void collide_adjoint(const R (&ob)[Q], const R (&u)[3], R rho_extra, const Consts<R>& k,
+                                                R (&fb)[Q], R (&gb)[3]) {
+  R rb = R(0.0);                         // sum_q w_q dL/de+_q
+  R s9[3] = {R(0.0), R(0.0), R(0.0)};    // sum_q w_q dL/de+_q (c_q.u) c_q
+  R ue[3] = {R(0.0), R(0.0), R(0.0)};    // dL/du_eq = sum_q 3 w_q dL/de-_q c_q
+  R hp[Q], hm[Q];                        // half of dL/dn+ and dL/dn- per pair
+  {
+    const R np_b = k.lp * ob[0];
+    rb = rb + R(WD[0]) * (-np_b);
+  }
+#define FSLBM_CADJ(q)                                   \
+  {                                                     \
+    const R np_b = k.lp * (ob[q] + ob[q + 1]);          \
+    const R nm_b = k.lm * (ob[q] - ob[q + 1]);          \
+    const R we = R(WD[q]) * (-np_b);                    \
+    rb = rb + we;                                       \
+    cadd<q>(s9, we * cdot<q>(u));                       \
+    cadd<q>(ue, R(W3D[q]) * (-nm_b));                   \
+    hp[q] = R(0.5) * np_b;                              \
+    hm[q] = R(0.5) * nm_b;                              \
+  }
+  FSLBM_CADJ(1) FSLBM_CADJ(3) FSLBM_CADJ(5) FSLBM_CADJ(7) FSLBM_CADJ(9) FSLBM_CADJ(11) FSLBM_CADJ(13)
+  FSLBM_CADJ(15) FSLBM_CADJ(17)
+#undef FSLBM_CADJ
+  R jb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R ub = R(9.0) * s9[a] - R(3.0) * (u[a] * rb);  // dL/du
+    jb[a] = ub + ue[a];                                   // u and u_eq both move with U = j
+    gb[a] = R(0.5) * ub - ue[a] * k.ilm;                  // u = U + g/2, u_eq = U - g/lambda_-
+  }
+  const R rt = rb + rho_extra;
+  fb[0] = (R(1.0) + k.lp) * ob[0] + rt;
+#define FSLBM_FADJ(q)                                   \
+  {                                                     \
+    const R cj = cdot<q>(jb);                           \
+    fb[q] = ((ob[q] + hp[q]) + hm[q]) + (rt + cj);      \
+    fb[q + 1] = ((ob[q + 1] + hp[q]) - hm[q]) + (rt - cj); \
+  }
+  FSLBM_FADJ(1) FSLBM_FADJ(3) FSLBM_FADJ(5) FSLBM_FADJ(7) FSLBM_FADJ(9) FSLBM_FADJ(11) FSLBM_FADJ(13)
+  FSLBM_FADJ(15) FSLBM_FADJ(17)
+#undef FSLBM_FADJ
+}
+
+// Sum of v over the block (wavefront shuffles, then the 4 wavefronts in
+// order), added by thread 0 to slot[0..NV).  Every thread of the block calls it.
+template <int NV>
+__device__ __forceinline__ void block_accumulate(double (&v)[NV], double* slot) {
+  __shared__ double sm[ABLOCK / 64][NV];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_down(v[i], o);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sm[threadIdx.x >> 6][i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < ABLOCK / 64; ++w) s += sm[w][i];
+      slot[i] += s;
+    }
+  }
+}
+
+// ------------------------------------------------------------ liquid cells
+// Same row mapping and pull offsets as the forward sweep; the push writes the
+// adjoint of each pulled value to the offset the pull read.
+template <class F>
+__global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
+  using R = typename F::R;
+  using S = typename F::S;
+  const Grid g = a.c.grid;
+  const int row = (int)blockIdx.x / a.cpr;
+  const int chunk = (int)blockIdx.x - row * a.cpr;
+  const int y = row % g.ny, z = row / g.ny;
+  const int x = chunk * ABLOCK + (int)threadIdx.x;
+  const unsigned rbase = (unsigned)row * (unsigned)g.nx;
+  const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
+  const bool liq = t == LIQ;
+  if (!__syncthreads_or(liq)) return;  // the whole block leaves together
+  double gs[3] = {0.0, 0.0, 0.0};
+  if (liq) {
+    const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
+    const int zm = step_axis(z, -1, g.nz, g.pz), zp = step_axis(z, 1, g.nz, g.pz);
+    auto row_of = [&](int sy, int sz) -> unsigned {
+      return (sy < 0 || sz < 0) ? WALL_ROW : (unsigned)(sy + g.ny * sz) * (unsigned)g.nx;
+    };
+    const unsigned srow[9] = {row_of(yp, zp), row_of(y, zp), row_of(ym, zp),
+                              row_of(yp, z),  rbase,         row_of(ym, z),
+                              row_of(yp, zm), row_of(y, zm), row_of(ym, zm)};
+    const int xm = step_axis(x, -1, g.nx, g.px), xp = step_axis(x, 1, g.nx, g.px);
+    const unsigned N = (unsigned)g.N;
+    const S* __restrict__ fin = reinterpret_cast<const S*>(a.fst);
+    const R* __restrict__ lin = reinterpret_cast<const R*>(a.lam_in);
+    unsigned off[Q];
+    R f[Q], ob[Q];
+#define FSLBM_APULL(q)                                                                            \
+  {                                                                                               \
+    const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                      \
+    const int sx = CX[q] == 1 ? xm : (CX[q] == -1 ? xp : x);                                      \
+    off[q] = (ro == WALL_ROW || sx < 0) ? (unsigned)OPP[q] * N + rbase + (unsigned)x              \
+                                        : (unsigned)q * N + ro + (unsigned)sx;                    \
+    f[q] = F::load_raw(fin + off[q]);                                                             \
+    ob[q] = lin[(unsigned)q * N + rbase + (unsigned)x];                                           \
+  }
+    FSLBM_APULL(0)
+    FSLBM_LINKS(FSLBM_APULL)
+#undef FSLBM_APULL
+    const Consts<R>& k = pick_consts<R>(a.c);
+    R rho_s, j[3];
+    moments(f, rho_s, j);
+    const R u[3] = {j[0] + k.hg[0], j[1] + k.hg[1], j[2] + k.hg[2]};
+    R fb[Q], gb[3];
+    collide_adjoint(ob, u, R(0.0), k, fb, gb);
+    R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lout[off[q]] = fb[q];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gs[i] = (double)gb[i];
+  }
+  block_accumulate<3>(gs, a.part_sweep + 3 * (size_t)blockIdx.x);
+}
+
+// --------------------------------------------------------- interface cells
+// Adjoint of the reconstruction of one gas-side population f_q (see rebuild):
+// r = dL/df_q is spread over the own populations, the pulled f_o, n+_o (and
+// through it rho_t, u_t), e+_o(rho_b, u_t), and, for the FSL rule, the link
+// distance delta = clamp((phi - 1/2)/(c_o.n), 0, 1).
+template <class F, int RULE, int q>
+__device__ __forceinline__ void rebuild_adj(const IfaceData<F>& d, uint32_t gasmask, bool have_n,
+                                            const double (&nv)[3], double dist, typename F::R rho_t,
+                                            const typename F::R (&u_t)[3], typename F::R usq_t,
+                                            const Consts<typename F::R>& k, typename F::R (&fb)[Q],
+                                            typename F::R (&ownb)[Q], double (&nvb)[3], double& distb,
+                                            typename F::R& rtb, typename F::R (&utb)[3], typename F::R& rbb) {
+  using R = typename F::R;
+  if (!((gasmask >> q) & 1u)) return;
+  constexpr int o = OPP[q];
+  const R r = fb[q];
+  fb[q] = R(0.0);  // reconstructed, not pulled: nothing to push
+  R ebb = R(0.0);  // dL/de+_o(rho_b, u_t)
+  bool fsl = false;
+  if (RULE == 1 && have_n && !((gasmask >> o) & 1u)) {
+    double nc = 0.0;
+    if (CX[o] == 1) nc = nc + nv[0];
+    if (CX[o] == -1) nc = nc - nv[0];
+    if (CY[o] == 1) nc = nc + nv[1];
+    if (CY[o] == -1) nc = nc - nv[1];
+    if (CZ[o] == 1) nc = nc + nv[2];
+    if (CZ[o] == -1) nc = nc - nv[2];
+    if (nc > 0.0) {
+      fsl = true;
+      const double raw = dist / nc;
+      double dl = raw;
+      if (dl < 0.0) dl = 0.0;
+      if (dl > 1.0) dl = 1.0;
+      const bool inside = !(raw < 0.0) && !(raw > 1.0);
+      const R delta = (R)dl;
+      const R own_o = d.own[o], own_q = d.own[q];
+      const R e_o_t = e_plus<o>(rho_t, R(1.0), true, false, u_t, usq_t);
+      const R n_plus = (R(0.5) * (own_o + own_q) - e_o_t) * k.inv1p;
+      const R a0 = R(1.0) - (R(0.5) + delta);
+      const R a1 = delta - R(1.0);
+      const R Cc = k.lp * (R(0.5) + delta) - R(2.0) * k.lp;
+      // f_q = a0 ft_o + ft_q / 2 + a1 f_o + C n+_o + e+_o(rho_b, u_t)
+      ownb[o] = ownb[o] + a0 * r;
+      ownb[q] = ownb[q] + R(0.5) * r;
+      fb[o] = fb[o] + a1 * r;
+      ebb = r;
+      const R npb = Cc * r;
+      // da0/ddelta = -1, da1/ddelta = 1, dC/ddelta = lambda_+
+      const R deltab = r * ((d.f[o] - own_o) + k.lp * n_plus);
+      // n+_o = ((ft_o + ft_q)/2 - e+_o(rho_t, u_t)) / (1 + lambda_+)
+      const R hb = R(0.5) * (k.inv1p * npb);
+      ownb[o] = ownb[o] + hb;
+      ownb[q] = ownb[q] + hb;
+      eplus_adj<o>(-(k.inv1p * npb), u_t, rtb, utb);
+      if (inside) {
+        distb += (double)deltab / nc;
+        const double ncb = -(double)deltab * raw / nc;
+        if (CX[o] == 1) nvb[0] += ncb;
+        if (CX[o] == -1) nvb[0] -= ncb;
+        if (CY[o] == 1) nvb[1] += ncb;
+        if (CY[o] == -1) nvb[1] -= ncb;
+        if (CZ[o] == 1) nvb[2] += ncb;
+        if (CZ[o] == -1) nvb[2] -= ncb;
+      }
+    }
+  }
+  if (!fsl) {  // FSK: f_q = -ft_o + 2 e+_o(rho_b, u_t)
+    ownb[o] = ownb[o] - r;
+    ebb = R(2.0) * r;
+  }
+  R ub[3] = {R(0.0), R(0.0), R(0.0)};
+  R rb = R(0.0);
+  eplus_adj<o>(ebb, u_t, rb, ub);  // rb: dL/drho_b; ub: dL/du_t (u_b = u_t)
+  rbb = rbb + rb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) utb[a] = utb[a] + ub[a];
+}
+
+// adjoint v of the fill value seen through link q (used by the normal)
+template <class F>
+__device__ __forceinline__ void seen_adj(const IfaceData<F>& d, int q, double v, double (&geo)[6], double& phis) {
+  if (d.ty[q] == IFACE) geo[q - 1] += v;
+  else if (d.ty[q] == WALL_CLASS) phis += v;  // beyond a wall the cell's own fill is used
+}
+
+template <class F, int RULE>
+__global__ __launch_bounds__(ABLOCK) void k_adj_iface(AdjArgs a) {
+  using R = typename F::R;
+  using S = typename F::S;
+  constexpr bool SH = F::shifted;
+  const Grid g = a.c.grid;
+  const size_t N = (size_t)g.N;
+  const size_t cap = (size_t)a.cap;
+  const S* __restrict__ fin = reinterpret_cast<const S*>(a.fst);
+  const R* __restrict__ lin = reinterpret_cast<const R*>(a.lam_in);
+  R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
+  R* __restrict__ own_t = reinterpret_cast<R*>(a.own);
+  const Consts<R>& k = pick_consts<R>(a.c);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dL/drho_b, dL/dg
+  for (int i = blockIdx.x * ABLOCK + threadIdx.x; i < a.n_i; i += gridDim.x * ABLOCK) {
+    const int idx = a.listI[i];
+    Nbr n;
+    coords(g, idx, n.x, n.y, n.z);
+    n.xm = step_axis(n.x, -1, g.nx, g.px);
+    n.xp = step_axis(n.x, 1, g.nx, g.px);
+    n.ym = step_axis(n.y, -1, g.ny, g.py);
+    n.yp = step_axis(n.y, 1, g.ny, g.py);
+    n.zm = step_axis(n.z, -1, g.nz, g.pz);
+    n.zp = step_axis(n.z, 1, g.nz, g.pz);
+    // ---- loads: the forward neighbourhood of time t and the adjoint of t+1
+    IfaceData<F> d;
+    unsigned off[Q];  // 19 N < 2^32 is checked at init
+    off[0] = (unsigned)idx;
+    d.f[0] = F::load_raw(fin + idx);
+    d.own[0] = d.f[0];
+    d.ty[0] = IFACE;
+    d.ph[0] = 0.0;
+#define FSLBM_AILOAD(q)                                                                 \
+  {                                                                                     \
+    const int s = pull_source<q>(g, n);                                                 \
+    const int sc = s >= 0 ? s : idx;                                                    \
+    off[q] = s >= 0 ? (unsigned)(q * N + s) : (unsigned)(OPP[q] * N + idx);             \
+    d.f[q] = F::load_raw(fin + off[q]);                                                 \
+    d.own[q] = F::load_raw(fin + (size_t)q * N + idx);                                  \
+    const uint8_t ts = a.flags[sc];                                                     \
+    d.ty[q] = s >= 0 ? ts : WALL_CLASS;                                                 \
+    d.ph[q] = a.phi[sc];                                                                \
+  }
+    FSLBM_LINKS(FSLBM_AILOAD)
+#undef FSLBM_AILOAD
+    d.m = a.mass[idx];
+    d.phix = a.phi[idx];
+    const double lam_m = a.lam_m[idx];
+    const double lam_p = a.lphi_in[idx];
+
+    // ---- forward recompute (the step's own arithmetic, intermediates kept)
+    uint32_t gasmask = 0;
+    double dm = 0.0;
+#define FSLBM_AEXCH(q)                                             \
+  {                                                                \
+    const uint8_t ts = d.ty[q];                                    \
+    if (ts == GAS) gasmask |= 1u << q;                             \
+    if (ts == LIQ || ts == IFACE) {                                \
+      const double diff = (double)d.f[q] - (double)d.own[OPP[q]];  \
+      if (ts == LIQ) {                                             \
+        dm = dm + diff;                                            \
+      } else {                                                     \
+        const double wgt = 0.5 * (d.phix + d.ph[q]);               \
+        dm = dm + wgt * diff;                                      \
+      }                                                            \
+    }                                                              \
+  }
+    FSLBM_LINKS(FSLBM_AEXCH)
+#undef FSLBM_AEXCH
+    const double m_new = d.m + dm;
+    const double dist = d.phix - 0.5;
+    double nv[3] = {0.0, 0.0, 0.0};
+    double nrm = 0.0;
+    bool have_n = false;
+    // (no branch on gasmask around the gas-link work: every per-link step below
+    // tests its own link, so a cell without gas links passes through unchanged)
+    R rho_t, u_t[3], usq_t;
+    {
+      const double gx = 0.5 * (phi_seen(d, 2) - phi_seen(d, 1));
+      const double gy = 0.5 * (phi_seen(d, 4) - phi_seen(d, 3));
+      const double gz = 0.5 * (phi_seen(d, 6) - phi_seen(d, 5));
+      const double nrm2 = (gx * gx + gy * gy) + gz * gz;
+      have_n = nrm2 > 0.0;
+      if (have_n) {
+        nrm = sqrt(nrm2);
+        nv[0] = -gx / nrm;
+        nv[1] = -gy / nrm;
+        nv[2] = -gz / nrm;
+      }
+      recover_moments<R, SH>(d.own, k, true, rho_t, u_t);
+      usq_t = usq_of(u_t);
+#define FSLBM_AREBUILD(q) \
+  rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, R(1.0), u_t, usq_t, k, true, false);
+      FSLBM_LINKS(FSLBM_AREBUILD)
+#undef FSLBM_AREBUILD
+    }
+    R rho_s, jj[3];
+    moments(d.f, rho_s, jj);
+    const R u[3] = {jj[0] + k.hg[0], jj[1] + k.hg[1], jj[2] + k.hg[2]};
+    const double rho = SH ? 1.0 + (double)rho_s : (double)rho_s;
+    const double phi_new = m_new / rho;
+    R ob[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) ob[q] = lin[(size_t)q * N + idx];
+
+    // ---- adjoint
+    // phi(t+1) = m(t+1) / rho: dL/dm(t+1) and the density term of the collision
+    const double mb = lam_m + lam_p / rho;
+    const double rho_b_phi = -lam_p * phi_new / rho;
+    R fb[Q], gb[3];
+    collide_adjoint(ob, u, (R)rho_b_phi, k, fb, gb);
+    R ownb[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) ownb[q] = R(0.0);
+    double geo[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // fill adjoint of the axis pull sources
+    double phis = 0.0;                                // fill adjoint of the cell itself
+    R rbb = R(0.0);                                   // dL/drho_b
+    {
+      double nvb[3] = {0.0, 0.0, 0.0}, distb = 0.0;
+      R rtb = R(0.0), utb[3] = {R(0.0), R(0.0), R(0.0)};
+#define FSLBM_AREBADJ(q) \
+  rebuild_adj<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, u_t, usq_t, k, fb, ownb, nvb, distb, rtb, utb, rbb);
+      FSLBM_LINKS(FSLBM_AREBADJ)
+#undef FSLBM_AREBADJ
+      if (RULE == 1 && have_n) {
+        // n = -grad/|grad|: dL/dgrad = (-nb + n (nb.n)) / |grad|
+        const double nd = (nvb[0] * nv[0] + nvb[1] * nv[1]) + nvb[2] * nv[2];
+        const double gbx = (-nvb[0] + nv[0] * nd) / nrm;
+        const double gby = (-nvb[1] + nv[1] * nd) / nrm;
+        const double gbz = (-nvb[2] + nv[2] * nd) / nrm;
+        // grad_x = (phi(x+1) - phi(x-1))/2: pull sources of links 2 and 1, etc.
+        seen_adj(d, 2, 0.5 * gbx, geo, phis);
+        seen_adj(d, 1, -0.5 * gbx, geo, phis);
+        seen_adj(d, 4, 0.5 * gby, geo, phis);
+        seen_adj(d, 3, -0.5 * gby, geo, phis);
+        seen_adj(d, 6, 0.5 * gbz, geo, phis);
+        seen_adj(d, 5, -0.5 * gbz, geo, phis);
+      }
+      phis += distb;  // dist = phi - 1/2
+      // rho_t = sum_q ft_q, u_t = (sum_q c_q ft_q - g) + g/2
+#define FSLBM_ARECOV(q) ownb[q] = ownb[q] + (rtb + cdot<q>(utb));
+      FSLBM_ARECOV(0)
+      FSLBM_LINKS(FSLBM_ARECOV)
+#undef FSLBM_ARECOV
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gb[c] = gb[c] - R(0.5) * utb[c];
+    }
+    // mass exchange: m(t+1) = m + sum_q w_q (f_q(pulled) - ft_qbar), w = 1 or (phi_x + phi_s)/2
+#define FSLBM_AEXADJ(q)                                                               \
+  {                                                                                   \
+    const uint8_t ts = d.ty[q];                                                       \
+    double pc = (q <= 6) ? geo[(q <= 6 ? q : 1) - 1] : 0.0;                           \
+    if (ts == LIQ || ts == IFACE) {                                                   \
+      const double w = ts == LIQ ? 1.0 : 0.5 * (d.phix + d.ph[q]);                    \
+      const R wm = (R)(w * mb);                                                       \
+      fb[q] = fb[q] + wm;                                                             \
+      ownb[OPP[q]] = ownb[OPP[q]] - wm;                                               \
+      if (ts == IFACE) {                                                              \
+        const double half = 0.5 * ((double)d.f[q] - (double)d.own[OPP[q]]) * mb;     \
+        phis += half;                                                                 \
+        pc += half;                                                                   \
+      }                                                                               \
+    }                                                                                 \
+    a.phic[(size_t)q * cap + i] = pc;                                                 \
+  }
+    FSLBM_LINKS(FSLBM_AEXADJ)
+#undef FSLBM_AEXADJ
+
+    // ---- stores: push of the pulled populations' adjoints, scratch terms
+    lout[off[0]] = fb[0];
+#define FSLBM_APUSH(q) \
+  if (d.ty[q] != GAS) lout[off[q]] = fb[q];
+    FSLBM_LINKS(FSLBM_APUSH)
+#undef FSLBM_APUSH
+#pragma unroll
+    for (int q = 0; q < Q; ++q) own_t[(size_t)q * cap + i] = ownb[q];
+    a.phic[i] = phis;
+    a.lam_m[idx] = mb;
+    acc[0] += (double)rbb;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[1 + c] += (double)gb[c];
+  }
+  block_accumulate<4>(acc, a.part_iface + 4 * (size_t)blockIdx.x);
+}
+
+// Own-population terms and the fill adjoint of each interface cell y.  The
+// element ft_q(y) is read by the pull of the cell y + c_q (or, beyond a wall,
+// by y itself); if that cell is gas nothing was pushed there this step.
+template <class F>
+__global__ __launch_bounds__(ABLOCK) void k_adj_iface2(AdjArgs a) {
+  using R = typename F::R;
+  const Grid g = a.c.grid;
+  const size_t N = (size_t)g.N;
+  const size_t cap = (size_t)a.cap;
+  R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
+  const R* __restrict__ own_t = reinterpret_cast<const R*>(a.own);
+  for (int i = blockIdx.x * ABLOCK + threadIdx.x; i < a.n_i; i += gridDim.x * ABLOCK) {
+    const int yc = a.listI[i];
+    int x, y, z;
+    coords(g, yc, x, y, z);
+    lout[yc] = lout[yc] + own_t[i];
+    double pb = a.phic[i];
+#define FSLBM_AOWN(q)                                                          \
+  {                                                                            \
+    const int p = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);                   \
+    const uint8_t tp = p >= 0 ? a.flags[p] : (uint8_t)LIQ;                     \
+    const size_t e = (size_t)q * N + yc;                                       \
+    const R v = own_t[(size_t)q * cap + i];                                    \
+    lout[e] = tp == GAS ? v : lout[e] + v;                                     \
+    if (tp == IFACE) pb += a.phic[(size_t)q * cap + a.islot[p]];               \
+  }
+    FSLBM_LINKS(FSLBM_AOWN)
+#undef FSLBM_AOWN
+    a.lphi_out[yc] = pb;
+  }
+}
+
+// ------------------------------------------------------- seed / output
+template <class R>
+__global__ __launch_bounds__(ABLOCK) void k_adj_seed(Grid g, const uint8_t* flags, const double* dLdf,
+                                                     const double* dLdm, const double* dLdphi, R* lam, R* lam2,
+                                                     double* lam_m, double* lphi, double* lphi2) {
+  const size_t N = (size_t)g.N;
+  for (size_t idx = (size_t)blockIdx.x * ABLOCK + threadIdx.x; idx < N; idx += (size_t)gridDim.x * ABLOCK) {
+    const uint8_t t = flags[idx];
+    const bool act = t != GAS, itf = t == IFACE;
+    for (int q = 0; q < Q; ++q) {
+      lam[(size_t)q * N + idx] = (act && dLdf) ? (R)dLdf[(size_t)q * N + idx] : R(0.0);
+      lam2[(size_t)q * N + idx] = R(0.0);
+    }
+    lam_m[idx] = (itf && dLdm) ? dLdm[idx] : 0.0;
+    lphi[idx] = (itf && dLdphi) ? dLdphi[idx] : 0.0;
+    lphi2[idx] = 0.0;
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(ABLOCK) void k_adj_out(Grid g, const uint8_t* flags, const R* lam, const double* lam_m,
+                                                    const double* lphi, double* dLdf, double* dLdm, double* dLdphi) {
+  const size_t N = (size_t)g.N;
+  for (size_t idx = (size_t)blockIdx.x * ABLOCK + threadIdx.x; idx < N; idx += (size_t)gridDim.x * ABLOCK) {
+    const uint8_t t = flags[idx];
+    if (dLdf)
+      for (int q = 0; q < Q; ++q) dLdf[(size_t)q * N + idx] = t != GAS ? (double)lam[(size_t)q * N + idx] : 0.0;
+    if (dLdm) dLdm[idx] = t == IFACE ? lam_m[idx] : 0.0;
+    if (dLdphi) dLdphi[idx] = t == IFACE ? lphi[idx] : 0.0;
+  }
+}
+
+// fixed-order sum of the block partials: out4 = {dL/drho_b, dL/dg}
+__global__ __launch_bounds__(ABLOCK) void k_adj_reduce(const double* ps, int nbs, const double* pi, int nbi,
+                                                       double* out4) {
+  __shared__ double sm[ABLOCK][4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nbs; b += ABLOCK)
+    for (int c = 0; c < 3; ++c) v[1 + c] += ps[3 * (size_t)b + c];
+  for (int b = threadIdx.x; b < nbi; b += ABLOCK)
+    for (int c = 0; c < 4; ++c) v[c] += pi[4 * (size_t)b + c];
+  for (int c = 0; c < 4; ++c) sm[threadIdx.x][c] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 4; ++c) {
+      double s = 0.0;
+      for (int t = 0; t < ABLOCK; ++t) s += sm[t][c];
+      out4[c] = s;
+    }
+  }
+}
+
+// ------------------------------------------- ascending interface-cell list
+// per block of ABLOCK cells: number of interface cells
+__global__ __launch_bounds__(ABLOCK) void k_list_count(const uint8_t* flags, int N, int32_t* bcount) {
+  const int idx = blockIdx.x * ABLOCK + threadIdx.x;
+  const bool it = idx < N && flags[idx] == IFACE;
+  const int c = __syncthreads_count(it);
+  if (threadIdx.x == 0) bcount[blockIdx.x] = c;
+}
+
+// exclusive scan of bcount[0..nb) in place (one block of SCAN threads); total to n_out
+constexpr int SCAN = 1024;
+__global__ __launch_bounds__(SCAN) void k_list_scan(int32_t* bcount, int nb, int32_t* n_out) {
+  __shared__ int32_t sm[SCAN];
+  const int per = (nb + SCAN - 1) / SCAN;
+  const int b0 = (int)threadIdx.x * per;
+  const int b1 = min(nb, b0 + per);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += bcount[b];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < SCAN; o <<= 1) {
+    const int v = (int)threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
+    __syncthreads();
+    sm[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = threadIdx.x > 0 ? sm[threadIdx.x - 1] : 0;
+  for (int b = b0; b < b1; ++b) {
+    const int c = bcount[b];
+    bcount[b] = run;
+    run += c;
+  }
+  if (threadIdx.x == SCAN - 1) *n_out = sm[SCAN - 1];
+}
+
+__global__ __launch_bounds__(ABLOCK) void k_list_write(const uint8_t* flags, int N, const int32_t* boff,
+                                                       int32_t* list, int32_t* islot) {
+  __shared__ int32_t wc[ABLOCK / 64];
+  const int idx = blockIdx.x * ABLOCK + threadIdx.x;
+  const bool it = idx < N && flags[idx] == IFACE;
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  const unsigned long long b = __ballot(it);
+  if (lane == 0) wc[w] = __popcll(b);
+  __syncthreads();
+  int base = boff[blockIdx.x];
+  for (int k = 0; k < w; ++k) base += wc[k];
+  if (it) {
+    const int pos = base + __popcll(b & ((1ull << lane) - 1ull));
+    list[pos] = idx;
+    islot[idx] = pos;
+  }
+}
+
+// number of interface cells (atomic add of per-block counts into *out)
+__global__ __launch_bounds__(ABLOCK) void k_count_iface(const uint8_t* flags, int N, int32_t* out) {
+  const int idx = blockIdx.x * ABLOCK + threadIdx.x;
+  const int c = __syncthreads_count(idx < N && flags[idx] == IFACE);
+  if (threadIdx.x == 0 && c) atomicAdd(out, c);
+}
+
+// ------------------------------------------------------------ launchers
+static inline unsigned ablocks(size_t n) { return (unsigned)((n + ABLOCK - 1) / ABLOCK); }
+
+unsigned adj_sweep_blocks(const Grid& g) {
+  return (unsigned)((g.nx + ABLOCK - 1) / ABLOCK) * (unsigned)g.ny * (unsigned)g.nz;
+}
+unsigned adj_iface_blocks(int n_i) { return std::max(1u, std::min(ADJ_IFACE_GRID, ablocks((size_t)n_i))); }
+unsigned list_blocks(const Grid& g) { return ablocks((size_t)g.N); }
+
+hipError_t launch_iface_list(const uint8_t* flags, const Grid& g, int32_t* bcount, int32_t* list, int32_t* islot,
+                             int32_t* n_out, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned nb = list_blocks(g);
+  k_list_count<<<nb, ABLOCK, 0, st>>>(flags, g.N, bcount);
+  k_list_scan<<<1, SCAN, 0, st>>>(bcount, (int)nb, n_out);
+  k_list_write<<<nb, ABLOCK, 0, st>>>(flags, g.N, bcount, list, islot);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_iface(const uint8_t* flags, const Grid& g, int32_t* out, void* stream) {
+  k_count_iface<<<list_blocks(g), ABLOCK, 0, (hipStream_t)stream>>>(flags, g.N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed(const Common& c, const uint8_t* flags, int precision, const double* dLdf,
+                           const double* dLdm, const double* dLdphi, void* lam, void* lam_other, double* lam_m,
+                           double* lphi, double* lphi_other, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned nb = std::min(8192u, ablocks((size_t)c.grid.N));
+  if (precision == 0)
+    k_adj_seed<double><<<nb, ABLOCK, 0, st>>>(c.grid, flags, dLdf, dLdm, dLdphi, (double*)lam, (double*)lam_other,
+                                              lam_m, lphi, lphi_other);
+  else
+    k_adj_seed<float><<<nb, ABLOCK, 0, st>>>(c.grid, flags, dLdf, dLdm, dLdphi, (float*)lam, (float*)lam_other,
+                                             lam_m, lphi, lphi_other);
+  return hipGetLastError();
+}
+
+template <class F>
+static void adj_form(const AdjArgs& a0, int rule, hipStream_t st) {
+  AdjArgs a = a0;
+  a.cpr = (a.c.grid.nx + ABLOCK - 1) / ABLOCK;
+  k_adj_sweep<F><<<adj_sweep_blocks(a.c.grid), ABLOCK, 0, st>>>(a);
+  if (a.n_i > 0) {
+    const unsigned nbi = adj_iface_blocks(a.n_i);
+    if (rule == 0)
+      k_adj_iface<F, 0><<<nbi, ABLOCK, 0, st>>>(a);
+    else
+      k_adj_iface<F, 1><<<nbi, ABLOCK, 0, st>>>(a);
+    k_adj_iface2<F><<<nbi, ABLOCK, 0, st>>>(a);
+  }
+}
+
+hipError_t launch_adjoint_step(const AdjArgs& a, int precision, int rule, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == 0) adj_form<FormF64>(a, rule, st);
+  else adj_form<FormF32>(a, rule, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_out(const Common& c, const uint8_t* flags, int precision, const void* lam,
+                          const double* lam_m, const double* lphi, double* dLdf, double* dLdm, double* dLdphi,
+                          void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned nb = std::min(8192u, ablocks((size_t)c.grid.N));
+  if (precision == 0)
+    k_adj_out<double><<<nb, ABLOCK, 0, st>>>(c.grid, flags, (const double*)lam, lam_m, lphi, dLdf, dLdm, dLdphi);
+  else
+    k_adj_out<float><<<nb, ABLOCK, 0, st>>>(c.grid, flags, (const float*)lam, lam_m, lphi, dLdf, dLdm, dLdphi);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(const double* part_sweep, int nb_sweep, const double* part_iface, int nb_iface,
+                             double* out4, void* stream) {
+  k_adj_reduce<<<1, ABLOCK, 0, (hipStream_t)stream>>>(part_sweep, nb_sweep, part_iface, nb_iface, out4);
+  return hipGetLastError();
+}
+
+}  // namespace fslbm

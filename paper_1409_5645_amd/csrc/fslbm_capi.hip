@@ -113,6 +113,7 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
   d.lp = lp;
   d.lm = lm;
   d.inv1p = 1.0 / (1.0 + lp);
+  d.ilm = 1.0 / lm;
   for (int a = 0; a < 3; ++a) {
     d.g[a] = p.g[a];
     d.hg[a] = 0.5 * p.g[a];
@@ -124,6 +125,7 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
   f.lp = (float)d.lp;
   f.lm = (float)d.lm;
   f.inv1p = (float)d.inv1p;
+  f.ilm = (float)d.ilm;
   for (int a = 0; a < 3; ++a) {
     f.g[a] = (float)d.g[a];
     f.hg[a] = (float)d.hg[a];
@@ -273,6 +275,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.fin = c->f[a];
     s.fout = c->f[b];
     s.flags = c->flags;
+    s.mass_in = c->mass;
     s.mass = c->mass;
     s.phi_in = c->phi[a];
     s.phi_out = c->phi[b];
@@ -456,6 +459,360 @@ fslbm_status fslbm_destroy(fslbm_ctx* c) {
 
 const char* fslbm_last_error(const fslbm_ctx* c) {
   return c ? c->last_error.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ adjoint window
+struct fslbm_window {
+  fslbm_ctx* ctx = nullptr;
+  Common com;           // constants at forward time (g, rho_b, relaxation)
+  int T = 0, K = 0, C = 0, rule = 0, precision = 0;
+  int n_i = 0, cap = 1, nb_sweep = 0, nb_iface = 0;
+  size_t N = 0;
+  struct Slot {
+    void* f;
+    double* m;
+    double* phi;
+  };
+  std::vector<Slot> ckpt, ring;  // states at t = jK; states jK + k (k = 1..K) of one segment
+  int ring_seg = -1;             // segment whose states the ring holds
+  uint8_t* flags = nullptr;      // cell classes, fixed over the window
+  void* lam[2] = {nullptr, nullptr};
+  double* lam_m = nullptr;
+  double* lphi[2] = {nullptr, nullptr};
+  int32_t *listI = nullptr, *islot = nullptr, *bcount = nullptr, *n_dev = nullptr;
+  void* own = nullptr;
+  double* phic = nullptr;
+  double *part_sweep = nullptr, *part_iface = nullptr, *grads = nullptr;
+  double *aux_rho = nullptr, *aux_u = nullptr;  // recompute steps (the context's stay untouched)
+  int32_t* counters = nullptr;
+  int32_t* listI_fwd = nullptr;
+};
+
+namespace {
+
+struct WinLayout {
+  // head (independent of the interface count)
+  size_t flags, listI, islot, bcount, n_dev;
+  // rest
+  size_t slots, slot_bytes, slot_m, slot_phi;
+  size_t lam[2], lam_m, lphi[2], own, phic, part_sweep, part_iface, grads, aux_rho, aux_u, counters, listI_fwd;
+  size_t total;
+};
+
+WinLayout win_layout(const Grid& g, int precision, int T, int K, int n_i) {
+  const size_t N = (size_t)g.N;
+  const size_t sb = storage_bytes(precision);
+  const size_t rb = precision == FSLBM_FP64 ? 8 : 4;  // compute type of the adjoint
+  const size_t cap = (size_t)std::max(n_i, 1);
+  const int C = (T + K - 1) / K;
+  WinLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.flags = take(N);
+  L.listI = take(4 * N);
+  L.islot = take(4 * N);
+  L.bcount = take(4 * (size_t)list_blocks(g));
+  L.n_dev = take(4);
+  L.slot_m = align_up(Q * N * sb);
+  L.slot_phi = L.slot_m + align_up(8 * N);
+  L.slot_bytes = L.slot_phi + align_up(8 * N);
+  L.slots = take(L.slot_bytes * (size_t)(C + K));
+  L.lam[0] = take(Q * N * rb);
+  L.lam[1] = take(Q * N * rb);
+  L.lam_m = take(8 * N);
+  L.lphi[0] = take(8 * N);
+  L.lphi[1] = take(8 * N);
+  L.own = take(Q * cap * rb);
+  L.phic = take(Q * cap * 8);
+  L.part_sweep = take(3 * 8 * (size_t)adj_sweep_blocks(g));
+  L.part_iface = take(4 * 8 * (size_t)adj_iface_blocks(n_i));
+  L.grads = take(4 * 8);
+  L.aux_rho = take(8 * N);
+  L.aux_u = take(24 * N);
+  L.counters = take(2 * NCOUNT * sizeof(int32_t));
+  L.listI_fwd = take(4 * N);
+  L.total = o;
+  return L;
+}
+
+fslbm_status window_checks(fslbm_ctx* c, int32_t T, int32_t K) {
+  if (T < 1) { c->last_error = "window length T must be >= 1"; return FSLBM_E_INVALID; }
+  if (K < 0) { c->last_error = "checkpoint spacing K must be >= 0 (0: ceil(sqrt(T)))"; return FSLBM_E_INVALID; }
+  if (c->p.precision == FSLBM_FP16S) {
+    c->last_error = "the adjoint window supports the FP64 and FP32 forms";
+    return FSLBM_E_UNSUPPORTED;
+  }
+  if (!c->p.incompressible || c->p.stokes) {
+    c->last_error = "the adjoint window supports the incompressible equilibrium with its quadratic term";
+    return FSLBM_E_UNSUPPORTED;
+  }
+  return FSLBM_OK;
+}
+
+int window_spacing(int32_t T, int32_t K) {
+  if (K == 0) {
+    int k = (int)std::ceil(std::sqrt((double)T));
+    while ((long long)k * k < T) ++k;
+    return std::max(k, 1);
+  }
+  return std::min(K, T);
+}
+
+// one frozen forward step from slot A (time t) to slot B (time t+1)
+hipError_t window_step(fslbm_window* w, const fslbm_window::Slot& A, const fslbm_window::Slot& B, int parity,
+                       bool forward_pass) {
+  fslbm_ctx* c = w->ctx;
+  StepLaunch L{};
+  SweepArgs& s = L.sweep;
+  s.c = w->com;
+  s.fin = A.f;
+  s.fout = B.f;
+  s.flags = w->flags;
+  s.mass_in = A.m;
+  s.mass = B.m;
+  s.phi_in = A.phi;
+  s.phi_out = B.phi;
+  // the forward pass leaves the context's collision moments at the final state
+  s.aux_rho = forward_pass ? c->aux_rho : w->aux_rho;
+  s.aux_u = forward_pass ? c->aux_u : w->aux_u;
+  s.f_epoch = c->f_epoch;
+  s.listF = c->listF;
+  s.listE = c->listE;
+  s.listI = w->listI_fwd;
+  s.counters = w->counters + (parity & 1) * NCOUNT;
+  s.counters_next = w->counters + ((parity + 1) & 1) * NCOUNT;
+  s.thr_hi = c->thr_hi;
+  s.thr_lo = c->thr_lo;
+  s.step = 0;
+  s.freeze = 1;
+  s.cpr = 0;
+  s.pairs = c->pairs;
+  L.stream = (void*)c->stream;
+  hipError_t e = launch_sweep(L, w->precision, w->rule);
+  if (e != hipSuccess) return e;
+  return launch_iface(L, w->precision, w->rule);
+}
+
+}  // namespace
+
+extern "C" {
+
+fslbm_status fslbm_set_forcing(fslbm_ctx* c, const double g[3], double rho_gas) {
+  if (!c) return FSLBM_E_INVALID;
+  if (!g) { c->last_error = "g is NULL"; return FSLBM_E_INVALID; }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(g[a])) { c->last_error = "g must be finite"; return FSLBM_E_INVALID; }
+  if (!(rho_gas > 0.0) || !std::isfinite(rho_gas)) { c->last_error = "rho_gas must be positive"; return FSLBM_E_INVALID; }
+  for (int a = 0; a < 3; ++a) c->p.g[a] = g[a];
+  c->p.rho_gas = rho_gas;
+  make_constants(c->p, c->com, c->thr_hi, c->thr_lo);
+  return FSLBM_OK;
+}
+
+fslbm_status fslbm_window_workspace_size(fslbm_ctx* c, int32_t T, int32_t K, size_t* bytes) {
+  if (!c) return FSLBM_E_INVALID;
+  if (!bytes) { c->last_error = "bytes is NULL"; return FSLBM_E_INVALID; }
+  fslbm_status st = window_checks(c, T, K);
+  if (st != FSLBM_OK) return st;
+  HIPCHK(c, launch_fill_i32(c->cnt + 3, 1, 0, c->stream), "count init");
+  HIPCHK(c, launch_count_iface(c->flags, c->com.grid, c->cnt + 3, c->stream), "count interface cells");
+  int32_t n_i = 0;
+  HIPCHK(c, hipMemcpyAsync(&n_i, c->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "count copy");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "count sync");
+  *bytes = win_layout(c->com.grid, c->p.precision, T, window_spacing(T, K), n_i).total;
+  return FSLBM_OK;
+}
+
+fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t rule, void* workspace,
+                                  size_t workspace_bytes, fslbm_window** out) {
+  if (!c) return FSLBM_E_INVALID;
+  if (!out || !workspace) { c->last_error = "out or workspace is NULL"; return FSLBM_E_INVALID; }
+  if (((uintptr_t)workspace) % ALIGN) { c->last_error = "window workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
+  if (rule != FSLBM_RULE_FSK && rule != FSLBM_RULE_FSL) { c->last_error = "unknown rule"; return FSLBM_E_INVALID; }
+  if (rule == FSLBM_RULE_FSL && c->p.tau == 1.0) {
+    c->last_error = "FSL needs tau != 1 (n+ is not recoverable from a fully relaxed state)";
+    return FSLBM_E_UNSUPPORTED;
+  }
+  fslbm_status st = window_checks(c, T, K);
+  if (st != FSLBM_OK) return st;
+  const Grid& g = c->com.grid;
+  const size_t N = (size_t)g.N;
+  char* wsp = (char*)workspace;
+  // the head of the layout does not depend on the interface count
+  const WinLayout H = win_layout(g, c->p.precision, T, window_spacing(T, K), 0);
+  if (workspace_bytes < H.slots) { c->last_error = "window workspace too small"; return FSLBM_E_INVALID; }
+  fslbm_window* w = new (std::nothrow) fslbm_window();
+  if (!w) { c->last_error = "out of host memory"; return FSLBM_E_INVALID; }
+  auto fail = [&](fslbm_status s) {
+    delete w;
+    return s;
+  };
+  w->ctx = c;
+  w->com = c->com;
+  w->T = T;
+  w->K = window_spacing(T, K);
+  w->C = (T + w->K - 1) / w->K;
+  w->rule = rule;
+  w->precision = c->p.precision;
+  w->N = N;
+  w->flags = (uint8_t*)(wsp + H.flags);
+  w->listI = (int32_t*)(wsp + H.listI);
+  w->islot = (int32_t*)(wsp + H.islot);
+  w->bcount = (int32_t*)(wsp + H.bcount);
+  w->n_dev = (int32_t*)(wsp + H.n_dev);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(w->flags, c->flags, N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+    return fail(dev_fail(c, e, "window flags copy"));
+  if ((e = launch_iface_list(w->flags, g, w->bcount, w->listI, w->islot, w->n_dev, c->stream)) != hipSuccess)
+    return fail(dev_fail(c, e, "interface list"));
+  int32_t n_i = 0;
+  if ((e = hipMemcpyAsync(&n_i, w->n_dev, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+    return fail(dev_fail(c, e, "interface count copy"));
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return fail(dev_fail(c, e, "window sync"));
+  const WinLayout L = win_layout(g, c->p.precision, T, w->K, n_i);
+  if (workspace_bytes < L.total) {
+    c->last_error = "window workspace too small (" + std::to_string(workspace_bytes) + " < " +
+                    std::to_string(L.total) + " bytes)";
+    return fail(FSLBM_E_INVALID);
+  }
+  w->n_i = n_i;
+  w->cap = std::max(n_i, 1);
+  w->nb_sweep = (int)adj_sweep_blocks(g);
+  w->nb_iface = (int)adj_iface_blocks(n_i);
+  for (int i = 0; i < w->C + w->K; ++i) {
+    char* b = wsp + L.slots + (size_t)i * L.slot_bytes;
+    fslbm_window::Slot sl{b, (double*)(b + L.slot_m), (double*)(b + L.slot_phi)};
+    if (i < w->C) w->ckpt.push_back(sl);
+    else w->ring.push_back(sl);
+  }
+  for (int i = 0; i < 2; ++i) {
+    w->lam[i] = wsp + L.lam[i];
+    w->lphi[i] = (double*)(wsp + L.lphi[i]);
+  }
+  w->lam_m = (double*)(wsp + L.lam_m);
+  w->own = wsp + L.own;
+  w->phic = (double*)(wsp + L.phic);
+  w->part_sweep = (double*)(wsp + L.part_sweep);
+  w->part_iface = (double*)(wsp + L.part_iface);
+  w->grads = (double*)(wsp + L.grads);
+  w->aux_rho = (double*)(wsp + L.aux_rho);
+  w->aux_u = (double*)(wsp + L.aux_u);
+  w->counters = (int32_t*)(wsp + L.counters);
+  w->listI_fwd = (int32_t*)(wsp + L.listI_fwd);
+
+  // checkpoint 0: the current state of the context
+  const size_t fb = Q * N * storage_bytes(c->p.precision);
+  const fslbm_window::Slot& c0 = w->ckpt[0];
+  if ((e = hipMemcpyAsync(c0.f, c->f[c->cur], fb, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(c0.m, c->mass, 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(c0.phi, c->phi[c->cur], 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+    return fail(dev_fail(c, e, "checkpoint copy"));
+  if ((e = launch_fill_i32(w->counters, 2 * NCOUNT, 0, c->stream)) != hipSuccess)
+    return fail(dev_fail(c, e, "window counters"));
+  // forward: each step writes straight into its slot (no copies); the last
+  // step of every segment but the final one writes the next checkpoint
+  for (int j = 0; j < w->C; ++j) {
+    const int Lj = std::min(w->K, T - j * w->K);
+    for (int k = 0; k < Lj; ++k) {
+      const fslbm_window::Slot& A = k == 0 ? w->ckpt[j] : w->ring[k - 1];
+      const fslbm_window::Slot& B = (k + 1 == Lj && j + 1 < w->C) ? w->ckpt[j + 1] : w->ring[k];
+      if ((e = window_step(w, A, B, j * w->K + k, true)) != hipSuccess)
+        return fail(dev_fail(c, e, "window step"));
+    }
+  }
+  w->ring_seg = w->C - 1;
+  // the final state becomes the context's current state
+  const int Llast = T - (w->C - 1) * w->K;
+  const fslbm_window::Slot& fin = w->ring[Llast - 1];
+  if ((e = hipMemcpyAsync(c->f[c->cur], fin.f, fb, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(c->mass, fin.m, 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(c->phi[c->cur], fin.phi, 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+    return fail(dev_fail(c, e, "final state copy"));
+  // no conversions happened: the last-step counters of the context read zero
+  if ((e = launch_fill_i32(c->counters, 2 * NCOUNT, 0, c->stream)) != hipSuccess)
+    return fail(dev_fail(c, e, "counters reset"));
+  c->step += T;
+  *out = w;
+  return FSLBM_OK;
+}
+
+fslbm_status fslbm_window_backward(fslbm_window* w, const double* dL_df, const double* dL_dm, const double* dL_dphi,
+                                   double* dL_df0, double* dL_dm0, double* dL_dphi0, double grads[4]) {
+  if (!w || !w->ctx) return FSLBM_E_INVALID;
+  fslbm_ctx* c = w->ctx;
+  hipStream_t st = c->stream;
+  const int T = w->T;
+  HIPCHK(c, launch_adj_seed(w->com, w->flags, w->precision, dL_df, dL_dm, dL_dphi, w->lam[T & 1],
+                            w->lam[(T + 1) & 1], w->lam_m, w->lphi[T & 1], w->lphi[(T + 1) & 1], st),
+         "adjoint seed");
+  HIPCHK(c, launch_fill_f64(w->part_sweep, 3 * (size_t)w->nb_sweep, 0.0, st), "adjoint partials");
+  HIPCHK(c, launch_fill_f64(w->part_iface, 4 * (size_t)w->nb_iface, 0.0, st), "adjoint partials");
+  for (int j = w->C - 1; j >= 0; --j) {
+    const int Lj = std::min(w->K, T - j * w->K);
+    if (w->ring_seg != j) {
+      // recompute the segment's states from its checkpoint
+      HIPCHK(c, launch_fill_i32(w->counters, 2 * NCOUNT, 0, st), "window counters");
+      for (int k = 0; k + 1 < Lj; ++k)
+        HIPCHK(c, window_step(w, k == 0 ? w->ckpt[j] : w->ring[k - 1], w->ring[k], k, false), "recompute step");
+      w->ring_seg = j;
+    }
+    for (int k = Lj - 1; k >= 0; --k) {
+      const int t = j * w->K + k;
+      const fslbm_window::Slot& S = k == 0 ? w->ckpt[j] : w->ring[k - 1];
+      AdjArgs a{};
+      a.c = w->com;
+      a.fst = S.f;
+      a.flags = w->flags;
+      a.mass = S.m;
+      a.phi = S.phi;
+      a.lam_in = w->lam[(t + 1) & 1];
+      a.lam_out = w->lam[t & 1];
+      a.lam_m = w->lam_m;
+      a.lphi_in = w->lphi[(t + 1) & 1];
+      a.lphi_out = w->lphi[t & 1];
+      a.listI = w->listI;
+      a.islot = w->islot;
+      a.own = w->own;
+      a.phic = w->phic;
+      a.part_sweep = w->part_sweep;
+      a.part_iface = w->part_iface;
+      a.n_i = w->n_i;
+      a.cap = w->cap;
+      a.cpr = 0;
+      HIPCHK(c, launch_adjoint_step(a, w->precision, w->rule, st), "adjoint step");
+    }
+  }
+  HIPCHK(c, launch_adj_out(w->com, w->flags, w->precision, w->lam[0], w->lam_m, w->lphi[0], dL_df0, dL_dm0,
+                           dL_dphi0, st), "adjoint output");
+  HIPCHK(c, launch_adj_reduce(w->part_sweep, w->nb_sweep, w->part_iface, w->nb_iface, w->grads, st),
+         "adjoint reduce");
+  double h[4] = {0.0, 0.0, 0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(h, w->grads, sizeof(h), hipMemcpyDeviceToHost, st), "gradient copy");
+  HIPCHK(c, hipStreamSynchronize(st), "adjoint sync");
+  if (grads)
+    for (int i = 0; i < 4; ++i) grads[i] = h[i];
+  return FSLBM_OK;
+}
+
+fslbm_status fslbm_window_info(const fslbm_window* w, int32_t info[4]) {
+  if (!w || !info) return FSLBM_E_INVALID;
+  info[0] = w->T;
+  info[1] = w->K;
+  info[2] = w->C;
+  info[3] = w->n_i;
+  return FSLBM_OK;
+}
+
+fslbm_status fslbm_window_destroy(fslbm_window* w) {
+  if (!w) return FSLBM_E_INVALID;
+  delete w;
+  return FSLBM_OK;
 }
 
 }  // extern "C"

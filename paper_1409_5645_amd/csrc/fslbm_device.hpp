@@ -72,6 +72,7 @@ struct FormF16 {
 template <class R>
 struct Consts {
   R lp, lm, inv1p;        // lambda_+, lambda_-, 1/(1+lambda_+)
+  R ilm;                  // 1/lambda_-
   R g[3], hg[3], glm[3];  // g, g/2, g/lambda_-
   R rhob_s;               // gas density in storage convention
   R rho0b;                // rho_0 used with the gas density

@@ -36,7 +36,8 @@ struct SweepArgs {
   const void* fin;
   void* fout;
   const uint8_t* flags;
-  double* mass;
+  const double* mass_in;  // interface mass of time t (may equal mass)
+  double* mass;           // interface mass of time t+1
   const double* phi_in;
   double* phi_out;
   double* aux_rho;
@@ -115,6 +116,27 @@ struct StatArgs {
   int32_t* cnt;   // [0] liquid cells, [1] bad cells, [2] interface cells
 };
 
+// One reverse step t+1 -> t of a window with frozen cell classes.
+struct AdjArgs {
+  Common c;
+  const void* fst;        // post-collision populations of time t (storage type)
+  const uint8_t* flags;   // cell classes (fixed over the window)
+  const double* mass;     // interface mass of time t
+  const double* phi;      // fill level of time t
+  const void* lam_in;     // dL/dft of time t+1 (compute type)
+  void* lam_out;          // dL/dft of time t (compute type)
+  double* lam_m;          // dL/dm: time t+1 on entry, time t on exit (interface cells)
+  const double* lphi_in;  // dL/dphi of time t+1 (interface cells)
+  double* lphi_out;       // dL/dphi of time t (interface cells)
+  const int32_t* listI;   // interface cells, ascending
+  const int32_t* islot;   // cell -> position in listI (interface cells only)
+  void* own;              // [Q][cap] own-population adjoint terms (compute type)
+  double* phic;           // [Q][cap] fill adjoint terms per pull source (0: the cell itself)
+  double* part_sweep;     // [sweep blocks][3] dL/dg partial sums
+  double* part_iface;     // [interface blocks][4] dL/drho_b, dL/dg partial sums
+  int n_i, cap, cpr;
+};
+
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
 hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
 hipError_t launch_convert(const StepLaunch& L, int precision);
@@ -127,5 +149,22 @@ hipError_t launch_set_state(const InitArgs& a, int precision, const double* f, c
                             const double* fill, void* stream);
 hipError_t launch_fields(const FieldArgs& a, int precision, void* stream);
 hipError_t launch_stats(const StatArgs& a, int precision, void* stream);
+
+// adjoint window (fslbm_adjoint.hip)
+unsigned adj_sweep_blocks(const Grid& g);
+unsigned adj_iface_blocks(int n_i);
+unsigned list_blocks(const Grid& g);
+hipError_t launch_count_iface(const uint8_t* flags, const Grid& g, int32_t* out, void* stream);
+hipError_t launch_iface_list(const uint8_t* flags, const Grid& g, int32_t* bcount, int32_t* list, int32_t* islot,
+                             int32_t* n_out, void* stream);
+hipError_t launch_adj_seed(const Common& c, const uint8_t* flags, int precision, const double* dLdf,
+                           const double* dLdm, const double* dLdphi, void* lam, void* lam_other, double* lam_m,
+                           double* lphi, double* lphi_other, void* stream);
+hipError_t launch_adjoint_step(const AdjArgs& a, int precision, int rule, void* stream);
+hipError_t launch_adj_out(const Common& c, const uint8_t* flags, int precision, const void* lam,
+                          const double* lam_m, const double* lphi, double* dLdf, double* dLdm, double* dLdphi,
+                          void* stream);
+hipError_t launch_adj_reduce(const double* part_sweep, int nb_sweep, const double* part_iface, int nb_iface,
+                             double* out4, void* stream);
 
 }  // namespace fslbm

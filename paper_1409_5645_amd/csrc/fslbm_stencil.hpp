@@ -1,0 +1,92 @@
+// Stencil helpers shared by the step and adjoint kernels: pull sources, the
+// neighbourhood of an interface cell, the link macro.
+#pragma once
+
+#include "fslbm_device.hpp"
+#include "fslbm_internal.hpp"
+
+namespace fslbm {
+
+#define FSLBM_LINKS(M) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16) M(17) M(18)
+
+// row offset marking a pull source row beyond a wall
+constexpr unsigned WALL_ROW = 0xffffffffu;
+
+// Neighbour coordinates of one cell (-1 beyond a wall).
+struct Nbr {
+  int x, y, z, xm, xp, ym, yp, zm, zp;
+};
+
+// linear index of the source x - c_q of the pull, or -1 beyond a wall
+template <int q>
+__device__ __forceinline__ int pull_source(const Grid& g, const Nbr& n) {
+  const int sx = CX[q] == 1 ? n.xm : (CX[q] == -1 ? n.xp : n.x);
+  const int sy = CY[q] == 1 ? n.ym : (CY[q] == -1 ? n.yp : n.y);
+  const int sz = CZ[q] == 1 ? n.zm : (CZ[q] == -1 ? n.zp : n.z);
+  return ((sx | sy | sz) < 0) ? -1 : sx + g.nx * (sy + g.ny * sz);
+}
+
+constexpr uint8_t WALL_CLASS = 3;  // class recorded for a pull source beyond a wall
+
+// Neighbourhood of one interface cell, loaded in a single pass (all loads
+// independent, so the cell costs one memory round trip, not a chain of them).
+template <class F>
+struct IfaceData {
+  using R = typename F::R;
+  R f[Q];         // pulled populations f_q(x, t+1) (gas links: placeholder)
+  R own[Q];       // own post-collision populations of time t
+  uint8_t ty[Q];  // class of the pull source x - c_q (WALL_CLASS beyond a wall)
+  double ph[Q];   // fill of the pull source (own fill beyond a wall)
+  double m, phix;
+};
+
+template <class F>
+__device__ __forceinline__ double phi_seen(const IfaceData<F>& d, int q) {
+  // fill level seen from the cell: liquid 1, gas 0, interface its fill,
+  // beyond a wall the cell's own fill
+  return d.ty[q] == LIQ ? 1.0 : (d.ty[q] == GAS ? 0.0 : d.ph[q]);
+}
+
+// Reconstruction of the population f_q that would stream in from a gas cell.
+// With o = qbar the link pointing to gas, the closure Eq. (closure) gives
+//   f_q = a0 ft_o(x) + a0bar ft_q(x) + a1 f_o(x,t+1) + C n+_o(x,t) + alpha_+ e+_o(rho_b,u_b)
+// with the FSK row of Table 1 (Eq. koerner) or Eq. (fsli1)-(fsli4) at alpha_+ = 1.
+template <class F, int RULE, int q>
+__device__ __forceinline__ void rebuild(IfaceData<F>& d, uint32_t gasmask, bool have_n, const double (&nv)[3],
+                                        double dist, typename F::R rho_t, typename F::R rho0_t,
+                                        const typename F::R (&u_t)[3], typename F::R usq_t,
+                                        const Consts<typename F::R>& k, bool incomp, bool stokes) {
+  using R = typename F::R;
+  if (!((gasmask >> q) & 1u)) return;
+  constexpr int o = OPP[q];
+  const R own_o = d.own[o];
+  const R e_b = e_plus<o>(k.rhob_s, k.rho0b, incomp, stokes, u_t, usq_t);
+  if (RULE == 1 && have_n && !((gasmask >> o) & 1u)) {
+    // link distance delta: plane with normal n at offset phi - 1/2
+    double nc = 0.0;
+    if (CX[o] == 1) nc = nc + nv[0];
+    if (CX[o] == -1) nc = nc - nv[0];
+    if (CY[o] == 1) nc = nc + nv[1];
+    if (CY[o] == -1) nc = nc - nv[1];
+    if (CZ[o] == 1) nc = nc + nv[2];
+    if (CZ[o] == -1) nc = nc - nv[2];
+    if (nc > 0.0) {
+      double dl = dist / nc;
+      if (dl < 0.0) dl = 0.0;
+      if (dl > 1.0) dl = 1.0;
+      const R delta = (R)dl;
+      const R own_q = d.own[q];
+      // n+_o(x,t) from ft+ = e+ + (1 + lambda_+) n+
+      const R e_o_t = e_plus<o>(rho_t, rho0_t, incomp, stokes, u_t, usq_t);
+      const R n_plus = (R(0.5) * (own_o + own_q) - e_o_t) * k.inv1p;
+      const R a0 = R(1.0) - (R(0.5) + delta);
+      const R a1 = delta - R(1.0);
+      const R Cc = k.lp * (R(0.5) + delta) - R(2.0) * k.lp;
+      d.f[q] = (((a0 * own_o + R(0.5) * own_q) + a1 * d.f[o]) + Cc * n_plus) + e_b;
+      return;
+    }
+  }
+  d.f[q] = R(2.0) * e_b - own_o;  // FSK: -ft_o + 2 e+_o(rho_b, u_b)
+}
+
+}  // namespace fslbm

@@ -45,8 +45,9 @@ class Buffers(ctypes.Structure):
 
 
 EXPORTS = ("fslbm_workspace_size", "fslbm_init", "fslbm_set_equilibrium", "fslbm_set_state", "fslbm_step",
-           "fslbm_fields", "fslbm_stats", "fslbm_conversions", "fslbm_timing", "fslbm_destroy",
-           "fslbm_last_error")
+           "fslbm_fields", "fslbm_stats", "fslbm_conversions", "fslbm_timing", "fslbm_set_forcing",
+           "fslbm_window_workspace_size", "fslbm_window_forward", "fslbm_window_backward", "fslbm_window_info",
+           "fslbm_window_destroy", "fslbm_destroy", "fslbm_last_error")
 
 _lib = None
 
@@ -69,6 +70,12 @@ def lib():
         L.fslbm_stats.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.fslbm_conversions.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(i32)), i32, ctypes.POINTER(i32)]
         L.fslbm_timing.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.fslbm_set_forcing.argtypes = [vp, dp, ctypes.c_double]
+        L.fslbm_window_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.fslbm_window_forward.argtypes = [vp, i32, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.fslbm_window_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, dp]
+        L.fslbm_window_info.argtypes = [vp, ctypes.POINTER(i32)]
+        L.fslbm_window_destroy.argtypes = [vp]
         L.fslbm_destroy.argtypes = [vp]
         L.fslbm_last_error.argtypes = [vp]
         L.fslbm_last_error.restype = ctypes.c_char_p
@@ -127,6 +134,12 @@ class Sim:
             msg = lib().fslbm_last_error(ctx).decode()
             raise FslbmError(st, msg)
 
+    def _as_dev64(self, a):
+        torch = self.torch
+        if isinstance(a, torch.Tensor):
+            return a.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        return self._dev(a)
+
     def _dev(self, a, dtype=None):
         t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=dtype or np.float64))
         return t.to(self.device)
@@ -144,7 +157,9 @@ class Sim:
         self._check(lib().fslbm_set_equilibrium(self.ctx, r.data_ptr(), uu.data_ptr(), fi.data_ptr()), self.ctx)
 
     def set_state(self, f, mass, fill, reservoir=0.0):
-        ff, m, fi = self._dev(f), self._dev(mass), self._dev(fill)
+        """Post-collision populations f[19, N] (unshifted), mass[N], fill[N]:
+        numpy arrays or float64 device tensors."""
+        ff, m, fi = (self._as_dev64(a) for a in (f, mass, fill))
         self.torch.cuda.synchronize(self.device)
         self._check(lib().fslbm_set_state(self.ctx, ff.data_ptr(), m.data_ptr(), fi.data_ptr(), float(reservoir)),
                     self.ctx)
@@ -199,6 +214,18 @@ class Sim:
         self._check(lib().fslbm_timing(self.ctx, int(bool(enable)), ctypes.byref(ms), ctypes.byref(n)), self.ctx)
         return ms.value, n.value
 
+    def set_forcing(self, g, rho_gas):
+        """Body acceleration g (3 values) and gas density rho_b = 3 P_b for the
+        steps enqueued from now on."""
+        gg = (ctypes.c_double * 3)(*[float(v) for v in g])
+        self._check(lib().fslbm_set_forcing(self.ctx, gg, float(rho_gas)), self.ctx)
+
+    def window(self, T, rule=FSL, K=0):
+        """Forward pass of an adjoint window of T frozen-class steps from the
+        current state (sqrt(T) checkpointing with spacing K, 0 = ceil(sqrt T)).
+        Returns a Window whose backward() gives the gradients."""
+        return Window(self, int(T), int(rule), int(K))
+
     def close(self):
         if getattr(self, "ctx", None):
             lib().fslbm_destroy(self.ctx)
@@ -209,3 +236,104 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+class Window:
+    """Adjoint window on a Sim: the forward pass runs at construction."""
+
+    def __init__(self, sim: Sim, T: int, rule: int, K: int = 0):
+        torch = sim.torch
+        L = lib()
+        self.sim = sim
+        nb = ctypes.c_size_t()
+        sim._check(L.fslbm_window_workspace_size(sim.ctx, T, K, ctypes.byref(nb)), sim.ctx)
+        with torch.cuda.device(sim.device):
+            self.ws = torch.empty(nb.value, dtype=torch.uint8, device=sim.device)
+        assert self.ws.data_ptr() % 256 == 0
+        h = ctypes.c_void_p()
+        sim._check(L.fslbm_window_forward(sim.ctx, T, K, int(rule), self.ws.data_ptr(), nb.value, ctypes.byref(h)),
+                   sim.ctx)
+        self.h = h
+        info = (ctypes.c_int32 * 4)()
+        L.fslbm_window_info(h, info)
+        self.T, self.K, self.checkpoints, self.n_interface = (int(v) for v in info)
+        self.workspace_bytes = nb.value
+
+    def backward(self, dL_df=None, dL_dm=None, dL_dphi=None) -> dict:
+        """Gradients of the state of time 0 and of (rho_b, g) from the loss
+        gradients of time T (float64 device tensors or None)."""
+        sim = self.sim
+        torch = sim.torch
+        N = sim.N
+
+        def ptr(t, n):
+            if t is None:
+                return None, None
+            t = t.detach().to(device=sim.device, dtype=torch.float64).contiguous().reshape(-1)
+            assert t.numel() == n
+            return t, t.data_ptr()
+
+        keep = [ptr(dL_df, 19 * N), ptr(dL_dm, N), ptr(dL_dphi, N)]
+        out = {"f": torch.empty((19, N), dtype=torch.float64, device=sim.device),
+               "mass": torch.empty(N, dtype=torch.float64, device=sim.device),
+               "phi": torch.empty(N, dtype=torch.float64, device=sim.device)}
+        g4 = (ctypes.c_double * 4)()
+        sim.torch.cuda.synchronize(sim.device)
+        sim._check(lib().fslbm_window_backward(self.h, keep[0][1], keep[1][1], keep[2][1], out["f"].data_ptr(),
+                                                 out["mass"].data_ptr(), out["phi"].data_ptr(), g4), sim.ctx)
+        out["rho_b"] = g4[0]
+        out["P_b"] = 3.0 * g4[0]
+        out["g"] = np.array([g4[1], g4[2], g4[3]])
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fslbm_window_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _window_function():
+    import torch
+
+    class FslbmWindow(torch.autograd.Function):
+        """(f0, m0, phi0, P_b, g) -> (f_T, m_T, phi_T) over T steps with frozen
+        cell classes on `sim` (whose state it overwrites), differentiable by the
+        library's hand-written adjoint with sqrt(T) checkpointing.  f is
+        [19, N] post-collision populations (unshifted), m and phi [N]; outputs
+        at gas cells (f) or outside interface cells (m, phi) are constants."""
+
+        @staticmethod
+        def forward(ctx, sim, T, rule, K, f0, m0, phi0, P_b, g):
+            sim.set_state(f0, m0, phi0)
+            sim.set_forcing([float(v) for v in g.detach().cpu()], 3.0 * float(P_b))
+            win = sim.window(T, rule, K)
+            ctx.win = win
+            out = sim.fields(("f", "mass", "phi"), device=True)
+            return out["f"], out["mass"], out["phi"]
+
+        @staticmethod
+        def backward(ctx, df, dm, dphi):
+            gr = ctx.win.backward(df, dm, dphi)
+            dev = gr["f"].device
+            return (None, None, None, None, gr["f"], gr["mass"], gr["phi"],
+                    torch.tensor(gr["P_b"], dtype=torch.float64, device=dev),
+                    torch.tensor(gr["g"], dtype=torch.float64, device=dev))
+
+    return FslbmWindow
+
+
+_FW = None
+
+
+def window_apply(sim, T, rule, f0, m0, phi0, P_b, g, K=0):
+    """FslbmWindow.apply with the window options first (see FslbmWindow)."""
+    global _FW
+    if _FW is None:
+        _FW = _window_function()
+    return _FW.apply(sim, int(T), int(rule), int(K), f0, m0, phi0, P_b, g)

@@ -1,0 +1,329 @@
+"""Adjoint window on the GPU (C-ABI and the torch.autograd.Function) against
+the oracle's exact directional derivatives (dual numbers) and central finite
+differences of the GPU's own FP64 forward pass.
+
+Loss: L = sum over interface cells at time T of |u_T - u*|^2 + (phi_T - phi*)^2
+(+ a random linear functional of all populations of time T, which reaches every
+element the adjoint pushes).  u_T is recovered from the post-collision
+populations, u = (j - g) + g/2, in torch.
+
+Bars: FP64 directional derivatives within 1e-6 relative of the oracle's dual
+numbers (the two compute the same derivative in different orders, so agreement
+is expected near 1e-12); within 1e-5 of FP64 central differences (O(h^2)
+truncation and rounding of the loss); the checkpoint spacing does not change
+the result (bit for bit).  FP32: error against the FP64 gradient stated.
+"""
+import dataclasses
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_1409_5645_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+from d3q19 import C as CV  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def fs():
+    from paper_1409_5645_amd import fslbm
+    return fslbm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+T = 20
+
+
+@pytest.fixture(scope="module")
+def case(oracle_mod):
+    w = W.sloshing(16, 14, 10, depth=7.0, amp=1.5, amp_z=1.0, seed=3, gy=-2e-4, tau=0.7)
+    o = oracle_mod.Oracle.from_workload(w)
+    o.step(40, oracle_mod.FSL)
+    st = {"f": o.populations(), "mass": o.mass(), "phi": o.phi(), "flags": o.flags()}
+    N = w.params.n_cells
+    rng = np.random.default_rng(0)
+    tg = {"u": rng.normal(0.0, 1e-3, (3, N)), "phi": rng.uniform(0.0, 1.0, N),
+          "a": rng.normal(0.0, 1.0, (19, N)) * (st["flags"] != W.GAS)}
+    dirs = {"f": rng.normal(0.0, 1.0, (19, N)) * (st["flags"] != W.GAS),
+            "m": rng.normal(0.0, 1.0, N) * (st["flags"] == W.INTERFACE),
+            "phi": rng.normal(0.0, 1.0, N) * (st["flags"] == W.INTERFACE)}
+    return w.params, st, tg, dirs
+
+
+def _loss(torch, fT, phiT, g, iface, tg, with_linear=True):
+    C = torch.as_tensor(CV, dtype=torch.float64, device=fT.device)
+    u = (C.T @ fT - g[:, None]) + 0.5 * g[:, None]
+    ut = torch.as_tensor(tg["u"], device=fT.device)
+    pt = torch.as_tensor(tg["phi"], device=fT.device)
+    m = torch.as_tensor(iface, device=fT.device)
+    L = ((u - ut) ** 2).sum(0)[m].sum() + ((phiT - pt) ** 2)[m].sum()
+    if with_linear:
+        L = L + (torch.as_tensor(tg["a"], device=fT.device) * fT).sum()
+    return L
+
+
+def _gpu_grad(fs, case, rule, precision="fp64", K=0, with_linear=True):
+    import torch
+    p, st, tg, _ = case
+    sim = fs.Sim(p, st["flags"], precision=precision)
+    dev = sim.device
+    leaf = lambda a: torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True)  # noqa: E731
+    f0, m0, phi0 = leaf(st["f"]), leaf(st["mass"]), leaf(st["phi"])
+    P_b = leaf(p.rho_gas / 3.0)
+    g = leaf(np.array(p.g, dtype=np.float64))
+    fT, mT, phiT = fs.window_apply(sim, T, rule, f0, m0, phi0, P_b, g, K=K)
+    L = _loss(torch, fT, phiT, g, st["flags"] == W.INTERFACE, tg, with_linear)
+    L.backward()
+    out = {"L": float(L.detach()), "f": f0.grad.cpu().numpy(), "m": m0.grad.cpu().numpy(), "phi": phi0.grad.cpu().numpy(),
+           "P_b": float(P_b.grad), "g": g.grad.cpu().numpy()}
+    sim.close()
+    return out
+
+
+def _dual(oracle_mod, case, rule, with_linear=True, **kw):
+    p, st, tg, _ = case
+    return oracle_mod.window_dual(p, st["flags"], st["f"], st["mass"], st["phi"], tg["u"], tg["phi"], T, rule,
+                                  f_weight=tg["a"] if with_linear else None, **kw)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_adjoint_matches_oracle_dual_fp64(fs, oracle_mod, case, rule):
+    _say(f"case adjoint fp64 rule={rule}: 16x14x10 T={T} vs oracle dual numbers")
+    gr = _gpu_grad(fs, case, rule)
+    _, st, _, dirs = case
+    L0, _ = _dual(oracle_mod, case, rule)
+    _say("loss gpu", gr["L"], "oracle", L0)
+    assert abs(gr["L"] - L0) <= 1e-12 * abs(L0)
+    checks = [
+        ("f0", dict(df0=dirs["f"]), float((gr["f"] * dirs["f"]).sum())),
+        ("m0", dict(dm0=dirs["m"]), float((gr["m"] * dirs["m"]).sum())),
+        ("phi0", dict(dphi0=dirs["phi"]), float((gr["phi"] * dirs["phi"]).sum())),
+        ("rho_b", dict(drho_b=1.0), gr["P_b"] / 3.0),
+    ] + [(f"g{a}", dict(dg=np.eye(3)[a]), float(gr["g"][a])) for a in range(3)]
+    worst = 0.0
+    for name, kw, gpu in checks:
+        _, ref = _dual(oracle_mod, case, rule, **kw)
+        rel = abs(gpu - ref) / max(abs(ref), 1e-300)
+        worst = max(worst, rel) if math.isfinite(rel) else math.inf
+        _say(f"  {name:6s} adjoint {gpu:+.15e} dual {ref:+.15e} rel {rel:.2e}")
+    assert worst <= 1e-6
+
+
+def test_adjoint_only_interface_loss(fs, oracle_mod, case):
+    """Without the linear term the gradient reaches the state only through the
+    interface cells' velocity and fill."""
+    _say("case adjoint fp64 FSL, interface-only loss")
+    gr = _gpu_grad(fs, case, 1, with_linear=False)
+    _, st, _, dirs = case
+    for name, kw, gpu in (("f0", dict(df0=dirs["f"]), float((gr["f"] * dirs["f"]).sum())),
+                          ("phi0", dict(dphi0=dirs["phi"]), float((gr["phi"] * dirs["phi"]).sum())),
+                          ("rho_b", dict(drho_b=1.0), gr["P_b"] / 3.0)):
+        _, ref = _dual(oracle_mod, case, 1, with_linear=False, **kw)
+        rel = abs(gpu - ref) / abs(ref)
+        _say(f"  {name:6s} rel {rel:.2e}")
+        assert math.isfinite(rel) and rel <= 1e-6
+
+
+def test_adjoint_vs_central_difference_fp64(fs, case):
+    """Central differences of the GPU's own FP64 forward window (steps small
+    enough that every run takes the same branches)."""
+    import torch
+    _say("case adjoint fp64 FSL vs GPU central differences")
+    p, st, tg, dirs = case
+    gr = _gpu_grad(fs, case, 1)
+    iface = st["flags"] == W.INTERFACE
+
+    def loss_at(f0, rho_b):
+        sim = fs.Sim(p, st["flags"], precision="fp64")
+        sim.set_state(f0, st["mass"], st["phi"])
+        sim.set_forcing(p.g, rho_b)
+        sim.window(T, 1)
+        out = sim.fields(("f", "phi"), device=True)
+        g = torch.tensor(p.g, dtype=torch.float64, device=sim.device)
+        L = float(_loss(torch, out["f"], out["phi"], g, iface, tg))
+        sim.close()
+        return L
+
+    h = 1e-6
+    fd = (loss_at(st["f"] + h * dirs["f"], p.rho_gas) - loss_at(st["f"] - h * dirs["f"], p.rho_gas)) / (2 * h)
+    ad = float((gr["f"] * dirs["f"]).sum())
+    _say("  f0    adjoint", ad, "fd", fd, "rel", abs(ad - fd) / abs(fd))
+    assert math.isfinite(ad) and abs(ad - fd) <= 1e-5 * abs(fd)
+    hr = 1e-5 * p.rho_gas
+    fd = (loss_at(st["f"], p.rho_gas + hr) - loss_at(st["f"], p.rho_gas - hr)) / (2 * hr)
+    ad = gr["P_b"] / 3.0
+    _say("  rho_b adjoint", ad, "fd", fd, "rel", abs(ad - fd) / abs(fd))
+    assert math.isfinite(ad) and abs(ad - fd) <= 1e-5 * abs(fd)
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient(fs, case):
+    _say("case adjoint fp64 FSL: checkpoint spacings 1, 3, 20 and the default")
+    ref = _gpu_grad(fs, case, 1)
+    for K in (1, 3, T):
+        gr = _gpu_grad(fs, case, 1, K=K)
+        for k in ("f", "m", "phi", "g"):
+            np.testing.assert_array_equal(gr[k], ref[k], err_msg=f"K={K} {k}")
+        assert gr["P_b"] == ref["P_b"]
+
+
+def test_fp32_gradient_error_stated(fs, case):
+    _say("case adjoint fp32 vs fp64 gradient")
+    g64 = _gpu_grad(fs, case, 1)
+    g32 = _gpu_grad(fs, case, 1, precision="fp32")
+    errs = {}
+    for k in ("f", "m", "phi", "g"):
+        errs[k] = float(np.linalg.norm(g32[k] - g64[k]) / np.linalg.norm(g64[k]))
+    errs["P_b"] = abs(g32["P_b"] - g64["P_b"]) / abs(g64["P_b"])
+    _say("  fp32 relative gradient error", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert all(math.isfinite(v) for v in errs.values()) and max(errs.values()) < 1e-2
+
+
+def test_no_interface_cells(fs, oracle_mod):
+    """A liquid-only periodic box: the adjoint is the liquid sweep alone."""
+    import torch
+    _say("case adjoint fp64, 12x10x8 periodic liquid box")
+    p = W.Params(nx=12, ny=10, nz=8, periodic=(1, 1, 1), tau=0.6, g=(1e-5, -2e-5, 3e-6))
+    N = p.n_cells
+    rng = np.random.default_rng(5)
+    flags = np.full(N, W.LIQUID, dtype=np.uint8)
+    rho = 1.0 + 1e-3 * rng.normal(size=N)
+    u = 1e-3 * rng.normal(size=(3, N))
+    o = oracle_mod.Oracle(p, flags, rho, u, np.ones(N))
+    st = {"f": o.populations(), "mass": np.zeros(N), "phi": np.zeros(N), "flags": flags}
+    a = rng.normal(size=(19, N))
+    d = rng.normal(size=(19, N))
+    sim = fs.Sim(p, flags, precision="fp64")
+    dev = sim.device
+    leaf = lambda v: torch.tensor(v, dtype=torch.float64, device=dev, requires_grad=True)  # noqa: E731
+    f0, m0, phi0, P_b, g = leaf(st["f"]), leaf(st["mass"]), leaf(st["phi"]), leaf(1.0 / 3.0), leaf(np.array(p.g))
+    fT, _, _ = fs.window_apply(sim, 15, 1, f0, m0, phi0, P_b, g, K=4)
+    L = (torch.as_tensor(a, device=dev) * fT).sum()
+    L.backward()
+    zero_u, zero_p = np.zeros((3, N)), np.zeros(N)
+    for name, kw, gpu in (("f0", dict(df0=d), float((f0.grad.cpu().numpy() * d).sum())),
+                          ("gx", dict(dg=[1.0, 0, 0]), float(g.grad[0])), ("gz", dict(dg=[0, 0, 1.0]), float(g.grad[2]))):
+        _, ref = oracle_mod.window_dual(p, flags, st["f"], st["mass"], st["phi"], zero_u, zero_p, 15, 1,
+                                        f_weight=a, **kw)
+        rel = abs(gpu - ref) / abs(ref)
+        _say(f"  {name} rel {rel:.2e}")
+        assert math.isfinite(rel) and rel <= 1e-6
+    assert float(P_b.grad) == 0.0
+    sim.close()
+
+
+def test_window_errors(fs, case):
+    p, st, _, _ = case
+    s16 = fs.Sim(p, st["flags"], precision="fp16s")
+    with pytest.raises(fs.FslbmError, match="UNSUPPORTED"):
+        s16.window(5, 1)
+    s16.close()
+    s = fs.Sim(p, st["flags"], precision="fp64")
+    s.set_state(st["f"], st["mass"], st["phi"])
+    with pytest.raises(fs.FslbmError, match="INVALID"):
+        s.window(0, 1)
+    with pytest.raises(fs.FslbmError, match="INVALID"):
+        s.window(5, 7)  # unknown rule
+    s.close()
+
+
+def test_full_size_fp64_fd_and_fp32_error(fs):
+    """128 x 96 x 128 sloshing tank, T = 400, loss against a seed-generated
+    target run (P_b, g scaled by 1 + 0.01 xi, f0 + 1e-4 w xi): FP64 adjoint
+    against FP64 central differences for rho_b and g_y; FP32 gradient error
+    against FP64 stated; cost of forward + backward against T plain steps."""
+    import torch
+    w = W.config("slosh128", seed=0)
+    p = w.params
+    N = p.n_cells
+    TT = 400
+    _say(f"case adjoint full size {p.nx}x{p.ny}x{p.nz} T={TT}")
+    rng = np.random.default_rng(7)
+    xi1, xi2 = rng.normal(size=2)
+    ref = fs.Sim.from_workload(w)
+    base = ref.fields(("f", "mass", "phi", "flags"), device=True)
+    ref.close()
+    iface = (base["flags"] == W.INTERFACE).cpu().numpy()
+    wq = torch.as_tensor(np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12), dtype=torch.float64,
+                         device=base["f"].device)
+    act = (base["flags"] != W.GAS).to(torch.float64)
+    tgt = fs.Sim(p, w.flags)
+    f_t = base["f"] + 1e-4 * wq[:, None] * torch.randn(base["f"].shape, dtype=torch.float64, device=base["f"].device,
+                                                       generator=torch.Generator(device=base["f"].device).manual_seed(7)) * act
+    tgt.set_state(f_t, base["mass"], base["phi"])
+    g_t = [v * (1 + 0.01 * xi2) for v in p.g]
+    tgt.set_forcing(g_t, p.rho_gas * (1 + 0.01 * xi1))
+    tgt.window(TT, 1)
+    out = tgt.fields(("u", "phi"), device=True)
+    tg = {"u": out["u"].cpu().numpy(), "phi": out["phi"].cpu().numpy()}
+    tgt.close()
+
+    def grad(precision):
+        sim = fs.Sim(p, w.flags, precision=precision)
+        leaf = lambda v: v.clone().detach().requires_grad_(True)  # noqa: E731
+        f0, m0, phi0 = leaf(base["f"]), leaf(base["mass"]), leaf(base["phi"])
+        P_b = torch.tensor(p.rho_gas / 3.0, dtype=torch.float64, device=sim.device, requires_grad=True)
+        g = torch.tensor(p.g, dtype=torch.float64, device=sim.device, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fT, mT, phiT = fs.window_apply(sim, TT, 1, f0, m0, phi0, P_b, g)
+        L = _loss(torch, fT, phiT, g, iface, tg, with_linear=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sim.set_state(base["f"], base["mass"], base["phi"])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        sim.window(TT, 1)  # forward pass alone (it includes the checkpoint writes)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        sim.close()
+        return {"L": float(L.detach()), "P_b": float(P_b.grad), "g": g.grad.cpu().numpy(), "f": f0.grad,
+                "t_fwd": t1 - t0, "t_bwd": t2 - t1, "t_fwd_only": t4 - t3}
+
+    g64 = grad("fp64")
+    _say(f"  fp64 L {g64['L']:.6e} dL/dP_b {g64['P_b']:.6e} dL/dg {g64['g']}  "
+         f"fwd {g64['t_fwd']*1e3:.1f} ms bwd {g64['t_bwd']*1e3:.1f} ms")
+
+    def loss_at(rho_b, gv):
+        sim = fs.Sim(p, w.flags, precision="fp64")
+        sim.set_state(base["f"], base["mass"], base["phi"])
+        sim.set_forcing(gv, rho_b)
+        sim.window(TT, 1)
+        out = sim.fields(("f", "phi"), device=True)
+        L = float(_loss(torch, out["f"], out["phi"], torch.tensor(gv, dtype=torch.float64, device=sim.device),
+                        iface, tg, with_linear=False))
+        sim.close()
+        return L
+
+    # 400 steps over ~10^4 interface cells: a relative step of 1e-5 already moves
+    # some link distances across a clamp; 1e-7 keeps the runs on one branch and
+    # is far from rounding-limited (the loss is O(1e-2))
+    hr = 1e-7 * p.rho_gas
+    fd = (loss_at(p.rho_gas + hr, p.g) - loss_at(p.rho_gas - hr, p.g)) / (2 * hr)
+    ad = g64["P_b"] / 3.0
+    _say(f"  rho_b adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}")
+    assert abs(ad - fd) <= 1e-5 * abs(fd)
+    hg = 1e-7 * abs(p.g[1])
+    gp, gm = list(p.g), list(p.g)
+    gp[1] += hg
+    gm[1] -= hg
+    fd = (loss_at(p.rho_gas, gp) - loss_at(p.rho_gas, gm)) / (2 * hg)
+    ad = float(g64["g"][1])
+    _say(f"  g_y   adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}")
+    assert abs(ad - fd) <= 1e-5 * abs(fd)
+
+    g32 = grad("fp32")
+    ef = float(torch.linalg.norm(g32["f"] - g64["f"]) / torch.linalg.norm(g64["f"]))
+    eP = abs(g32["P_b"] - g64["P_b"]) / abs(g64["P_b"])
+    eg = float(np.linalg.norm(g32["g"] - g64["g"]) / np.linalg.norm(g64["g"]))
+    _say(f"  fp32 gradient error: f0 {ef:.2e}  P_b {eP:.2e}  g {eg:.2e}")
+    _say(f"  fp32 fwd {g32['t_fwd']*1e3:.1f} ms bwd {g32['t_bwd']*1e3:.1f} ms fwd-only {g32['t_fwd_only']*1e3:.1f} ms")
+    assert math.isfinite(ef) and ef < 0.1

@@ -126,3 +126,18 @@ def test_derivative_is_linear_in_the_direction(oracle_mod, case):
     c = run(df0=d1 + d2, drho_b=0.5, dg=[0.0, 2.0, 0.0])
     assert abs(c - (a + b)) <= 1e-9 * (abs(a) + abs(b))
     assert run() == 0.0
+
+
+def test_linear_population_term_vs_central_difference(oracle_mod, case):
+    p, st, ut, pt, rng = case
+    act = st["flags"] != W.GAS
+    a = rng.normal(0.0, 1.0, st["f"].shape) * act
+    d = rng.normal(0.0, 1.0, st["f"].shape) * act
+    run = lambda f, **kw: oracle_mod.window_dual(p, st["flags"], f, st["mass"], st["phi"], ut, pt, T, 1,  # noqa
+                                                  f_weight=a, **kw)
+    L0, dL = run(st["f"], df0=d)
+    L1 = oracle_mod.window_dual(p, st["flags"], st["f"], st["mass"], st["phi"], ut, pt, T, 1)[0]
+    assert L0 != L1
+    h = 1e-6
+    fd = (run(st["f"] + h * d)[0] - run(st["f"] - h * d)[0]) / (2 * h)
+    assert abs(fd - dL) <= 1e-6 * abs(dL), (fd, dL)
