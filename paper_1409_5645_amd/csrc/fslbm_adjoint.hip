@@ -34,7 +34,8 @@
 namespace fslbm {
 
 constexpr int ABLOCK = 256;
-static constexpr unsigned ADJ_IFACE_GRID = 2048;
+constexpr int AIBLOCK = 64;  // interface-list kernels: one wavefront per block
+static constexpr unsigned ADJ_IFACE_GRID = 16384;
 
 // v += c_q t
 template <int q, class R>
@@ -112,9 +113,9 @@ __device__ __forceinline__ void collide_adjoint(const R (&ob)[Q], const R (&u)[3
 
 // Sum of v over the block (wavefront shuffles, then the 4 wavefronts in
 // order), added by thread 0 to slot[0..NV).  Every thread of the block calls it.
-template <int NV>
+template <int NV, int BS>
 __device__ __forceinline__ void block_accumulate(double (&v)[NV], double* slot) {
-  __shared__ double sm[ABLOCK / 64][NV];
+  __shared__ double sm[BS / 64][NV];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
@@ -127,7 +128,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NV], double* slot) 
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double s = 0.0;
-      for (int w = 0; w < ABLOCK / 64; ++w) s += sm[w][i];
+      for (int w = 0; w < BS / 64; ++w) s += sm[w][i];
       slot[i] += s;
     }
   }
@@ -135,7 +136,8 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NV], double* slot) 
 
 // ------------------------------------------------------------ liquid cells
 // Same row mapping and pull offsets as the forward sweep; the push writes the
-// adjoint of each pulled value to the offset the pull read.
+// adjoint of each pulled value to the offset the pull read.  The collision
+// adjoint needs only the collision velocity, which the forward step stored.
 template <class F>
 __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
   using R = typename F::R;
@@ -161,26 +163,23 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
                               row_of(yp, zm), row_of(y, zm), row_of(ym, zm)};
     const int xm = step_axis(x, -1, g.nx, g.px), xp = step_axis(x, 1, g.nx, g.px);
     const unsigned N = (unsigned)g.N;
-    const S* __restrict__ fin = reinterpret_cast<const S*>(a.fst);
     const R* __restrict__ lin = reinterpret_cast<const R*>(a.lam_in);
+    const R* __restrict__ un = reinterpret_cast<const R*>(a.u);
     unsigned off[Q];
-    R f[Q], ob[Q];
+    R ob[Q];
 #define FSLBM_APULL(q)                                                                            \
   {                                                                                               \
     const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                      \
     const int sx = CX[q] == 1 ? xm : (CX[q] == -1 ? xp : x);                                      \
     off[q] = (ro == WALL_ROW || sx < 0) ? (unsigned)OPP[q] * N + rbase + (unsigned)x              \
                                         : (unsigned)q * N + ro + (unsigned)sx;                    \
-    f[q] = F::load_raw(fin + off[q]);                                                             \
     ob[q] = lin[(unsigned)q * N + rbase + (unsigned)x];                                           \
   }
     FSLBM_APULL(0)
     FSLBM_LINKS(FSLBM_APULL)
 #undef FSLBM_APULL
     const Consts<R>& k = pick_consts<R>(a.c);
-    R rho_s, j[3];
-    moments(f, rho_s, j);
-    const R u[3] = {j[0] + k.hg[0], j[1] + k.hg[1], j[2] + k.hg[2]};
+    const R u[3] = {un[rbase + (unsigned)x], un[N + rbase + (unsigned)x], un[2u * N + rbase + (unsigned)x]};
     R fb[Q], gb[3];
     collide_adjoint(ob, u, R(0.0), k, fb, gb);
     R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
@@ -189,7 +188,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) gs[i] = (double)gb[i];
   }
-  block_accumulate<3>(gs, a.part_sweep + 3 * (size_t)blockIdx.x);
+  block_accumulate<3, ABLOCK>(gs, a.part_sweep + 3 * (size_t)blockIdx.x);
 }
 
 // --------------------------------------------------------- interface cells
@@ -278,21 +277,22 @@ __device__ __forceinline__ void seen_adj(const IfaceData<F>& d, int q, double v,
 }
 
 template <class F, int RULE>
-__global__ __launch_bounds__(ABLOCK) void k_adj_iface(AdjArgs a) {
+__global__ __launch_bounds__(AIBLOCK) void k_adj_iface(AdjArgs a) {
   using R = typename F::R;
-  using S = typename F::S;
   constexpr bool SH = F::shifted;
   const Grid g = a.c.grid;
-  const size_t N = (size_t)g.N;
-  const size_t cap = (size_t)a.cap;
-  const S* __restrict__ fin = reinterpret_cast<const S*>(a.fst);
+  const unsigned N = (unsigned)g.N;
+  const unsigned cap = (unsigned)a.cap;
+  const R* __restrict__ rf = reinterpret_cast<const R*>(a.rec_f);
+  const R* __restrict__ ro = reinterpret_cast<const R*>(a.rec_own);
   const R* __restrict__ lin = reinterpret_cast<const R*>(a.lam_in);
   R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
   R* __restrict__ own_t = reinterpret_cast<R*>(a.own);
   const Consts<R>& k = pick_consts<R>(a.c);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dL/drho_b, dL/dg
-  for (int i = blockIdx.x * ABLOCK + threadIdx.x; i < a.n_i; i += gridDim.x * ABLOCK) {
+  for (int i = blockIdx.x * AIBLOCK + threadIdx.x; i < a.n_i; i += gridDim.x * AIBLOCK) {
     const int idx = a.listI[i];
+    const unsigned ui = (unsigned)i;
     Nbr n;
     coords(g, idx, n.x, n.y, n.z);
     n.xm = step_axis(n.x, -1, g.nx, g.px);
@@ -301,29 +301,31 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_iface(AdjArgs a) {
     n.yp = step_axis(n.y, 1, g.ny, g.py);
     n.zm = step_axis(n.z, -1, g.nz, g.pz);
     n.zp = step_axis(n.z, 1, g.nz, g.pz);
-    // ---- loads: the forward neighbourhood of time t and the adjoint of t+1
+    // ---- loads: the step's record at this cell (list order: coalesced), the
+    // classes of the pull sources, the fill of interface sources
     IfaceData<F> d;
     unsigned off[Q];  // 19 N < 2^32 is checked at init
+    const uint64_t cls = a.ncls[i];
+    d.phix = a.rec_phi[i];
+    d.m = a.rec_m[i];
     off[0] = (unsigned)idx;
-    d.f[0] = F::load_raw(fin + idx);
-    d.own[0] = d.f[0];
+    d.f[0] = rf[ui];
+    d.own[0] = ro[ui];
     d.ty[0] = IFACE;
     d.ph[0] = 0.0;
 #define FSLBM_AILOAD(q)                                                                 \
   {                                                                                     \
     const int s = pull_source<q>(g, n);                                                 \
-    const int sc = s >= 0 ? s : idx;                                                    \
-    off[q] = s >= 0 ? (unsigned)(q * N + s) : (unsigned)(OPP[q] * N + idx);             \
-    d.f[q] = F::load_raw(fin + off[q]);                                                 \
-    d.own[q] = F::load_raw(fin + (size_t)q * N + idx);                                  \
-    const uint8_t ts = a.flags[sc];                                                     \
-    d.ty[q] = s >= 0 ? ts : WALL_CLASS;                                                 \
-    d.ph[q] = a.phi[sc];                                                                \
+    off[q] = s >= 0 ? (unsigned)q * N + (unsigned)s : (unsigned)OPP[q] * N + (unsigned)idx; \
+    d.f[q] = rf[(unsigned)q * cap + ui];                                                \
+    d.own[q] = ro[(unsigned)q * cap + ui];                                              \
+    const unsigned c2 = (unsigned)(cls >> (2 * q)) & 3u;                                \
+    d.ty[q] = c2 == 0 ? GAS : (c2 == 1 ? IFACE : (c2 == 2 ? LIQ : WALL_CLASS));         \
+    d.ph[q] = a.rec_phi[a.nslot[(unsigned)q * cap + ui]];                               \
+    if (c2 == 3) d.ph[q] = d.phix;                                                      \
   }
     FSLBM_LINKS(FSLBM_AILOAD)
 #undef FSLBM_AILOAD
-    d.m = a.mass[idx];
-    d.phix = a.phi[idx];
     const double lam_m = a.lam_m[idx];
     const double lam_p = a.lphi_in[idx];
 
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_iface(AdjArgs a) {
     const double phi_new = m_new / rho;
     R ob[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) ob[q] = lin[(size_t)q * N + idx];
+    for (int q = 0; q < Q; ++q) ob[q] = lin[(unsigned)q * N + (unsigned)idx];
 
     // ---- adjoint
     // phi(t+1) = m(t+1) / rho: dL/dm(t+1) and the density term of the collision
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_iface(AdjArgs a) {
         pc += half;                                                                   \
       }                                                                               \
     }                                                                                 \
-    a.phic[(size_t)q * cap + i] = pc;                                                 \
+    a.phic[(unsigned)q * cap + ui] = pc;                                              \
   }
     FSLBM_LINKS(FSLBM_AEXADJ)
 #undef FSLBM_AEXADJ
@@ -452,46 +454,87 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_iface(AdjArgs a) {
     FSLBM_LINKS(FSLBM_APUSH)
 #undef FSLBM_APUSH
 #pragma unroll
-    for (int q = 0; q < Q; ++q) own_t[(size_t)q * cap + i] = ownb[q];
+    for (int q = 0; q < Q; ++q) own_t[(unsigned)q * cap + ui] = ownb[q];
     a.phic[i] = phis;
     a.lam_m[idx] = mb;
     acc[0] += (double)rbb;
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[1 + c] += (double)gb[c];
   }
-  block_accumulate<4>(acc, a.part_iface + 4 * (size_t)blockIdx.x);
+  block_accumulate<4, AIBLOCK>(acc, a.part_iface + 4 * (size_t)blockIdx.x);
 }
 
 // Own-population terms and the fill adjoint of each interface cell y.  The
-// element ft_q(y) is read by the pull of the cell y + c_q (or, beyond a wall,
-// by y itself); if that cell is gas nothing was pushed there this step.
+// element ft_q(y) is read by the pull of the cell y + c_q, the pull source of
+// link qbar of y (beyond a wall: by y itself).  If that cell is gas nothing was
+// pushed there this step.  Classes and list positions come from the fixed
+// topology, so the loads are two independent batches.
 template <class F>
-__global__ __launch_bounds__(ABLOCK) void k_adj_iface2(AdjArgs a) {
+__global__ __launch_bounds__(AIBLOCK) void k_adj_iface2(AdjArgs a) {
   using R = typename F::R;
-  const Grid g = a.c.grid;
-  const size_t N = (size_t)g.N;
-  const size_t cap = (size_t)a.cap;
+  const unsigned N = (unsigned)a.c.grid.N;
+  const unsigned cap = (unsigned)a.cap;
   R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
   const R* __restrict__ own_t = reinterpret_cast<const R*>(a.own);
-  for (int i = blockIdx.x * ABLOCK + threadIdx.x; i < a.n_i; i += gridDim.x * ABLOCK) {
-    const int yc = a.listI[i];
-    int x, y, z;
-    coords(g, yc, x, y, z);
-    lout[yc] = lout[yc] + own_t[i];
-    double pb = a.phic[i];
-#define FSLBM_AOWN(q)                                                          \
-  {                                                                            \
-    const int p = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);                   \
-    const uint8_t tp = p >= 0 ? a.flags[p] : (uint8_t)LIQ;                     \
-    const size_t e = (size_t)q * N + yc;                                       \
-    const R v = own_t[(size_t)q * cap + i];                                    \
-    lout[e] = tp == GAS ? v : lout[e] + v;                                     \
-    if (tp == IFACE) pb += a.phic[(size_t)q * cap + a.islot[p]];               \
+  for (int i = blockIdx.x * AIBLOCK + threadIdx.x; i < a.n_i; i += gridDim.x * AIBLOCK) {
+    const unsigned yc = (unsigned)a.listI[i];
+    const unsigned ui = (unsigned)i;
+    const uint64_t cls = a.ncls[i];
+    R v[Q], cur[Q];
+    double pc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      v[q] = own_t[(unsigned)q * cap + ui];
+      cur[q] = lout[(unsigned)q * N + yc];
+    }
+    pc[0] = a.phic[ui];
+#define FSLBM_A2PC(q) pc[q] = a.phic[(unsigned)q * cap + (unsigned)a.nslot[(unsigned)OPP[q] * cap + ui]];
+    FSLBM_LINKS(FSLBM_A2PC)
+#undef FSLBM_A2PC
+    lout[yc] = cur[0] + v[0];
+    double pb = pc[0];
+#define FSLBM_A2ST(q)                                                           \
+  {                                                                             \
+    const unsigned c2 = (unsigned)(cls >> (2 * OPP[q])) & 3u; /* class of y + c_q */ \
+    lout[(unsigned)q * N + yc] = c2 == 0 ? v[q] : cur[q] + v[q];                \
+    if (c2 == 1) pb += pc[q];                                                   \
   }
-    FSLBM_LINKS(FSLBM_AOWN)
-#undef FSLBM_AOWN
+    FSLBM_LINKS(FSLBM_A2ST)
+#undef FSLBM_A2ST
     a.lphi_out[yc] = pb;
   }
+}
+
+// Fixed topology of the interface cells (list order): the class of the pull
+// source of every link (2 bits each: 0 gas, 1 interface, 2 liquid, 3 beyond a
+// wall) and, for interface sources, their list position (else the cell's own).
+__global__ __launch_bounds__(ABLOCK) void k_adj_topo(const uint8_t* flags, Grid g, const int32_t* list,
+                                                     const int32_t* islot, int n_i, int cap, uint64_t* ncls,
+                                                     int32_t* nslot) {
+  const int i = blockIdx.x * ABLOCK + threadIdx.x;
+  if (i >= n_i) return;
+  const int idx = list[i];
+  Nbr n;
+  coords(g, idx, n.x, n.y, n.z);
+  n.xm = step_axis(n.x, -1, g.nx, g.px);
+  n.xp = step_axis(n.x, 1, g.nx, g.px);
+  n.ym = step_axis(n.y, -1, g.ny, g.py);
+  n.yp = step_axis(n.y, 1, g.ny, g.py);
+  n.zm = step_axis(n.z, -1, g.nz, g.pz);
+  n.zp = step_axis(n.z, 1, g.nz, g.pz);
+  uint64_t cls = 1;  // link 0: the cell itself
+  nslot[i] = i;
+#define FSLBM_TOPO(q)                                                                       \
+  {                                                                                         \
+    const int s = pull_source<q>(g, n);                                                     \
+    const uint8_t t = s >= 0 ? flags[s] : (uint8_t)0xff;                                    \
+    const uint64_t c2 = s < 0 ? 3u : (t == GAS ? 0u : (t == IFACE ? 1u : 2u));              \
+    cls |= c2 << (2 * q);                                                                   \
+    nslot[(size_t)q * cap + i] = (s >= 0 && t == IFACE) ? islot[s] : i;                     \
+  }
+  FSLBM_LINKS(FSLBM_TOPO)
+#undef FSLBM_TOPO
+  ncls[i] = cls;
 }
 
 // ------------------------------------------------------- seed / output
@@ -612,7 +655,9 @@ static inline unsigned ablocks(size_t n) { return (unsigned)((n + ABLOCK - 1) / 
 unsigned adj_sweep_blocks(const Grid& g) {
   return (unsigned)((g.nx + ABLOCK - 1) / ABLOCK) * (unsigned)g.ny * (unsigned)g.nz;
 }
-unsigned adj_iface_blocks(int n_i) { return std::max(1u, std::min(ADJ_IFACE_GRID, ablocks((size_t)n_i))); }
+unsigned adj_iface_blocks(int n_i) {
+  return std::max(1u, std::min(ADJ_IFACE_GRID, (unsigned)(((size_t)n_i + AIBLOCK - 1) / AIBLOCK)));
+}
 unsigned list_blocks(const Grid& g) { return ablocks((size_t)g.N); }
 
 hipError_t launch_iface_list(const uint8_t* flags, const Grid& g, int32_t* bcount, int32_t* list, int32_t* islot,
@@ -622,6 +667,13 @@ hipError_t launch_iface_list(const uint8_t* flags, const Grid& g, int32_t* bcoun
   k_list_count<<<nb, ABLOCK, 0, st>>>(flags, g.N, bcount);
   k_list_scan<<<1, SCAN, 0, st>>>(bcount, (int)nb, n_out);
   k_list_write<<<nb, ABLOCK, 0, st>>>(flags, g.N, bcount, list, islot);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_topo(const uint8_t* flags, const Grid& g, const int32_t* list, const int32_t* islot, int n_i,
+                           int cap, uint64_t* ncls, int32_t* nslot, void* stream) {
+  if (n_i <= 0) return hipSuccess;
+  k_adj_topo<<<ablocks((size_t)n_i), ABLOCK, 0, (hipStream_t)stream>>>(flags, g, list, islot, n_i, cap, ncls, nslot);
   return hipGetLastError();
 }
 
@@ -645,24 +697,43 @@ hipError_t launch_adj_seed(const Common& c, const uint8_t* flags, int precision,
 }
 
 template <class F>
-static void adj_form(const AdjArgs& a0, int rule, hipStream_t st) {
+static void adj_sweep_form(const AdjArgs& a0, hipStream_t st) {
   AdjArgs a = a0;
   a.cpr = (a.c.grid.nx + ABLOCK - 1) / ABLOCK;
   k_adj_sweep<F><<<adj_sweep_blocks(a.c.grid), ABLOCK, 0, st>>>(a);
-  if (a.n_i > 0) {
-    const unsigned nbi = adj_iface_blocks(a.n_i);
-    if (rule == 0)
-      k_adj_iface<F, 0><<<nbi, ABLOCK, 0, st>>>(a);
-    else
-      k_adj_iface<F, 1><<<nbi, ABLOCK, 0, st>>>(a);
-    k_adj_iface2<F><<<nbi, ABLOCK, 0, st>>>(a);
-  }
 }
 
-hipError_t launch_adjoint_step(const AdjArgs& a, int precision, int rule, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  if (precision == 0) adj_form<FormF64>(a, rule, st);
-  else adj_form<FormF32>(a, rule, st);
+template <class F>
+static void adj_iface_form(const AdjArgs& a, int rule, hipStream_t st) {
+  if (a.n_i <= 0) return;
+  const unsigned nbi = adj_iface_blocks(a.n_i);
+  if (rule == 0)
+    k_adj_iface<F, 0><<<nbi, AIBLOCK, 0, st>>>(a);
+  else
+    k_adj_iface<F, 1><<<nbi, AIBLOCK, 0, st>>>(a);
+}
+
+template <class F>
+static void adj_iface2_form(const AdjArgs& a, hipStream_t st) {
+  if (a.n_i <= 0) return;
+  k_adj_iface2<F><<<adj_iface_blocks(a.n_i), AIBLOCK, 0, st>>>(a);
+}
+
+hipError_t launch_adj_sweep(const AdjArgs& a, int precision, void* stream) {
+  if (precision == 0) adj_sweep_form<FormF64>(a, (hipStream_t)stream);
+  else adj_sweep_form<FormF32>(a, (hipStream_t)stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_iface(const AdjArgs& a, int precision, int rule, void* stream) {
+  if (precision == 0) adj_iface_form<FormF64>(a, rule, (hipStream_t)stream);
+  else adj_iface_form<FormF32>(a, rule, (hipStream_t)stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_iface2(const AdjArgs& a, int precision, void* stream) {
+  if (precision == 0) adj_iface2_form<FormF64>(a, (hipStream_t)stream);
+  else adj_iface2_form<FormF32>(a, (hipStream_t)stream);
   return hipGetLastError();
 }
 

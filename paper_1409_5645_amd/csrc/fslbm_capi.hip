@@ -268,7 +268,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     return FSLBM_E_UNSUPPORTED;
   }
   for (int32_t i = 0; i < n; ++i) {
-    StepLaunch L;
+    StepLaunch L{};
     const int a = c->cur, b = 1 - c->cur;
     SweepArgs& s = L.sweep;
     s.c = c->com;
@@ -293,6 +293,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.freeze = c->p.freeze ? 1 : 0;
     s.cpr = 0;
     s.pairs = c->pairs;
+    s.u_out = nullptr;
     ConvArgs& v = L.conv;
     v.c = c->com;
     v.fout = c->f[b];
@@ -464,29 +465,50 @@ const char* fslbm_last_error(const fslbm_ctx* c) {
 }  // extern "C"
 
 // ------------------------------------------------------------ adjoint window
+// Storage (all in the caller's window workspace):
+//   - two hot states that the forward and recompute steps ping-pong between;
+//   - a full checkpoint every K steps (state 0, K, 2K, ...);
+//   - a ring of K step records: what the adjoint of a step needs, namely the
+//     collision velocity of the liquid cells and, per interface cell in list
+//     order, the pulled and own populations, fill and mass of time t.
+// The backward pass rebuilds the records of a segment by re-running it from its
+// checkpoint (the last segment's records are kept from the forward pass), then
+// runs the reverse steps of the segment from the records.
 struct fslbm_window {
   fslbm_ctx* ctx = nullptr;
   Common com;           // constants at forward time (g, rho_b, relaxation)
   int T = 0, K = 0, C = 0, rule = 0, precision = 0;
   int n_i = 0, cap = 1, nb_sweep = 0, nb_iface = 0;
   size_t N = 0;
-  struct Slot {
+  struct State {
     void* f;
     double* m;
     double* phi;
   };
-  std::vector<Slot> ckpt, ring;  // states at t = jK; states jK + k (k = 1..K) of one segment
-  int ring_seg = -1;             // segment whose states the ring holds
-  uint8_t* flags = nullptr;      // cell classes, fixed over the window
+  struct Record {
+    void* u;       // [3][N] compute type
+    void* f;       // [Q][cap] compute type
+    void* own;     // [Q][cap] compute type
+    double* phi;   // [cap]
+    double* m;     // [cap]
+  };
+  std::vector<State> ckpt;  // states at t = jK
+  State hot[2];             // hot[*].m is one shared array (mass is updated in place)
+  std::vector<Record> rec;  // records of steps jK + k, k = 0..K-1, of one segment
+  int rec_seg = -1;         // segment whose records the ring holds
+  uint8_t* flags = nullptr;  // cell classes, fixed over the window
   void* lam[2] = {nullptr, nullptr};
   double* lam_m = nullptr;
   double* lphi[2] = {nullptr, nullptr};
   int32_t *listI = nullptr, *islot = nullptr, *bcount = nullptr, *n_dev = nullptr;
+  uint64_t* ncls = nullptr;
+  int32_t* nslot = nullptr;
   void* own = nullptr;
   double* phic = nullptr;
   double *part_sweep = nullptr, *part_iface = nullptr, *grads = nullptr;
   double *aux_rho = nullptr, *aux_u = nullptr;  // recompute steps (the context's stay untouched)
   int32_t* counters = nullptr;
+  int32_t* fixed_count = nullptr;  // counter set whose interface count is n_i (for the fixed list)
   int32_t* listI_fwd = nullptr;
 };
 
@@ -496,8 +518,11 @@ struct WinLayout {
   // head (independent of the interface count)
   size_t flags, listI, islot, bcount, n_dev;
   // rest
-  size_t slots, slot_bytes, slot_m, slot_phi;
-  size_t lam[2], lam_m, lphi[2], own, phic, part_sweep, part_iface, grads, aux_rho, aux_u, counters, listI_fwd;
+  size_t ckpt, state_bytes, st_m, st_phi;
+  size_t hot[2], hot_m;
+  size_t rec, rec_bytes, rc_f, rc_own, rc_phi, rc_m;
+  size_t ncls, nslot, lam[2], lam_m, lphi[2], own, phic, part_sweep, part_iface, grads, aux_rho, aux_u, counters,
+      fixed_count, listI_fwd;
   size_t total;
 };
 
@@ -519,10 +544,27 @@ WinLayout win_layout(const Grid& g, int precision, int T, int K, int n_i) {
   L.islot = take(4 * N);
   L.bcount = take(4 * (size_t)list_blocks(g));
   L.n_dev = take(4);
-  L.slot_m = align_up(Q * N * sb);
-  L.slot_phi = L.slot_m + align_up(8 * N);
-  L.slot_bytes = L.slot_phi + align_up(8 * N);
-  L.slots = take(L.slot_bytes * (size_t)(C + K));
+  // full state: f, mass, fill
+  L.st_m = align_up(Q * N * sb);
+  L.st_phi = L.st_m + align_up(8 * N);
+  L.state_bytes = L.st_phi + align_up(8 * N);
+  L.ckpt = take(L.state_bytes * (size_t)C);
+  L.hot[0] = take(Q * N * sb + 0);
+  L.hot[1] = take(Q * N * sb);
+  L.hot_m = take(8 * N);
+  const size_t hot_phi0 = take(8 * N);
+  const size_t hot_phi1 = take(8 * N);
+  (void)hot_phi0;
+  (void)hot_phi1;
+  // step record
+  L.rc_f = align_up(3 * N * rb);
+  L.rc_own = L.rc_f + align_up(Q * cap * rb);
+  L.rc_phi = L.rc_own + align_up(Q * cap * rb);
+  L.rc_m = L.rc_phi + align_up(8 * cap);
+  L.rec_bytes = L.rc_m + align_up(8 * cap);
+  L.rec = take(L.rec_bytes * (size_t)K);
+  L.ncls = take(8 * cap);
+  L.nslot = take(4 * Q * cap);
   L.lam[0] = take(Q * N * rb);
   L.lam[1] = take(Q * N * rb);
   L.lam_m = take(8 * N);
@@ -536,6 +578,7 @@ WinLayout win_layout(const Grid& g, int precision, int T, int K, int n_i) {
   L.aux_rho = take(8 * N);
   L.aux_u = take(24 * N);
   L.counters = take(2 * NCOUNT * sizeof(int32_t));
+  L.fixed_count = take(NCOUNT * sizeof(int32_t));
   L.listI_fwd = take(4 * N);
   L.total = o;
   return L;
@@ -564,9 +607,12 @@ int window_spacing(int32_t T, int32_t K) {
   return std::min(K, T);
 }
 
-// one frozen forward step from slot A (time t) to slot B (time t+1)
-hipError_t window_step(fslbm_window* w, const fslbm_window::Slot& A, const fslbm_window::Slot& B, int parity,
-                       bool forward_pass) {
+// One frozen forward step from state A (time t) to state B (time t+1) that
+// also writes the step's record R.  The sweep stores the liquid cells'
+// collision velocity; the interface kernel takes the window's fixed ascending
+// list (so records are in list order) and stores its cells' inputs.
+hipError_t window_step(fslbm_window* w, const fslbm_window::State& A, const fslbm_window::State& B,
+                       const fslbm_window::Record& R, int parity, bool forward_pass) {
   fslbm_ctx* c = w->ctx;
   StepLaunch L{};
   SweepArgs& s = L.sweep;
@@ -593,10 +639,39 @@ hipError_t window_step(fslbm_window* w, const fslbm_window::Slot& A, const fslbm
   s.freeze = 1;
   s.cpr = 0;
   s.pairs = c->pairs;
+  s.u_out = R.u;
   L.stream = (void*)c->stream;
   hipError_t e = launch_sweep(L, w->precision, w->rule);
   if (e != hipSuccess) return e;
-  return launch_iface(L, w->precision, w->rule);
+  StepLaunch Li = L;
+  Li.sweep.listI = w->listI;
+  Li.sweep.counters = w->fixed_count;
+  Li.sweep.rec_f = R.f;
+  Li.sweep.rec_own = R.own;
+  Li.sweep.rec_phi = R.phi;
+  Li.sweep.rec_m = R.m;
+  Li.sweep.rec_cap = w->cap;
+  return launch_iface(Li, w->precision, w->rule);
+}
+
+// State of time t during a pass over the window: checkpoint at multiples of K,
+// else a hot buffer (t = T included).
+const fslbm_window::State& state_at(const fslbm_window* w, int t) {
+  if (t % w->K == 0 && t < w->T) return w->ckpt[t / w->K];
+  return w->hot[t & 1];
+}
+
+// Steps t0 .. t1-1 writing records k = t - t0.  In the forward pass every
+// state goes where state_at says (so checkpoints are written); in a recompute
+// the outputs stay in the hot buffers.
+hipError_t window_run(fslbm_window* w, int t0, int t1, bool forward_pass) {
+  for (int t = t0; t < t1; ++t) {
+    const fslbm_window::State& A = state_at(w, t);
+    const fslbm_window::State& B = forward_pass ? state_at(w, t + 1) : w->hot[(t + 1) & 1];
+    hipError_t e = window_step(w, A, B, w->rec[t - t0], t, forward_pass);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -646,7 +721,7 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   char* wsp = (char*)workspace;
   // the head of the layout does not depend on the interface count
   const WinLayout H = win_layout(g, c->p.precision, T, window_spacing(T, K), 0);
-  if (workspace_bytes < H.slots) { c->last_error = "window workspace too small"; return FSLBM_E_INVALID; }
+  if (workspace_bytes < H.ckpt) { c->last_error = "window workspace too small"; return FSLBM_E_INVALID; }
   fslbm_window* w = new (std::nothrow) fslbm_window();
   if (!w) { c->last_error = "out of host memory"; return FSLBM_E_INVALID; }
   auto fail = [&](fslbm_status s) {
@@ -685,12 +760,19 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   w->cap = std::max(n_i, 1);
   w->nb_sweep = (int)adj_sweep_blocks(g);
   w->nb_iface = (int)adj_iface_blocks(n_i);
-  for (int i = 0; i < w->C + w->K; ++i) {
-    char* b = wsp + L.slots + (size_t)i * L.slot_bytes;
-    fslbm_window::Slot sl{b, (double*)(b + L.slot_m), (double*)(b + L.slot_phi)};
-    if (i < w->C) w->ckpt.push_back(sl);
-    else w->ring.push_back(sl);
+  for (int j = 0; j < w->C; ++j) {
+    char* b = wsp + L.ckpt + (size_t)j * L.state_bytes;
+    w->ckpt.push_back({b, (double*)(b + L.st_m), (double*)(b + L.st_phi)});
   }
+  // hot states: own population and fill buffers, one mass array (in place)
+  w->hot[0] = {wsp + L.hot[0], (double*)(wsp + L.hot_m), (double*)(wsp + L.hot_m + align_up(8 * N))};
+  w->hot[1] = {wsp + L.hot[1], (double*)(wsp + L.hot_m), (double*)(wsp + L.hot_m + 2 * align_up(8 * N))};
+  for (int k = 0; k < w->K; ++k) {
+    char* b = wsp + L.rec + (size_t)k * L.rec_bytes;
+    w->rec.push_back({b, b + L.rc_f, b + L.rc_own, (double*)(b + L.rc_phi), (double*)(b + L.rc_m)});
+  }
+  w->ncls = (uint64_t*)(wsp + L.ncls);
+  w->nslot = (int32_t*)(wsp + L.nslot);
   for (int i = 0; i < 2; ++i) {
     w->lam[i] = wsp + L.lam[i];
     w->lphi[i] = (double*)(wsp + L.lphi[i]);
@@ -704,32 +786,32 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   w->aux_rho = (double*)(wsp + L.aux_rho);
   w->aux_u = (double*)(wsp + L.aux_u);
   w->counters = (int32_t*)(wsp + L.counters);
+  w->fixed_count = (int32_t*)(wsp + L.fixed_count);
   w->listI_fwd = (int32_t*)(wsp + L.listI_fwd);
+  if ((e = launch_fill_i32(w->fixed_count, NCOUNT, 0, c->stream)) != hipSuccess ||
+      (e = launch_fill_i32(w->fixed_count + C_I, 1, n_i, c->stream)) != hipSuccess ||
+      (e = launch_adj_topo(w->flags, g, w->listI, w->islot, n_i, w->cap, w->ncls, w->nslot, c->stream)) !=
+          hipSuccess)
+    return fail(dev_fail(c, e, "window topology"));
 
   // checkpoint 0: the current state of the context
   const size_t fb = Q * N * storage_bytes(c->p.precision);
-  const fslbm_window::Slot& c0 = w->ckpt[0];
+  const fslbm_window::State& c0 = w->ckpt[0];
   if ((e = hipMemcpyAsync(c0.f, c->f[c->cur], fb, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(c0.m, c->mass, 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(c0.phi, c->phi[c->cur], 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
     return fail(dev_fail(c, e, "checkpoint copy"));
   if ((e = launch_fill_i32(w->counters, 2 * NCOUNT, 0, c->stream)) != hipSuccess)
     return fail(dev_fail(c, e, "window counters"));
-  // forward: each step writes straight into its slot (no copies); the last
-  // step of every segment but the final one writes the next checkpoint
+  // forward: segment by segment, records into the ring (the last segment's
+  // stay for the backward pass), checkpoints at multiples of K
   for (int j = 0; j < w->C; ++j) {
-    const int Lj = std::min(w->K, T - j * w->K);
-    for (int k = 0; k < Lj; ++k) {
-      const fslbm_window::Slot& A = k == 0 ? w->ckpt[j] : w->ring[k - 1];
-      const fslbm_window::Slot& B = (k + 1 == Lj && j + 1 < w->C) ? w->ckpt[j + 1] : w->ring[k];
-      if ((e = window_step(w, A, B, j * w->K + k, true)) != hipSuccess)
-        return fail(dev_fail(c, e, "window step"));
-    }
+    const int t0 = j * w->K, t1 = std::min(T, t0 + w->K);
+    if ((e = window_run(w, t0, t1, true)) != hipSuccess) return fail(dev_fail(c, e, "window step"));
   }
-  w->ring_seg = w->C - 1;
+  w->rec_seg = w->C - 1;
   // the final state becomes the context's current state
-  const int Llast = T - (w->C - 1) * w->K;
-  const fslbm_window::Slot& fin = w->ring[Llast - 1];
+  const fslbm_window::State& fin = state_at(w, T);
   if ((e = hipMemcpyAsync(c->f[c->cur], fin.f, fb, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(c->mass, fin.m, 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(c->phi[c->cur], fin.phi, 8 * N, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
@@ -754,23 +836,25 @@ fslbm_status fslbm_window_backward(fslbm_window* w, const double* dL_df, const d
   HIPCHK(c, launch_fill_f64(w->part_sweep, 3 * (size_t)w->nb_sweep, 0.0, st), "adjoint partials");
   HIPCHK(c, launch_fill_f64(w->part_iface, 4 * (size_t)w->nb_iface, 0.0, st), "adjoint partials");
   for (int j = w->C - 1; j >= 0; --j) {
-    const int Lj = std::min(w->K, T - j * w->K);
-    if (w->ring_seg != j) {
-      // recompute the segment's states from its checkpoint
+    const int t0 = j * w->K, t1 = std::min(T, t0 + w->K);
+    if (w->rec_seg != j) {
+      // rebuild the segment's records from its checkpoint
       HIPCHK(c, launch_fill_i32(w->counters, 2 * NCOUNT, 0, st), "window counters");
-      for (int k = 0; k + 1 < Lj; ++k)
-        HIPCHK(c, window_step(w, k == 0 ? w->ckpt[j] : w->ring[k - 1], w->ring[k], k, false), "recompute step");
-      w->ring_seg = j;
+      HIPCHK(c, window_run(w, t0, t1, false), "recompute step");
+      w->rec_seg = j;
     }
-    for (int k = Lj - 1; k >= 0; --k) {
-      const int t = j * w->K + k;
-      const fslbm_window::Slot& S = k == 0 ? w->ckpt[j] : w->ring[k - 1];
+    for (int t = t1 - 1; t >= t0; --t) {
+      const fslbm_window::Record& R = w->rec[t - t0];
       AdjArgs a{};
       a.c = w->com;
-      a.fst = S.f;
+      a.u = R.u;
+      a.rec_f = R.f;
+      a.rec_own = R.own;
+      a.rec_phi = R.phi;
+      a.rec_m = R.m;
+      a.ncls = w->ncls;
+      a.nslot = w->nslot;
       a.flags = w->flags;
-      a.mass = S.m;
-      a.phi = S.phi;
       a.lam_in = w->lam[(t + 1) & 1];
       a.lam_out = w->lam[t & 1];
       a.lam_m = w->lam_m;
@@ -785,7 +869,9 @@ fslbm_status fslbm_window_backward(fslbm_window* w, const double* dL_df, const d
       a.n_i = w->n_i;
       a.cap = w->cap;
       a.cpr = 0;
-      HIPCHK(c, launch_adjoint_step(a, w->precision, w->rule, st), "adjoint step");
+      HIPCHK(c, launch_adj_sweep(a, w->precision, st), "adjoint sweep");
+      HIPCHK(c, launch_adj_iface(a, w->precision, w->rule, st), "adjoint interface");
+      HIPCHK(c, launch_adj_iface2(a, w->precision, st), "adjoint gather");
     }
   }
   HIPCHK(c, launch_adj_out(w->com, w->flags, w->precision, w->lam[0], w->lam_m, w->lphi[0], dL_df0, dL_dm0,
@@ -811,8 +897,9 @@ fslbm_status fslbm_window_info(const fslbm_window* w, int32_t info[4]) {
 
 fslbm_status fslbm_window_destroy(fslbm_window* w) {
   if (!w) return FSLBM_E_INVALID;
+  const hipError_t e = w->ctx ? hipStreamSynchronize(w->ctx->stream) : hipSuccess;
   delete w;
-  return FSLBM_OK;
+  return e == hipSuccess ? FSLBM_OK : FSLBM_E_DEVICE;
 }
 
 }  // extern "C"

@@ -53,6 +53,15 @@ struct SweepArgs {
   int freeze;
   int cpr;   // blocks per lattice row (set by the launcher)
   int pairs; // FP16 form: two cells per lane when rows have even length
+  void* u_out;  // optional (FP64 / FP32 forms): collision velocity of liquid cells, [3][N] compute type
+  // optional per-step record of the interface cells (list order, capacity
+  // rec_cap): pulled and own populations of time t (compute type, [Q][cap]),
+  // fill and mass of time t
+  void* rec_f;
+  void* rec_own;
+  double* rec_phi;
+  double* rec_m;
+  int rec_cap;
 };
 
 struct ConvArgs {
@@ -119,10 +128,16 @@ struct StatArgs {
 // One reverse step t+1 -> t of a window with frozen cell classes.
 struct AdjArgs {
   Common c;
-  const void* fst;        // post-collision populations of time t (storage type)
+  // record of the step t -> t+1 (written by the forward step)
+  const void* u;          // collision velocity at liquid cells ([3][N], compute type)
+  const void* rec_f;      // interface cells: pulled populations ([Q][cap], compute type)
+  const void* rec_own;    // interface cells: own post-collision populations of time t
+  const double* rec_phi;  // interface cells: fill of time t
+  const double* rec_m;    // interface cells: mass of time t
+  // fixed topology of the interface cells (list order)
+  const uint64_t* ncls;   // class of the pull source of each link, 2 bits per link (gas, interface, liquid, wall)
+  const int32_t* nslot;   // [Q][cap] list position of an interface pull source, else the cell's own
   const uint8_t* flags;   // cell classes (fixed over the window)
-  const double* mass;     // interface mass of time t
-  const double* phi;      // fill level of time t
   const void* lam_in;     // dL/dft of time t+1 (compute type)
   void* lam_out;          // dL/dft of time t (compute type)
   double* lam_m;          // dL/dm: time t+1 on entry, time t on exit (interface cells)
@@ -155,12 +170,18 @@ unsigned adj_sweep_blocks(const Grid& g);
 unsigned adj_iface_blocks(int n_i);
 unsigned list_blocks(const Grid& g);
 hipError_t launch_count_iface(const uint8_t* flags, const Grid& g, int32_t* out, void* stream);
+hipError_t launch_adj_topo(const uint8_t* flags, const Grid& g, const int32_t* list, const int32_t* islot, int n_i,
+                           int cap, uint64_t* ncls, int32_t* nslot, void* stream);
 hipError_t launch_iface_list(const uint8_t* flags, const Grid& g, int32_t* bcount, int32_t* list, int32_t* islot,
                              int32_t* n_out, void* stream);
 hipError_t launch_adj_seed(const Common& c, const uint8_t* flags, int precision, const double* dLdf,
                            const double* dLdm, const double* dLdphi, void* lam, void* lam_other, double* lam_m,
                            double* lphi, double* lphi_other, void* stream);
-hipError_t launch_adjoint_step(const AdjArgs& a, int precision, int rule, void* stream);
+// one reverse step = adj_sweep (liquid cells) and adj_iface (interface cells;
+// independent of adj_sweep, may run concurrently), then adj_iface2 after both
+hipError_t launch_adj_sweep(const AdjArgs& a, int precision, void* stream);
+hipError_t launch_adj_iface(const AdjArgs& a, int precision, int rule, void* stream);
+hipError_t launch_adj_iface2(const AdjArgs& a, int precision, void* stream);
 hipError_t launch_adj_out(const Common& c, const uint8_t* flags, int precision, const void* lam,
                           const double* lam_m, const double* lphi, double* dLdf, double* dLdm, double* dLdphi,
                           void* stream);

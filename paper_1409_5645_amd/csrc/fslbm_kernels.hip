@@ -106,7 +106,7 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
 // loads of a cell are in flight together.  MODEL 1 fixes the incompressible
 // non-Stokes equilibrium at compile time; MODEL 0 reads both switches.
 
-template <class F, int MODEL>
+template <class F, int MODEL, bool WITH_U = false>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
@@ -179,6 +179,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
 #pragma unroll
   for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+  if constexpr (WITH_U) {
+    // collision velocity, kept for the adjoint of this step
+    R* __restrict__ uo = reinterpret_cast<R*>(a.u_out);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) uo[(unsigned)c * N + rbase + (unsigned)x] = u[c];
+  }
 }
 
 // FP16-storage sweep with two cells per lane (rows of even length): the 19
@@ -326,8 +332,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
 // Interface cells of the list built by the sweep: one cell per thread, in
 // three phases -- load the whole neighbourhood (independent loads), compute in
 // registers, store.
-template <class F, int RULE>
-__global__ __launch_bounds__(BLOCK) void k_iface(SweepArgs a) {
+constexpr int IBLOCK = 64;  // interface-list kernels: one wavefront per block
+
+template <class F, int RULE, bool REC = false>
+__global__ __launch_bounds__(IBLOCK) void k_iface(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
   constexpr bool SH = F::shifted;
@@ -337,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void k_iface(SweepArgs a) {
   S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
   const size_t N = (size_t)g.N;
   const float isc = a.c.inv_scale;
-  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n_i; i += gridDim.x * BLOCK) {
+  for (int i = blockIdx.x * IBLOCK + threadIdx.x; i < n_i; i += gridDim.x * IBLOCK) {
     const int idx = a.listI[i];
     Nbr n;
     coords(g, idx, n.x, n.y, n.z);
@@ -369,6 +377,20 @@ __global__ __launch_bounds__(BLOCK) void k_iface(SweepArgs a) {
 #undef FSLBM_ILOAD
     d.m = a.mass_in[idx];
     d.phix = a.phi_in[idx];
+    if constexpr (REC) {
+      // what the adjoint of this step needs at this cell, in list order
+      using RR = typename F::R;
+      RR* rf = reinterpret_cast<RR*>(a.rec_f);
+      RR* ro = reinterpret_cast<RR*>(a.rec_own);
+      const unsigned cap = (unsigned)a.rec_cap;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        rf[(unsigned)q * cap + (unsigned)i] = d.f[q];
+        ro[(unsigned)q * cap + (unsigned)i] = d.own[q];
+      }
+      a.rec_phi[i] = d.phix;
+      a.rec_m[i] = d.m;
+    }
     // ---- phase 2: interface treatment and collision
     R rho_s, u[3];
     const double m_new = iface_compute<F, RULE>(d, a.c, rho_s, u);
@@ -719,7 +741,7 @@ __global__ __launch_bounds__(BLOCK) void k_stats(StatArgs a) {
 // ------------------------------------------------------------ launchers
 static inline unsigned blocks_for(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 static constexpr unsigned LIST_GRID = 512;
-static constexpr unsigned IFACE_GRID = 2048;
+static constexpr unsigned IFACE_GRID = 8192;
 
 template <class F>
 static void sweep_form(const StepLaunch& L) {
@@ -728,7 +750,9 @@ static void sweep_form(const StepLaunch& L) {
   const Grid& g = a.c.grid;
   a.cpr = (g.nx + BLOCK - 1) / BLOCK;
   const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
-  if (a.c.incomp && !a.c.stokes)
+  if (a.u_out && a.c.incomp && !a.c.stokes)
+    k_sweep<F, 1, true><<<nb, BLOCK, 0, st>>>(a);
+  else if (a.c.incomp && !a.c.stokes)
     k_sweep<F, 1><<<nb, BLOCK, 0, st>>>(a);
   else
     k_sweep<F, 0><<<nb, BLOCK, 0, st>>>(a);
@@ -737,11 +761,19 @@ static void sweep_form(const StepLaunch& L) {
 template <class F>
 static void iface_form(const StepLaunch& L, int rule) {
   hipStream_t st = (hipStream_t)L.stream;
-  const unsigned nb = std::min<unsigned>(IFACE_GRID, blocks_for(L.sweep.c.grid.N));
-  if (rule == 0)
-    k_iface<F, 0><<<nb, BLOCK, 0, st>>>(L.sweep);
-  else
-    k_iface<F, 1><<<nb, BLOCK, 0, st>>>(L.sweep);
+  // the interface count is on the device: enough one-wavefront blocks for
+  // every cell up to IFACE_GRID * IBLOCK, grid-stride beyond
+  const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
+  if (L.sweep.rec_f) {
+    if (rule == 0)
+      k_iface<F, 0, true><<<nb, IBLOCK, 0, st>>>(L.sweep);
+    else
+      k_iface<F, 1, true><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  } else if (rule == 0) {
+    k_iface<F, 0><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  } else {
+    k_iface<F, 1><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  }
 }
 
 template <class F>
