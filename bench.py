@@ -32,11 +32,13 @@ HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32"}
 HEADLINE = "fp16s"
+SWEEP_KERNEL = {"fp64": "k_sweep<FormF64, 1, false>", "fp32": "k_sweep<FormF32, 1, false>",
+                "fp16s": "k_sweep_h2<1>"}
 
 
 def sweep_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fslbm_device.hpp", "fslbm_kernels.hip"):
+    for f in ("fslbm_device.hpp", "fslbm_sweep.hip"):
         h.update(open(os.path.join(ROOT, "paper_1409_5645_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -272,7 +274,7 @@ def main():
     traffic = traffic_for(head, r["active_cells"], w.params.n_cells)
     roof = {"bound": "hbm", "achieved": r["sweep_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": f"k_sweep<{head}, FSL>",
+            "kernel": SWEEP_KERNEL[head],
             "bytes_per_launch": r["alg_bytes_per_sweep"], "avg_launch_ms": r["sweep_ms"]}
     for form in forms:
         results[form]["roofline_frac"] = results[form]["sweep_gbs"] / HBM_PEAK_GBS

@@ -180,12 +180,11 @@ fslbm_status fslbm_set_forcing(fslbm_ctx* c, const double g[3], double rho_gas);
  * are kept by sqrt(T) checkpointing: every K-th state (K = ceil(sqrt T) by
  * default) is stored during the forward pass, and each segment's states are
  * recomputed from its checkpoint during the backward pass (the last segment's
- * are kept from the forward pass).  Interface-cell kernels of a window run on a
- * second, library-owned stream beside the sweeps; every call still orders its
- * work after earlier work on the context's stream and returns with it ordered
- * before later work there.  Supported: FP64 and FP32 forms, the
- * incompressible equilibrium with its quadratic term (otherwise
- * FSLBM_E_UNSUPPORTED).  The caller owns the window workspace; it must stay
+ * are kept from the forward pass).  Between checkpoints only a compact record
+ * per step is kept: the collision velocity of the liquid cells and the inputs
+ * of the interface cells.  All work runs on the context's stream.
+ * Supported: FP64 and FP32 forms, the incompressible equilibrium with its
+ * quadratic term (otherwise FSLBM_E_UNSUPPORTED).  The caller owns the window workspace; it must stay
  * allocated, and the context alive, until fslbm_window_destroy. */
 typedef struct fslbm_window fslbm_window;
 
@@ -217,8 +216,8 @@ fslbm_status fslbm_window_backward(fslbm_window* w, const double* dL_df, const d
 /* info = {T, K, number of checkpoints, interface cells}. */
 fslbm_status fslbm_window_info(const fslbm_window* w, int32_t info[4]);
 
-/* Wait for the window's work, then release its host state and its internal
- * stream (not the workspace).  Synchronises. */
+/* Wait for the window's work, then release its host state (not the
+ * workspace).  Synchronises. */
 fslbm_status fslbm_window_destroy(fslbm_window* w);
 
 /* Release the context (not the caller's buffers).  Synchronises. */

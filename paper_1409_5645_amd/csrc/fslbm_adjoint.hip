@@ -141,7 +141,6 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NV], double* slot) 
 template <class F>
 __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
   using R = typename F::R;
-  using S = typename F::S;
   const Grid g = a.c.grid;
   const int row = (int)blockIdx.x / a.cpr;
   const int chunk = (int)blockIdx.x - row * a.cpr;

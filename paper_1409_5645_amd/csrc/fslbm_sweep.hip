@@ -1,0 +1,284 @@
+// Stream/collide sweep of the liquid cells for gfx950: the kernel that moves
+// the populations (Eq. lbe1, lbe2), in one file of its own.  Every other step
+// of the method is in fslbm_kernels.hip.
+#include "fslbm_device.hpp"
+#include "fslbm_internal.hpp"
+#include "fslbm_stencil.hpp"
+
+namespace fslbm {
+
+constexpr int BLOCK = 256;
+
+// Stream/collide sweep over liquid cells, one cell per lane; a block covers a
+// chunk of one lattice row, so the row, its y and z and the source rows of
+// every link are uniform (scalar) values.  Interface cells are appended to the
+// interface list (one atomic per wavefront) and updated by k_iface; gas cells
+// are skipped.
+//
+// Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q).  A source beyond a wall gives
+// halfway bounce-back f_q(x) = ft_qbar(x).  Every load is unconditional with a
+// 32-bit element offset from the buffer start (selected per lane), so all 19
+// loads of a cell are in flight together.  MODEL 1 fixes the incompressible
+// non-Stokes equilibrium at compile time; MODEL 0 reads both switches.
+
+template <class F, int MODEL, bool WITH_U = false>
+__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
+  using R = typename F::R;
+  using S = typename F::S;
+  constexpr bool SH = F::shifted;
+  const Grid g = a.c.grid;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
+  }
+  const int row = (int)blockIdx.x / a.cpr;
+  const int chunk = (int)blockIdx.x - row * a.cpr;
+  const int y = row % g.ny, z = row / g.ny;
+  const int x = chunk * BLOCK + (int)threadIdx.x;
+  const unsigned rbase = (unsigned)row * (unsigned)g.nx;
+  const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
+  const int lane = (int)threadIdx.x & 63;
+  {
+    // interface cells -> list (wavefront-aggregated append)
+    const unsigned long long b = __ballot(t == IFACE);
+    if (b) {
+      const int leader = __ffsll((long long)b) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
+      base = __shfl(base, leader);
+      if (t == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)(rbase + x);
+    }
+  }
+  if (t != LIQ) return;
+
+  // source rows (element offsets) of the nine (c_y, c_z) combinations
+  const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
+  const int zm = step_axis(z, -1, g.nz, g.pz), zp = step_axis(z, 1, g.nz, g.pz);
+  auto row_of = [&](int sy, int sz) -> unsigned {
+    return (sy < 0 || sz < 0) ? WALL_ROW : (unsigned)(sy + g.ny * sz) * (unsigned)g.nx;
+  };
+  // index: (c_y + 1) + 3 (c_z + 1); source row is (y - c_y, z - c_z)
+  const unsigned srow[9] = {row_of(yp, zp), row_of(y, zp), row_of(ym, zp),
+                            row_of(yp, z),  rbase,         row_of(ym, z),
+                            row_of(yp, zm), row_of(y, zm), row_of(ym, zm)};
+  // source columns (-1 beyond a wall at a row end: bounce-back)
+  const int xm = step_axis(x, -1, g.nx, g.px), xp = step_axis(x, 1, g.nx, g.px);
+  const unsigned N = (unsigned)g.N;  // 19 N < 2^32 is checked at init
+  const S* __restrict__ fin = reinterpret_cast<const S*>(a.fin);
+
+  // Every load is unconditional with a 32-bit element offset (selected per
+  // lane), so all 19 loads of a cell are in flight together.  F::load_raw
+  // keeps the FP16 form in its storage units (the collision absorbs the scale).
+  R f[Q];
+#define FSLBM_PULL(q)                                                                               \
+  {                                                                                                 \
+    const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                        \
+    const int sx = CX[q] == 1 ? xm : (CX[q] == -1 ? xp : x);                                        \
+    const unsigned off = (ro == WALL_ROW || sx < 0) ? (unsigned)OPP[q] * N + rbase + (unsigned)x     \
+                                                    : (unsigned)q * N + ro + (unsigned)sx;          \
+    f[q] = F::load_raw(fin + off);                                                                  \
+  }
+  FSLBM_PULL(0)
+  FSLBM_LINKS(FSLBM_PULL)
+#undef FSLBM_PULL
+
+  // ---- TRT collision, Eq. (lbe2)
+  const Consts<R>& k = pick_consts<R>(a.c);
+  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+  R rho_s, u[3];
+  if constexpr (sizeof(R) == 4)
+    collide_f32_scaled<SH, F::scaled>(f, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  else
+    collide<R, SH>(f, k, incomp, stokes, rho_s, u);
+  S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+  if constexpr (WITH_U) {
+    // collision velocity, kept for the adjoint of this step
+    R* __restrict__ uo = reinterpret_cast<R*>(a.u_out);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) uo[(unsigned)c * N + rbase + (unsigned)x] = u[c];
+  }
+}
+
+// FP16-storage sweep with two cells per lane (rows of even length): the 19
+// populations of a pair are 4-byte aligned loads; the x-shifted neighbour comes
+// from the adjacent lane by a wavefront shift (DPP), and the one element beyond
+// the wavefront (or the row end: periodic wrap, or bounce-back at a wall) is a
+// broadcast load from a wavefront-uniform address.  Liquid cells only; a pair
+// store also covers an interface or gas partner (k_iface, which runs after this
+// kernel, writes interface cells; gas slots are never read).
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i receives lane i-1
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i receives lane i+1
+
+__device__ __forceinline__ float h_lo(uint32_t p) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(p & 0xffffu));
+}
+__device__ __forceinline__ float h_hi(uint32_t p) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(p >> 16)); }
+__device__ __forceinline__ float h_one(uint16_t v) { return (float)__builtin_bit_cast(_Float16, v); }
+__device__ __forceinline__ uint32_t h_pack(float a, float b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+}
+
+// Pull of the 19 populations of a lane's cell pair (see k_sweep_h2).  Phase 1
+// issues all loads (19 pairs, 10 wavefront-edge elements); phase 2 shifts and
+// selects, so no load waits on another link's data movement.
+template <bool WALLS>
+__device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const uint16_t* __restrict__ fin,
+                                          const Grid& g, size_t N, const unsigned (&srow)[9], unsigned rbase,
+                                          int xl, int wx0, int wend, bool row_end) {
+  uint32_t p[Q], e[Q];
+#define FSLBM_LOAD2(q)                                                                            \
+  {                                                                                               \
+    const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                      \
+    const bool wall = WALLS && ro == WALL_ROW;                                                    \
+    const uint16_t* own_qb = fin + (size_t)OPP[q] * N + rbase;                                    \
+    const uint16_t* src = wall ? own_qb : fin + (size_t)q * N + ro;                               \
+    p[q] = *reinterpret_cast<const uint32_t*>(src + xl);                                          \
+    if (CX[q] == 1) {                                                                             \
+      const uint16_t* ep = wx0 > 0 ? src + (wx0 - 1) : (g.px ? src + (g.nx - 1) : own_qb);        \
+      e[q] = (uint32_t)*ep << 16;                                                                 \
+    } else if (CX[q] == -1) {                                                                     \
+      const uint16_t* ep = wend < g.nx ? src + wend : (g.px ? src : own_qb + (g.nx - 1));         \
+      e[q] = (uint32_t)*ep;                                                                       \
+    }                                                                                             \
+  }
+  FSLBM_LOAD2(0)
+  FSLBM_LINKS(FSLBM_LOAD2)
+#undef FSLBM_LOAD2
+#define FSLBM_SHIFT2(q)                                                                           \
+  {                                                                                               \
+    const bool wall = WALLS && srow[(CY[q] + 1) + 3 * (CZ[q] + 1)] == WALL_ROW;                   \
+    uint32_t lo = p[q], hi = p[q];                                                                \
+    if (CX[q] == 1) {                                                                             \
+      /* cell x0 <- x0-1 (lane 0: the edge element as the shift's fill), cell x0+1 <- x0 */       \
+      const uint32_t nb = (uint32_t)__builtin_amdgcn_update_dpp((int)e[q], (int)p[q], DPP_WAVE_SHR1, 0xf, 0xf, false); \
+      lo = wall ? p[q] : (nb >> 16);                                                              \
+      hi = wall ? p[q] : (p[q] << 16);                                                            \
+    } else if (CX[q] == -1) {                                                                     \
+      /* cell x0 <- x0+1, cell x0+1 <- x0+2 (lane 63 and the row's last pair: the edge element) */ \
+      const uint32_t nb = (uint32_t)__builtin_amdgcn_update_dpp((int)e[q], (int)p[q], DPP_WAVE_SHL1, 0xf, 0xf, false); \
+      const uint32_t nx2 = row_end ? e[q] : nb;                                                   \
+      lo = wall ? p[q] : (p[q] >> 16);                                                            \
+      hi = wall ? p[q] : (nx2 << 16);                                                             \
+    }                                                                                             \
+    f0[q] = h_lo(lo);                                                                             \
+    f1[q] = h_hi(hi);                                                                             \
+  }
+  FSLBM_SHIFT2(0)
+  FSLBM_LINKS(FSLBM_SHIFT2)
+#undef FSLBM_SHIFT2
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
+  const Grid g = a.c.grid;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
+  }
+  const int row = (int)blockIdx.x / a.cpr;
+  const int chunk = (int)blockIdx.x - row * a.cpr;
+  const int y = row % g.ny, z = row / g.ny;
+  const int x0 = (chunk * BLOCK + (int)threadIdx.x) * 2;
+  const bool valid = x0 < g.nx;
+  const int xl = valid ? x0 : 0;  // in-bounds pair for lanes past the row end
+  const unsigned rbase = (unsigned)row * (unsigned)g.nx;
+  const uint16_t fl2 = valid ? *reinterpret_cast<const uint16_t*>(a.flags + rbase + xl) : (uint16_t)0;
+  const uint8_t tt[2] = {(uint8_t)(fl2 & 0xffu), (uint8_t)(fl2 >> 8)};
+  const int lane = (int)threadIdx.x & 63;
+  // interface cells -> list (wavefront-aggregated append, one cell of the pair at a time)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const unsigned long long b = __ballot(tt[j] == IFACE);
+    if (b) {
+      const int leader = __ffsll((long long)b) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
+      base = __shfl(base, leader);
+      if (tt[j] == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)rbase + x0 + j;
+    }
+  }
+  const bool liq = tt[0] == LIQ || tt[1] == LIQ;
+  if (__ballot(liq) == 0) return;  // lanes exchange data below: whole wavefronts only
+
+  const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
+  const int zm = step_axis(z, -1, g.nz, g.pz), zp = step_axis(z, 1, g.nz, g.pz);
+  auto row_of = [&](int sy, int sz) -> unsigned {
+    return (sy < 0 || sz < 0) ? WALL_ROW : (unsigned)(sy + g.ny * sz) * (unsigned)g.nx;
+  };
+  const unsigned srow[9] = {row_of(yp, zp), row_of(y, zp), row_of(ym, zp),
+                            row_of(yp, z),  rbase,         row_of(ym, z),
+                            row_of(yp, zm), row_of(y, zm), row_of(ym, zm)};
+  // first column of the wavefront (uniform over it; readfirstlane says so) and after it
+  const int wx0 = __builtin_amdgcn_readfirstlane((chunk * BLOCK + ((int)threadIdx.x & ~63)) * 2);
+  const int wend = wx0 + 128;
+  const bool row_end = xl + 2 == g.nx;  // last pair of the row (its right neighbour is past the row)
+  const size_t N = (size_t)g.N;
+  const uint16_t* __restrict__ fin = reinterpret_cast<const uint16_t*>(a.fin);
+
+  float f0[Q], f1[Q];
+  // interior blocks (no source row beyond a y/z wall) take a select-only pull;
+  // the few blocks on the y/z faces take the general one
+  bool wall_rows = false;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
+  if (!wall_rows)
+    pull_pair<false>(f0, f1, fin, g, N, srow, rbase, xl, wx0, wend, row_end);
+  else
+    pull_pair<true>(f0, f1, fin, g, N, srow, rbase, xl, wx0, wend, row_end);
+
+  // ---- TRT collision, Eq. (lbe2), in storage units
+  const Consts<float>& k = a.c.kf;
+  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+  float rho_s, u[3];
+  collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  if (liq) {
+    uint16_t* __restrict__ fout = reinterpret_cast<uint16_t*>(a.fout) + rbase + x0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fout + (size_t)q * N) = h_pack(f0[q], f1[q]);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+template <class F>
+static void sweep_form(const StepLaunch& L) {
+  hipStream_t st = (hipStream_t)L.stream;
+  SweepArgs a = L.sweep;
+  const Grid& g = a.c.grid;
+  a.cpr = (g.nx + BLOCK - 1) / BLOCK;
+  const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
+  if (a.u_out && a.c.incomp && !a.c.stokes)
+    k_sweep<F, 1, true><<<nb, BLOCK, 0, st>>>(a);
+  else if (a.c.incomp && !a.c.stokes)
+    k_sweep<F, 1><<<nb, BLOCK, 0, st>>>(a);
+  else
+    k_sweep<F, 0><<<nb, BLOCK, 0, st>>>(a);
+}
+
+static void sweep_h2(const StepLaunch& L) {
+  hipStream_t st = (hipStream_t)L.stream;
+  SweepArgs a = L.sweep;
+  const Grid& g = a.c.grid;
+  a.cpr = (g.nx + 2 * BLOCK - 1) / (2 * BLOCK);
+  const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
+  if (a.c.incomp && !a.c.stokes)
+    k_sweep_h2<1><<<nb, BLOCK, 0, st>>>(a);
+  else
+    k_sweep_h2<0><<<nb, BLOCK, 0, st>>>(a);
+}
+
+hipError_t launch_sweep(const StepLaunch& L, int precision, int rule) {
+  (void)rule;  // the sweep covers liquid cells only; the rule acts in k_iface
+  if (precision == 0) sweep_form<FormF64>(L);
+  else if (precision == 1) sweep_form<FormF32>(L);
+  else if (L.sweep.c.grid.nx % 2 == 0 && L.sweep.pairs) sweep_h2(L);
+  else sweep_form<FormF16>(L);
+  return hipGetLastError();
+}
+
+}  // namespace fslbm
