@@ -218,7 +218,8 @@ def window_dual(params, flags, f0, m0, phi0, u_target, phi_target, T: int, rule:
                 df0=None, dm0=None, dphi0=None, drho_b: float = 0.0, dg=None, want_state: bool = False,
                 f_weight=None):
     """Frozen-topology window of T steps and the loss
-    L = sum over interface cells of |u_T - u*|^2 + (phi_T - phi*)^2
+    L = sum over interface cells of |u_T - u*|^2 + (phi_T - phi*)^2  (left out
+        when u_target and phi_target are None)
         [+ sum over non-gas cells and q of f_weight[q, cell] ft_q(T)],
     with its exact directional derivative along (df0, dm0, dphi0, drho_b, dg)
     from a dual-number run of the oracle.  Returns (L, dL) or, with want_state,
@@ -230,10 +231,11 @@ def window_dual(params, flags, f0, m0, phi0, u_target, phi_target, T: int, rule:
 
     fl = np.ascontiguousarray(flags, dtype=np.uint8)
     f0, m0, phi0 = arr(f0, 19 * N), arr(m0, N), arr(phi0, N)
-    ut, pt = arr(u_target, 3 * N), arr(phi_target, N)
+    ut, pt = arr(u_target, 3 * N), arr(phi_target, N)  # both None: no interface term
     d = [arr(df0, 19 * N), arr(dm0, N), arr(dphi0, N), arr(dg, 3)]
     fw = arr(f_weight, 19 * N)
-    assert f0.size == 19 * N and m0.size == N and phi0.size == N and ut.size == 3 * N and pt.size == N
+    assert f0.size == 19 * N and m0.size == N and phi0.size == N
+    assert (ut is None) == (pt is None) and (ut is None or (ut.size == 3 * N and pt.size == N))
     out2 = np.zeros(2)
     fT = np.empty(19 * N) if want_state else None
     mT = np.empty(N) if want_state else None
@@ -242,7 +244,7 @@ def window_dual(params, flags, f0, m0, phi0, u_target, phi_target, T: int, rule:
     p = _params(params)
     rc = lib().ref_window_dual(ctypes.byref(p), fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                _dptr(f0), _dptr(m0), _dptr(phi0), opt(d[0]), opt(d[1]), opt(d[2]),
-                               float(drho_b), opt(d[3]), int(T), int(rule), _dptr(ut), _dptr(pt), opt(fw), _dptr(out2),
+                               float(drho_b), opt(d[3]), int(T), int(rule), opt(ut), opt(pt), opt(fw), _dptr(out2),
                                opt(fT), opt(mT), opt(pT))
     if rc != 0:
         raise ValueError("oracle window failed: " + lib().ref_create_error().decode())

@@ -191,7 +191,8 @@ void ref_coeffs(void* hp, int rule, double alpha_p, double delta, double* out5) 
 // 19 N values) are given.  The run is
 // made on dual numbers, so next to L it yields dL along the input direction
 // (dft0, dm0, dphi0, drho_b, dg): the exact derivative of the same arithmetic.
-// Any direction pointer may be NULL (no change).  out2 = {L, dL}; fT, mT, phiT
+// Any direction pointer may be NULL (no change); with u_target and phi_target
+// both NULL the interface term is left out.  out2 = {L, dL}; fT, mT, phiT
 // (optional) receive the value part of the final state.  Returns 0, or 1 with
 // the message in ref_create_error().
 int ref_window_dual(const ref_params* rp, const uint8_t* flags, const double* ft0, const double* m0,
@@ -223,7 +224,7 @@ int ref_window_dual(const ref_params* rp, const uint8_t* flags, const double* ft
     s->freeze = true;
     for (int t = 0; t < T; ++t) s->step(rule);
     Dual L(0.0);
-    for (int cell = 0; cell < N; ++cell) {
+    for (int cell = 0; cell < N && u_target && phi_target; ++cell) {
       if (s->type[cell] != fsref::INTERFACE) continue;
       Dual f[fsref::Q], r, u[3];
       for (int q = 0; q < fsref::Q; ++q) f[q] = s->ft[(size_t)q * N + cell];

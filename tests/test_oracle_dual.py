@@ -141,3 +141,16 @@ def test_linear_population_term_vs_central_difference(oracle_mod, case):
     h = 1e-6
     fd = (run(st["f"] + h * d)[0] - run(st["f"] - h * d)[0]) / (2 * h)
     assert abs(fd - dL) <= 1e-6 * abs(dL), (fd, dL)
+
+
+def test_linear_term_alone(oracle_mod, case):
+    """Without targets the loss is the linear functional alone: its derivative
+    along d equals that of the full loss minus that of the interface term."""
+    p, st, ut, pt, rng = case
+    act = st["flags"] != W.GAS
+    a = rng.normal(0.0, 1.0, st["f"].shape) * act
+    d = rng.normal(0.0, 1.0, st["f"].shape) * act
+    run = lambda u, ph, fw: oracle_mod.window_dual(p, st["flags"], st["f"], st["mass"], st["phi"], u, ph,  # noqa
+                                                    T, 1, df0=d, f_weight=fw)[1]
+    lin, full, inter = run(None, None, a), run(ut, pt, a), run(ut, pt, None)
+    assert abs(lin - (full - inter)) <= 1e-9 * (abs(full) + abs(inter))
