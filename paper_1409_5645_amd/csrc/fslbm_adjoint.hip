@@ -15,7 +15,9 @@
 //
 //   k_adj_sweep    liquid cells: pull of time t (for the collision velocity),
 //                  collision adjoint, push.
-//   k_adj_iface    interface cells: forward recompute keeping intermediates;
+//   k_adj_iface    interface cells, four lanes per cell: recompute of the
+//                  exchange, normal and moments of time t (the collision state
+//                  is in the record);
 //                  adjoint of phi = m/rho, of the collision, reconstruction,
 //                  normal and mass exchange; push; own-population and fill
 //                  terms to per-cell scratch.
@@ -46,18 +48,6 @@ __device__ __forceinline__ void cadd(R (&v)[3], R t) {
   if (CY[q] == -1) v[1] = v[1] - t;
   if (CZ[q] == 1) v[2] = v[2] + t;
   if (CZ[q] == -1) v[2] = v[2] - t;
-}
-
-// Adjoint of e+_q(rho, u) = w_q (rho + 4.5 (c_q.u)^2 - 1.5 u.u) for a given
-// eb = dL/de+_q: rb += w_q eb, ub += w_q eb (9 (c_q.u) c_q - 3 u).
-template <int q, class R>
-__device__ __forceinline__ void eplus_adj(R eb, const R (&u)[3], R& rb, R (&ub)[3]) {
-  const R we = R(WD[q]) * eb;
-  rb = rb + we;
-  const R t = R(9.0) * (we * cdot<q>(u));
-  cadd<q>(ub, t);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) ub[a] = ub[a] - R(3.0) * (we * u[a]);
 }
 
 // Adjoint of the TRT collision, Eq. (lbe2), with the force in
@@ -191,274 +181,414 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
 }
 
 // --------------------------------------------------------- interface cells
-// Adjoint of the reconstruction of one gas-side population f_q (see rebuild):
-// r = dL/df_q is spread over the own populations, the pulled f_o, n+_o (and
-// through it rho_t, u_t), e+_o(rho_b, u_t), and, for the FSL rule, the link
-// distance delta = clamp((phi - 1/2)/(c_o.n), 0, 1).
-template <class F, int RULE, int q>
-__device__ __forceinline__ void rebuild_adj(const IfaceData<F>& d, uint32_t gasmask, bool have_n,
-                                            const double (&nv)[3], double dist, typename F::R rho_t,
-                                            const typename F::R (&u_t)[3], typename F::R usq_t,
-                                            const Consts<typename F::R>& k, typename F::R (&fb)[Q],
-                                            typename F::R (&ownb)[Q], double (&nvb)[3], double& distb,
-                                            typename F::R& rtb, typename F::R (&utb)[3], typename F::R& rbb) {
-  using R = typename F::R;
-  if (!((gasmask >> q) & 1u)) return;
-  constexpr int o = OPP[q];
-  const R r = fb[q];
-  fb[q] = R(0.0);  // reconstructed, not pulled: nothing to push
-  R ebb = R(0.0);  // dL/de+_o(rho_b, u_t)
-  bool fsl = false;
-  if (RULE == 1 && have_n && !((gasmask >> o) & 1u)) {
-    double nc = 0.0;
-    if (CX[o] == 1) nc = nc + nv[0];
-    if (CX[o] == -1) nc = nc - nv[0];
-    if (CY[o] == 1) nc = nc + nv[1];
-    if (CY[o] == -1) nc = nc - nv[1];
-    if (CZ[o] == 1) nc = nc + nv[2];
-    if (CZ[o] == -1) nc = nc - nv[2];
-    if (nc > 0.0) {
-      fsl = true;
-      const double raw = dist / nc;
-      double dl = raw;
-      if (dl < 0.0) dl = 0.0;
-      if (dl > 1.0) dl = 1.0;
-      const bool inside = !(raw < 0.0) && !(raw > 1.0);
-      const R delta = (R)dl;
-      const R own_o = d.own[o], own_q = d.own[q];
-      const R e_o_t = e_plus<o>(rho_t, R(1.0), true, false, u_t, usq_t);
-      const R n_plus = (R(0.5) * (own_o + own_q) - e_o_t) * k.inv1p;
-      const R a0 = R(1.0) - (R(0.5) + delta);
-      const R a1 = delta - R(1.0);
-      const R Cc = k.lp * (R(0.5) + delta) - R(2.0) * k.lp;
-      // f_q = a0 ft_o + ft_q / 2 + a1 f_o + C n+_o + e+_o(rho_b, u_t)
-      ownb[o] = ownb[o] + a0 * r;
-      ownb[q] = ownb[q] + R(0.5) * r;
-      fb[o] = fb[o] + a1 * r;
-      ebb = r;
-      const R npb = Cc * r;
-      // da0/ddelta = -1, da1/ddelta = 1, dC/ddelta = lambda_+
-      const R deltab = r * ((d.f[o] - own_o) + k.lp * n_plus);
-      // n+_o = ((ft_o + ft_q)/2 - e+_o(rho_t, u_t)) / (1 + lambda_+)
-      const R hb = R(0.5) * (k.inv1p * npb);
-      ownb[o] = ownb[o] + hb;
-      ownb[q] = ownb[q] + hb;
-      eplus_adj<o>(-(k.inv1p * npb), u_t, rtb, utb);
-      if (inside) {
-        distb += (double)deltab / nc;
-        const double ncb = -(double)deltab * raw / nc;
-        if (CX[o] == 1) nvb[0] += ncb;
-        if (CX[o] == -1) nvb[0] -= ncb;
-        if (CY[o] == 1) nvb[1] += ncb;
-        if (CY[o] == -1) nvb[1] -= ncb;
-        if (CZ[o] == 1) nvb[2] += ncb;
-        if (CZ[o] == -1) nvb[2] -= ncb;
-      }
-    }
+// Four lanes per interface cell (a quad).  The 18 moving links form 9 pairs of
+// opposites (q, q+1), q odd; lane s of the quad owns pairs s and s + 4, lane 0
+// also pair 8 and lane 1 the rest link.  The reconstruction of a gas-side f_q
+// involves only q and its opposite, and the mass exchange of link q only q and
+// its opposite, so all per-link work of a pair stays in its lane.  Sums over
+// the links (moments, mass change, collision and reconstruction adjoints) are
+// per-lane partial sums combined across the quad by two DPP exchanges, which
+// leave the same bits in all four lanes.
+constexpr int QUAD = 4;
+constexpr int PAIRS = 9;
+constexpr int CELLS_PER_BLOCK = AIBLOCK / QUAD;
+
+// direction of the odd link 2p + 1 of every pair p, 6 bits per pair
+constexpr uint64_t pack_pair_dirs() {
+  uint64_t c = 0;
+  for (int p = 0; p < PAIRS; ++p) {
+    const int q = 2 * p + 1;
+    c |= (uint64_t)((CX[q] + 1) | ((CY[q] + 1) << 2) | ((CZ[q] + 1) << 4)) << (6 * p);
   }
-  if (!fsl) {  // FSK: f_q = -ft_o + 2 e+_o(rho_b, u_t)
-    ownb[o] = ownb[o] - r;
-    ebb = R(2.0) * r;
-  }
-  R ub[3] = {R(0.0), R(0.0), R(0.0)};
-  R rb = R(0.0);
-  eplus_adj<o>(ebb, u_t, rb, ub);  // rb: dL/drho_b; ub: dL/du_t (u_b = u_t)
-  rbb = rbb + rb;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) utb[a] = utb[a] + ub[a];
+  return c;
+}
+constexpr uint64_t PAIR_DIRS = pack_pair_dirs();
+static_assert(WD[1] == WD[6] && WD[7] == WD[18], "axis and diagonal weights");
+
+__device__ __forceinline__ void pair_dir(int p, int (&d)[3]) {
+  const unsigned c = (unsigned)(PAIR_DIRS >> (6 * p)) & 63u;
+  d[0] = (int)(c & 3u) - 1;
+  d[1] = (int)((c >> 2) & 3u) - 1;
+  d[2] = (int)(c >> 4) - 1;
 }
 
-// adjoint v of the fill value seen through link q (used by the normal)
-template <class F>
-__device__ __forceinline__ void seen_adj(const IfaceData<F>& d, int q, double v, double (&geo)[6], double& phis) {
-  if (d.ty[q] == IFACE) geo[q - 1] += v;
-  else if (d.ty[q] == WALL_CLASS) phis += v;  // beyond a wall the cell's own fill is used
+// d . v for a direction with components in {-1, 0, 1}
+template <class R>
+__device__ __forceinline__ R ddot(const R (&d)[3], const R (&v)[3]) {
+  return (d[0] * v[0] + d[1] * v[1]) + d[2] * v[2];
+}
+__device__ __forceinline__ double ddot(const int (&d)[3], const double (&v)[3]) {
+  return ((double)d[0] * v[0] + (double)d[1] * v[1]) + (double)d[2] * v[2];
+}
+
+// quad_perm DPP controls: lanes (1,0,3,2) and (2,3,0,1) of each quad
+constexpr int QP_XOR1 = 0xB1;
+constexpr int QP_XOR2 = 0x4E;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t qperm(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double qperm(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t r = (uint64_t)qperm<CTRL>((uint32_t)b) | ((uint64_t)qperm<CTRL>((uint32_t)(b >> 32)) << 32);
+  return __longlong_as_double((long long)r);
+}
+template <int CTRL>
+__device__ __forceinline__ float qperm(float v) {
+  return __uint_as_float(qperm<CTRL>(__float_as_uint(v)));
+}
+// (v0 + v1) + (v2 + v3) in every lane of the quad (addition is commutative in
+// IEEE arithmetic, so the four lanes agree bit for bit); the whole quad must be
+// active
+template <class T>
+__device__ __forceinline__ T quad_sum(T v) {
+  v = v + qperm<QP_XOR1>(v);
+  return v + qperm<QP_XOR2>(v);
 }
 
 template <class F, int RULE>
 __global__ __launch_bounds__(AIBLOCK) void k_adj_iface(AdjArgs a) {
   using R = typename F::R;
-  constexpr bool SH = F::shifted;
   const Grid g = a.c.grid;
   const unsigned N = (unsigned)g.N;
   const unsigned cap = (unsigned)a.cap;
   const R* __restrict__ rf = reinterpret_cast<const R*>(a.rec_f);
   const R* __restrict__ ro = reinterpret_cast<const R*>(a.rec_own);
+  const R* __restrict__ ru = reinterpret_cast<const R*>(a.rec_u);
   const R* __restrict__ lin = reinterpret_cast<const R*>(a.lam_in);
   R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
   R* __restrict__ own_t = reinterpret_cast<R*>(a.own);
   const Consts<R>& k = pick_consts<R>(a.c);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dL/drho_b, dL/dg
-  for (int i = blockIdx.x * AIBLOCK + threadIdx.x; i < a.n_i; i += gridDim.x * AIBLOCK) {
+  const int sub = (int)threadIdx.x & (QUAD - 1);
+  const int nsl = sub == 0 ? 3 : 2;  // pairs of this lane
+  const bool rest = sub == 1;        // lane with the rest link
+  const bool lead = sub == 0;        // lane that stores the cell's scalars
+  int pp[3], dI[3][3];
+  R dR[3][3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    pp[s] = s == 2 ? PAIRS - 1 : sub + 4 * s;
+    pair_dir(pp[s], dI[s]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dR[s][c] = R(dI[s][c]);
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dL/drho_b, dL/dg (lead lanes)
+  for (int i = (int)(blockIdx.x * CELLS_PER_BLOCK) + ((int)threadIdx.x >> 2); i < a.n_i;
+       i += (int)gridDim.x * CELLS_PER_BLOCK) {
     const int idx = a.listI[i];
     const unsigned ui = (unsigned)i;
-    Nbr n;
-    coords(g, idx, n.x, n.y, n.z);
-    n.xm = step_axis(n.x, -1, g.nx, g.px);
-    n.xp = step_axis(n.x, 1, g.nx, g.px);
-    n.ym = step_axis(n.y, -1, g.ny, g.py);
-    n.yp = step_axis(n.y, 1, g.ny, g.py);
-    n.zm = step_axis(n.z, -1, g.nz, g.pz);
-    n.zp = step_axis(n.z, 1, g.nz, g.pz);
-    // ---- loads: the step's record at this cell (list order: coalesced), the
-    // classes of the pull sources, the fill of interface sources
-    IfaceData<F> d;
-    unsigned off[Q];  // 19 N < 2^32 is checked at init
+    int x, y, z;
+    coords(g, idx, x, y, z);
+    // ---- loads: the cell's scalars (all four lanes) and the lane's pairs, from
+    // the step's record (list order) and the fixed topology
     const uint64_t cls = a.ncls[i];
-    d.phix = a.rec_phi[i];
-    d.m = a.rec_m[i];
-    off[0] = (unsigned)idx;
-    d.f[0] = rf[ui];
-    d.own[0] = ro[ui];
-    d.ty[0] = IFACE;
-    d.ph[0] = 0.0;
-#define FSLBM_AILOAD(q)                                                                 \
-  {                                                                                     \
-    const int s = pull_source<q>(g, n);                                                 \
-    off[q] = s >= 0 ? (unsigned)q * N + (unsigned)s : (unsigned)OPP[q] * N + (unsigned)idx; \
-    d.f[q] = rf[(unsigned)q * cap + ui];                                                \
-    d.own[q] = ro[(unsigned)q * cap + ui];                                              \
-    const unsigned c2 = (unsigned)(cls >> (2 * q)) & 3u;                                \
-    d.ty[q] = c2 == 0 ? GAS : (c2 == 1 ? IFACE : (c2 == 2 ? LIQ : WALL_CLASS));         \
-    d.ph[q] = a.rec_phi[a.nslot[(unsigned)q * cap + ui]];                               \
-    if (c2 == 3) d.ph[q] = d.phix;                                                      \
-  }
-    FSLBM_LINKS(FSLBM_AILOAD)
-#undef FSLBM_AILOAD
+    const double phix = a.rec_phi[i];
+    const double m0 = a.rec_m[i];
     const double lam_m = a.lam_m[idx];
     const double lam_p = a.lphi_in[idx];
-
-    // ---- forward recompute (the step's own arithmetic, intermediates kept)
-    uint32_t gasmask = 0;
-    double dm = 0.0;
-#define FSLBM_AEXCH(q)                                             \
-  {                                                                \
-    const uint8_t ts = d.ty[q];                                    \
-    if (ts == GAS) gasmask |= 1u << q;                             \
-    if (ts == LIQ || ts == IFACE) {                                \
-      const double diff = (double)d.f[q] - (double)d.own[OPP[q]];  \
-      if (ts == LIQ) {                                             \
-        dm = dm + diff;                                            \
-      } else {                                                     \
-        const double wgt = 0.5 * (d.phix + d.ph[q]);               \
-        dm = dm + wgt * diff;                                      \
-      }                                                            \
-    }                                                              \
-  }
-    FSLBM_LINKS(FSLBM_AEXCH)
-#undef FSLBM_AEXCH
-    const double m_new = d.m + dm;
-    const double dist = d.phix - 0.5;
-    double nv[3] = {0.0, 0.0, 0.0};
-    double nrm = 0.0;
-    bool have_n = false;
-    // (no branch on gasmask around the gas-link work: every per-link step below
-    // tests its own link, so a cell without gas links passes through unchanged)
-    R rho_t, u_t[3], usq_t;
-    {
-      const double gx = 0.5 * (phi_seen(d, 2) - phi_seen(d, 1));
-      const double gy = 0.5 * (phi_seen(d, 4) - phi_seen(d, 3));
-      const double gz = 0.5 * (phi_seen(d, 6) - phi_seen(d, 5));
-      const double nrm2 = (gx * gx + gy * gy) + gz * gz;
-      have_n = nrm2 > 0.0;
-      if (have_n) {
-        nrm = sqrt(nrm2);
-        nv[0] = -gx / nrm;
-        nv[1] = -gy / nrm;
-        nv[2] = -gz / nrm;
-      }
-      recover_moments<R, SH>(d.own, k, true, rho_t, u_t);
-      usq_t = usq_of(u_t);
-#define FSLBM_AREBUILD(q) \
-  rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, R(1.0), u_t, usq_t, k, true, false);
-      FSLBM_LINKS(FSLBM_AREBUILD)
-#undef FSLBM_AREBUILD
-    }
-    R rho_s, jj[3];
-    moments(d.f, rho_s, jj);
-    const R u[3] = {jj[0] + k.hg[0], jj[1] + k.hg[1], jj[2] + k.hg[2]};
-    const double rho = SH ? 1.0 + (double)rho_s : (double)rho_s;
-    const double phi_new = m_new / rho;
-    R ob[Q];
+    const double rho = a.rec_rho[i];
+    const R u[3] = {ru[ui], ru[cap + ui], ru[2u * cap + ui]};
+    R f[3][2], own[3][2], ob[3][2];
+    int ty[3][2];
+    double ph[3][2];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) ob[q] = lin[(unsigned)q * N + (unsigned)idx];
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        f[s][h] = own[s][h] = ob[s][h] = R(0.0);
+        ty[s][h] = GAS;
+        ph[s][h] = 0.0;
+        if (s < nsl) {
+          const unsigned L = 2u * (unsigned)pp[s] + 1u + (unsigned)h;
+          f[s][h] = rf[L * cap + ui];
+          own[s][h] = ro[L * cap + ui];
+          ob[s][h] = lin[L * N + (unsigned)idx];
+          ty[s][h] = (int)(cls >> (2 * L)) & 3;  // 0 gas, 1 interface, 2 liquid, 3 beyond a wall
+          ph[s][h] = ty[s][h] == WALL_CLASS ? phix : a.rec_phi[a.nslot[L * cap + ui]];
+        }
+      }
+    const R own0 = rest ? ro[ui] : R(0.0);
+    const R ob0 = rest ? lin[idx] : R(0.0);
+
+    // ---- forward recompute of what the reverse steps need (the collision's
+    // velocity and density come from the record)
+    // mass exchange: dm = sum_q w (f_q(pulled) - ft_qbar), w = 1 liquid, (phi_x + phi_s)/2 interface
+    double dm = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = ty[s][h];
+        if (s < nsl && (t == LIQ || t == IFACE)) {
+          const double diff = (double)f[s][h] - (double)own[s][1 - h];
+          dm = dm + (t == LIQ ? diff : (0.5 * (phix + ph[s][h])) * diff);
+        }
+      }
+    dm = quad_sum(dm);
+    const double m_new = m0 + dm;
+    // normal n = -grad(phi)/|grad(phi)|, central differences over the axis pull
+    // sources (pairs 0, 1, 2 are the x, y, z axes: link 2p+2 sees x + e_p)
+    auto seen = [&](int s, int h) -> double {
+      return ty[s][h] == LIQ ? 1.0 : (ty[s][h] == GAS ? 0.0 : ph[s][h]);
+    };
+    double gr[3] = {0.0, 0.0, 0.0};
+    {
+      const double ga = sub < 3 ? 0.5 * (seen(0, 1) - seen(0, 0)) : 0.0;
+      gr[0] = quad_sum(sub == 0 ? ga : 0.0);
+      gr[1] = quad_sum(sub == 1 ? ga : 0.0);
+      gr[2] = quad_sum(sub == 2 ? ga : 0.0);
+    }
+    const double nrm2 = (gr[0] * gr[0] + gr[1] * gr[1]) + gr[2] * gr[2];
+    const bool have_n = nrm2 > 0.0;
+    double nrm = 0.0, nv[3] = {0.0, 0.0, 0.0};
+    if (have_n) {
+      nrm = sqrt(nrm2);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nv[c] = -gr[c] / nrm;
+    }
+    const double dist = phix - 0.5;
+    // moments of time t from the own populations: rho_t = sum ft, u_t = (sum c ft - g) + g/2
+    R rho_t, u_t[3];
+    {
+      R rs = own0, js[3] = {R(0.0), R(0.0), R(0.0)};
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
+        if (s < nsl) {
+          rs = rs + (own[s][0] + own[s][1]);
+          const R dl = own[s][0] - own[s][1];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) js[c] = js[c] + dR[s][c] * dl;
+        }
+      rho_t = quad_sum(rs);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u_t[c] = (quad_sum(js[c]) - k.g[c]) + k.hg[c];
+    }
+    const R usq_t = usq_of(u_t);
+    const double phi_new = m_new / rho;
 
     // ---- adjoint
     // phi(t+1) = m(t+1) / rho: dL/dm(t+1) and the density term of the collision
     const double mb = lam_m + lam_p / rho;
     const double rho_b_phi = -lam_p * phi_new / rho;
-    R fb[Q], gb[3];
-    collide_adjoint(ob, u, (R)rho_b_phi, k, fb, gb);
-    R ownb[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) ownb[q] = R(0.0);
-    double geo[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // fill adjoint of the axis pull sources
-    double phis = 0.0;                                // fill adjoint of the cell itself
-    R rbb = R(0.0);                                   // dL/drho_b
+    // collision, Eq. (lbe2): out_q = f_q + lambda_+ n+ + lambda_- n-, with
+    // n+- = (f_q +- f_qbar)/2 - e+-_q and u = U + g/2, u_eq = U - g/lambda_-
+    R fb[3][2], hp[3], hm[3], gb[3];
+    R fb0;
     {
-      double nvb[3] = {0.0, 0.0, 0.0}, distb = 0.0;
-      R rtb = R(0.0), utb[3] = {R(0.0), R(0.0), R(0.0)};
-#define FSLBM_AREBADJ(q) \
-  rebuild_adj<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, u_t, usq_t, k, fb, ownb, nvb, distb, rtb, utb, rbb);
-      FSLBM_LINKS(FSLBM_AREBADJ)
-#undef FSLBM_AREBADJ
-      if (RULE == 1 && have_n) {
-        // n = -grad/|grad|: dL/dgrad = (-nb + n (nb.n)) / |grad|
-        const double nd = (nvb[0] * nv[0] + nvb[1] * nv[1]) + nvb[2] * nv[2];
-        const double gbx = (-nvb[0] + nv[0] * nd) / nrm;
-        const double gby = (-nvb[1] + nv[1] * nd) / nrm;
-        const double gbz = (-nvb[2] + nv[2] * nd) / nrm;
-        // grad_x = (phi(x+1) - phi(x-1))/2: pull sources of links 2 and 1, etc.
-        seen_adj(d, 2, 0.5 * gbx, geo, phis);
-        seen_adj(d, 1, -0.5 * gbx, geo, phis);
-        seen_adj(d, 4, 0.5 * gby, geo, phis);
-        seen_adj(d, 3, -0.5 * gby, geo, phis);
-        seen_adj(d, 6, 0.5 * gbz, geo, phis);
-        seen_adj(d, 5, -0.5 * gbz, geo, phis);
+      R rb = rest ? R(WD[0]) * (-(k.lp * ob0)) : R(0.0);
+      R s9[3] = {R(0.0), R(0.0), R(0.0)}, ue[3] = {R(0.0), R(0.0), R(0.0)};
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        hp[s] = hm[s] = R(0.0);
+        if (s < nsl) {
+          const R w = pp[s] < 3 ? R(WD[1]) : R(WD[7]);
+          const R w3 = pp[s] < 3 ? R(W3D[1]) : R(W3D[7]);
+          const R np_b = k.lp * (ob[s][0] + ob[s][1]);
+          const R nm_b = k.lm * (ob[s][0] - ob[s][1]);
+          const R we = w * (-np_b);
+          rb = rb + we;
+          const R t9 = we * ddot(dR[s], u);
+          const R te = w3 * (-nm_b);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            s9[c] = s9[c] + dR[s][c] * t9;
+            ue[c] = ue[c] + dR[s][c] * te;
+          }
+          hp[s] = R(0.5) * np_b;
+          hm[s] = R(0.5) * nm_b;
+        }
       }
-      phis += distb;  // dist = phi - 1/2
-      // rho_t = sum_q ft_q, u_t = (sum_q c_q ft_q - g) + g/2
-#define FSLBM_ARECOV(q) ownb[q] = ownb[q] + (rtb + cdot<q>(utb));
-      FSLBM_ARECOV(0)
-      FSLBM_LINKS(FSLBM_ARECOV)
-#undef FSLBM_ARECOV
+      rb = quad_sum(rb);
+      R jb[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) gb[c] = gb[c] - R(0.5) * utb[c];
+      for (int c = 0; c < 3; ++c) {
+        s9[c] = quad_sum(s9[c]);
+        ue[c] = quad_sum(ue[c]);
+        const R ub = R(9.0) * s9[c] - R(3.0) * (u[c] * rb);  // dL/du
+        jb[c] = ub + ue[c];                                   // u and u_eq both move with U = j
+        gb[c] = R(0.5) * ub - ue[c] * k.ilm;                  // u = U + g/2, u_eq = U - g/lambda_-
+      }
+      const R rt = rb + (R)rho_b_phi;
+      fb0 = (R(1.0) + k.lp) * ob0 + rt;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const R cj = ddot(dR[s], jb);
+        fb[s][0] = ((ob[s][0] + hp[s]) + hm[s]) + (rt + cj);
+        fb[s][1] = ((ob[s][1] + hp[s]) - hm[s]) + (rt - cj);
+      }
     }
-    // mass exchange: m(t+1) = m + sum_q w_q (f_q(pulled) - ft_qbar), w = 1 or (phi_x + phi_s)/2
-#define FSLBM_AEXADJ(q)                                                               \
-  {                                                                                   \
-    const uint8_t ts = d.ty[q];                                                       \
-    double pc = (q <= 6) ? geo[(q <= 6 ? q : 1) - 1] : 0.0;                           \
-    if (ts == LIQ || ts == IFACE) {                                                   \
-      const double w = ts == LIQ ? 1.0 : 0.5 * (d.phix + d.ph[q]);                    \
-      const R wm = (R)(w * mb);                                                       \
-      fb[q] = fb[q] + wm;                                                             \
-      ownb[OPP[q]] = ownb[OPP[q]] - wm;                                               \
-      if (ts == IFACE) {                                                              \
-        const double half = 0.5 * ((double)d.f[q] - (double)d.own[OPP[q]]) * mb;     \
-        phis += half;                                                                 \
-        pc += half;                                                                   \
-      }                                                                               \
-    }                                                                                 \
-    a.phic[(unsigned)q * cap + ui] = pc;                                              \
-  }
-    FSLBM_LINKS(FSLBM_AEXADJ)
-#undef FSLBM_AEXADJ
+    // reconstruction of the gas-side populations (see rebuild): the adjoint r
+    // of a rebuilt f_q is spread over the own populations, the pulled f_o,
+    // n+_o (and through it rho_t, u_t), e+_o(rho_b, u_t) and, for the FSL rule,
+    // the link distance delta = clamp((phi - 1/2)/(c_o.n), 0, 1)
+    R ownb[3][2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) ownb[s][0] = ownb[s][1] = R(0.0);
+    R ownb0 = R(0.0);
+    double nvb[3] = {0.0, 0.0, 0.0}, distb = 0.0;
+    R rtb = R(0.0), utb[3] = {R(0.0), R(0.0), R(0.0)}, rbb = R(0.0);
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (!(s < nsl && ty[s][h] == GAS)) continue;
+        const int o = 1 - h;                    // the opposite link o = qbar, in the same pair
+        const R sgo = h == 0 ? R(-1.0) : R(1.0);  // c_o = sgo * (direction of the pair's odd link)
+        R cob[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cob[c] = sgo * dR[s][c];
+        const R w = pp[s] < 3 ? R(WD[1]) : R(WD[7]);
+        const R r = fb[s][h];
+        fb[s][h] = R(0.0);  // reconstructed, not pulled: nothing to push
+        R ebb = R(0.0);     // dL/de+_o(rho_b, u_t)
+        bool fsl = false;
+        if (RULE == 1 && have_n && ty[s][o] != GAS) {
+          const double nc = h == 0 ? -ddot(dI[s], nv) : ddot(dI[s], nv);
+          if (nc > 0.0) {
+            fsl = true;
+            const double raw = dist / nc;
+            double dl = raw;
+            if (dl < 0.0) dl = 0.0;
+            if (dl > 1.0) dl = 1.0;
+            const bool inside = !(raw < 0.0) && !(raw > 1.0);
+            const R delta = (R)dl;
+            const R own_o = own[s][o], own_q = own[s][h];
+            const R cu = ddot(cob, u_t);
+            const R e_o_t = w * (rho_t + (R(4.5) * (cu * cu) - R(1.5) * usq_t));
+            const R n_plus = (R(0.5) * (own_o + own_q) - e_o_t) * k.inv1p;
+            const R a0 = R(1.0) - (R(0.5) + delta);
+            const R a1 = delta - R(1.0);
+            const R Cc = k.lp * (R(0.5) + delta) - R(2.0) * k.lp;
+            // f_q = a0 ft_o + ft_q / 2 + a1 f_o + C n+_o + e+_o(rho_b, u_t)
+            ownb[s][o] = ownb[s][o] + a0 * r;
+            ownb[s][h] = ownb[s][h] + R(0.5) * r;
+            fb[s][o] = fb[s][o] + a1 * r;
+            ebb = r;
+            const R npb = Cc * r;
+            // da0/ddelta = -1, da1/ddelta = 1, dC/ddelta = lambda_+
+            const R deltab = r * ((f[s][o] - own_o) + k.lp * n_plus);
+            // n+_o = ((ft_o + ft_q)/2 - e+_o(rho_t, u_t)) / (1 + lambda_+)
+            const R hb = R(0.5) * (k.inv1p * npb);
+            ownb[s][o] = ownb[s][o] + hb;
+            ownb[s][h] = ownb[s][h] + hb;
+            {  // adjoint of e+_o(rho_t, u_t) for dL/de = -npb/(1 + lambda_+)
+              const R we = w * (-(k.inv1p * npb));
+              rtb = rtb + we;
+              const R t = R(9.0) * (we * cu);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) utb[c] = (utb[c] + cob[c] * t) - R(3.0) * (we * u_t[c]);
+            }
+            if (inside) {
+              distb += (double)deltab / nc;
+              const double ncb = -(double)deltab * raw / nc;
+              const double so = h == 0 ? -1.0 : 1.0;
+#pragma unroll
+              for (int c = 0; c < 3; ++c) nvb[c] += (so * (double)dI[s][c]) * ncb;
+            }
+          }
+        }
+        if (!fsl) {  // FSK: f_q = -ft_o + 2 e+_o(rho_b, u_t)
+          ownb[s][o] = ownb[s][o] - r;
+          ebb = R(2.0) * r;
+        }
+        {  // adjoint of e+_o(rho_b, u_t): dL/drho_b and dL/du_t (u_b = u_t)
+          const R we = w * ebb;
+          rbb = rbb + we;
+          const R t = R(9.0) * (we * ddot(cob, u_t));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) utb[c] = (utb[c] + cob[c] * t) - R(3.0) * (we * u_t[c]);
+        }
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      nvb[c] = quad_sum(nvb[c]);
+      utb[c] = quad_sum(utb[c]);
+    }
+    distb = quad_sum(distb);
+    rtb = quad_sum(rtb);
+    rbb = quad_sum(rbb);
+    // normal: dL/dgrad = (-nb + n (nb.n)) / |grad|, grad_p = (phi(x+e_p) - phi(x-e_p))/2
+    double geo[2] = {0.0, 0.0};  // fill adjoint of the axis pull sources of pair 0 of this lane
+    double phis = lead ? distb : 0.0;  // fill adjoint of the cell itself (dist = phi - 1/2)
+    if (RULE == 1 && have_n && sub < 3) {
+      const double nd = (nvb[0] * nv[0] + nvb[1] * nv[1]) + nvb[2] * nv[2];
+      const double nvb_a = sub == 0 ? nvb[0] : (sub == 1 ? nvb[1] : nvb[2]);  // axis of this lane's pair 0
+      const double nv_a = sub == 0 ? nv[0] : (sub == 1 ? nv[1] : nv[2]);
+      const double gbp = (-nvb_a + nv_a * nd) / nrm;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double v = h == 1 ? 0.5 * gbp : -0.5 * gbp;
+        if (ty[0][h] == IFACE) geo[h] += v;
+        else if (ty[0][h] == WALL_CLASS) phis += v;  // beyond a wall the cell's own fill is used
+      }
+    }
+    // rho_t = sum_q ft_q, u_t = (sum_q c_q ft_q - g) + g/2
+    ownb0 = ownb0 + rtb;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const R cu = ddot(dR[s], utb);
+      ownb[s][0] = ownb[s][0] + (rtb + cu);
+      ownb[s][1] = ownb[s][1] + (rtb - cu);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gb[c] = gb[c] - R(0.5) * utb[c];
+    // mass exchange: m(t+1) = m + sum_q w_q (f_q(pulled) - ft_qbar)
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (!(s < nsl)) continue;
+        const unsigned L = 2u * (unsigned)pp[s] + 1u + (unsigned)h;
+        const int t = ty[s][h];
+        double pc = s == 0 ? geo[h] : 0.0;
+        if (t == LIQ || t == IFACE) {
+          const double w = t == LIQ ? 1.0 : 0.5 * (phix + ph[s][h]);
+          const R wm = (R)(w * mb);
+          fb[s][h] = fb[s][h] + wm;
+          ownb[s][1 - h] = ownb[s][1 - h] - wm;
+          if (t == IFACE) {
+            const double half = 0.5 * ((double)f[s][h] - (double)own[s][1 - h]) * mb;
+            phis += half;
+            pc += half;
+          }
+        }
+        a.phic[L * cap + ui] = pc;
+      }
+    phis = quad_sum(phis);
 
-    // ---- stores: push of the pulled populations' adjoints, scratch terms
-    lout[off[0]] = fb[0];
-#define FSLBM_APUSH(q) \
-  if (d.ty[q] != GAS) lout[off[q]] = fb[q];
-    FSLBM_LINKS(FSLBM_APUSH)
-#undef FSLBM_APUSH
+    // ---- stores: push of the pulled populations' adjoints (to the element each
+    // pull read), own-population terms, the cell's scalars
 #pragma unroll
-    for (int q = 0; q < Q; ++q) own_t[(unsigned)q * cap + ui] = ownb[q];
-    a.phic[i] = phis;
-    a.lam_m[idx] = mb;
-    acc[0] += (double)rbb;
+    for (int s = 0; s < 3; ++s)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[1 + c] += (double)gb[c];
+      for (int h = 0; h < 2; ++h) {
+        if (!(s < nsl)) continue;
+        const unsigned L = 2u * (unsigned)pp[s] + 1u + (unsigned)h;
+        own_t[L * cap + ui] = ownb[s][h];
+        if (ty[s][h] == GAS) continue;
+        // pull source x - c_L (c_L = +-d for the odd / even link of the pair)
+        const int sg = h == 0 ? -1 : 1;
+        const int sx = step_axis(x, sg * dI[s][0], g.nx, g.px);
+        const int sy = step_axis(y, sg * dI[s][1], g.ny, g.py);
+        const int sz = step_axis(z, sg * dI[s][2], g.nz, g.pz);
+        const unsigned Lo = (L & 1u) ? L + 1u : L - 1u;  // beyond a wall: the cell's own opposite population
+        const unsigned off = ((sx | sy | sz) < 0) ? Lo * N + (unsigned)idx
+                                                  : L * N + (unsigned)(sx + g.nx * (sy + g.ny * sz));
+        lout[off] = fb[s][h];
+      }
+    if (rest) {
+      lout[idx] = fb0;
+      own_t[ui] = ownb0;
+    }
+    if (lead) {
+      a.phic[ui] = phis;
+      a.lam_m[idx] = mb;
+      acc[0] += (double)rbb;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[1 + c] += (double)gb[c];
+    }
   }
   block_accumulate<4, AIBLOCK>(acc, a.part_iface + 4 * (size_t)blockIdx.x);
 }
@@ -654,7 +784,10 @@ static inline unsigned ablocks(size_t n) { return (unsigned)((n + ABLOCK - 1) / 
 unsigned adj_sweep_blocks(const Grid& g) {
   return (unsigned)((g.nx + ABLOCK - 1) / ABLOCK) * (unsigned)g.ny * (unsigned)g.nz;
 }
-unsigned adj_iface_blocks(int n_i) {
+unsigned adj_iface_blocks(int n_i) {  // blocks of the quad kernel (their partial sums are reduced)
+  return std::max(1u, std::min(ADJ_IFACE_GRID, (unsigned)(((size_t)n_i + CELLS_PER_BLOCK - 1) / CELLS_PER_BLOCK)));
+}
+static unsigned adj_iface2_blocks(int n_i) {
   return std::max(1u, std::min(ADJ_IFACE_GRID, (unsigned)(((size_t)n_i + AIBLOCK - 1) / AIBLOCK)));
 }
 unsigned list_blocks(const Grid& g) { return ablocks((size_t)g.N); }
@@ -715,7 +848,7 @@ static void adj_iface_form(const AdjArgs& a, int rule, hipStream_t st) {
 template <class F>
 static void adj_iface2_form(const AdjArgs& a, hipStream_t st) {
   if (a.n_i <= 0) return;
-  k_adj_iface2<F><<<adj_iface_blocks(a.n_i), AIBLOCK, 0, st>>>(a);
+  k_adj_iface2<F><<<adj_iface2_blocks(a.n_i), AIBLOCK, 0, st>>>(a);
 }
 
 hipError_t launch_adj_sweep(const AdjArgs& a, int precision, void* stream) {

@@ -491,6 +491,8 @@ struct fslbm_window {
     void* own;     // [Q][cap] compute type
     double* phi;   // [cap]
     double* m;     // [cap]
+    void* ui;      // [3][cap] compute type: collision velocity of the interface cells
+    double* rho;   // [cap] collision density of the interface cells
   };
   std::vector<State> ckpt;  // states at t = jK
   State hot[2];             // hot[*].m is one shared array (mass is updated in place)
@@ -520,7 +522,7 @@ struct WinLayout {
   // rest
   size_t ckpt, state_bytes, st_m, st_phi;
   size_t hot[2], hot_m;
-  size_t rec, rec_bytes, rc_f, rc_own, rc_phi, rc_m;
+  size_t rec, rec_bytes, rc_f, rc_own, rc_phi, rc_m, rc_ui, rc_rho;
   size_t ncls, nslot, lam[2], lam_m, lphi[2], own, phic, part_sweep, part_iface, grads, aux_rho, aux_u, counters,
       fixed_count, listI_fwd;
   size_t total;
@@ -561,7 +563,9 @@ WinLayout win_layout(const Grid& g, int precision, int T, int K, int n_i) {
   L.rc_own = L.rc_f + align_up(Q * cap * rb);
   L.rc_phi = L.rc_own + align_up(Q * cap * rb);
   L.rc_m = L.rc_phi + align_up(8 * cap);
-  L.rec_bytes = L.rc_m + align_up(8 * cap);
+  L.rc_ui = L.rc_m + align_up(8 * cap);
+  L.rc_rho = L.rc_ui + align_up(3 * cap * rb);
+  L.rec_bytes = L.rc_rho + align_up(8 * cap);
   L.rec = take(L.rec_bytes * (size_t)K);
   L.ncls = take(8 * cap);
   L.nslot = take(4 * Q * cap);
@@ -650,6 +654,8 @@ hipError_t window_step(fslbm_window* w, const fslbm_window::State& A, const fslb
   Li.sweep.rec_own = R.own;
   Li.sweep.rec_phi = R.phi;
   Li.sweep.rec_m = R.m;
+  Li.sweep.rec_u = R.ui;
+  Li.sweep.rec_rho = R.rho;
   Li.sweep.rec_cap = w->cap;
   return launch_iface(Li, w->precision, w->rule);
 }
@@ -769,7 +775,8 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   w->hot[1] = {wsp + L.hot[1], (double*)(wsp + L.hot_m), (double*)(wsp + L.hot_m + 2 * align_up(8 * N))};
   for (int k = 0; k < w->K; ++k) {
     char* b = wsp + L.rec + (size_t)k * L.rec_bytes;
-    w->rec.push_back({b, b + L.rc_f, b + L.rc_own, (double*)(b + L.rc_phi), (double*)(b + L.rc_m)});
+    w->rec.push_back({b, b + L.rc_f, b + L.rc_own, (double*)(b + L.rc_phi), (double*)(b + L.rc_m), b + L.rc_ui,
+                      (double*)(b + L.rc_rho)});
   }
   w->ncls = (uint64_t*)(wsp + L.ncls);
   w->nslot = (int32_t*)(wsp + L.nslot);
@@ -852,6 +859,8 @@ fslbm_status fslbm_window_backward(fslbm_window* w, const double* dL_df, const d
       a.rec_own = R.own;
       a.rec_phi = R.phi;
       a.rec_m = R.m;
+      a.rec_u = R.ui;
+      a.rec_rho = R.rho;
       a.ncls = w->ncls;
       a.nslot = w->nslot;
       a.flags = w->flags;

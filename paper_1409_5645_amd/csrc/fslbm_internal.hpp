@@ -56,11 +56,14 @@ struct SweepArgs {
   void* u_out;  // optional (FP64 / FP32 forms): collision velocity of liquid cells, [3][N] compute type
   // optional per-step record of the interface cells (list order, capacity
   // rec_cap): pulled and own populations of time t (compute type, [Q][cap]),
-  // fill and mass of time t
+  // fill and mass of time t, collision velocity ([3][cap], compute type) and
+  // density of the step
   void* rec_f;
   void* rec_own;
   double* rec_phi;
   double* rec_m;
+  void* rec_u;
+  double* rec_rho;
   int rec_cap;
 };
 
@@ -134,6 +137,8 @@ struct AdjArgs {
   const void* rec_own;    // interface cells: own post-collision populations of time t
   const double* rec_phi;  // interface cells: fill of time t
   const double* rec_m;    // interface cells: mass of time t
+  const void* rec_u;      // interface cells: collision velocity ([3][cap], compute type)
+  const double* rec_rho;  // interface cells: collision density
   // fixed topology of the interface cells (list order)
   const uint64_t* ncls;   // class of the pull source of each link, 2 bits per link (gas, interface, liquid, wall)
   const int32_t* nslot;   // [Q][cap] list position of an interface pull source, else the cell's own

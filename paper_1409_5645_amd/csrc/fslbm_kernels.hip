@@ -165,6 +165,13 @@ __global__ __launch_bounds__(IBLOCK) void k_iface(SweepArgs a) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, d.f[q], a.c.scale);
     const double rho = SH ? 1.0 + (double)rho_s : (double)rho_s;
+    if constexpr (REC) {
+      typename F::R* ru = reinterpret_cast<typename F::R*>(a.rec_u);
+      const unsigned cap = (unsigned)a.rec_cap;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ru[(unsigned)c * cap + (unsigned)i] = u[c];
+      a.rec_rho[i] = rho;
+    }
     a.mass[idx] = m_new;
     a.phi_out[idx] = m_new / rho;
     a.aux_rho[idx] = rho;

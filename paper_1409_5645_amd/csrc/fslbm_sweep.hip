@@ -125,24 +125,30 @@ __device__ __forceinline__ uint32_t h_pack(float a, float b) {
 // Pull of the 19 populations of a lane's cell pair (see k_sweep_h2).  Phase 1
 // issues all loads (19 pairs, 10 wavefront-edge elements); phase 2 shifts and
 // selects, so no load waits on another link's data movement.
+// All addresses are 32-bit byte offsets from the buffer start (the two-cells
+// form is used only while 19 N populations of 2 bytes stay below 2^32 bytes),
+// so the per-link source and edge offsets are a few 32-bit scalar operations
+// and every load is base + 32-bit offset.
 template <bool WALLS>
-__device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const uint16_t* __restrict__ fin,
-                                          const Grid& g, size_t N, const unsigned (&srow)[9], unsigned rbase,
-                                          int xl, int wx0, int wend, bool row_end) {
+__device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const char* __restrict__ fb,
+                                          const Grid& g, unsigned N2, const unsigned (&srow2)[9], unsigned rbase2,
+                                          unsigned xl2, int wx0, int wend, bool row_end) {
   uint32_t p[Q], e[Q];
 #define FSLBM_LOAD2(q)                                                                            \
   {                                                                                               \
-    const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                      \
+    const unsigned ro = srow2[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                     \
     const bool wall = WALLS && ro == WALL_ROW;                                                    \
-    const uint16_t* own_qb = fin + (size_t)OPP[q] * N + rbase;                                    \
-    const uint16_t* src = wall ? own_qb : fin + (size_t)q * N + ro;                               \
-    p[q] = *reinterpret_cast<const uint32_t*>(src + xl);                                          \
+    const unsigned own_qb = (unsigned)OPP[q] * N2 + rbase2;                                       \
+    const unsigned src = wall ? own_qb : (unsigned)q * N2 + ro;                                   \
+    p[q] = *reinterpret_cast<const uint32_t*>(fb + (src + xl2));                                  \
     if (CX[q] == 1) {                                                                             \
-      const uint16_t* ep = wx0 > 0 ? src + (wx0 - 1) : (g.px ? src + (g.nx - 1) : own_qb);        \
-      e[q] = (uint32_t)*ep << 16;                                                                 \
+      const unsigned eo = wx0 > 0 ? src + 2u * (unsigned)(wx0 - 1)                                \
+                                  : (g.px ? src + 2u * (unsigned)(g.nx - 1) : own_qb);            \
+      e[q] = (uint32_t)*reinterpret_cast<const uint16_t*>(fb + eo) << 16;                         \
     } else if (CX[q] == -1) {                                                                     \
-      const uint16_t* ep = wend < g.nx ? src + wend : (g.px ? src : own_qb + (g.nx - 1));         \
-      e[q] = (uint32_t)*ep;                                                                       \
+      const unsigned eo = wend < g.nx ? src + 2u * (unsigned)wend                                 \
+                                      : (g.px ? src : own_qb + 2u * (unsigned)(g.nx - 1));        \
+      e[q] = (uint32_t)*reinterpret_cast<const uint16_t*>(fb + eo);                               \
     }                                                                                             \
   }
   FSLBM_LOAD2(0)
@@ -150,7 +156,7 @@ __device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const 
 #undef FSLBM_LOAD2
 #define FSLBM_SHIFT2(q)                                                                           \
   {                                                                                               \
-    const bool wall = WALLS && srow[(CY[q] + 1) + 3 * (CZ[q] + 1)] == WALL_ROW;                   \
+    const bool wall = WALLS && srow2[(CY[q] + 1) + 3 * (CZ[q] + 1)] == WALL_ROW;                  \
     uint32_t lo = p[q], hi = p[q];                                                                \
     if (CX[q] == 1) {                                                                             \
       /* cell x0 <- x0-1 (lane 0: the edge element as the shift's fill), cell x0+1 <- x0 */       \
@@ -216,8 +222,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   const int wx0 = __builtin_amdgcn_readfirstlane((chunk * BLOCK + ((int)threadIdx.x & ~63)) * 2);
   const int wend = wx0 + 128;
   const bool row_end = xl + 2 == g.nx;  // last pair of the row (its right neighbour is past the row)
-  const size_t N = (size_t)g.N;
-  const uint16_t* __restrict__ fin = reinterpret_cast<const uint16_t*>(a.fin);
+  const unsigned N2 = 2u * (unsigned)g.N;  // bytes per population plane
+  const char* __restrict__ fb = reinterpret_cast<const char*>(a.fin);
+  unsigned srow2[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) srow2[i] = srow[i] == WALL_ROW ? WALL_ROW : 2u * srow[i];
 
   float f0[Q], f1[Q];
   // interior blocks (no source row beyond a y/z wall) take a select-only pull;
@@ -226,9 +235,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
   if (!wall_rows)
-    pull_pair<false>(f0, f1, fin, g, N, srow, rbase, xl, wx0, wend, row_end);
+    pull_pair<false>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end);
   else
-    pull_pair<true>(f0, f1, fin, g, N, srow, rbase, xl, wx0, wend, row_end);
+    pull_pair<true>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end);
 
   // ---- TRT collision, Eq. (lbe2), in storage units
   const Consts<float>& k = a.c.kf;
@@ -238,9 +247,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
   collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
   if (liq) {
-    uint16_t* __restrict__ fout = reinterpret_cast<uint16_t*>(a.fout) + rbase + x0;
+    char* __restrict__ fo = reinterpret_cast<char*>(a.fout);
+    const unsigned o = 2u * (rbase + (unsigned)x0);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fout + (size_t)q * N) = h_pack(f0[q], f1[q]);
+    for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fo + ((unsigned)q * N2 + o)) = h_pack(f0[q], f1[q]);
   }
 }
 
@@ -276,7 +286,8 @@ hipError_t launch_sweep(const StepLaunch& L, int precision, int rule) {
   (void)rule;  // the sweep covers liquid cells only; the rule acts in k_iface
   if (precision == 0) sweep_form<FormF64>(L);
   else if (precision == 1) sweep_form<FormF32>(L);
-  else if (L.sweep.c.grid.nx % 2 == 0 && L.sweep.pairs) sweep_h2(L);
+  else if (L.sweep.c.grid.nx % 2 == 0 && L.sweep.pairs && 38.0 * (double)L.sweep.c.grid.N < 4294967296.0)
+    sweep_h2(L);
   else sweep_form<FormF16>(L);
   return hipGetLastError();
 }
