@@ -24,14 +24,15 @@
 //   k_adj_iface2   interface cells: add the own-population terms (set them where
 //                  the pull that reads the element comes from gas) and gather the
 //                  fill adjoint from the cell and its interface neighbours.
-// Parameter gradients (dL/drho_b, dL/dg) are summed per block in FP64 into
-// fixed slots and reduced at the end in a fixed order: a run is reproducible
+// Parameter gradients (dL/drho_b, dL/dg) are summed per wavefront or block in
+// FP64 into fixed slots and reduced at the end in a fixed order: a run is reproducible
 // bit for bit.
 #include "fslbm_device.hpp"
 #include "fslbm_internal.hpp"
 #include "fslbm_stencil.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace fslbm {
 
@@ -101,6 +102,53 @@ __device__ __forceinline__ void collide_adjoint(const R (&ob)[Q], const R (&u)[3
 #undef FSLBM_FADJ
 }
 
+// quad_perm DPP controls: lanes (1,0,3,2) and (2,3,0,1) of each quad
+constexpr int QP_XOR1 = 0xB1;
+constexpr int QP_XOR2 = 0x4E;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t qperm(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double qperm(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t r = (uint64_t)qperm<CTRL>((uint32_t)b) | ((uint64_t)qperm<CTRL>((uint32_t)(b >> 32)) << 32);
+  return __longlong_as_double((long long)r);
+}
+template <int CTRL>
+__device__ __forceinline__ float qperm(float v) {
+  return __uint_as_float(qperm<CTRL>(__float_as_uint(v)));
+}
+// (v0 + v1) + (v2 + v3) in every lane of the quad (addition is commutative in
+// IEEE arithmetic, so the four lanes agree bit for bit); the whole quad must be
+// active
+template <class T>
+__device__ __forceinline__ T quad_sum(T v) {
+  v = v + qperm<QP_XOR1>(v);
+  return v + qperm<QP_XOR2>(v);
+}
+
+// row_ror:4 and row_ror:8: lane i of a row of 16 receives lane (i - 4) mod 16, (i - 8) mod 16
+constexpr int DPP_ROW_ROR4 = 0x124;
+constexpr int DPP_ROW_ROR8 = 0x128;
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum of v over the wavefront in a fixed order (quads, rows of 16, then the
+// four rows), the same value in every lane; all 64 lanes must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = quad_sum(v);
+  v = v + qperm<DPP_ROW_ROR4>(v);
+  v = v + qperm<DPP_ROW_ROR8>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Sum of v over the block (wavefront shuffles, then the 4 wavefronts in
 // order), added by thread 0 to slot[0..NV).  Every thread of the block calls it.
 template <int NV, int BS>
@@ -128,9 +176,20 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NV], double* slot) 
 // Same row mapping and pull offsets as the forward sweep; the push writes the
 // adjoint of each pulled value to the offset the pull read.  The collision
 // adjoint needs only the collision velocity, which the forward step stored.
-template <class F>
+// OFF32: every population plane array is below 4 GiB, so elements are reached
+// as base + 32-bit byte offset (one VALU op less per access).
+template <class F, bool OFF32>
 __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
   using R = typename F::R;
+  auto elem = [](auto* base, unsigned e) -> auto& {
+    if constexpr (OFF32)
+      return *reinterpret_cast<std::remove_pointer_t<decltype(base)>*>(
+          reinterpret_cast<std::conditional_t<std::is_const_v<std::remove_pointer_t<decltype(base)>>, const char*,
+                                              char*>>(base) +
+          e * (unsigned)sizeof(R));
+    else
+      return base[e];
+  };
   const Grid g = a.c.grid;
   const int row = (int)blockIdx.x / a.cpr;
   const int chunk = (int)blockIdx.x - row * a.cpr;
@@ -139,7 +198,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
   const bool liq = t == LIQ;
-  if (!__syncthreads_or(liq)) return;  // the whole block leaves together
+  if (__ballot(liq) == 0) return;  // whole wavefronts leave together (the sum below exchanges lanes)
   double gs[3] = {0.0, 0.0, 0.0};
   if (liq) {
     const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
@@ -162,22 +221,30 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
     const int sx = CX[q] == 1 ? xm : (CX[q] == -1 ? xp : x);                                      \
     off[q] = (ro == WALL_ROW || sx < 0) ? (unsigned)OPP[q] * N + rbase + (unsigned)x              \
                                         : (unsigned)q * N + ro + (unsigned)sx;                    \
-    ob[q] = lin[(unsigned)q * N + rbase + (unsigned)x];                                           \
+    ob[q] = elem(lin, (unsigned)q * N + rbase + (unsigned)x);                                     \
   }
     FSLBM_APULL(0)
     FSLBM_LINKS(FSLBM_APULL)
 #undef FSLBM_APULL
     const Consts<R>& k = pick_consts<R>(a.c);
-    const R u[3] = {un[rbase + (unsigned)x], un[N + rbase + (unsigned)x], un[2u * N + rbase + (unsigned)x]};
+    const R u[3] = {elem(un, rbase + (unsigned)x), elem(un, N + rbase + (unsigned)x),
+                    elem(un, 2u * N + rbase + (unsigned)x)};
     R fb[Q], gb[3];
     collide_adjoint(ob, u, R(0.0), k, fb, gb);
     R* __restrict__ lout = reinterpret_cast<R*>(a.lam_out);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lout[off[q]] = fb[q];
+    for (int q = 0; q < Q; ++q) elem(lout, off[q]) = fb[q];
 #pragma unroll
     for (int i = 0; i < 3; ++i) gs[i] = (double)gb[i];
   }
-  block_accumulate<3, ABLOCK>(gs, a.part_sweep + 3 * (size_t)blockIdx.x);
+  // dL/dg of the wavefront, added to its own slot
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gs[c] = wave_sum(gs[c]);
+  if ((threadIdx.x & 63) == 0) {
+    double* slot = a.part_sweep + 3 * ((size_t)blockIdx.x * (ABLOCK / 64) + (threadIdx.x >> 6));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) slot[c] += gs[c];
+  }
 }
 
 // --------------------------------------------------------- interface cells
@@ -219,33 +286,6 @@ __device__ __forceinline__ R ddot(const R (&d)[3], const R (&v)[3]) {
 }
 __device__ __forceinline__ double ddot(const int (&d)[3], const double (&v)[3]) {
   return ((double)d[0] * v[0] + (double)d[1] * v[1]) + (double)d[2] * v[2];
-}
-
-// quad_perm DPP controls: lanes (1,0,3,2) and (2,3,0,1) of each quad
-constexpr int QP_XOR1 = 0xB1;
-constexpr int QP_XOR2 = 0x4E;
-
-template <int CTRL>
-__device__ __forceinline__ uint32_t qperm(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
-}
-template <int CTRL>
-__device__ __forceinline__ double qperm(double v) {
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint64_t r = (uint64_t)qperm<CTRL>((uint32_t)b) | ((uint64_t)qperm<CTRL>((uint32_t)(b >> 32)) << 32);
-  return __longlong_as_double((long long)r);
-}
-template <int CTRL>
-__device__ __forceinline__ float qperm(float v) {
-  return __uint_as_float(qperm<CTRL>(__float_as_uint(v)));
-}
-// (v0 + v1) + (v2 + v3) in every lane of the quad (addition is commutative in
-// IEEE arithmetic, so the four lanes agree bit for bit); the whole quad must be
-// active
-template <class T>
-__device__ __forceinline__ T quad_sum(T v) {
-  v = v + qperm<QP_XOR1>(v);
-  return v + qperm<QP_XOR2>(v);
 }
 
 template <class F, int RULE>
@@ -784,6 +824,7 @@ static inline unsigned ablocks(size_t n) { return (unsigned)((n + ABLOCK - 1) / 
 unsigned adj_sweep_blocks(const Grid& g) {
   return (unsigned)((g.nx + ABLOCK - 1) / ABLOCK) * (unsigned)g.ny * (unsigned)g.nz;
 }
+unsigned adj_sweep_slots(const Grid& g) { return adj_sweep_blocks(g) * (ABLOCK / 64); }
 unsigned adj_iface_blocks(int n_i) {  // blocks of the quad kernel (their partial sums are reduced)
   return std::max(1u, std::min(ADJ_IFACE_GRID, (unsigned)(((size_t)n_i + CELLS_PER_BLOCK - 1) / CELLS_PER_BLOCK)));
 }
@@ -832,7 +873,10 @@ template <class F>
 static void adj_sweep_form(const AdjArgs& a0, hipStream_t st) {
   AdjArgs a = a0;
   a.cpr = (a.c.grid.nx + ABLOCK - 1) / ABLOCK;
-  k_adj_sweep<F><<<adj_sweep_blocks(a.c.grid), ABLOCK, 0, st>>>(a);
+  if ((double)Q * (double)a.c.grid.N * (double)sizeof(typename F::R) < 4294967296.0)
+    k_adj_sweep<F, true><<<adj_sweep_blocks(a.c.grid), ABLOCK, 0, st>>>(a);
+  else
+    k_adj_sweep<F, false><<<adj_sweep_blocks(a.c.grid), ABLOCK, 0, st>>>(a);
 }
 
 template <class F>

@@ -576,7 +576,7 @@ WinLayout win_layout(const Grid& g, int precision, int T, int K, int n_i) {
   L.lphi[1] = take(8 * N);
   L.own = take(Q * cap * rb);
   L.phic = take(Q * cap * 8);
-  L.part_sweep = take(3 * 8 * (size_t)adj_sweep_blocks(g));
+  L.part_sweep = take(3 * 8 * (size_t)adj_sweep_slots(g));
   L.part_iface = take(4 * 8 * (size_t)adj_iface_blocks(n_i));
   L.grads = take(4 * 8);
   L.aux_rho = take(8 * N);
@@ -764,7 +764,7 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   }
   w->n_i = n_i;
   w->cap = std::max(n_i, 1);
-  w->nb_sweep = (int)adj_sweep_blocks(g);
+  w->nb_sweep = (int)adj_sweep_slots(g);
   w->nb_iface = (int)adj_iface_blocks(n_i);
   for (int j = 0; j < w->C; ++j) {
     char* b = wsp + L.ckpt + (size_t)j * L.state_bytes;

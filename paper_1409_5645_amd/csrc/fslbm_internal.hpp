@@ -152,7 +152,7 @@ struct AdjArgs {
   const int32_t* islot;   // cell -> position in listI (interface cells only)
   void* own;              // [Q][cap] own-population adjoint terms (compute type)
   double* phic;           // [Q][cap] fill adjoint terms per pull source (0: the cell itself)
-  double* part_sweep;     // [sweep blocks][3] dL/dg partial sums
+  double* part_sweep;     // [sweep wavefronts][3] dL/dg partial sums
   double* part_iface;     // [interface blocks][4] dL/drho_b, dL/dg partial sums
   int n_i, cap, cpr;
 };
@@ -172,6 +172,7 @@ hipError_t launch_stats(const StatArgs& a, int precision, void* stream);
 
 // adjoint window (fslbm_adjoint.hip)
 unsigned adj_sweep_blocks(const Grid& g);
+unsigned adj_sweep_slots(const Grid& g);  // dL/dg partial-sum slots of the sweep (one per wavefront)
 unsigned adj_iface_blocks(int n_i);
 unsigned list_blocks(const Grid& g);
 hipError_t launch_count_iface(const uint8_t* flags, const Grid& g, int32_t* out, void* stream);
