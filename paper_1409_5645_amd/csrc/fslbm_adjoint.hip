@@ -140,6 +140,12 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// *slot += v as an atomic add without return: the wavefront need not wait for
+// its stores to complete (a load of the slot would).  Every slot is owned by one
+// wavefront per launch and launches are ordered, so the additions into a slot
+// happen in the same order on every run.
+__device__ __forceinline__ void slot_add(double* slot, double v) { (void)atomicAdd(slot, v); }
+
 // Sum of v over the wavefront in a fixed order (quads, rows of 16, then the
 // four rows), the same value in every lane; all 64 lanes must be active.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -147,29 +153,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   v = v + qperm<DPP_ROW_ROR4>(v);
   v = v + qperm<DPP_ROW_ROR8>(v);
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
-
-// Sum of v over the block (wavefront shuffles, then the 4 wavefronts in
-// order), added by thread 0 to slot[0..NV).  Every thread of the block calls it.
-template <int NV, int BS>
-__device__ __forceinline__ void block_accumulate(double (&v)[NV], double* slot) {
-  __shared__ double sm[BS / 64][NV];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] += __shfl_down(v[i], o);
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) sm[threadIdx.x >> 6][i] = v[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int w = 0; w < BS / 64; ++w) s += sm[w][i];
-      slot[i] += s;
-    }
-  }
 }
 
 // ------------------------------------------------------------ liquid cells
@@ -243,7 +226,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_sweep(AdjArgs a) {
   if ((threadIdx.x & 63) == 0) {
     double* slot = a.part_sweep + 3 * ((size_t)blockIdx.x * (ABLOCK / 64) + (threadIdx.x >> 6));
 #pragma unroll
-    for (int c = 0; c < 3; ++c) slot[c] += gs[c];
+    for (int c = 0; c < 3; ++c) slot_add(slot + c, gs[c]);
   }
 }
 
@@ -315,6 +298,7 @@ __global__ __launch_bounds__(AIBLOCK) void k_adj_iface(AdjArgs a) {
     for (int c = 0; c < 3; ++c) dR[s][c] = R(dI[s][c]);
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dL/drho_b, dL/dg (lead lanes)
+  static_assert(AIBLOCK == 64, "one wavefront per block");
   for (int i = (int)(blockIdx.x * CELLS_PER_BLOCK) + ((int)threadIdx.x >> 2); i < a.n_i;
        i += (int)gridDim.x * CELLS_PER_BLOCK) {
     const int idx = a.listI[i];
@@ -630,7 +614,13 @@ __global__ __launch_bounds__(AIBLOCK) void k_adj_iface(AdjArgs a) {
       for (int c = 0; c < 3; ++c) acc[1 + c] += (double)gb[c];
     }
   }
-  block_accumulate<4, AIBLOCK>(acc, a.part_iface + 4 * (size_t)blockIdx.x);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = wave_sum(acc[c]);
+  if (threadIdx.x == 0) {
+    double* slot = a.part_iface + 4 * (size_t)blockIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) slot_add(slot + c, acc[c]);
+  }
 }
 
 // Own-population terms and the fill adjoint of each interface cell y.  The

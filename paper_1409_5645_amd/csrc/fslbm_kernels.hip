@@ -524,10 +524,12 @@ static void iface_form(const StepLaunch& L, int rule) {
   // every cell up to IFACE_GRID * IBLOCK, grid-stride beyond
   const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
   if (L.sweep.rec_f) {
+    // a window step: the list is fixed and its length (rec_cap) known here
+    const unsigned nbr = std::min<unsigned>(nb, (unsigned)((L.sweep.rec_cap + IBLOCK - 1) / IBLOCK));
     if (rule == 0)
-      k_iface<F, 0, true><<<nb, IBLOCK, 0, st>>>(L.sweep);
+      k_iface<F, 0, true><<<nbr, IBLOCK, 0, st>>>(L.sweep);
     else
-      k_iface<F, 1, true><<<nb, IBLOCK, 0, st>>>(L.sweep);
+      k_iface<F, 1, true><<<nbr, IBLOCK, 0, st>>>(L.sweep);
   } else if (rule == 0) {
     k_iface<F, 0><<<nb, IBLOCK, 0, st>>>(L.sweep);
   } else {
