@@ -102,7 +102,7 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
 constexpr int IBLOCK = 64;  // interface-list kernels: one wavefront per block
 
 template <class F, int RULE, bool REC = false>
-__global__ __launch_bounds__(IBLOCK) void k_iface(SweepArgs a) {
+__global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_iface(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
   constexpr bool SH = F::shifted;
