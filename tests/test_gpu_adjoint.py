@@ -327,3 +327,67 @@ def test_full_size_fp64_fd_and_fp32_error(fs):
     _say(f"  fp32 gradient error: f0 {ef:.2e}  P_b {eP:.2e}  g {eg:.2e}")
     _say(f"  fp32 fwd {g32['t_fwd']*1e3:.1f} ms bwd {g32['t_bwd']*1e3:.1f} ms fwd-only {g32['t_fwd_only']*1e3:.1f} ms")
     assert math.isfinite(ef) and ef < 0.1
+
+
+@pytest.mark.gpu
+def test_many_interface_cells_fd_and_spacing(fs):
+    """512 x 48 x 512 tank with ~286 K interface cells: more than one grid of
+    the four-lanes-per-cell interface kernel (16 K blocks x 16 cells), so some
+    wavefronts take a second pass of its loop.  FP64, T = 4: adjoint against
+    central differences for rho_b and a random direction of f0, and the same
+    gradient bit for bit with two checkpoint spacings."""
+    import torch
+    w = W.sloshing(512, 48, 512, depth=24.0, amp=10.0, amp_z=8.0, seed=0)
+    p = w.params
+    n_if = int((w.flags == W.INTERFACE).sum())
+    assert n_if > 16384 * 16
+    TT = 4
+    _say(f"case adjoint many interface cells {p.nx}x{p.ny}x{p.nz} ({n_if} interface) T={TT}")
+    ref = fs.Sim.from_workload(w)
+    base = ref.fields(("f", "mass", "phi", "flags"), device=True)
+    ref.close()
+    dev = base["f"].device
+    gen = torch.Generator(device=dev).manual_seed(11)
+    act = (base["flags"] != W.GAS).to(torch.float64)
+    a = torch.randn(base["f"].shape, dtype=torch.float64, device=dev, generator=gen) * act
+    d = torch.randn(base["f"].shape, dtype=torch.float64, device=dev, generator=gen) * act
+    b = torch.randn(base["phi"].shape, dtype=torch.float64, device=dev, generator=gen) * (base["flags"] == W.INTERFACE)
+
+    def loss(fT, phiT):
+        return (a * fT).sum() + (b * phiT).sum()
+
+    def grad(K):
+        sim = fs.Sim(p, w.flags)
+        f0 = base["f"].clone().requires_grad_(True)
+        P_b = torch.tensor(p.rho_gas / 3.0, dtype=torch.float64, device=sim.device, requires_grad=True)
+        g = torch.tensor(p.g, dtype=torch.float64, device=sim.device, requires_grad=True)
+        fT, _, phiT = fs.window_apply(sim, TT, 1, f0, base["mass"], base["phi"], P_b, g, K=K)
+        loss(fT, phiT).backward()
+        out = {"df": float((f0.grad * d).sum()), "P_b": float(P_b.grad), "f": f0.grad.detach().clone()}
+        sim.close()
+        return out
+
+    def loss_at(f0, rho_b):
+        sim = fs.Sim(p, w.flags)
+        sim.set_state(f0, base["mass"], base["phi"])
+        sim.set_forcing(p.g, rho_b)
+        sim.window(TT, 1)
+        out = sim.fields(("f", "phi"), device=True)
+        L = float(loss(out["f"], out["phi"]))
+        sim.close()
+        return L
+
+    g2 = grad(0)  # K = ceil(sqrt(4)) = 2: two segments, one recomputed
+    g4 = grad(TT)  # every step's record kept
+    assert torch.equal(g2["f"], g4["f"]) and g2["P_b"] == g4["P_b"]
+    hr = 1e-7 * p.rho_gas
+    fd = (loss_at(base["f"], p.rho_gas + hr) - loss_at(base["f"], p.rho_gas - hr)) / (2 * hr)
+    ad = g2["P_b"] / 3.0
+    _say(f"  rho_b adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}")
+    assert abs(ad - fd) <= 1e-5 * abs(fd)
+    # a step of 1e-7 keeps the runs on one branch of every clamp (see the test above)
+    h = 1e-7
+    fd = (loss_at(base["f"] + h * d, p.rho_gas) - loss_at(base["f"] - h * d, p.rho_gas)) / (2 * h)
+    ad = g2["df"]
+    _say(f"  f0 dir adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}")
+    assert abs(ad - fd) <= 1e-5 * abs(fd)
