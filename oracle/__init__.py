@@ -75,6 +75,8 @@ def lib():
         L.ref_equilibrium_post.argtypes = [vp, ctypes.c_double, dp, dp]
         L.ref_collide.argtypes = [vp, dp, dp, dp, dp]
         L.ref_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        L.ref_shear.argtypes = [vp, dp, dp]
+        L.ref_boundary_shear.argtypes = [dp, dp, ctypes.c_double, dp]
         L.ref_window_dual.restype = ctypes.c_int
         L.ref_window_dual.argtypes = [ctypes.POINTER(_RefParams), u8p, dp, dp, dp, dp, dp, dp, ctypes.c_double,
                                       dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
@@ -93,6 +95,7 @@ def _params(p) -> _RefParams:
 
 
 FSK, FSL = 0, 1
+FSK_STRESS, FSL_STRESS = 2, 3  # with the shear-rate boundary term (Table 1, column D)
 LISTS = {"F": 0, "E": 1, "E'": 2, "NI": 3, "NL": 4}
 
 
@@ -208,10 +211,27 @@ class Oracle:
         lib().ref_collide(self._h, _dptr(ff), _dptr(out), ctypes.byref(rho), _dptr(u))
         return out, rho.value, u
 
+    def shear(self, own) -> np.ndarray:
+        """Shear rate [xx, yy, zz, xy, xz, yz] from 19 post-collision populations
+        (section 3.4; Eq. nqp at leading order)."""
+        ff = np.ascontiguousarray(own, dtype=np.float64)
+        out = np.empty(6)
+        lib().ref_shear(self._h, _dptr(ff), _dptr(out))
+        return out
+
     def coeffs(self, rule: int, alpha_p: float = 1.0, delta: float = 0.0) -> np.ndarray:
         out = np.empty(5)
         lib().ref_coeffs(self._h, int(rule), float(alpha_p), float(delta), _dptr(out))
         return out
+
+
+def boundary_shear(S, n, s_nn: float) -> np.ndarray:
+    """S^b = P S P + s_nn n n^T (section 3.4) for S = [xx, yy, zz, xy, xz, yz]."""
+    SS = np.ascontiguousarray(S, dtype=np.float64)
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    out = np.empty(6)
+    lib().ref_boundary_shear(_dptr(SS), _dptr(nn), float(s_nn), _dptr(out))
+    return out
 
 
 def window_dual(params, flags, f0, m0, phi0, u_target, phi_target, T: int, rule: int = FSL,

@@ -87,9 +87,14 @@ const char* ref_error(void* hp) { return static_cast<Handle*>(hp)->err.c_str(); 
 
 void ref_set_freeze(void* hp, int freeze) { static_cast<Handle*>(hp)->sim.freeze = freeze != 0; }
 
-// n steps with rule 0 = FSK, 1 = FSL.  Returns 0, or 1 with ref_error() set.
+// n steps with rule 0 = FSK, 1 = FSL, 2 / 3 = FSK / FSL with the shear-rate
+// boundary term (D of Table 1).  Returns 0, or 1 with ref_error() set.
 int ref_step(void* hp, int n, int rule) {
   auto* h = static_cast<Handle*>(hp);
+  if (rule < 0 || rule > 3) {
+    h->err = "unknown rule";
+    return 1;
+  }
   try {
     for (int i = 0; i < n; ++i) h->sim.step(rule);
     return 0;
@@ -171,6 +176,19 @@ void ref_equilibrium_post(void* hp, double rho, const double* u, double* out19) 
 void ref_collide(void* hp, const double* f19, double* out19, double* rho, double* u3) {
   static_cast<Handle*>(hp)->sim.collide(f19, out19, *rho, u3);
 }
+// Shear rate S = [xx, yy, zz, xy, xz, yz] of section 3.4 from 19 post-collision
+// populations of time t (moments recovered from them).
+void ref_shear(void* hp, const double* own19, double* S6) {
+  auto& s = static_cast<Handle*>(hp)->sim;
+  double rho, u[3];
+  s.recover_moments(own19, rho, u);
+  s.shear_from_own(own19, rho, s.rho0_of(rho), u, S6);
+}
+// Boundary value S^b = P S P + s_nn n n^T of section 3.4 (n a unit vector).
+void ref_boundary_shear(const double* S6, const double* n3, double s_nn, double* Sb6) {
+  fsref::Oracle<double>::boundary_shear(S6, n3, s_nn, Sb6);
+}
+
 // Closure coefficients: rule 0 = FSK row, rule 1 = Eq. (fsli) with alpha_+.
 void ref_coeffs(void* hp, int rule, double alpha_p, double delta, double* out5) {
   auto& s = static_cast<Handle*>(hp)->sim;

@@ -50,7 +50,10 @@ inline double weight(int q) {
 }
 
 enum CellType : uint8_t { GAS = 0, INTERFACE = 1, LIQUID = 2 };
-enum Rule { FSK = 0, FSL = 1 };
+// Rules: bit 0 selects the FSL construction (else the FSK row of Table 1),
+// bit 1 the full boundary value term of Eq. (bterm) with the shear-rate entry
+// D c_a c_b S^b_ab (Table 1, column D; section 3.4), else D = 0.
+enum Rule { FSK = 0, FSL = 1, FSK_STRESS = 2, FSL_STRESS = 3 };
 
 // Model parameters.  tau is the symmetric relaxation time (lambda_+ = -1/tau),
 // Lambda = Lambda_+ Lambda_- fixes lambda_- (section 3.1).  g is the body
@@ -79,6 +82,7 @@ struct Oracle {
   T gvec[3], half_g[3], g_over_lam_m[3];
   T thr_hi, thr_lo;     // (1+eps), (-eps)
   T rho_b;              // gas density rho_b = 3 P_b of the boundary term
+  T Lam_p;              // Lambda_+ = -(1/2 + 1/lambda_+) = tau - 1/2 (section 3.1)
 
   std::vector<uint8_t> type;  // cell classes
   std::vector<T> ft;          // post-collision populations ft[q*N + cell]
@@ -118,6 +122,7 @@ struct Oracle {
     thr_hi = T(1.0 + p.eps);
     thr_lo = T(-p.eps);
     rho_b = T(p.rho_gas);
+    Lam_p = T(Lp);
   }
 
   // neighbour of cell (x,y,z) at offset d; -1 if it lies beyond a wall
@@ -264,6 +269,95 @@ struct Oracle {
     return c;
   }
 
+  // ------------------------------------------ boundary shear rate (3.4)
+  // Shear rate S_ab = (d_a j_b + d_b j_a)/2 from the even non-equilibrium of
+  // post-collision populations of time t.  At leading order Eq. (nqp) gives
+  // n+_q = (1/lambda_+)(w_q/c_s^2) c_qa c_qb S_ab, and the fourth moment of the
+  // D3Q19 weights, sum_q w_q c_a c_b c_c c_d = c_s^4 (d_ab d_cd + d_ac d_bd +
+  // d_ad d_bc), turns M_ab = sum_q c_qa c_qb n+_q into
+  // (c_s^2/lambda_+)(d_ab tr S + 2 S_ab); hence tr S = lambda_+ tr M / (5 c_s^2)
+  // and S = (lambda_+ / (2 c_s^2)) (M - d tr M / 5).  n+_q is recovered from
+  // ft+ = e+ + (1 + lambda_+) n+ with the moments (rho, u) of time t.
+  // Components: [xx, yy, zz, xy, xz, yz].
+  void shear_from_own(const T own[Q], const T& rho, const T& rho0, const T u[3], T S[6]) const {
+    T M[6] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+    for (int q = 1; q < Q; q += 2) {  // n+ is even: each pair once, counted twice
+      T fplus = T(0.5) * (own[q] + own[q + 1]);
+      T np = (fplus - e_plus(q, rho, rho0, u)) * inv_1p_lam_p;
+      T n2 = T(2.0) * np;
+      const int* c = CV[q];
+      M[0] = M[0] + T(c[0] * c[0]) * n2;
+      M[1] = M[1] + T(c[1] * c[1]) * n2;
+      M[2] = M[2] + T(c[2] * c[2]) * n2;
+      M[3] = M[3] + T(c[0] * c[1]) * n2;
+      M[4] = M[4] + T(c[0] * c[2]) * n2;
+      M[5] = M[5] + T(c[1] * c[2]) * n2;
+    }
+    T tr5 = ((M[0] + M[1]) + M[2]) / T(5.0);
+    T f = T(1.5) * lam_p;  // lambda_+ / (2 c_s^2)
+    S[0] = f * (M[0] - tr5);
+    S[1] = f * (M[1] - tr5);
+    S[2] = f * (M[2] - tr5);
+    S[3] = f * M[3];
+    S[4] = f * M[4];
+    S[5] = f * M[5];
+  }
+
+  // Boundary value S^b of section 3.4: in a local orthonormal basis {t1, t2, n}
+  // the tangential block of S is kept, the tangential-normal entries are set by
+  // Eq. (proj2) (d_t j_n + d_n j_t = 0, i.e. zero) and the normal-normal entry
+  // by Eq. (proj1) with sigma = 0 (d_n j_n = s_nn).  In the standard basis that
+  // is S^b = P S P + s_nn n n^T with the tangential projector P = I - n n^T,
+  // whatever t1 and t2 are:  S^b = S - (S n) n^T - n (S n)^T + (n.S.n + s_nn) n n^T.
+  static void boundary_shear(const T S[6], const T n[3], const T& s_nn, T Sb[6]) {
+    // full matrix view of the symmetric S
+    const int ix[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    T Sn[3];
+    for (int a = 0; a < 3; ++a) Sn[a] = (S[ix[a][0]] * n[0] + S[ix[a][1]] * n[1]) + S[ix[a][2]] * n[2];
+    T nSn = (n[0] * Sn[0] + n[1] * Sn[1]) + n[2] * Sn[2];
+    T k = nSn + s_nn;
+    const int ab[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    for (int i = 0; i < 6; ++i) {
+      int a = ab[i][0], b = ab[i][1];
+      Sb[i] = ((S[i] - Sn[a] * n[b]) - n[a] * Sn[b]) + k * (n[a] * n[b]);
+    }
+  }
+
+  // Liquid neighbour x + c_k with the largest -c_k.n / |c_k| (lowest k on
+  // ties), or -1 if no neighbour is liquid.  |c_k| is 1 or sqrt 2, so the
+  // comparison is made on (c_k.n)^2 / |c_k|^2 with the sign of -c_k.n.
+  int bulk_neighbour(int x, int y, int z, const T n[3]) const {
+    int best = -1;
+    T best_v = T(0.0);
+    for (int k = 1; k < Q; ++k) {
+      int s = neighbor(x, y, z, CV[k][0], CV[k][1], CV[k][2]);
+      if (s < 0 || type[s] != LIQUID) continue;
+      T cn = -cdot(k, n);
+      T len2 = T(k <= 6 ? 1.0 : 2.0);
+      T v = cn < T(0.0) ? -(cn * cn) / len2 : (cn * cn) / len2;
+      if (best < 0 || v > best_v) {
+        best = s;
+        best_v = v;
+      }
+    }
+    return best;
+  }
+
+  // n . S . n for a symmetric S given as [xx, yy, zz, xy, xz, yz]
+  static T normal_normal(const T S[6], const T n[3]) {
+    T d = (S[0] * (n[0] * n[0]) + S[1] * (n[1] * n[1])) + S[2] * (n[2] * n[2]);
+    T o = (S[3] * (n[0] * n[1]) + S[4] * (n[0] * n[2])) + S[5] * (n[1] * n[2]);
+    return d + T(2.0) * o;
+  }
+
+  // c_q . S . c_q for a symmetric S given as [xx, yy, zz, xy, xz, yz]
+  static T cSc(int q, const T S[6]) {
+    const int* c = CV[q];
+    T d = (T(c[0] * c[0]) * S[0] + T(c[1] * c[1]) * S[1]) + T(c[2] * c[2]) * S[2];
+    T o = (T(c[0] * c[1]) * S[3] + T(c[0] * c[2]) * S[4]) + T(c[1] * c[2]) * S[5];
+    return d + T(2.0) * o;
+  }
+
   // --------------------------------------------------------------- init
   // flags: cell classes; rho, u (u[a*N+cell]): initial macroscopic state;
   // fill: fill level (used at interface cells; m = fill * rho there).
@@ -407,6 +501,31 @@ struct Oracle {
         recover_moments(own, rho_t, u_t);
         const T rho0_t = rho0_of(rho_t);
         const T rho0_b = rho0_of(rho_b);
+        // Boundary shear rate for the rules with D != 0 (section 3.4): S
+        // extrapolated from the bulk at order zero, i.e. taken from the
+        // non-equilibrium of time t of the liquid neighbour x + c_k whose link
+        // points most directly into the liquid (largest -c_k.n / |c_k|, lowest
+        // k on ties; the cell itself if no neighbour is liquid).  In the basis
+        // {t1, t2, n}: tangential block kept,
+        // tangential-normal entries zero (Eq. proj2), normal-normal entry
+        // S_nn / 3.  The closure, Taylor-expanded at the surface point, holds
+        // P - P_b = Lambda_+ (S_nn - S^b_nn) on the links it reconstructs;
+        // Eq. (proj1) with sigma = 0 asks P - P_b = 2 nu S_nn, and with
+        // nu = c_s^2 Lambda_+ that is S^b_nn = (1 - 2 c_s^2) S_nn = S_nn / 3.
+        // Without a normal there is no local basis and the term is left out.
+        const bool stress = (rule & 2) && have_normal;
+        T Sb[6] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+        if (stress) {
+          int nb = bulk_neighbour(x, y, z, nvec);
+          T fb[Q];
+          for (int q = 0; q < Q; ++q) fb[q] = nb < 0 ? own[q] : ft[(size_t)q * N + nb];
+          T rho_n, u_n[3];
+          recover_moments(fb, rho_n, u_n);
+          T S[6];
+          shear_from_own(fb, rho_n, rho0_of(rho_n), u_n, S);
+          T s_nn = normal_normal(S, nvec) / T(3.0);
+          boundary_shear(S, nvec, s_nn, Sb);
+        }
         for (int q = 1; q < Q; ++q) {
           if (!gaslink[q]) continue;
           int o = opposite(q);
@@ -417,7 +536,7 @@ struct Oracle {
           T e_b = e_plus(o, rho_b, rho0_b, u_t);  // boundary value, u_b = u(x,t)
           Coeffs k = coeffs_fsk();
           T f_o_next = T(0.0);
-          if (rule == FSL) {
+          if (rule & 1) {
             // ft_o(x - c_o, t) = f_o(x, t+1): the value the pull delivers
             // along o; unavailable when that source is gas too.
             bool ok = have_normal && !gaslink[o];
@@ -434,6 +553,11 @@ struct Oracle {
           //                                  + C n+_o + alpha_+ e+_o(rho_b,u_b)
           f[q] = (((k.a0 * own[o] + k.a0bar * own[q]) + k.a1 * f_o_next) + k.C * n_plus) +
                  k.alpha_p * e_b;
+          // + D c_o c_o : S^b with D = -alpha_+ Lambda_+ w/c_s^2 (Eq. bterm, Table 1)
+          if (stress) {
+            T D = -((k.alpha_p * Lam_p) * T(3.0 * weight(o)));
+            f[q] = f[q] + D * cSc(o, Sb);
+          }
         }
       }
 
