@@ -57,8 +57,14 @@ typedef enum {
   FSLBM_E_CAPACITY = 6      /* an output array is too small */
 } fslbm_status;
 
-/* Gas-side reconstruction rule (Table 1). */
-enum { FSLBM_RULE_FSK = 0, FSLBM_RULE_FSL = 1 };
+/* Gas-side reconstruction rule (Table 1).  FSK and FSL use the boundary value
+ * term of Eq. (bterm) with S^b = 0 (D = 0).  The _STRESS variants add its
+ * shear-rate part D c_a c_b S^b_ab with D = -alpha_+ Lambda_+ w_q / c_s^2
+ * (Table 1, column D; section 3.4): S is taken from the non-equilibrium of the
+ * liquid neighbour opposite the surface normal, and S^b keeps its tangential
+ * block, has zero tangential-normal entries (Eq. proj2) and normal entry
+ * S_nn / 3 (Eq. proj1 with sigma = 0). */
+enum { FSLBM_RULE_FSK = 0, FSLBM_RULE_FSL = 1, FSLBM_RULE_FSK_STRESS = 2, FSLBM_RULE_FSL_STRESS = 3 };
 
 /* Precision forms.  FP64: populations f stored and computed in double.
  * FP32: shifted populations f - w_q stored and computed in float.
@@ -120,8 +126,8 @@ fslbm_status fslbm_set_equilibrium(fslbm_ctx* c, const double* rho, const double
 fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, const double* fill,
                              double reservoir);
 
-/* Enqueue n time steps with rule FSLBM_RULE_FSK or FSLBM_RULE_FSL.  FSL with
- * tau = 1 is FSLBM_E_UNSUPPORTED (n+ cannot be recovered from the
+/* Enqueue n time steps with one of the FSLBM_RULE_* rules.  Every rule but
+ * FSK with tau = 1 is FSLBM_E_UNSUPPORTED (n+ cannot be recovered from the
  * post-collision state).  Asynchronous. */
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule);
 
@@ -192,7 +198,8 @@ typedef struct fslbm_window fslbm_window;
  * default) for the current cell classes of c.  Synchronises. */
 fslbm_status fslbm_window_workspace_size(fslbm_ctx* c, int32_t T, int32_t K, size_t* bytes);
 
-/* Forward pass: T steps with rule FSK or FSL from the current state of c,
+/* Forward pass: T steps with rule FSK or FSL (the _STRESS rules are
+ * FSLBM_E_UNSUPPORTED here) from the current state of c,
  * conversions disabled, storing checkpoints in the workspace (device memory,
  * 256-byte aligned, at least fslbm_window_workspace_size bytes).  On return the
  * state of c is that of time T (read it with fslbm_fields) and *out is the

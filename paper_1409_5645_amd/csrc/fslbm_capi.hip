@@ -121,6 +121,7 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
   }
   d.rhob_s = shifted ? p.rho_gas - 1.0 : p.rho_gas;
   d.rho0b = p.incompressible ? 1.0 : p.rho_gas;
+  d.Lp = Lp;
   Consts<float>& f = com.kf;
   f.lp = (float)d.lp;
   f.lm = (float)d.lm;
@@ -133,6 +134,7 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
   }
   f.rhob_s = (float)d.rhob_s;
   f.rho0b = (float)d.rho0b;
+  f.Lp = (float)d.Lp;
   com.incomp = p.incompressible ? 1 : 0;
   com.stokes = p.stokes ? 1 : 0;
   com.scale = std::ldexp(1.0f, p.fp16_scale_log2);
@@ -262,9 +264,9 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
   if (!c) return FSLBM_E_INVALID;
   if (n < 0) { c->last_error = "n must be >= 0"; return FSLBM_E_INVALID; }
-  if (rule != FSLBM_RULE_FSK && rule != FSLBM_RULE_FSL) { c->last_error = "unknown rule"; return FSLBM_E_INVALID; }
-  if (rule == FSLBM_RULE_FSL && c->p.tau == 1.0) {
-    c->last_error = "FSL needs tau != 1 (n+ is not recoverable from a fully relaxed state)";
+  if (rule < FSLBM_RULE_FSK || rule > FSLBM_RULE_FSL_STRESS) { c->last_error = "unknown rule"; return FSLBM_E_INVALID; }
+  if (rule != FSLBM_RULE_FSK && c->p.tau == 1.0) {
+    c->last_error = "this rule needs tau != 1 (n+ is not recoverable from a fully relaxed state)";
     return FSLBM_E_UNSUPPORTED;
   }
   for (int32_t i = 0; i < n; ++i) {
@@ -715,6 +717,10 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   if (!c) return FSLBM_E_INVALID;
   if (!out || !workspace) { c->last_error = "out or workspace is NULL"; return FSLBM_E_INVALID; }
   if (((uintptr_t)workspace) % ALIGN) { c->last_error = "window workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
+  if (rule == FSLBM_RULE_FSK_STRESS || rule == FSLBM_RULE_FSL_STRESS) {
+    c->last_error = "the adjoint window supports the FSK and FSL rules (D = 0)";
+    return FSLBM_E_UNSUPPORTED;
+  }
   if (rule != FSLBM_RULE_FSK && rule != FSLBM_RULE_FSL) { c->last_error = "unknown rule"; return FSLBM_E_INVALID; }
   if (rule == FSLBM_RULE_FSL && c->p.tau == 1.0) {
     c->last_error = "FSL needs tau != 1 (n+ is not recoverable from a fully relaxed state)";

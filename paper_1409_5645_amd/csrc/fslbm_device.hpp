@@ -76,6 +76,7 @@ struct Consts {
   R g[3], hg[3], glm[3];  // g, g/2, g/lambda_-
   R rhob_s;               // gas density in storage convention
   R rho0b;                // rho_0 used with the gas density
+  R Lp;                   // Lambda_+ = -(1/2 + 1/lambda_+) = tau - 1/2
 };
 
 // c_q . v with the non-zero components only, in axis order

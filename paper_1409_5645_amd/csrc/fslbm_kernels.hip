@@ -27,13 +27,107 @@ namespace fslbm {
 constexpr int BLOCK = 256;
 
 // ------------------------------------------------------------------ sweep
+// Boundary shear rate S^b (section 3.4) of the rules with D != 0, for an
+// interface cell with a normal.  S is extrapolated from the bulk at order zero:
+// it is read from the non-equilibrium of time t of the liquid neighbour x + c_k
+// whose link points most directly into the liquid (largest -c_k.n / |c_k|,
+// lowest k on ties; the cell's own populations if no neighbour is liquid), by
+// Eq. (nqp) at leading order with the fourth-moment isotropy of D3Q19:
+//   M = sum_q c_q c_q n+_q,   S = (lambda_+ / (2 c_s^2)) (M - I tr M / 5).
+// In the basis {t1, t2, n} the tangential block of S is kept, the
+// tangential-normal entries are zero (Eq. proj2) and the normal entry is S_nn/3
+// (the closure holds P - P_b = Lambda_+ (S_nn - S^b_nn) on the links it
+// rebuilds; Eq. (proj1) with sigma = 0 asks 2 nu S_nn = (2/3) Lambda_+ S_nn):
+//   S^b = S - (S n) n^T - n (S n)^T + (n.S.n + S_nn/3) n n^T.
+// Components [xx, yy, zz, xy, xz, yz]; the geometry is FP64.
+template <class F>
+__device__ __forceinline__ void boundary_shear(const IfaceData<F>& d, const Nbr& n, const Grid& g,
+                                               const typename F::S* __restrict__ fin, float isc,
+                                               const double (&nv)[3], const Consts<typename F::R>& k,
+                                               bool incomp, bool stokes, typename F::R (&Sb)[6]) {
+  using R = typename F::R;
+  constexpr bool SH = F::shifted;
+  int best = -1, bx = 0, by = 0, bz = 0;
+  double best_v = 0.0;
+#define FSLBM_BULK(kk)                                                               \
+  if (d.ty[OPP[kk]] == LIQ) { /* x + c_k is the pull source of link kbar */           \
+    const double cn = -cdot<kk>(nv);                                                 \
+    const double len2 = kk <= 6 ? 1.0 : 2.0;                                         \
+    const double v = cn < 0.0 ? -(cn * cn) / len2 : (cn * cn) / len2;                \
+    if (best < 0 || v > best_v) {                                                    \
+      best = kk;                                                                     \
+      best_v = v;                                                                    \
+      bx = CX[kk];                                                                   \
+      by = CY[kk];                                                                   \
+      bz = CZ[kk];                                                                   \
+    }                                                                                \
+  }
+  FSLBM_LINKS(FSLBM_BULK)
+#undef FSLBM_BULK
+  R f[Q];
+  if (best < 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = d.own[q];
+  } else {
+    const int sx = step_axis(n.x, bx, g.nx, g.px), sy = step_axis(n.y, by, g.ny, g.py);
+    const int sz = step_axis(n.z, bz, g.nz, g.pz);
+    const unsigned s = (unsigned)(sx + g.nx * (sy + g.ny * sz));  // a liquid cell: inside the lattice
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = F::load(fin + ((unsigned)q * (unsigned)g.N + s), isc);
+  }
+  R rho_n, u_n[3];
+  recover_moments<R, SH>(f, k, incomp, rho_n, u_n);
+  const R rho0_n = rho0_of<R, SH>(rho_n, incomp);
+  const R usq_n = usq_of(u_n);
+  R M[6] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
+#define FSLBM_MNEQ(q)                                                                \
+  {                                                                                  \
+    const R fplus = R(0.5) * (f[q] + f[q + 1]);                                      \
+    const R np = (fplus - e_plus<q>(rho_n, rho0_n, incomp, stokes, u_n, usq_n)) * k.inv1p; \
+    const R n2 = R(2.0) * np;                                                        \
+    M[0] = M[0] + R(CX[q] * CX[q]) * n2;                                             \
+    M[1] = M[1] + R(CY[q] * CY[q]) * n2;                                             \
+    M[2] = M[2] + R(CZ[q] * CZ[q]) * n2;                                             \
+    M[3] = M[3] + R(CX[q] * CY[q]) * n2;                                             \
+    M[4] = M[4] + R(CX[q] * CZ[q]) * n2;                                             \
+    M[5] = M[5] + R(CY[q] * CZ[q]) * n2;                                             \
+  }
+  FSLBM_MNEQ(1) FSLBM_MNEQ(3) FSLBM_MNEQ(5) FSLBM_MNEQ(7) FSLBM_MNEQ(9) FSLBM_MNEQ(11) FSLBM_MNEQ(13)
+  FSLBM_MNEQ(15) FSLBM_MNEQ(17)
+#undef FSLBM_MNEQ
+  const R tr5 = ((M[0] + M[1]) + M[2]) / R(5.0);
+  const R fs = R(1.5) * k.lp;  // lambda_+ / (2 c_s^2)
+  double S[6];
+  S[0] = (double)(fs * (M[0] - tr5));
+  S[1] = (double)(fs * (M[1] - tr5));
+  S[2] = (double)(fs * (M[2] - tr5));
+  S[3] = (double)(fs * M[3]);
+  S[4] = (double)(fs * M[4]);
+  S[5] = (double)(fs * M[5]);
+  // normal entry of the boundary value: n.S.n / 3
+  const double ndg = (S[0] * (nv[0] * nv[0]) + S[1] * (nv[1] * nv[1])) + S[2] * (nv[2] * nv[2]);
+  const double nof = (S[3] * (nv[0] * nv[1]) + S[4] * (nv[0] * nv[2])) + S[5] * (nv[1] * nv[2]);
+  const double s_nn = (ndg + 2.0 * nof) / 3.0;
+  // S^b = P S P + s_nn n n^T
+  double Sn[3];
+  Sn[0] = (S[0] * nv[0] + S[3] * nv[1]) + S[4] * nv[2];
+  Sn[1] = (S[3] * nv[0] + S[1] * nv[1]) + S[5] * nv[2];
+  Sn[2] = (S[4] * nv[0] + S[5] * nv[1]) + S[2] * nv[2];
+  const double kk = ((nv[0] * Sn[0] + nv[1] * Sn[1]) + nv[2] * Sn[2]) + s_nn;
+  constexpr int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+    Sb[i] = (R)(((S[i] - Sn[A[i]] * nv[B[i]]) - nv[A[i]] * Sn[B[i]]) + kk * (nv[A[i]] * nv[B[i]]));
+}
+
 // Update of one interface cell from its loaded neighbourhood: mass exchange,
 // geometry, reconstruction of the gas-side populations, TRT collision.  On exit
 // d.f holds the post-collision populations; returns the new mass, the density
 // (storage convention) and the velocity of the collision.
 template <class F, int RULE>
 __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& cm, typename F::R& rho_s,
-                                                typename F::R (&u)[3]) {
+                                                typename F::R (&u)[3], const Nbr& nb,
+                                                const typename F::S* __restrict__ fin) {
   using R = typename F::R;
   constexpr bool SH = F::shifted;
   const Consts<R>& k = pick_consts<R>(cm);
@@ -83,7 +177,14 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
     recover_moments<R, SH>(d.own, k, incomp, rho_t, u_t);
     const R rho0_t = rho0_of<R, SH>(rho_t, incomp);
     const R usq_t = usq_of(u_t);
-#define FSLBM_REBUILD(q) rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, rho0_t, u_t, usq_t, k, incomp, stokes);
+    // boundary shear rate for the rules with D != 0 (needs the local basis)
+    R Sb[6] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
+    const bool stress = (RULE & 2) && have_n;
+    if constexpr ((RULE & 2) != 0) {
+      if (stress) boundary_shear<F>(d, nb, cm.grid, fin, cm.inv_scale, nv, k, incomp, stokes, Sb);
+    }
+#define FSLBM_REBUILD(q) \
+  rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, rho0_t, u_t, usq_t, k, incomp, stokes, Sb, stress);
     FSLBM_LINKS(FSLBM_REBUILD)
 #undef FSLBM_REBUILD
   }
@@ -160,7 +261,7 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
     }
     // ---- phase 2: interface treatment and collision
     R rho_s, u[3];
-    const double m_new = iface_compute<F, RULE>(d, a.c, rho_s, u);
+    const double m_new = iface_compute<F, RULE>(d, a.c, rho_s, u, n, fin);
     // ---- phase 3: populations, fill level and classification (FP64 bookkeeping)
 #pragma unroll
     for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, d.f[q], a.c.scale);
@@ -524,7 +625,7 @@ static void iface_form(const StepLaunch& L, int rule) {
   // every cell up to IFACE_GRID * IBLOCK, grid-stride beyond
   const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
   if (L.sweep.rec_f) {
-    // a window step: the list is fixed and its length (rec_cap) known here
+    // a window step (rules 0 and 1): the list is fixed and its length (rec_cap) known here
     const unsigned nbr = std::min<unsigned>(nb, (unsigned)((L.sweep.rec_cap + IBLOCK - 1) / IBLOCK));
     if (rule == 0)
       k_iface<F, 0, true><<<nbr, IBLOCK, 0, st>>>(L.sweep);
@@ -532,8 +633,12 @@ static void iface_form(const StepLaunch& L, int rule) {
       k_iface<F, 1, true><<<nbr, IBLOCK, 0, st>>>(L.sweep);
   } else if (rule == 0) {
     k_iface<F, 0><<<nb, IBLOCK, 0, st>>>(L.sweep);
-  } else {
+  } else if (rule == 1) {
     k_iface<F, 1><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  } else if (rule == 2) {
+    k_iface<F, 2><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  } else {
+    k_iface<F, 3><<<nb, IBLOCK, 0, st>>>(L.sweep);
   }
 }
 

@@ -47,21 +47,32 @@ __device__ __forceinline__ double phi_seen(const IfaceData<F>& d, int q) {
   return d.ty[q] == LIQ ? 1.0 : (d.ty[q] == GAS ? 0.0 : d.ph[q]);
 }
 
+// c_q . S . c_q for a symmetric S = [xx, yy, zz, xy, xz, yz]
+template <int q, class R>
+__device__ __forceinline__ R c_S_c(const R (&S)[6]) {
+  const R dg = (R(CX[q] * CX[q]) * S[0] + R(CY[q] * CY[q]) * S[1]) + R(CZ[q] * CZ[q]) * S[2];
+  const R of = (R(CX[q] * CY[q]) * S[3] + R(CX[q] * CZ[q]) * S[4]) + R(CY[q] * CZ[q]) * S[5];
+  return dg + R(2.0) * of;
+}
+
 // Reconstruction of the population f_q that would stream in from a gas cell.
 // With o = qbar the link pointing to gas, the closure Eq. (closure) gives
 //   f_q = a0 ft_o(x) + a0bar ft_q(x) + a1 f_o(x,t+1) + C n+_o(x,t) + alpha_+ e+_o(rho_b,u_b)
-// with the FSK row of Table 1 (Eq. koerner) or Eq. (fsli1)-(fsli4) at alpha_+ = 1.
+// with the FSK row of Table 1 (Eq. koerner) or Eq. (fsli1)-(fsli4) at alpha_+ = 1
+// (RULE bit 0), plus, with RULE bit 1, the shear-rate part of the boundary value
+// Eq. (bterm): D c_o c_o : S^b with D = -alpha_+ Lambda_+ w_o / c_s^2 (Table 1).
 template <class F, int RULE, int q>
 __device__ __forceinline__ void rebuild(IfaceData<F>& d, uint32_t gasmask, bool have_n, const double (&nv)[3],
                                         double dist, typename F::R rho_t, typename F::R rho0_t,
                                         const typename F::R (&u_t)[3], typename F::R usq_t,
-                                        const Consts<typename F::R>& k, bool incomp, bool stokes) {
+                                        const Consts<typename F::R>& k, bool incomp, bool stokes,
+                                        const typename F::R (&Sb)[6], bool stress) {
   using R = typename F::R;
   if (!((gasmask >> q) & 1u)) return;
   constexpr int o = OPP[q];
   const R own_o = d.own[o];
   const R e_b = e_plus<o>(k.rhob_s, k.rho0b, incomp, stokes, u_t, usq_t);
-  if (RULE == 1 && have_n && !((gasmask >> o) & 1u)) {
+  if ((RULE & 1) && have_n && !((gasmask >> o) & 1u)) {
     // link distance delta: plane with normal n at offset phi - 1/2
     double nc = 0.0;
     if (CX[o] == 1) nc = nc + nv[0];
@@ -83,10 +94,16 @@ __device__ __forceinline__ void rebuild(IfaceData<F>& d, uint32_t gasmask, bool 
       const R a1 = delta - R(1.0);
       const R Cc = k.lp * (R(0.5) + delta) - R(2.0) * k.lp;
       d.f[q] = (((a0 * own_o + R(0.5) * own_q) + a1 * d.f[o]) + Cc * n_plus) + e_b;
+      if constexpr ((RULE & 2) != 0) {
+        if (stress) d.f[q] = d.f[q] + (-((R(1.0) * k.Lp) * R(3.0 * WD[o]))) * c_S_c<o>(Sb);  // alpha_+ = 1
+      }
       return;
     }
   }
   d.f[q] = R(2.0) * e_b - own_o;  // FSK: -ft_o + 2 e+_o(rho_b, u_b)
+  if constexpr ((RULE & 2) != 0) {
+    if (stress) d.f[q] = d.f[q] + (-((R(2.0) * k.Lp) * R(3.0 * WD[o]))) * c_S_c<o>(Sb);  // alpha_+ = 2
+  }
 }
 
 }  // namespace fslbm

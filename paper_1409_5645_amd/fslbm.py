@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfslbm.so")
 
 FSK, FSL = 0, 1
+FSK_STRESS, FSL_STRESS = 2, 3  # with the shear-rate boundary term (Table 1, column D)
 FP64, FP32, FP16S = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 GAS, INTERFACE, LIQUID = 0, 1, 2

@@ -229,6 +229,9 @@ def test_window_errors(fs, case):
         s.window(0, 1)
     with pytest.raises(fs.FslbmError, match="INVALID"):
         s.window(5, 7)  # unknown rule
+    for rule in (fs.FSK_STRESS, fs.FSL_STRESS):  # no adjoint of the shear-rate boundary term
+        with pytest.raises(fs.FslbmError, match="UNSUPPORTED"):
+            s.window(5, rule)
     s.close()
 
 

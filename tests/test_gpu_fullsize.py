@@ -68,13 +68,14 @@ def _subbox(t3, box):
     return t3[..., z0:z1, y0:y1, x0:x1].contiguous()
 
 
-def test_slosh512_fp64_subbox_step(fs, oracle_mod):
+@pytest.mark.parametrize("rule", [1, 3])
+def test_slosh512_fp64_subbox_step(fs, oracle_mod, rule):
     w = W.config("slosh512", seed=0)
     p = w.params
     nx, ny, nz = p.nx, p.ny, p.nz
-    _say("case slosh512 fp64: 20 GPU steps, then one step on a sub-box vs the oracle")
+    _say(f"case slosh512 fp64 rule {rule}: 20 GPU steps, then one step on a sub-box vs the oracle")
     s = fs.Sim.from_workload(w)
-    s.step(20, fs.FSL)
+    s.step(20, rule)
     g0 = s.fields(("f", "mass", "phi", "flags"), device=True)
     # sub-box around the surface, touching the x = 0 wall (a real wall) and cut elsewhere
     box = ((0, 72), (170, 220), (200, 240))
@@ -91,8 +92,8 @@ def test_slosh512_fp64_subbox_step(fs, oracle_mod):
                   g=p.g, rho_gas=p.rho_gas, eps=p.eps)
     o = oracle_mod.Oracle(ps, state=sub)
     assert (sub["flags"] == W.INTERFACE).sum() > 1000
-    s.step(1, fs.FSL)
-    o.step(1, oracle_mod.FSL)
+    s.step(1, rule)
+    o.step(1, rule)
     g1 = s.fields(("f", "flags", "mass"), device=True)
     gf = _subbox(g1["f"].reshape(19, nz, ny, nx), box).cpu().numpy()
     gfl = _subbox(g1["flags"].reshape(nz, ny, nx), box).cpu().numpy()

@@ -65,9 +65,10 @@ def _run_pair(fs, oracle_mod, w, rule, steps, every, precision="fp64", rel=REL):
     return o, s, errs
 
 
-@pytest.mark.parametrize("rule", [0, 1])
+@pytest.mark.parametrize("rule", [0, 1, 2, 3])
 def test_channel_fp64_parity(fs, oracle_mod, rule):
-    """Channel film 8 x 48 x 8 (frozen topology in practice)."""
+    """Channel film 8 x 48 x 8 (frozen topology in practice); rules 2 and 3
+    add the shear-rate boundary term."""
     w = W.channel()
     o, s, errs = _run_pair(fs, oracle_mod, w, rule, 600, 200)
     _say("channel max rel err", max(errs))
@@ -75,11 +76,13 @@ def test_channel_fp64_parity(fs, oracle_mod, rule):
     assert st["total_mass"] == pytest.approx(o.total_mass(), rel=1e-12)
 
 
-@pytest.mark.parametrize("rule", [1, 0])
+@pytest.mark.parametrize("rule", [1, 0, 3, 2])
 def test_sloshing_fp64_parity_with_conversions(fs, oracle_mod, rule):
     """Small tank with a ragged x extent (37 cells: several wavefronts and a
     partial one per row) and strong gravity so that cells convert every few
-    steps: classes and lists bit-exact after every step."""
+    steps: classes and lists bit-exact after every step (rules 3 and 2: with
+    the shear-rate boundary term, whose bulk neighbour and projection follow
+    the surface as it moves)."""
     w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
     o = oracle_mod.Oracle.from_workload(w)
     s = fs.Sim.from_workload(w)
@@ -229,3 +232,21 @@ def test_fp16_pair_sweep_matches_single(fs, monkeypatch, nx, periodic):
         np.testing.assert_array_equal(fa["f"][:, act], fb["f"][:, act])
         np.testing.assert_array_equal(fa["mass"], fb["mass"])
     assert a.stats()["interface"] > 0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp16s", 5e-2)])
+def test_reduced_precision_stress_rule(fs, oracle_mod, precision, tol):
+    """FSL with the shear-rate boundary term in the FP32 and FP16-storage forms
+    against the FP64 oracle on a sloshing tank: velocity error relative to the
+    largest velocity after 40 steps, over cells active in both."""
+    w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    o.step(40, oracle_mod.FSL_STRESS)
+    s.step(40, fs.FSL_STRESS)
+    _, uo = o.macro()
+    g = s.fields(("u", "flags"))
+    act = (g["flags"] != W.GAS) & (o.flags() != W.GAS)
+    err = np.abs(g["u"][:, act] - uo[:, act]).max() / np.abs(uo[:, act]).max()
+    _say(precision, "stress rule sloshing u rel err", err, "flag mismatches", int((g["flags"] != o.flags()).sum()))
+    assert err < tol
