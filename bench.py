@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32"}
 HEADLINE = "fp16s"
+RULE_NAME = {0: "FSK", 1: "FSL", 2: "FSK with the shear-rate boundary term", 3: "FSL with the shear-rate boundary term"}
 SWEEP_KERNEL = {"fp64": "k_sweep<FormF64, 1, false>", "fp32": "k_sweep<FormF32, 1, false>",
                 "fp16s": "k_sweep_h2<1>"}
 
@@ -212,7 +213,7 @@ def adjoint_leg(log, T=400, config="slosh128"):
             "fp32_grad_err_vs_fp64": err, "forms": out}
 
 
-def cpu_baseline(w_full, log, budget_s=12.0):
+def cpu_baseline(w_full, log, budget_s=12.0, rule=1):
     """The serial FP64 oracle on a z-slab of the same tank (same x-y profile,
     walls on all faces), timed on one host core."""
     import oracle
@@ -225,16 +226,16 @@ def cpu_baseline(w_full, log, budget_s=12.0):
     o = oracle.Oracle.from_workload(w)
     n_act = int((w.flags != 0).sum())
     t0 = time.time()
-    o.step(1, 1)
+    o.step(1, rule)
     t1 = time.time() - t0
     n = max(1, int(budget_s / max(t1, 1e-3)) - 1)
     t0 = time.time()
-    o.step(n, 1)
+    o.step(n, rule)
     dt = time.time() - t0
     mlups = n_act * n / dt / 1e6
     log(f"[cpu oracle] {n} steps of {p.nx}x{p.ny}x{nz}: {mlups:.2f} MLUPS")
     return {"value": mlups, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{n} FSL steps (after 1 untimed) of a {p.nx}x{p.ny}x{nz} z-slab of the same tank "
+            "sample": f"{n} {RULE_NAME[rule]} steps (after 1 untimed) of a {p.nx}x{p.ny}x{nz} z-slab of the same tank "
                       f"({n_act} active cells), serial FP64 oracle, 1 thread"}
 
 
@@ -303,7 +304,7 @@ def main():
         "storage": "f16" if head == "fp16s" else DTYPE[head],
         "data": "synthetic",
         "config": {"workload": f"sloshing tank {w.params.nx}x{w.params.ny}x{w.params.nz} "
-                               f"(depth {w.meta['depth']:g}, amplitude {w.meta['amp']:g}, seed 0), FSL rule, "
+                               f"(depth {w.meta['depth']:g}, amplitude {w.meta['amp']:g}, seed 0), {RULE_NAME[args.rule]} rule, "
                                f"tau {w.params.tau}, g_y {w.params.g[1]:g}",
                    "cells": w.params.n_cells, "active_cells": r["active_cells"], "form": head},
         "roofline": roof,
@@ -312,7 +313,7 @@ def main():
     if not args.no_adjoint:
         line["adjoint"] = adjoint_leg(log)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, log)
+        line["cpu_baseline"] = cpu_baseline(w, log, rule=args.rule)
     print(json.dumps(line), flush=True)
 
 
