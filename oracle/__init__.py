@@ -35,7 +35,8 @@ class _RefParams(ctypes.Structure):
                 ("tau", ctypes.c_double), ("Lambda", ctypes.c_double),
                 ("incompressible", ctypes.c_int), ("stokes", ctypes.c_int),
                 ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
-                ("rho_gas", ctypes.c_double), ("eps", ctypes.c_double)]
+                ("rho_gas", ctypes.c_double), ("eps", ctypes.c_double),
+                ("wall_u", ctypes.c_double * 18), ("shear_b", ctypes.c_double * 6)]
 
 
 _lib = None
@@ -89,13 +90,18 @@ def _dptr(a: np.ndarray):
 
 
 def _params(p) -> _RefParams:
+    wall = getattr(p, "wall_u", ((0.0, 0.0, 0.0),) * 6)
+    shear = getattr(p, "shear_b", (0.0,) * 6)
     return _RefParams(p.nx, p.ny, p.nz, int(p.periodic[0]), int(p.periodic[1]), int(p.periodic[2]),
                       float(p.tau), float(p.Lambda), int(p.incompressible), int(p.stokes),
-                      float(p.g[0]), float(p.g[1]), float(p.g[2]), float(p.rho_gas), float(p.eps))
+                      float(p.g[0]), float(p.g[1]), float(p.g[2]), float(p.rho_gas), float(p.eps),
+                      (ctypes.c_double * 18)(*[float(v) for face in wall for v in face]),
+                      (ctypes.c_double * 6)(*[float(v) for v in shear]))
 
 
 FSK, FSL = 0, 1
-FSK_STRESS, FSL_STRESS = 2, 3  # with the shear-rate boundary term (Table 1, column D)
+FSK_STRESS, FSL_STRESS = 2, 3  # with the shear-rate boundary term (Table 1, column D) from the bulk
+FSK_SHEAR, FSL_SHEAR = 4, 5    # the same term with the prescribed S^b (params.shear_b)
 LISTS = {"F": 0, "E": 1, "E'": 2, "NI": 3, "NL": 4}
 
 

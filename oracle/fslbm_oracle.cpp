@@ -27,6 +27,8 @@ struct ref_params {
   int incompressible, stokes;
   double gx, gy, gz;
   double rho_gas, eps;
+  double wall_u[18];  // faces x-, x+, y-, y+, z-, z+
+  double shear_b[6];  // prescribed S^b [xx, yy, zz, xy, xz, yz]
 };
 
 static Params to_params(const ref_params* r) {
@@ -46,6 +48,9 @@ static Params to_params(const ref_params* r) {
   p.g[2] = r->gz;
   p.rho_gas = r->rho_gas;
   p.eps = r->eps;
+  for (int f = 0; f < 6; ++f)
+    for (int a = 0; a < 3; ++a) p.wall_u[f][a] = r->wall_u[3 * f + a];
+  for (int i = 0; i < 6; ++i) p.shear_b[i] = r->shear_b[i];
   return p;
 }
 
@@ -88,10 +93,11 @@ const char* ref_error(void* hp) { return static_cast<Handle*>(hp)->err.c_str(); 
 void ref_set_freeze(void* hp, int freeze) { static_cast<Handle*>(hp)->sim.freeze = freeze != 0; }
 
 // n steps with rule 0 = FSK, 1 = FSL, 2 / 3 = FSK / FSL with the shear-rate
-// boundary term (D of Table 1).  Returns 0, or 1 with ref_error() set.
+// boundary term (D of Table 1) from the bulk, 4 / 5 = the same with the
+// prescribed S^b.  Returns 0, or 1 with ref_error() set.
 int ref_step(void* hp, int n, int rule) {
   auto* h = static_cast<Handle*>(hp);
-  if (rule < 0 || rule > 3) {
+  if (rule < 0 || rule > 5) {
     h->err = "unknown rule";
     return 1;
   }

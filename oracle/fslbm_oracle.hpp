@@ -50,10 +50,11 @@ inline double weight(int q) {
 }
 
 enum CellType : uint8_t { GAS = 0, INTERFACE = 1, LIQUID = 2 };
-// Rules: bit 0 selects the FSL construction (else the FSK row of Table 1),
-// bit 1 the full boundary value term of Eq. (bterm) with the shear-rate entry
-// D c_a c_b S^b_ab (Table 1, column D; section 3.4), else D = 0.
-enum Rule { FSK = 0, FSL = 1, FSK_STRESS = 2, FSL_STRESS = 3 };
+// Rules: bit 0 selects the FSL construction (else the FSK row of Table 1).
+// Bit 1 adds the shear-rate entry D c_a c_b S^b_ab of Eq. (bterm) (Table 1,
+// column D; section 3.4) with S^b from the bulk; bit 2 adds it with a
+// prescribed S^b (section 4.2, linear Couette flow).  Without either, D = 0.
+enum Rule { FSK = 0, FSL = 1, FSK_STRESS = 2, FSL_STRESS = 3, FSK_SHEAR = 4, FSL_SHEAR = 5 };
 
 // Model parameters.  tau is the symmetric relaxation time (lambda_+ = -1/tau),
 // Lambda = Lambda_+ Lambda_- fixes lambda_- (section 3.1).  g is the body
@@ -67,6 +68,8 @@ struct Params {
   double g[3];
   double rho_gas;
   double eps;          // conversion threshold margin
+  double wall_u[6][3]; // velocity of the wall faces x-, x+, y-, y+, z-, z+
+  double shear_b[6];   // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules with bit 2)
 };
 
 // ---------------------------------------------------------------------------
@@ -123,6 +126,20 @@ struct Oracle {
     thr_lo = T(-p.eps);
     rho_b = T(p.rho_gas);
     Lam_p = T(Lp);
+  }
+
+  // Velocity of the wall a link's source lies beyond: the first non-periodic
+  // face crossed, in axis order x, y, z (faces x-, x+, y-, y+, z-, z+).
+  const double* wall_velocity(int x, int y, int z, int q) const {
+    static const double zero[3] = {0.0, 0.0, 0.0};
+    const int c[3] = {x - CV[q][0], y - CV[q][1], z - CV[q][2]};
+    const int n[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (p.periodic[a]) continue;
+      if (c[a] < 0) return p.wall_u[2 * a];
+      if (c[a] >= n[a]) return p.wall_u[2 * a + 1];
+    }
+    return zero;
   }
 
   // neighbour of cell (x,y,z) at offset d; -1 if it lies beyond a wall
@@ -440,7 +457,12 @@ struct Oracle {
         int s = neighbor(x, y, z, -CV[q][0], -CV[q][1], -CV[q][2]);
         src[q] = s;
         if (s < 0) {
+          // halfway bounce-back off a wall moving with u_w (section 4.1):
+          // f_q = ft_qbar + 2 w_q (c_q . u_w) / c_s^2, with rho_w = 1
           f[q] = own[opposite(q)];
+          const double* uw = wall_velocity(x, y, z, q);
+          double cu = (CV[q][0] * uw[0] + CV[q][1] * uw[1]) + CV[q][2] * uw[2];
+          if (cu != 0.0) f[q] = f[q] + T(6.0 * weight(q) * cu);
         } else if (type[s] == GAS) {
           if (!iface) throw std::runtime_error("liquid cell with gas neighbour");
           gaslink[q] = true;
@@ -513,9 +535,11 @@ struct Oracle {
         // Eq. (proj1) with sigma = 0 asks P - P_b = 2 nu S_nn, and with
         // nu = c_s^2 Lambda_+ that is S^b_nn = (1 - 2 c_s^2) S_nn = S_nn / 3.
         // Without a normal there is no local basis and the term is left out.
-        const bool stress = (rule & 2) && have_normal;
+        const bool stress = ((rule & 2) && have_normal) || (rule & 4);
         T Sb[6] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
-        if (stress) {
+        if (rule & 4) {
+          for (int i = 0; i < 6; ++i) Sb[i] = T(p.shear_b[i]);  // prescribed boundary value
+        } else if (stress) {
           int nb = bulk_neighbour(x, y, z, nvec);
           T fb[Q];
           for (int q = 0; q < Q; ++q) fb[q] = nb < 0 ? own[q] : ft[(size_t)q * N + nb];

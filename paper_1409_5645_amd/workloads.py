@@ -44,6 +44,8 @@ class Params:
     g: tuple = (0.0, 0.0, 0.0)
     rho_gas: float = 1.0
     eps: float = 1e-3
+    wall_u: tuple = ((0.0, 0.0, 0.0),) * 6   # wall face velocities: x-, x+, y-, y+, z-, z+
+    shear_b: tuple = (0.0,) * 6               # prescribed S^b [xx, yy, zz, xy, xz, yz]
 
     @property
     def n_cells(self) -> int:
