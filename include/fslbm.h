@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define FSLBM_ABI_VERSION 1
+#define FSLBM_ABI_VERSION 2
 
 typedef struct fslbm_ctx fslbm_ctx;
 
@@ -64,7 +64,15 @@ typedef enum {
  * liquid neighbour opposite the surface normal, and S^b keeps its tangential
  * block, has zero tangential-normal entries (Eq. proj2) and normal entry
  * S_nn / 3 (Eq. proj1 with sigma = 0). */
-enum { FSLBM_RULE_FSK = 0, FSLBM_RULE_FSL = 1, FSLBM_RULE_FSK_STRESS = 2, FSLBM_RULE_FSL_STRESS = 3 };
+enum {
+  FSLBM_RULE_FSK = 0,
+  FSLBM_RULE_FSL = 1,
+  FSLBM_RULE_FSK_STRESS = 2,
+  FSLBM_RULE_FSL_STRESS = 3,
+  /* the same D term with S^b given in fslbm_params.shear_b (section 4.2) */
+  FSLBM_RULE_FSK_SHEAR = 4,
+  FSLBM_RULE_FSL_SHEAR = 5
+};
 
 /* Precision forms.  FP64: populations f stored and computed in double.
  * FP32: shifted populations f - w_q stored and computed in float.
@@ -90,6 +98,12 @@ typedef struct {
   double conv_eps;          /* conversion margin: filled m > (1+eps) rho, emptied m < -eps rho */
   int32_t fp16_scale_log2;  /* FP16S scale exponent k (storage 2^k (f - w)); 0..24 */
   int32_t freeze;           /* nonzero: frozen flag topology, no conversions */
+  double wall_u[6][3];      /* velocity of each wall face, in the order x-, x+, y-, y+, z-, z+
+                               (ignored on periodic axes).  Halfway bounce-back off a moving
+                               wall adds 2 w_q (c_q . u_w) / c_s^2 (rho_w = 1); a link leaving
+                               through an edge takes the first crossed face in x, y, z order */
+  double shear_b[6];        /* prescribed boundary shear rate S^b = [xx, yy, zz, xy, xz, yz]
+                               of the FSLBM_RULE_*_SHEAR rules (section 4.2) */
 } fslbm_params;
 
 typedef struct {

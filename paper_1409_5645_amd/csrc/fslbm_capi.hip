@@ -137,6 +137,13 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
   f.Lp = (float)d.Lp;
   com.incomp = p.incompressible ? 1 : 0;
   com.stokes = p.stokes ? 1 : 0;
+  com.moving = 0;
+  for (int f = 0; f < 6; ++f)
+    for (int a = 0; a < 3; ++a) {
+      com.wall_u[f][a] = p.periodic[f / 2] ? 0.0 : p.wall_u[f][a];
+      if (com.wall_u[f][a] != 0.0) com.moving = 1;
+    }
+  for (int i = 0; i < 6; ++i) com.shear_b[i] = p.shear_b[i];
   com.scale = std::ldexp(1.0f, p.fp16_scale_log2);
   com.inv_scale = std::ldexp(1.0f, -p.fp16_scale_log2);
   com.grid.nx = p.nx;
@@ -264,7 +271,7 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
   if (!c) return FSLBM_E_INVALID;
   if (n < 0) { c->last_error = "n must be >= 0"; return FSLBM_E_INVALID; }
-  if (rule < FSLBM_RULE_FSK || rule > FSLBM_RULE_FSL_STRESS) { c->last_error = "unknown rule"; return FSLBM_E_INVALID; }
+  if (rule < FSLBM_RULE_FSK || rule > FSLBM_RULE_FSL_SHEAR) { c->last_error = "unknown rule"; return FSLBM_E_INVALID; }
   if (rule != FSLBM_RULE_FSK && c->p.tau == 1.0) {
     c->last_error = "this rule needs tau != 1 (n+ is not recoverable from a fully relaxed state)";
     return FSLBM_E_UNSUPPORTED;
@@ -717,7 +724,7 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   if (!c) return FSLBM_E_INVALID;
   if (!out || !workspace) { c->last_error = "out or workspace is NULL"; return FSLBM_E_INVALID; }
   if (((uintptr_t)workspace) % ALIGN) { c->last_error = "window workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
-  if (rule == FSLBM_RULE_FSK_STRESS || rule == FSLBM_RULE_FSL_STRESS) {
+  if (rule >= FSLBM_RULE_FSK_STRESS && rule <= FSLBM_RULE_FSL_SHEAR) {
     c->last_error = "the adjoint window supports the FSK and FSL rules (D = 0)";
     return FSLBM_E_UNSUPPORTED;
   }

@@ -18,6 +18,9 @@ struct Common {
   Consts<float> kf;
   int incomp, stokes;
   float scale, inv_scale;  // FP16 storage scaling (powers of two)
+  int moving;              // some wall face moves (wall_u not all zero)
+  double wall_u[6][3];     // wall face velocities: x-, x+, y-, y+, z-, z+
+  double shear_b[6];       // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules 4, 5)
 };
 
 template <class R>

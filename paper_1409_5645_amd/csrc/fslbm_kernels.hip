@@ -177,11 +177,16 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
     recover_moments<R, SH>(d.own, k, incomp, rho_t, u_t);
     const R rho0_t = rho0_of<R, SH>(rho_t, incomp);
     const R usq_t = usq_of(u_t);
-    // boundary shear rate for the rules with D != 0 (needs the local basis)
+    // boundary shear rate for the rules with D != 0: from the bulk (needs the
+    // local basis) or prescribed
     R Sb[6] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
-    const bool stress = (RULE & 2) && have_n;
+    const bool stress = ((RULE & 2) && have_n) || (RULE & 4);
     if constexpr ((RULE & 2) != 0) {
       if (stress) boundary_shear<F>(d, nb, cm.grid, fin, cm.inv_scale, nv, k, incomp, stokes, Sb);
+    }
+    if constexpr ((RULE & 4) != 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) Sb[i] = (R)cm.shear_b[i];
     }
 #define FSLBM_REBUILD(q) \
   rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, rho0_t, u_t, usq_t, k, incomp, stokes, Sb, stress);
@@ -243,6 +248,19 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
   }
     FSLBM_LINKS(FSLBM_ILOAD)
 #undef FSLBM_ILOAD
+    if (a.c.moving) {
+      // moving walls (uniform branch): halfway bounce-back gains 2 w_q (c_q . u_w) / c_s^2
+#define FSLBM_IWALLU(q)                                                                        \
+  {                                                                                            \
+    const int face = wall_face<q>(n.xm, n.xp, n.ym, n.yp, n.zm, n.zp);                         \
+    if (face >= 0) {                                                                           \
+      const double t = wall_term<q>(a.c, face);                                                \
+      if (t != 0.0) d.f[q] = d.f[q] + (R)t;                                                    \
+    }                                                                                          \
+  }
+      FSLBM_LINKS(FSLBM_IWALLU)
+#undef FSLBM_IWALLU
+    }
     d.m = a.mass_in[idx];
     d.phix = a.phi_in[idx];
     if constexpr (REC) {
@@ -637,8 +655,12 @@ static void iface_form(const StepLaunch& L, int rule) {
     k_iface<F, 1><<<nb, IBLOCK, 0, st>>>(L.sweep);
   } else if (rule == 2) {
     k_iface<F, 2><<<nb, IBLOCK, 0, st>>>(L.sweep);
-  } else {
+  } else if (rule == 3) {
     k_iface<F, 3><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  } else if (rule == 4) {
+    k_iface<F, 4><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  } else {
+    k_iface<F, 5><<<nb, IBLOCK, 0, st>>>(L.sweep);
   }
 }
 

@@ -47,6 +47,29 @@ __device__ __forceinline__ double phi_seen(const IfaceData<F>& d, int q) {
   return d.ty[q] == LIQ ? 1.0 : (d.ty[q] == GAS ? 0.0 : d.ph[q]);
 }
 
+// Halfway bounce-back off a moving wall: the population pulled along q from
+// beyond wall face `face` (x-, x+, y-, y+, z-, z+) gains 2 w_q (c_q . u_w) / c_s^2
+// (rho_w = 1).  Returns that term in FP64, 0 when the wall is at rest.
+template <int q>
+__device__ __forceinline__ double wall_term(const Common& cm, int face) {
+  const double* uw = cm.wall_u[face];
+  const double cu = (CX[q] * uw[0] + CY[q] * uw[1]) + CZ[q] * uw[2];
+  return cu != 0.0 ? 6.0 * WD[q] * cu : 0.0;
+}
+
+// Face crossed by the pull source x - c_q of a wall link (first in axis order
+// x, y, z), from the neighbour coordinates (-1 beyond a wall); -1 if none.
+template <int q>
+__device__ __forceinline__ int wall_face(int xm, int xp, int ym, int yp, int zm, int zp) {
+  if (CX[q] == 1 && xm < 0) return 0;
+  if (CX[q] == -1 && xp < 0) return 1;
+  if (CY[q] == 1 && ym < 0) return 2;
+  if (CY[q] == -1 && yp < 0) return 3;
+  if (CZ[q] == 1 && zm < 0) return 4;
+  if (CZ[q] == -1 && zp < 0) return 5;
+  return -1;
+}
+
 // c_q . S . c_q for a symmetric S = [xx, yy, zz, xy, xz, yz]
 template <int q, class R>
 __device__ __forceinline__ R c_S_c(const R (&S)[6]) {
@@ -59,8 +82,9 @@ __device__ __forceinline__ R c_S_c(const R (&S)[6]) {
 // With o = qbar the link pointing to gas, the closure Eq. (closure) gives
 //   f_q = a0 ft_o(x) + a0bar ft_q(x) + a1 f_o(x,t+1) + C n+_o(x,t) + alpha_+ e+_o(rho_b,u_b)
 // with the FSK row of Table 1 (Eq. koerner) or Eq. (fsli1)-(fsli4) at alpha_+ = 1
-// (RULE bit 0), plus, with RULE bit 1, the shear-rate part of the boundary value
-// Eq. (bterm): D c_o c_o : S^b with D = -alpha_+ Lambda_+ w_o / c_s^2 (Table 1).
+// (RULE bit 0), plus, with RULE bit 1 (S^b from the bulk) or bit 2 (S^b
+// prescribed), the shear-rate part of the boundary value Eq. (bterm):
+// D c_o c_o : S^b with D = -alpha_+ Lambda_+ w_o / c_s^2 (Table 1).
 template <class F, int RULE, int q>
 __device__ __forceinline__ void rebuild(IfaceData<F>& d, uint32_t gasmask, bool have_n, const double (&nv)[3],
                                         double dist, typename F::R rho_t, typename F::R rho0_t,
@@ -94,14 +118,14 @@ __device__ __forceinline__ void rebuild(IfaceData<F>& d, uint32_t gasmask, bool 
       const R a1 = delta - R(1.0);
       const R Cc = k.lp * (R(0.5) + delta) - R(2.0) * k.lp;
       d.f[q] = (((a0 * own_o + R(0.5) * own_q) + a1 * d.f[o]) + Cc * n_plus) + e_b;
-      if constexpr ((RULE & 2) != 0) {
+      if constexpr ((RULE & 6) != 0) {
         if (stress) d.f[q] = d.f[q] + (-((R(1.0) * k.Lp) * R(3.0 * WD[o]))) * c_S_c<o>(Sb);  // alpha_+ = 1
       }
       return;
     }
   }
   d.f[q] = R(2.0) * e_b - own_o;  // FSK: -ft_o + 2 e+_o(rho_b, u_b)
-  if constexpr ((RULE & 2) != 0) {
+  if constexpr ((RULE & 6) != 0) {
     if (stress) d.f[q] = d.f[q] + (-((R(2.0) * k.Lp) * R(3.0 * WD[o]))) * c_S_c<o>(Sb);  // alpha_+ = 2
   }
 }

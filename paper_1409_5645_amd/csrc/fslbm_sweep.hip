@@ -81,6 +81,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   FSLBM_PULL(0)
   FSLBM_LINKS(FSLBM_PULL)
 #undef FSLBM_PULL
+  if (a.c.moving) {
+    // moving walls (uniform branch): halfway bounce-back gains 2 w_q (c_q . u_w) / c_s^2,
+    // in storage units for the FP16 form
+    const double su = F::scaled ? (double)a.c.scale : 1.0;
+#define FSLBM_WALLU(q)                                                         \
+  {                                                                            \
+    const int face = wall_face<q>(xm, xp, ym, yp, zm, zp);                     \
+    if (face >= 0) {                                                           \
+      const double t = wall_term<q>(a.c, face);                                \
+      if (t != 0.0) f[q] = f[q] + (R)(t * su);                                 \
+    }                                                                          \
+  }
+    FSLBM_LINKS(FSLBM_WALLU)
+#undef FSLBM_WALLU
+  }
 
   // ---- TRT collision, Eq. (lbe2)
   const Consts<R>& k = pick_consts<R>(a.c);
@@ -286,8 +301,9 @@ hipError_t launch_sweep(const StepLaunch& L, int precision, int rule) {
   (void)rule;  // the sweep covers liquid cells only; the rule acts in k_iface
   if (precision == 0) sweep_form<FormF64>(L);
   else if (precision == 1) sweep_form<FormF32>(L);
-  else if (L.sweep.c.grid.nx % 2 == 0 && L.sweep.pairs && 38.0 * (double)L.sweep.c.grid.N < 4294967296.0)
-    sweep_h2(L);
+  else if (L.sweep.c.grid.nx % 2 == 0 && L.sweep.pairs && !L.sweep.c.moving &&
+           38.0 * (double)L.sweep.c.grid.N < 4294967296.0)
+    sweep_h2(L);  // two cells per lane (moving walls take the one-cell form)
   else sweep_form<FormF16>(L);
   return hipGetLastError();
 }

@@ -16,13 +16,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfslbm.so")
 
 FSK, FSL = 0, 1
-FSK_STRESS, FSL_STRESS = 2, 3  # with the shear-rate boundary term (Table 1, column D)
+FSK_STRESS, FSL_STRESS = 2, 3  # with the shear-rate boundary term (Table 1, column D) from the bulk
+FSK_SHEAR, FSL_SHEAR = 4, 5    # the same term with the prescribed S^b (params.shear_b)
 FP64, FP32, FP16S = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 GAS, INTERFACE, LIQUID = 0, 1, 2
 STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "DEVICE", 4: "UNSTABLE", 5: "INVARIANT", 6: "CAPACITY"}
 FIELDS = ("rho", "u", "phi", "flags", "f", "mass", "rho_c", "u_c")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class FslbmError(RuntimeError):
@@ -36,7 +37,8 @@ class Params(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("periodic", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("magic", ctypes.c_double), ("incompressible", ctypes.c_int32),
                 ("stokes", ctypes.c_int32), ("g", ctypes.c_double * 3), ("rho_gas", ctypes.c_double),
-                ("conv_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32), ("freeze", ctypes.c_int32)]
+                ("conv_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32), ("freeze", ctypes.c_int32),
+                ("wall_u", (ctypes.c_double * 3) * 6), ("shear_b", ctypes.c_double * 6)]
 
 
 class Buffers(ctypes.Structure):
@@ -92,7 +94,10 @@ def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13) -> Params:
     return Params(ABI_VERSION, p.nx, p.ny, p.nz, (ctypes.c_int32 * 3)(*[int(v) for v in p.periodic]),
                   int(precision), float(p.tau), float(p.Lambda), int(p.incompressible), int(p.stokes),
                   (ctypes.c_double * 3)(*[float(v) for v in p.g]), float(p.rho_gas), float(p.eps),
-                  int(fp16_scale_log2), int(bool(freeze)))
+                  int(fp16_scale_log2), int(bool(freeze)),
+                  ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*[float(v) for v in face])
+                                                 for face in getattr(p, "wall_u", ((0.0, 0.0, 0.0),) * 6)]),
+                  (ctypes.c_double * 6)(*[float(v) for v in getattr(p, "shear_b", (0.0,) * 6)]))
 
 
 class Sim:

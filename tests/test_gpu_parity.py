@@ -250,3 +250,52 @@ def test_reduced_precision_stress_rule(fs, oracle_mod, precision, tol):
     err = np.abs(g["u"][:, act] - uo[:, act]).max() / np.abs(uo[:, act]).max()
     _say(precision, "stress rule sloshing u rel err", err, "flag mismatches", int((g["flags"] != o.flags()).sum()))
     assert err < tol
+
+
+def _with(w, **kw):
+    import dataclasses
+    return dataclasses.replace(w, params=dataclasses.replace(w.params, **kw))
+
+
+_MOVING = ((0.0, 0.0, 3e-3), (0.0, 0.0, 0.0), (1e-3, 0.0, -5e-4), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (2e-3, 0.0, 0.0))
+
+
+@pytest.mark.parametrize("rule", [1, 5, 4, 3])
+def test_moving_walls_and_prescribed_shear_parity(fs, oracle_mod, rule):
+    """Walls moving along themselves (x-, y- and z+ faces, so links leaving
+    through edges take the first crossed face) and the prescribed boundary
+    shear S^b (rules 5, 4): classes, lists and populations bit-exact against
+    the oracle on a converting tank (37 x 24 x 10, ragged rows)."""
+    w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
+    w = _with(w, wall_u=_MOVING, shear_b=(1e-4, -2e-4, 5e-5, 3e-4, -1e-4, 2e-4))
+    _say(f"case moving walls + shear, rule {rule}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(60):
+        o.step(1, rule)
+        s.step(1, rule)
+        if it % 10 == 9:
+            _compare(o, s, f"step {it + 1}")
+    st = s.stats()
+    assert st["total_mass"] == pytest.approx(o.total_mass(), rel=1e-12)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp16s", 3e-2)])
+def test_plate_driven_reduced_precision(fs, oracle_mod, precision, tol):
+    """A film dragged by its bottom wall (x, z periodic, so the FP16 form would
+    otherwise take the two-cells sweep): FP32 and FP16 storage against the FP64
+    oracle, velocity error relative to the wall speed after 400 steps."""
+    w = W.channel(h=16.5, nx=64, ny=20, nz=2, gx=0.0, tau=0.8, Lambda=0.25)
+    w = _with(w, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (1e-3, 0.0, 0.0), (0.0, 0.0, 0.0),
+                         (0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    o.step(400, 1)
+    s.step(400, 1)
+    _, uo = o.macro()
+    ug = s.fields(("u",))["u"]
+    act = w.flags != W.GAS
+    err = np.abs(ug[0, act] - uo[0, act]).max() / 1e-3
+    _say(precision, "plate-driven u err / u_wall", err)
+    assert uo[0, act].min() > 1e-5
+    assert err < tol
