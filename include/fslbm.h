@@ -104,6 +104,11 @@ typedef struct {
                                through an edge takes the first crossed face in x, y, z order */
   double shear_b[6];        /* prescribed boundary shear rate S^b = [xx, yy, zz, xy, xz, yz]
                                of the FSLBM_RULE_*_SHEAR rules (section 4.2) */
+  double sigma;             /* surface tension coefficient (>= 0).  The boundary term takes the
+                               gas pressure P_b - sigma kappa (Eq. freeboundary) with kappa =
+                               -div n from the fill field's gradient and Hessian by central
+                               differences over the D3Q19 neighbourhood; not supported by the
+                               adjoint window */
 } fslbm_params;
 
 typedef struct {

@@ -36,7 +36,8 @@ class _RefParams(ctypes.Structure):
                 ("incompressible", ctypes.c_int), ("stokes", ctypes.c_int),
                 ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
                 ("rho_gas", ctypes.c_double), ("eps", ctypes.c_double),
-                ("wall_u", ctypes.c_double * 18), ("shear_b", ctypes.c_double * 6)]
+                ("wall_u", ctypes.c_double * 18), ("shear_b", ctypes.c_double * 6),
+                ("sigma", ctypes.c_double)]
 
 
 _lib = None
@@ -78,6 +79,8 @@ def lib():
         L.ref_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         L.ref_shear.argtypes = [vp, dp, dp]
         L.ref_boundary_shear.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.ref_curvature.restype = ctypes.c_double
+        L.ref_curvature.argtypes = [dp]
         L.ref_window_dual.restype = ctypes.c_int
         L.ref_window_dual.argtypes = [ctypes.POINTER(_RefParams), u8p, dp, dp, dp, dp, dp, dp, ctypes.c_double,
                                       dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
@@ -96,7 +99,8 @@ def _params(p) -> _RefParams:
                       float(p.tau), float(p.Lambda), int(p.incompressible), int(p.stokes),
                       float(p.g[0]), float(p.g[1]), float(p.g[2]), float(p.rho_gas), float(p.eps),
                       (ctypes.c_double * 18)(*[float(v) for face in wall for v in face]),
-                      (ctypes.c_double * 6)(*[float(v) for v in shear]))
+                      (ctypes.c_double * 6)(*[float(v) for v in shear]),
+                      float(getattr(p, "sigma", 0.0)))
 
 
 FSK, FSL = 0, 1
@@ -238,6 +242,13 @@ def boundary_shear(S, n, s_nn: float) -> np.ndarray:
     out = np.empty(6)
     lib().ref_boundary_shear(_dptr(SS), _dptr(nn), float(s_nn), _dptr(out))
     return out
+
+
+def curvature(block) -> float:
+    """Curvature kappa = -div n of a fill field given on the 3x3x3 block around a
+    cell, block[dx+1, dy+1, dz+1] (corners unused)."""
+    b = np.ascontiguousarray(np.asarray(block, dtype=np.float64).transpose(2, 1, 0)).reshape(-1)
+    return float(lib().ref_curvature(_dptr(b)))
 
 
 def window_dual(params, flags, f0, m0, phi0, u_target, phi_target, T: int, rule: int = FSL,

@@ -29,6 +29,7 @@ struct ref_params {
   double rho_gas, eps;
   double wall_u[18];  // faces x-, x+, y-, y+, z-, z+
   double shear_b[6];  // prescribed S^b [xx, yy, zz, xy, xz, yz]
+  double sigma;       // surface tension coefficient
 };
 
 static Params to_params(const ref_params* r) {
@@ -51,6 +52,7 @@ static Params to_params(const ref_params* r) {
   for (int f = 0; f < 6; ++f)
     for (int a = 0; a < 3; ++a) p.wall_u[f][a] = r->wall_u[3 * f + a];
   for (int i = 0; i < 6; ++i) p.shear_b[i] = r->shear_b[i];
+  p.sigma = r->sigma;
   return p;
 }
 
@@ -190,6 +192,16 @@ void ref_shear(void* hp, const double* own19, double* S6) {
   s.recover_moments(own19, rho, u);
   s.shear_from_own(own19, rho, s.rho0_of(rho), u, S6);
 }
+// Curvature of the fill field from the 3x3x3 block v27[(dx+1) + 3(dy+1) + 9(dz+1)]
+// around a cell (corners unused); kappa = -div n, n = -grad/|grad|.
+double ref_curvature(const double* v27) {
+  double v[3][3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) v[a][b][c] = v27[a + 3 * b + 9 * c];
+  return fsref::Oracle<double>::curvature(v);
+}
+
 // Boundary value S^b = P S P + s_nn n n^T of section 3.4 (n a unit vector).
 void ref_boundary_shear(const double* S6, const double* n3, double s_nn, double* Sb6) {
   fsref::Oracle<double>::boundary_shear(S6, n3, s_nn, Sb6);

@@ -70,6 +70,7 @@ struct Params {
   double eps;          // conversion threshold margin
   double wall_u[6][3]; // velocity of the wall faces x-, x+, y-, y+, z-, z+
   double shear_b[6];   // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules with bit 2)
+  double sigma;        // surface tension coefficient (0: none)
 };
 
 // ---------------------------------------------------------------------------
@@ -360,6 +361,39 @@ struct Oracle {
     return best;
   }
 
+  // ----------------------------------------------------- curvature (2.3)
+  // Curvature kappa of the free boundary for the pressure jump of Eq.
+  // (freeboundary): with the fill gradient g and Hessian H by central
+  // differences over the D3Q19 neighbourhood (v[dx+1][dy+1][dz+1]: fill seen
+  // from the cell, corners unused), the normal n = -g/|g| points to the gas and
+  //   kappa = div(g/|g|) = (|g|^2 tr H - g.H.g) / |g|^3 = -div n,
+  // so that P = P_b - sigma kappa is the Laplace pressure P_b + sigma div n
+  // (a sphere of radius R: kappa = -2/R).  Zero if g = 0.
+  static T curvature(const T v[3][3][3]) {
+    const T c = v[1][1][1];
+    T g[3], H[3][3];
+    g[0] = T(0.5) * (v[2][1][1] - v[0][1][1]);
+    g[1] = T(0.5) * (v[1][2][1] - v[1][0][1]);
+    g[2] = T(0.5) * (v[1][1][2] - v[1][1][0]);
+    H[0][0] = (v[2][1][1] - T(2.0) * c) + v[0][1][1];
+    H[1][1] = (v[1][2][1] - T(2.0) * c) + v[1][0][1];
+    H[2][2] = (v[1][1][2] - T(2.0) * c) + v[1][1][0];
+    H[0][1] = H[1][0] = T(0.25) * (((v[2][2][1] - v[2][0][1]) - v[0][2][1]) + v[0][0][1]);
+    H[0][2] = H[2][0] = T(0.25) * (((v[2][1][2] - v[2][1][0]) - v[0][1][2]) + v[0][1][0]);
+    H[1][2] = H[2][1] = T(0.25) * (((v[1][2][2] - v[1][2][0]) - v[1][0][2]) + v[1][0][0]);
+    T g2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+    if (!(g2 > T(0.0))) return T(0.0);
+    T trH = (H[0][0] + H[1][1]) + H[2][2];
+    T gHg = T(0.0);
+    for (int a = 0; a < 3; ++a) {
+      T r = (H[a][0] * g[0] + H[a][1] * g[1]) + H[a][2] * g[2];
+      gHg = gHg + g[a] * r;
+    }
+    using std::sqrt;
+    T gn = sqrt(g2);
+    return (g2 * trH - gHg) / (g2 * gn);
+  }
+
   // n . S . n for a symmetric S given as [xx, yy, zz, xy, xz, yz]
   static T normal_normal(const T S[6], const T n[3]) {
     T d = (S[0] * (n[0] * n[0]) + S[1] * (n[1] * n[1])) + S[2] * (n[2] * n[2]);
@@ -516,13 +550,31 @@ struct Oracle {
         }
         T dist = phix - T(0.5);
 
+        // Laplace pressure: the boundary term takes P_b - sigma kappa (Eq.
+        // freeboundary), i.e. rho_b - 3 sigma kappa
+        T rho_bc = rho_b;
+        if (p.sigma != 0.0 && have_normal) {
+          T v[3][3][3];
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              for (int cc = 0; cc < 3; ++cc) {
+                v[a][b][cc] = T(0.0);
+                int nz_ = (a != 1) + (b != 1) + (cc != 1);
+                if (nz_ == 0) { v[a][b][cc] = phix; continue; }
+                if (nz_ == 3) continue;  // corners: not D3Q19 neighbours, unused
+                int sN = neighbor(x, y, z, a - 1, b - 1, cc - 1);
+                v[a][b][cc] = sN < 0 ? phix : phi_of(sN);
+              }
+          rho_bc = rho_b - T(3.0 * p.sigma) * curvature(v);
+        }
+
         // ---- S3 reconstruction of every population streaming in from gas.
         // In the paper's notation the link to gas is o (x + c_o is gas) and the
         // unknown is f_{obar} = f_q.  Moments of time t from the own state:
         T rho_t, u_t[3];
         recover_moments(own, rho_t, u_t);
         const T rho0_t = rho0_of(rho_t);
-        const T rho0_b = rho0_of(rho_b);
+        const T rho0_b = rho0_of(rho_bc);
         // Boundary shear rate for the rules with D != 0 (section 3.4): S
         // extrapolated from the bulk at order zero, i.e. taken from the
         // non-equilibrium of time t of the liquid neighbour x + c_k whose link
@@ -557,7 +609,7 @@ struct Oracle {
           // ft+ = e+ + (1 + lambda_+) n+
           T fplus = T(0.5) * (own[o] + own[q]);
           T n_plus = (fplus - e_plus(o, rho_t, rho0_t, u_t)) * inv_1p_lam_p;
-          T e_b = e_plus(o, rho_b, rho0_b, u_t);  // boundary value, u_b = u(x,t)
+          T e_b = e_plus(o, rho_bc, rho0_b, u_t);  // boundary value, u_b = u(x,t)
           Coeffs k = coeffs_fsk();
           T f_o_next = T(0.0);
           if (rule & 1) {

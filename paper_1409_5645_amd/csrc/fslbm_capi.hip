@@ -31,6 +31,8 @@ struct fslbm_ctx {
   int32_t *listF, *listE, *listEP, *listNI, *listNL, *listR, *listI;
   int32_t* counters;    // 2 sets of NCOUNT
   double* reservoir;
+  double* kappa = nullptr;  // surface tension only
+  double* wall_t = nullptr; // moving-wall terms [6][19]
   double* acc;
   int32_t* err;
   int32_t* cnt;
@@ -50,10 +52,28 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, total;
+  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, wall_t, kappa, total;
 };
 
-Layout layout(size_t N) {
+// Moving-wall bounce-back terms per face (x-, x+, y-, y+, z-, z+) and link:
+// 2 w_q (c_q . u_w) / c_s^2 in FP64 (zero on periodic axes and for walls at
+// rest), computed on the host as (c_x u_x + c_y u_y) + c_z u_z, times 6 w_q.
+void wall_table(const fslbm_params& p, double out[6 * Q]) {
+  static const int CV[Q][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                               {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                               {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                               {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  for (int f = 0; f < 6; ++f)
+    for (int q = 0; q < Q; ++q) {
+      const double* u = p.wall_u[f];
+      const double cu = (CV[q][0] * u[0] + CV[q][1] * u[1]) + CV[q][2] * u[2];
+      const double w = q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+      out[f * Q + q] = (p.periodic[f / 2] || cu == 0.0) ? 0.0 : 6.0 * w * cu;
+    }
+}
+
+// kappa: with surface tension, one Laplace-pressure correction per listed cell
+Layout layout(size_t N, bool kappa) {
   Layout L{};
   size_t o = 0;
   L.aux_rho = o;
@@ -72,6 +92,10 @@ Layout layout(size_t N) {
   o = align_up(o + 2 * NCOUNT * sizeof(int32_t));
   L.scalars = o;  // reservoir, acc, err(int), cnt[4] (int)
   o = align_up(o + 2 * sizeof(double) + 8 * sizeof(int32_t));
+  L.wall_t = o;
+  o = align_up(o + 8 * 6 * Q);
+  L.kappa = o;
+  if (kappa) o = align_up(o + 8 * N);
   L.total = o;
   return L;
 }
@@ -89,6 +113,12 @@ fslbm_status check_params(const fslbm_params* p, std::string& why) {
   if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24) { why = "fp16_scale_log2 must be in 0..24"; return FSLBM_E_INVALID; }
   if (!(p->rho_gas > 0.0)) { why = "rho_gas must be positive"; return FSLBM_E_INVALID; }
   if (!(p->conv_eps >= 0.0)) { why = "conv_eps must be >= 0"; return FSLBM_E_INVALID; }
+  if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be finite and >= 0"; return FSLBM_E_INVALID; }
+  for (int f = 0; f < 6; ++f)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->wall_u[f][a])) { why = "wall_u must be finite"; return FSLBM_E_INVALID; }
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(p->shear_b[i])) { why = "shear_b must be finite"; return FSLBM_E_INVALID; }
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->g[a])) { why = "g must be finite"; return FSLBM_E_INVALID; }
   return FSLBM_OK;
@@ -139,11 +169,11 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
   com.stokes = p.stokes ? 1 : 0;
   com.moving = 0;
   for (int f = 0; f < 6; ++f)
-    for (int a = 0; a < 3; ++a) {
-      com.wall_u[f][a] = p.periodic[f / 2] ? 0.0 : p.wall_u[f][a];
-      if (com.wall_u[f][a] != 0.0) com.moving = 1;
-    }
+    for (int a = 0; a < 3; ++a)
+      if (!p.periodic[f / 2] && p.wall_u[f][a] != 0.0) com.moving = 1;
   for (int i = 0; i < 6; ++i) com.shear_b[i] = p.shear_b[i];
+  com.sigma = p.sigma;
+  com.rho_gas = p.rho_gas;
   com.scale = std::ldexp(1.0f, p.fp16_scale_log2);
   com.inv_scale = std::ldexp(1.0f, -p.fp16_scale_log2);
   com.grid.nx = p.nx;
@@ -172,7 +202,7 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes) {
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!bytes) { g_init_error = "bytes is NULL"; return FSLBM_E_INVALID; }
-  *bytes = layout((size_t)p->nx * p->ny * p->nz).total;
+  *bytes = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0).total;
   return FSLBM_OK;
 }
 
@@ -186,7 +216,7 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
     return FSLBM_E_INVALID;
   }
   const size_t N = (size_t)p->nx * p->ny * p->nz;
-  const Layout L = layout(N);
+  const Layout L = layout(N, p->sigma != 0.0);
   if (b->workspace_bytes < L.total) { g_init_error = "workspace too small"; return FSLBM_E_INVALID; }
   if (((uintptr_t)b->workspace) % ALIGN) { g_init_error = "workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
 
@@ -211,6 +241,14 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   for (int i = 0; i < 7; ++i) *ls[i] = (int32_t*)(w + L.lists[i]);
   c->counters = (int32_t*)(w + L.counters);
   c->reservoir = (double*)(w + L.scalars);
+  if (p->sigma != 0.0) c->kappa = (double*)(w + L.kappa);
+  c->wall_t = (double*)(w + L.wall_t);
+  {
+    double tab[6 * Q];
+    wall_table(*p, tab);
+    HIPCHK(c, hipMemcpyAsync(c->wall_t, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream), "wall terms");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "wall terms sync");
+  }
   c->acc = c->reservoir + 1;
   c->err = (int32_t*)(c->reservoir + 2);
   c->cnt = c->err + 1;
@@ -303,6 +341,8 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.cpr = 0;
     s.pairs = c->pairs;
     s.u_out = nullptr;
+    s.kappa = c->kappa;
+    s.wall_t = c->wall_t;
     ConvArgs& v = L.conv;
     v.c = c->com;
     v.fout = c->f[b];
@@ -338,6 +378,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
       HIPCHK(c, hipEventRecord(c->events[c->events_used + 1], c->stream), "event record");
       c->events_used += 2;
     }
+    if (c->kappa) HIPCHK(c, launch_curvature(L), "curvature launch");
     HIPCHK(c, launch_iface(L, c->p.precision, rule), "interface launch");
     if (!c->p.freeze) HIPCHK(c, launch_convert(L, c->p.precision), "conversion launch");
     c->cur = b;
@@ -608,6 +649,10 @@ fslbm_status window_checks(fslbm_ctx* c, int32_t T, int32_t K) {
     c->last_error = "the adjoint window supports the incompressible equilibrium with its quadratic term";
     return FSLBM_E_UNSUPPORTED;
   }
+  if (c->p.sigma != 0.0) {
+    c->last_error = "the adjoint window does not support surface tension";
+    return FSLBM_E_UNSUPPORTED;
+  }
   return FSLBM_OK;
 }
 
@@ -653,6 +698,7 @@ hipError_t window_step(fslbm_window* w, const fslbm_window::State& A, const fslb
   s.cpr = 0;
   s.pairs = c->pairs;
   s.u_out = R.u;
+  s.wall_t = c->wall_t;
   L.stream = (void*)c->stream;
   hipError_t e = launch_sweep(L, w->precision, w->rule);
   if (e != hipSuccess) return e;

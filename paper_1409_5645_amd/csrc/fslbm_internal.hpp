@@ -18,9 +18,10 @@ struct Common {
   Consts<float> kf;
   int incomp, stokes;
   float scale, inv_scale;  // FP16 storage scaling (powers of two)
-  int moving;              // some wall face moves (wall_u not all zero)
-  double wall_u[6][3];     // wall face velocities: x-, x+, y-, y+, z-, z+
+  int moving;              // some wall face moves (then SweepArgs::wall_t holds the terms)
   double shear_b[6];       // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules 4, 5)
+  double sigma;            // surface tension coefficient (0: none)
+  double rho_gas;          // gas density rho_b (actual, not in storage convention)
 };
 
 template <class R>
@@ -68,6 +69,8 @@ struct SweepArgs {
   void* rec_u;
   double* rec_rho;
   int rec_cap;
+  double* kappa;  // surface tension: 3 sigma kappa per listed interface cell (list order)
+  const double* wall_t;  // moving walls: [6 faces][19 links] bounce-back terms 2 w_q (c_q.u_w)/c_s^2
 };
 
 struct ConvArgs {
@@ -162,6 +165,7 @@ struct AdjArgs {
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
 hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
+hipError_t launch_curvature(const StepLaunch& L);
 hipError_t launch_convert(const StepLaunch& L, int precision);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, void* stream);
 hipError_t launch_fill_f64(double* p, size_t n, double v, void* stream);

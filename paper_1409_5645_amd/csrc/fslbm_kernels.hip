@@ -124,10 +124,10 @@ __device__ __forceinline__ void boundary_shear(const IfaceData<F>& d, const Nbr&
 // geometry, reconstruction of the gas-side populations, TRT collision.  On exit
 // d.f holds the post-collision populations; returns the new mass, the density
 // (storage convention) and the velocity of the collision.
-template <class F, int RULE>
+template <class F, int RULE, bool EXTRA>
 __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& cm, typename F::R& rho_s,
                                                 typename F::R (&u)[3], const Nbr& nb,
-                                                const typename F::S* __restrict__ fin) {
+                                                const typename F::S* __restrict__ fin, double drho) {
   using R = typename F::R;
   constexpr bool SH = F::shifted;
   const Consts<R>& k = pick_consts<R>(cm);
@@ -188,8 +188,18 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
 #pragma unroll
       for (int i = 0; i < 6; ++i) Sb[i] = (R)cm.shear_b[i];
     }
+    // Laplace pressure: the boundary term takes P_b - sigma kappa (Eq.
+    // freeboundary); drho = 3 sigma kappa comes from k_curvature (0 without a normal)
+    R rhob_c = k.rhob_s, rho0b_c = k.rho0b;
+    if constexpr (EXTRA) {
+      if (cm.sigma != 0.0) {
+        rhob_c = (R)((double)k.rhob_s - drho);
+        if (!incomp) rho0b_c = (R)(cm.rho_gas - drho);
+      }
+    }
 #define FSLBM_REBUILD(q) \
-  rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, rho0_t, u_t, usq_t, k, incomp, stokes, Sb, stress);
+  rebuild<F, RULE, q>(d, gasmask, have_n, nv, dist, rho_t, rho0_t, u_t, usq_t, k, incomp, stokes, Sb, stress, \
+                      rhob_c, rho0b_c);
     FSLBM_LINKS(FSLBM_REBUILD)
 #undef FSLBM_REBUILD
   }
@@ -207,7 +217,9 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
 // registers, store.
 constexpr int IBLOCK = 64;  // interface-list kernels: one wavefront per block
 
-template <class F, int RULE, bool REC = false>
+// EXTRA: moving walls or surface tension present (a separate instantiation, so
+// that the plain path keeps its registers).
+template <class F, int RULE, bool REC = false, bool EXTRA = false>
 __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_iface(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
@@ -248,15 +260,12 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
   }
     FSLBM_LINKS(FSLBM_ILOAD)
 #undef FSLBM_ILOAD
-    if (a.c.moving) {
+    if (EXTRA && a.c.moving) {
       // moving walls (uniform branch): halfway bounce-back gains 2 w_q (c_q . u_w) / c_s^2
 #define FSLBM_IWALLU(q)                                                                        \
   {                                                                                            \
-    const int face = wall_face<q>(n.xm, n.xp, n.ym, n.yp, n.zm, n.zp);                         \
-    if (face >= 0) {                                                                           \
-      const double t = wall_term<q>(a.c, face);                                                \
-      if (t != 0.0) d.f[q] = d.f[q] + (R)t;                                                    \
-    }                                                                                          \
+    const double t = wall_term<q>(a.wall_t, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp);               \
+    if (t != 0.0) d.f[q] = d.f[q] + (R)t;                                                      \
   }
       FSLBM_LINKS(FSLBM_IWALLU)
 #undef FSLBM_IWALLU
@@ -279,7 +288,8 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
     }
     // ---- phase 2: interface treatment and collision
     R rho_s, u[3];
-    const double m_new = iface_compute<F, RULE>(d, a.c, rho_s, u, n, fin);
+    const double drho = (EXTRA && a.c.sigma != 0.0) ? a.kappa[i] : 0.0;
+    const double m_new = iface_compute<F, RULE, EXTRA>(d, a.c, rho_s, u, n, fin, drho);
     // ---- phase 3: populations, fill level and classification (FP64 bookkeeping)
 #pragma unroll
     for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, d.f[q], a.c.scale);
@@ -304,6 +314,38 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
       }
       if (m_new < a.thr_lo * rho) a.listE[atomicAdd(&a.counters[C_E], 1)] = idx;
     }
+  }
+}
+
+// Laplace-pressure correction of each listed interface cell (surface tension):
+// kappa[i] = 3 sigma kappa, with kappa = -div n from the fill seen over the
+// D3Q19 neighbourhood (Eq. freeboundary; see curvature).  Runs between the
+// sweep (which builds the list) and k_iface, only when sigma != 0.
+__global__ __launch_bounds__(IBLOCK) void k_curvature(SweepArgs a) {
+  const Grid g = a.c.grid;
+  const int n_i = a.counters[C_I];
+  for (int i = blockIdx.x * IBLOCK + threadIdx.x; i < n_i; i += gridDim.x * IBLOCK) {
+    const int idx = a.listI[i];
+    Nbr n;
+    coords(g, idx, n.x, n.y, n.z);
+    n.xm = step_axis(n.x, -1, g.nx, g.px);
+    n.xp = step_axis(n.x, 1, g.nx, g.px);
+    n.ym = step_axis(n.y, -1, g.ny, g.py);
+    n.yp = step_axis(n.y, 1, g.ny, g.py);
+    n.zm = step_axis(n.z, -1, g.nz, g.pz);
+    n.zp = step_axis(n.z, 1, g.nz, g.pz);
+    IfaceData<FormF64> d;
+    d.phix = a.phi_in[idx];
+#define FSLBM_CLOAD(q)                                            \
+  {                                                               \
+    const int s = pull_source<q>(g, n);                           \
+    const int sc = s >= 0 ? s : idx;                              \
+    d.ty[q] = s >= 0 ? a.flags[sc] : WALL_CLASS;                  \
+    d.ph[q] = a.phi_in[sc];                                       \
+  }
+    FSLBM_LINKS(FSLBM_CLOAD)
+#undef FSLBM_CLOAD
+    a.kappa[i] = 3.0 * a.c.sigma * curvature(d);
   }
 }
 
@@ -636,31 +678,33 @@ static inline unsigned blocks_for(size_t n) { return (unsigned)((n + BLOCK - 1) 
 static constexpr unsigned LIST_GRID = 512;
 static constexpr unsigned IFACE_GRID = 8192;
 
+template <class F, int RULE, bool REC, bool EXTRA>
+static void iface_go(const StepLaunch& L, unsigned nb) {
+  k_iface<F, RULE, REC, EXTRA><<<nb, IBLOCK, 0, (hipStream_t)L.stream>>>(L.sweep);
+}
+
 template <class F>
 static void iface_form(const StepLaunch& L, int rule) {
-  hipStream_t st = (hipStream_t)L.stream;
   // the interface count is on the device: enough one-wavefront blocks for
   // every cell up to IFACE_GRID * IBLOCK, grid-stride beyond
   const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
+  const bool extra = L.sweep.c.moving || L.sweep.c.sigma != 0.0;
   if (L.sweep.rec_f) {
     // a window step (rules 0 and 1): the list is fixed and its length (rec_cap) known here
     const unsigned nbr = std::min<unsigned>(nb, (unsigned)((L.sweep.rec_cap + IBLOCK - 1) / IBLOCK));
     if (rule == 0)
-      k_iface<F, 0, true><<<nbr, IBLOCK, 0, st>>>(L.sweep);
+      extra ? iface_go<F, 0, true, true>(L, nbr) : iface_go<F, 0, true, false>(L, nbr);
     else
-      k_iface<F, 1, true><<<nbr, IBLOCK, 0, st>>>(L.sweep);
-  } else if (rule == 0) {
-    k_iface<F, 0><<<nb, IBLOCK, 0, st>>>(L.sweep);
-  } else if (rule == 1) {
-    k_iface<F, 1><<<nb, IBLOCK, 0, st>>>(L.sweep);
-  } else if (rule == 2) {
-    k_iface<F, 2><<<nb, IBLOCK, 0, st>>>(L.sweep);
-  } else if (rule == 3) {
-    k_iface<F, 3><<<nb, IBLOCK, 0, st>>>(L.sweep);
-  } else if (rule == 4) {
-    k_iface<F, 4><<<nb, IBLOCK, 0, st>>>(L.sweep);
-  } else {
-    k_iface<F, 5><<<nb, IBLOCK, 0, st>>>(L.sweep);
+      extra ? iface_go<F, 1, true, true>(L, nbr) : iface_go<F, 1, true, false>(L, nbr);
+    return;
+  }
+  switch (rule) {
+    case 0: extra ? iface_go<F, 0, false, true>(L, nb) : iface_go<F, 0, false, false>(L, nb); break;
+    case 1: extra ? iface_go<F, 1, false, true>(L, nb) : iface_go<F, 1, false, false>(L, nb); break;
+    case 2: extra ? iface_go<F, 2, false, true>(L, nb) : iface_go<F, 2, false, false>(L, nb); break;
+    case 3: extra ? iface_go<F, 3, false, true>(L, nb) : iface_go<F, 3, false, false>(L, nb); break;
+    case 4: extra ? iface_go<F, 4, false, true>(L, nb) : iface_go<F, 4, false, false>(L, nb); break;
+    default: extra ? iface_go<F, 5, false, true>(L, nb) : iface_go<F, 5, false, false>(L, nb); break;
   }
 }
 
@@ -671,6 +715,12 @@ static void convert_form(const StepLaunch& L) {
   k_commit<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
   k_share<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
   k_gather<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
+}
+
+hipError_t launch_curvature(const StepLaunch& L) {
+  const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
+  k_curvature<<<nb, IBLOCK, 0, (hipStream_t)L.stream>>>(L.sweep);
+  return hipGetLastError();
 }
 
 hipError_t launch_iface(const StepLaunch& L, int precision, int rule) {

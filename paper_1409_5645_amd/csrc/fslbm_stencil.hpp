@@ -48,26 +48,54 @@ __device__ __forceinline__ double phi_seen(const IfaceData<F>& d, int q) {
 }
 
 // Halfway bounce-back off a moving wall: the population pulled along q from
-// beyond wall face `face` (x-, x+, y-, y+, z-, z+) gains 2 w_q (c_q . u_w) / c_s^2
-// (rho_w = 1).  Returns that term in FP64, 0 when the wall is at rest.
+// beyond a wall face gains 2 w_q (c_q . u_w) / c_s^2 (rho_w = 1), read from the
+// table wt[face * 19 + q].  The face is the first one the pull source x - c_q
+// crosses, in axis order x, y, z (faces x-, x+, y-, y+, z-, z+); the arguments
+// are the neighbour coordinates (-1 beyond a wall).  Every candidate face is
+// known at compile time from c_q.  0 if the link is not a wall link.
 template <int q>
-__device__ __forceinline__ double wall_term(const Common& cm, int face) {
-  const double* uw = cm.wall_u[face];
-  const double cu = (CX[q] * uw[0] + CY[q] * uw[1]) + CZ[q] * uw[2];
-  return cu != 0.0 ? 6.0 * WD[q] * cu : 0.0;
+__device__ __forceinline__ double wall_term(const double* __restrict__ wt, int xm, int xp, int ym, int yp, int zm,
+                                            int zp) {
+  if (CX[q] == 1 && xm < 0) return wt[0 * Q + q];
+  if (CX[q] == -1 && xp < 0) return wt[1 * Q + q];
+  if (CY[q] == 1 && ym < 0) return wt[2 * Q + q];
+  if (CY[q] == -1 && yp < 0) return wt[3 * Q + q];
+  if (CZ[q] == 1 && zm < 0) return wt[4 * Q + q];
+  if (CZ[q] == -1 && zp < 0) return wt[5 * Q + q];
+  return 0.0;
 }
 
-// Face crossed by the pull source x - c_q of a wall link (first in axis order
-// x, y, z), from the neighbour coordinates (-1 beyond a wall); -1 if none.
-template <int q>
-__device__ __forceinline__ int wall_face(int xm, int xp, int ym, int yp, int zm, int zp) {
-  if (CX[q] == 1 && xm < 0) return 0;
-  if (CX[q] == -1 && xp < 0) return 1;
-  if (CY[q] == 1 && ym < 0) return 2;
-  if (CY[q] == -1 && yp < 0) return 3;
-  if (CZ[q] == 1 && zm < 0) return 4;
-  if (CZ[q] == -1 && zp < 0) return 5;
-  return -1;
+// Curvature kappa = -div n = (|g|^2 tr H - g.H.g) / |g|^3 of the fill field seen
+// from an interface cell (Eq. freeboundary: the gas pressure becomes P_b -
+// sigma kappa; a sphere of radius R has kappa = -2/R), with the gradient g and
+// Hessian H by central differences over the D3Q19 neighbourhood.  The pull
+// source of link q sits at offset -c_q.  Zero if g = 0.  FP64.
+template <class F>
+__device__ __forceinline__ double curvature(const IfaceData<F>& d) {
+  double v[3][3][3];
+  v[1][1][1] = d.phix;
+#define FSLBM_KV(q) v[1 - CX[q]][1 - CY[q]][1 - CZ[q]] = phi_seen(d, q);
+  FSLBM_LINKS(FSLBM_KV)
+#undef FSLBM_KV
+  const double c = v[1][1][1];
+  double g[3], H[3][3];
+  g[0] = 0.5 * (v[2][1][1] - v[0][1][1]);
+  g[1] = 0.5 * (v[1][2][1] - v[1][0][1]);
+  g[2] = 0.5 * (v[1][1][2] - v[1][1][0]);
+  H[0][0] = (v[2][1][1] - 2.0 * c) + v[0][1][1];
+  H[1][1] = (v[1][2][1] - 2.0 * c) + v[1][0][1];
+  H[2][2] = (v[1][1][2] - 2.0 * c) + v[1][1][0];
+  H[0][1] = H[1][0] = 0.25 * (((v[2][2][1] - v[2][0][1]) - v[0][2][1]) + v[0][0][1]);
+  H[0][2] = H[2][0] = 0.25 * (((v[2][1][2] - v[2][1][0]) - v[0][1][2]) + v[0][1][0]);
+  H[1][2] = H[2][1] = 0.25 * (((v[1][2][2] - v[1][2][0]) - v[1][0][2]) + v[1][0][0]);
+  const double g2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+  if (!(g2 > 0.0)) return 0.0;
+  const double trH = (H[0][0] + H[1][1]) + H[2][2];
+  double gHg = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) gHg = gHg + g[a] * ((H[a][0] * g[0] + H[a][1] * g[1]) + H[a][2] * g[2]);
+  const double gn = sqrt(g2);
+  return (g2 * trH - gHg) / (g2 * gn);
 }
 
 // c_q . S . c_q for a symmetric S = [xx, yy, zz, xy, xz, yz]
@@ -78,7 +106,8 @@ __device__ __forceinline__ R c_S_c(const R (&S)[6]) {
   return dg + R(2.0) * of;
 }
 
-// Reconstruction of the population f_q that would stream in from a gas cell.
+// Reconstruction of the population f_q that would stream in from a gas cell
+// (rhob_s: the cell's gas density in storage convention, rho0b its rho_0).
 // With o = qbar the link pointing to gas, the closure Eq. (closure) gives
 //   f_q = a0 ft_o(x) + a0bar ft_q(x) + a1 f_o(x,t+1) + C n+_o(x,t) + alpha_+ e+_o(rho_b,u_b)
 // with the FSK row of Table 1 (Eq. koerner) or Eq. (fsli1)-(fsli4) at alpha_+ = 1
@@ -90,12 +119,13 @@ __device__ __forceinline__ void rebuild(IfaceData<F>& d, uint32_t gasmask, bool 
                                         double dist, typename F::R rho_t, typename F::R rho0_t,
                                         const typename F::R (&u_t)[3], typename F::R usq_t,
                                         const Consts<typename F::R>& k, bool incomp, bool stokes,
-                                        const typename F::R (&Sb)[6], bool stress) {
+                                        const typename F::R (&Sb)[6], bool stress, typename F::R rhob_s,
+                                        typename F::R rho0b) {
   using R = typename F::R;
   if (!((gasmask >> q) & 1u)) return;
   constexpr int o = OPP[q];
   const R own_o = d.own[o];
-  const R e_b = e_plus<o>(k.rhob_s, k.rho0b, incomp, stokes, u_t, usq_t);
+  const R e_b = e_plus<o>(rhob_s, rho0b, incomp, stokes, u_t, usq_t);
   if ((RULE & 1) && have_n && !((gasmask >> o) & 1u)) {
     // link distance delta: plane with normal n at offset phi - 1/2
     double nc = 0.0;

@@ -87,11 +87,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
     const double su = F::scaled ? (double)a.c.scale : 1.0;
 #define FSLBM_WALLU(q)                                                         \
   {                                                                            \
-    const int face = wall_face<q>(xm, xp, ym, yp, zm, zp);                     \
-    if (face >= 0) {                                                           \
-      const double t = wall_term<q>(a.c, face);                                \
-      if (t != 0.0) f[q] = f[q] + (R)(t * su);                                 \
-    }                                                                          \
+    const double t = wall_term<q>(a.wall_t, xm, xp, ym, yp, zm, zp);           \
+    if (t != 0.0) f[q] = f[q] + (R)(t * su);                                   \
   }
     FSLBM_LINKS(FSLBM_WALLU)
 #undef FSLBM_WALLU

@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("magic", ctypes.c_double), ("incompressible", ctypes.c_int32),
                 ("stokes", ctypes.c_int32), ("g", ctypes.c_double * 3), ("rho_gas", ctypes.c_double),
                 ("conv_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32), ("freeze", ctypes.c_int32),
-                ("wall_u", (ctypes.c_double * 3) * 6), ("shear_b", ctypes.c_double * 6)]
+                ("wall_u", (ctypes.c_double * 3) * 6), ("shear_b", ctypes.c_double * 6),
+                ("sigma", ctypes.c_double)]
 
 
 class Buffers(ctypes.Structure):
@@ -97,7 +98,8 @@ def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13) -> Params:
                   int(fp16_scale_log2), int(bool(freeze)),
                   ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*[float(v) for v in face])
                                                  for face in getattr(p, "wall_u", ((0.0, 0.0, 0.0),) * 6)]),
-                  (ctypes.c_double * 6)(*[float(v) for v in getattr(p, "shear_b", (0.0,) * 6)]))
+                  (ctypes.c_double * 6)(*[float(v) for v in getattr(p, "shear_b", (0.0,) * 6)]),
+                  float(getattr(p, "sigma", 0.0)))
 
 
 class Sim:

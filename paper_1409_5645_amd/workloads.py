@@ -46,6 +46,7 @@ class Params:
     eps: float = 1e-3
     wall_u: tuple = ((0.0, 0.0, 0.0),) * 6   # wall face velocities: x-, x+, y-, y+, z-, z+
     shear_b: tuple = (0.0,) * 6               # prescribed S^b [xx, yy, zz, xy, xz, yz]
+    sigma: float = 0.0                        # surface tension coefficient
 
     @property
     def n_cells(self) -> int:
@@ -172,6 +173,32 @@ def pool(nx: int = 32, ny: int = 64, nz: int = 32, level: float = 40.5, gy: floa
     """Flat pool at hydrostatic rest in a closed tank."""
     p = Params(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 0), tau=tau, Lambda=Lambda, g=(0.0, gy, 0.0))
     return _from_height(p, np.full(nx, float(level)), "pool", {"level": level})
+
+
+def droplet(n: int = 32, radius: float = 8.0, sigma: float = 1e-3, tau: float = 0.8,
+            Lambda: float = 3.0 / 16.0, offset=(0.1, 0.23, 0.37), sub: int = 6) -> Workload:
+    """Spherical liquid droplet at rest in a periodic box of gas, no gravity.
+    Fill = volume fraction of the sphere in each cell (sub^3 sample points);
+    density rho_b + 6 sigma / R inside (the Laplace pressure P_b + 2 sigma / R)."""
+    p = Params(nx=n, ny=n, nz=n, periodic=(1, 1, 1), tau=tau, Lambda=Lambda, sigma=sigma)
+    c = np.array([n / 2 + offset[0], n / 2 + offset[1], n / 2 + offset[2]])
+    k = (np.arange(sub) + 0.5) / sub
+    idx = np.indices((n, n, n)).astype(np.float64)  # [3 (z, y, x), n, n, n]
+    fill3 = np.zeros((n, n, n))
+    for a in k:
+        for b in k:
+            for cc in k:
+                r2 = (idx[2] + a - c[0]) ** 2 + (idx[1] + b - c[1]) ** 2 + (idx[0] + cc - c[2]) ** 2
+                fill3 += r2 <= radius * radius
+    fill3 /= sub ** 3
+    types3 = np.where(fill3 >= 1.0, LIQUID, np.where(fill3 <= 0.0, GAS, INTERFACE)).astype(np.uint8)
+    gas_near = _shift_any(types3 == GAS, p.periodic)
+    promote = (types3 == LIQUID) & gas_near
+    types3[promote] = INTERFACE
+    fill3[promote] = 1.0
+    rho3 = np.where(types3 == GAS, p.rho_gas, p.rho_gas + 6.0 * sigma / radius)
+    return Workload(name="droplet", params=p, flags=types3.reshape(-1), rho=rho3.reshape(-1), u=None,
+                    fill=fill3.reshape(-1), meta={"radius": radius, "sigma": sigma})
 
 
 # Named configurations (sizes of the measured workloads).

@@ -229,10 +229,16 @@ def test_window_errors(fs, case):
         s.window(0, 1)
     with pytest.raises(fs.FslbmError, match="INVALID"):
         s.window(5, 7)  # unknown rule
-    for rule in (fs.FSK_STRESS, fs.FSL_STRESS):  # no adjoint of the shear-rate boundary term
+    for rule in (fs.FSK_STRESS, fs.FSL_STRESS, fs.FSK_SHEAR, fs.FSL_SHEAR):  # no adjoint of the D term
         with pytest.raises(fs.FslbmError, match="UNSUPPORTED"):
             s.window(5, rule)
     s.close()
+    import dataclasses
+    st_ = fs.Sim(dataclasses.replace(p, sigma=1e-3), st["flags"], precision="fp64")
+    st_.set_state(st["f"], st["mass"], st["phi"])
+    with pytest.raises(fs.FslbmError, match="UNSUPPORTED"):  # no adjoint of the curvature
+        st_.window(5, 1)
+    st_.close()
 
 
 def test_full_size_fp64_fd_and_fp32_error(fs):

@@ -299,3 +299,44 @@ def test_plate_driven_reduced_precision(fs, oracle_mod, precision, tol):
     _say(precision, "plate-driven u err / u_wall", err)
     assert uo[0, act].min() > 1e-5
     assert err < tol
+
+
+@pytest.mark.parametrize("rule", [1, 0, 3])
+def test_surface_tension_parity(fs, oracle_mod, rule):
+    """Surface tension (curvature kernel, Laplace-pressure boundary term) on a
+    droplet, then on a converting tank with moving walls: bit-exact against the
+    oracle."""
+    w = W.droplet(n=20, radius=6.0, sigma=1e-3)
+    _say(f"case droplet sigma rule {rule}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(3):
+        o.step(40, rule)
+        s.step(40, rule)
+        _compare(o, s, f"droplet step {40 * (it + 1)}")
+    w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
+    w = _with(w, sigma=2e-3, wall_u=_MOVING)
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(40):
+        o.step(1, rule)
+        s.step(1, rule)
+        if it % 10 == 9:
+            _compare(o, s, f"tank step {it + 1}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("fp16s", 5e-2)])
+def test_surface_tension_reduced_precision(fs, oracle_mod, precision, tol):
+    """Laplace pressure of a droplet in the FP32 and FP16-storage forms against
+    the FP64 oracle (pressure jump relative to 2 sigma / R after 300 steps)."""
+    w = W.droplet(n=20, radius=6.0, sigma=1e-3)
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    o.step(300, 1)
+    s.step(300, 1)
+    ro, _ = o.macro()
+    g = s.fields(("rho", "flags"))
+    liq = (o.flags() == W.LIQUID) & (g["flags"] == W.LIQUID)
+    d = abs(g["rho"][liq].mean() - ro[liq].mean()) / 3.0 / (2e-3 / 6.0)
+    _say(precision, "droplet pressure difference / (2 sigma/R)", d)
+    assert d < tol
