@@ -37,7 +37,7 @@ class _RefParams(ctypes.Structure):
                 ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
                 ("rho_gas", ctypes.c_double), ("eps", ctypes.c_double),
                 ("wall_u", ctypes.c_double * 18), ("shear_b", ctypes.c_double * 6),
-                ("sigma", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("plic", ctypes.c_int)]
 
 
 _lib = None
@@ -81,6 +81,10 @@ def lib():
         L.ref_boundary_shear.argtypes = [dp, dp, ctypes.c_double, dp]
         L.ref_curvature.restype = ctypes.c_double
         L.ref_curvature.argtypes = [dp]
+        L.ref_cut_volume.restype = ctypes.c_double
+        L.ref_cut_volume.argtypes = [dp, ctypes.c_double]
+        L.ref_plic_offset.restype = ctypes.c_double
+        L.ref_plic_offset.argtypes = [ctypes.c_double, dp]
         L.ref_window_dual.restype = ctypes.c_int
         L.ref_window_dual.argtypes = [ctypes.POINTER(_RefParams), u8p, dp, dp, dp, dp, dp, dp, ctypes.c_double,
                                       dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
@@ -100,7 +104,7 @@ def _params(p) -> _RefParams:
                       float(p.g[0]), float(p.g[1]), float(p.g[2]), float(p.rho_gas), float(p.eps),
                       (ctypes.c_double * 18)(*[float(v) for face in wall for v in face]),
                       (ctypes.c_double * 6)(*[float(v) for v in shear]),
-                      float(getattr(p, "sigma", 0.0)))
+                      float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)))
 
 
 FSK, FSL = 0, 1
@@ -249,6 +253,18 @@ def curvature(block) -> float:
     cell, block[dx+1, dy+1, dz+1] (corners unused)."""
     b = np.ascontiguousarray(np.asarray(block, dtype=np.float64).transpose(2, 1, 0)).reshape(-1)
     return float(lib().ref_curvature(_dptr(b)))
+
+
+def cut_volume(m, a: float) -> float:
+    """Volume of the unit cube below the plane m.x = a (m_i >= 0)."""
+    mm = np.ascontiguousarray(m, dtype=np.float64)
+    return float(lib().ref_cut_volume(_dptr(mm), float(a)))
+
+
+def plic_offset(phi: float, n) -> float:
+    """Offset d of the plane n.(x - x_node) = d cutting the fill fraction phi."""
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    return float(lib().ref_plic_offset(float(phi), _dptr(nn)))
 
 
 def window_dual(params, flags, f0, m0, phi0, u_target, phi_target, T: int, rule: int = FSL,

@@ -30,6 +30,7 @@ struct ref_params {
   double wall_u[18];  // faces x-, x+, y-, y+, z-, z+
   double shear_b[6];  // prescribed S^b [xx, yy, zz, xy, xz, yz]
   double sigma;       // surface tension coefficient
+  int plic;           // FSL link distance from the PLIC plane
 };
 
 static Params to_params(const ref_params* r) {
@@ -53,6 +54,7 @@ static Params to_params(const ref_params* r) {
     for (int a = 0; a < 3; ++a) p.wall_u[f][a] = r->wall_u[3 * f + a];
   for (int i = 0; i < 6; ++i) p.shear_b[i] = r->shear_b[i];
   p.sigma = r->sigma;
+  p.plic = r->plic;
   return p;
 }
 
@@ -201,6 +203,11 @@ double ref_curvature(const double* v27) {
       for (int c = 0; c < 3; ++c) v[a][b][c] = v27[a + 3 * b + 9 * c];
   return fsref::Oracle<double>::curvature(v);
 }
+
+// PLIC: volume of the unit cube below m.x = a (m_i >= 0), and the plane offset
+// d from the cell centre (n unit, liquid below) that cuts the fraction phi.
+double ref_cut_volume(const double* m3, double a) { return fsref::Oracle<double>::cut_volume(m3, a); }
+double ref_plic_offset(double phi, const double* n3) { return fsref::Oracle<double>::plic_offset(phi, n3); }
 
 // Boundary value S^b = P S P + s_nn n n^T of section 3.4 (n a unit vector).
 void ref_boundary_shear(const double* S6, const double* n3, double s_nn, double* Sb6) {

@@ -71,6 +71,7 @@ struct Params {
   double wall_u[6][3]; // velocity of the wall faces x-, x+, y-, y+, z-, z+
   double shear_b[6];   // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules with bit 2)
   double sigma;        // surface tension coefficient (0: none)
+  int plic;            // FSL link distance from the PLIC plane (nonzero) or phi - 1/2
 };
 
 // ---------------------------------------------------------------------------
@@ -394,6 +395,69 @@ struct Oracle {
     return (g2 * trH - gHg) / (g2 * gn);
   }
 
+  // ------------------------------------------ PLIC plane offset (sec. 5)
+  // Volume of the unit cube [0,1]^3 below the plane m.x = a, m_i >= 0 (not all
+  // zero).  The forward relation of Scardovelli & Zaleski (J. Comput. Phys.
+  // 164, 2000) by regions of the normalised offset, with the components sorted
+  // m1 <= m2 <= m3 and scaled to sum 1; the offset is reflected to the lower
+  // half (V(a) = 1 - V(1 - a)).  Regions that divide by m1 carry the
+  // difference quotients in closed form, so a vanishing component (a plane
+  // parallel to an axis) leaves no cancelled difference divided by it.
+  static T cut_volume(const T m[3], const T& a) {
+    T s = (m[0] + m[1]) + m[2];
+    T m1 = m[0] / s, m2 = m[1] / s, m3 = m[2] / s;
+    if (m1 > m2) std::swap(m1, m2);
+    if (m2 > m3) std::swap(m2, m3);
+    if (m1 > m2) std::swap(m1, m2);
+    T b = a / s;
+    if (b <= T(0.0)) return T(0.0);
+    if (b >= T(1.0)) return T(1.0);
+    bool upper = b > T(0.5);
+    T al = upper ? T(1.0) - b : b;
+    T m12 = m1 + m2;
+    T v;
+    if (al <= m1) {
+      // corner tetrahedron
+      v = ((al * al) * al) / (T(6.0) * ((m1 * m2) * m3));
+    } else if (al <= m2) {
+      // the plane has passed the corner on the smallest axis
+      v = (al * (al - m1)) / (T(2.0) * (m2 * m3)) + (m1 * m1) / (T(6.0) * (m2 * m3));
+    } else if (al <= m12 && al <= m3) {
+      // [al^3 - (al - m1)^3 - (al - m2)^3] / (6 m1 m2 m3), the first
+      // difference divided by m1 in closed form
+      T t = al - m2;
+      T q = ((T(3.0) * (al * al) - T(3.0) * (al * m1)) + m1 * m1) - ((t * t) * t) / m1;
+      v = q / (T(6.0) * (m2 * m3));
+    } else if (al <= m3) {
+      // m1 + m2 <= al <= m3: a prism under a sloped roof, linear in al
+      v = ((T(2.0) * al) - m12) / (T(2.0) * m3);
+    } else {
+      // m3 < al <= 1/2 (only when m3 < m1 + m2): all three corners passed
+      T t2 = al - m2, t3 = al - m3;
+      T q = ((T(3.0) * (al * al) - T(3.0) * (al * m1)) + m1 * m1) - (((t2 * t2) * t2) + ((t3 * t3) * t3)) / m1;
+      v = q / (T(6.0) * (m2 * m3));
+    }
+    return upper ? T(1.0) - v : v;
+  }
+
+  // Offset d of the plane n.(x - x_node) = d (n a unit normal, liquid below)
+  // that cuts the fill fraction phi from the cell: V(a) = phi with
+  // a = d + (|n_x| + |n_y| + |n_z|)/2, by 64 bisection steps on [0, sum |n_i|].
+  // For an axis-aligned normal d = phi - 1/2.
+  static T plic_offset(const T& phi, const T n[3]) {
+    // (the bisection carries no derivative: the dual-number path never sets plic)
+    T m[3];
+    for (int i = 0; i < 3; ++i) m[i] = n[i] < T(0.0) ? -n[i] : n[i];
+    T sum = (m[0] + m[1]) + m[2];
+    T lo = T(0.0), hi = sum;
+    for (int it = 0; it < 64; ++it) {
+      T mid = T(0.5) * (lo + hi);
+      if (cut_volume(m, mid) < phi) lo = mid;
+      else hi = mid;
+    }
+    return T(0.5) * (lo + hi) - T(0.5) * sum;
+  }
+
   // n . S . n for a symmetric S given as [xx, yy, zz, xy, xz, yz]
   static T normal_normal(const T S[6], const T n[3]) {
     T d = (S[0] * (n[0] * n[0]) + S[1] * (n[1] * n[1])) + S[2] * (n[2] * n[2]);
@@ -549,6 +613,9 @@ struct Oracle {
           for (int a = 0; a < 3; ++a) nvec[a] = -grad[a] / nrm;
         }
         T dist = phix - T(0.5);
+        // second-order interface position (section 5): the plane that cuts the
+        // cell's fill fraction with the normal n (PLIC) instead of phi - 1/2
+        if (p.plic && have_normal && (rule & 1)) dist = plic_offset(phix, nvec);
 
         // Laplace pressure: the boundary term takes P_b - sigma kappa (Eq.
         // freeboundary), i.e. rho_b - 3 sigma kappa

@@ -47,6 +47,7 @@ class Params:
     wall_u: tuple = ((0.0, 0.0, 0.0),) * 6   # wall face velocities: x-, x+, y-, y+, z-, z+
     shear_b: tuple = (0.0,) * 6               # prescribed S^b [xx, yy, zz, xy, xz, yz]
     sigma: float = 0.0                        # surface tension coefficient
+    plic: int = 0                             # FSL link distance from the PLIC plane
 
     @property
     def n_cells(self) -> int:
