@@ -81,6 +81,8 @@ def lib():
         L.ref_boundary_shear.argtypes = [dp, dp, ctypes.c_double, dp]
         L.ref_curvature.restype = ctypes.c_double
         L.ref_curvature.argtypes = [dp]
+        L.ref_set_walls.restype = ctypes.c_int
+        L.ref_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp]
         L.ref_cut_volume.restype = ctypes.c_double
         L.ref_cut_volume.argtypes = [dp, ctypes.c_double]
         L.ref_plic_offset.restype = ctypes.c_double
@@ -144,7 +146,25 @@ class Oracle:
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w.params, w.flags, w.rho, w.u, w.fill)
+        o = cls(w.params, w.flags, w.rho, w.u, w.fill)
+        walls = getattr(w, "walls", None)
+        if walls is not None:
+            o.set_walls(walls["cells"], walls.get("delta"), walls.get("uw"))
+        return o
+
+    def set_walls(self, cells, delta=None, uw=None):
+        """Wall table of the solid cells: ascending non-solid cells next to a
+        solid cell, delta[19, n] (wall point x + delta c_p), uw[3, 19, n]."""
+        c = np.ascontiguousarray(cells, dtype=np.int32)
+        n = c.size
+        d = None if delta is None else np.ascontiguousarray(delta, dtype=np.float64).reshape(-1)
+        v = None if uw is None else np.ascontiguousarray(uw, dtype=np.float64).reshape(-1)
+        assert d is None or d.size == 19 * n
+        assert v is None or v.size == 3 * 19 * n
+        rc = lib().ref_set_walls(self._h, n, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                 None if d is None else _dptr(d), None if v is None else _dptr(v))
+        if rc != 0:
+            raise RuntimeError("oracle wall table rejected: " + lib().ref_error(self._h).decode())
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -90,6 +90,21 @@ void* ref_create_state(const ref_params* rp, const uint8_t* flags, const double*
 
 const char* ref_create_error() { return g_create_error.c_str(); }
 
+// Solid walls: the ascending list of the n non-solid cells next to solid
+// cells, per listed cell and link p the wall distance delta[p*n + i] (NULL:
+// 1/2) and the wall velocity uvel[(a*19 + p)*n + i] (NULL: at rest).  Returns
+// 0, or -1 with ref_error() saying why.
+int ref_set_walls(void* hp, int n, const int* cells, const double* delta, const double* uvel) {
+  auto* h = static_cast<Handle*>(hp);
+  try {
+    h->sim.set_walls(n, cells, delta, uvel);
+    return 0;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return -1;
+  }
+}
+
 void ref_destroy(void* hp) { delete static_cast<Handle*>(hp); }
 
 const char* ref_error(void* hp) { return static_cast<Handle*>(hp)->err.c_str(); }

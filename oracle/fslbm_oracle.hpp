@@ -49,7 +49,7 @@ inline double weight(int q) {
   return 1.0 / 36.0;
 }
 
-enum CellType : uint8_t { GAS = 0, INTERFACE = 1, LIQUID = 2 };
+enum CellType : uint8_t { GAS = 0, INTERFACE = 1, LIQUID = 2, SOLID = 3 };
 // Rules: bit 0 selects the FSL construction (else the FSK row of Table 1).
 // Bit 1 adds the shear-rate entry D c_a c_b S^b_ab of Eq. (bterm) (Table 1,
 // column D; section 3.4) with S^b from the bulk; bit 2 adds it with a
@@ -102,6 +102,15 @@ struct Oracle {
   // conversion lists of the last step, ascending cell index
   std::vector<int> listF, listE, listEp, listNI, listNL;
 
+  // Solid obstacles (class SOLID, never converted): the non-solid cells with a
+  // link into a solid cell, ascending, and per listed cell i and link p
+  // (from the cell towards c_p) the wall distance delta in (0, 1] of the wall
+  // point x + delta c_p and the wall velocity, where x + c_p is solid.
+  bool any_solid = false;
+  std::vector<int> wall_cells;
+  std::vector<double> wall_delta;  // [19][n]
+  std::vector<double> wall_uvel;   // [3][19][n]
+
   // ---------------------------------------------------------------- setup
   void set_params(const Params& q) {
     p = q;
@@ -144,8 +153,8 @@ struct Oracle {
     return zero;
   }
 
-  // neighbour of cell (x,y,z) at offset d; -1 if it lies beyond a wall
-  int neighbor(int x, int y, int z, int dx, int dy, int dz) const {
+  // cell at offset d from (x,y,z) (periodic wrap); -1 beyond a wall face
+  int raw_neighbor(int x, int y, int z, int dx, int dy, int dz) const {
     int c[3] = {x + dx, y + dy, z + dz};
     int n[3] = {p.nx, p.ny, p.nz};
     for (int a = 0; a < 3; ++a) {
@@ -155,6 +164,56 @@ struct Oracle {
       }
     }
     return c[0] + p.nx * (c[1] + p.ny * c[2]);
+  }
+  // neighbour of cell (x,y,z) at offset d; -1 if it lies beyond a wall face or
+  // is solid (a solid cell is a wall to the fluid)
+  int neighbor(int x, int y, int z, int dx, int dy, int dz) const {
+    int s = raw_neighbor(x, y, z, dx, dy, dz);
+    return (s >= 0 && type[s] == SOLID) ? -1 : s;
+  }
+  // slot of a cell in the wall list (binary search), -1 if not listed
+  int wall_slot(int cell) const {
+    auto it = std::lower_bound(wall_cells.begin(), wall_cells.end(), cell);
+    return (it != wall_cells.end() && *it == cell) ? (int)(it - wall_cells.begin()) : -1;
+  }
+
+  // The wall table: validated against the classes (every non-solid cell with
+  // a link into a solid cell listed, nothing else; delta in (0, 1] on those
+  // links).  NULL delta: 1/2 (halfway); NULL velocities: resting walls.
+  void set_walls(int n, const int* cells, const double* delta, const double* uvel) {
+    std::vector<int> need;
+    for (int cell = 0; cell < N; ++cell) {
+      if (type[cell] == SOLID) continue;
+      int x, y, z;
+      coords(cell, x, y, z);
+      for (int q = 1; q < Q; ++q) {
+        int s = raw_neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s >= 0 && type[s] == SOLID) { need.push_back(cell); break; }
+      }
+    }
+    if (n != (int)need.size()) throw std::runtime_error("wall list must hold exactly the non-solid cells next to solid cells");
+    for (int i = 0; i < n; ++i)
+      if (cells[i] != need[i]) throw std::runtime_error("wall list must hold exactly the non-solid cells next to solid cells, ascending");
+    wall_cells.assign(cells, cells + n);
+    wall_delta.assign((size_t)Q * n, 0.5);
+    wall_uvel.assign((size_t)3 * Q * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      int x, y, z;
+      coords(cells[i], x, y, z);
+      for (int q = 1; q < Q; ++q) {
+        int s = raw_neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+        if (s < 0 || type[s] != SOLID) continue;
+        double d = delta ? delta[(size_t)q * n + i] : 0.5;
+        if (!(d > 0.0 && d <= 1.0)) throw std::runtime_error("wall distance outside (0, 1]");
+        wall_delta[(size_t)q * n + i] = d;
+        if (uvel)
+          for (int a = 0; a < 3; ++a) {
+            double v = uvel[((size_t)a * Q + q) * n + i];
+            if (!std::isfinite(v)) throw std::runtime_error("wall velocity must be finite");
+            wall_uvel[((size_t)a * Q + q) * n + i] = v;
+          }
+      }
+    }
   }
   void coords(int cell, int& x, int& y, int& z) const {
     x = cell % p.nx;
@@ -166,7 +225,7 @@ struct Oracle {
   // direct neighbour of a gas cell (the interface layer separates them).
   void check_layer_invariant() const {
     for (int cell = 0; cell < N; ++cell) {
-      if (type[cell] > LIQUID) throw std::runtime_error("unknown cell type");
+      if (type[cell] > SOLID) throw std::runtime_error("unknown cell type");
       if (type[cell] != LIQUID) continue;
       int x, y, z;
       coords(cell, x, y, z);
@@ -485,8 +544,10 @@ struct Oracle {
     rho_c.assign(N, T(0.0));
     u_c.assign((size_t)3 * N, T(0.0));
     reservoir = T(0.0);
+    any_solid = false;
     for (int cell = 0; cell < N; ++cell) {
-      if (type[cell] == GAS) continue;
+      if (type[cell] == SOLID) any_solid = true;
+      if (type[cell] == GAS || type[cell] == SOLID) continue;
       T r = T(rho[cell]);
       T uu[3] = {T(u[cell]), T(u[N + cell]), T(u[2 * N + cell])};
       T out[Q];
@@ -505,6 +566,7 @@ struct Oracle {
   void init_from_state(const uint8_t* flags, const T* ftin, const T* m, const T* fill, const T& res) {
     type.assign(flags, flags + N);
     check_layer_invariant();
+    any_solid = std::find(type.begin(), type.end(), (uint8_t)SOLID) != type.end();
     ft.assign(ftin, ftin + (size_t)Q * N);
     mass.assign(m, m + N);
     phi.assign(fill, fill + N);
@@ -532,12 +594,13 @@ struct Oracle {
   std::vector<T> ftn;  // second population buffer (pull scheme ping-pong)
 
   void step(int rule) {
+    if (any_solid && wall_cells.empty()) throw std::runtime_error("solid cells present but no wall table set");
     ftn.resize((size_t)Q * N);
     std::vector<T> massn = mass;
     std::vector<T> phin = phi;
 
     for (int cell = 0; cell < N; ++cell) {
-      if (type[cell] == GAS) continue;
+      if (type[cell] == GAS || type[cell] == SOLID) continue;
       int x, y, z;
       coords(cell, x, y, z);
       const bool iface = type[cell] == INTERFACE;
@@ -551,10 +614,17 @@ struct Oracle {
       T f[Q];
       bool gaslink[Q] = {false};
       int src[Q];
+      bool solidlink[Q] = {false};
       for (int q = 0; q < Q; ++q) {
         int s = neighbor(x, y, z, -CV[q][0], -CV[q][1], -CV[q][2]);
         src[q] = s;
-        if (s < 0) {
+        if (s < 0 && q > 0) {
+          int r = raw_neighbor(x, y, z, -CV[q][0], -CV[q][1], -CV[q][2]);
+          solidlink[q] = r >= 0;  // a solid source (not a wall face)
+        }
+        if (s < 0 && solidlink[q]) {
+          f[q] = own[opposite(q)];  // completed below (CLI)
+        } else if (s < 0) {
           // halfway bounce-back off a wall moving with u_w (section 4.1):
           // f_q = ft_qbar + 2 w_q (c_q . u_w) / c_s^2, with rho_w = 1
           f[q] = own[opposite(q)];
@@ -567,6 +637,39 @@ struct Oracle {
           f[q] = T(0.0);
         } else {
           f[q] = ft[(size_t)q * N + s];
+        }
+      }
+
+      // Solid walls: the linear-interpolation closure (CLI) for the link p =
+      // qbar that points from the cell to the wall point x + delta c_p.  In the
+      // closure f_q(x,t+1) = a0 ft_p(x) + a0bar ft_q(x) + a1 ft_p(x - c_p) + f^b
+      // the fitting conditions alpha_+ = 0 (no pressure term) and beta_+ /
+      // lambda_+ = alpha_- delta (momentum at the wall point to first order,
+      // Eq. fitting and cl1) with C = 0 leave one free coefficient; a0 = 1
+      // gives kappa = (1 - 2 delta)/(1 + 2 delta), a1 = kappa, a0bar = -kappa,
+      // and f^b = alpha_- e-_p(u_w) with alpha_- = -4/(1 + 2 delta).  Exact for
+      // linear velocity profiles; halfway bounce-back at delta = 1/2.  Where
+      // ft_p(x - c_p) is not a fluid population (a wall, a solid or gas there)
+      // the link takes halfway bounce-back.
+      if (any_solid) {
+        const int slot = wall_slot(cell);
+        const int nw = (int)wall_cells.size();
+        for (int q = 1; q < Q; ++q) {
+          if (!solidlink[q]) continue;
+          if (slot < 0) throw std::runtime_error("cell next to a solid missing from the wall table");
+          const int pl = opposite(q);
+          const double d = wall_delta[(size_t)pl * nw + slot];
+          double uw[3];
+          for (int a = 0; a < 3; ++a) uw[a] = wall_uvel[((size_t)a * Q + pl) * nw + slot];
+          // 2 w (c_q . u_w) / c_s^2 of halfway bounce-back (rho_w = 1)
+          const double bb = 6.0 * weight(q) * ((CV[q][0] * uw[0] + CV[q][1] * uw[1]) + CV[q][2] * uw[2]);
+          const bool upstream = src[pl] >= 0 && type[src[pl]] != GAS;
+          if (upstream) {
+            const double kap = (1.0 - 2.0 * d) / (1.0 + 2.0 * d);
+            f[q] = (own[pl] + T(kap) * (f[pl] - own[q])) + T(bb * (2.0 / (1.0 + 2.0 * d)));
+          } else {
+            f[q] = own[pl] + T(bb);
+          }
         }
       }
 

@@ -24,7 +24,16 @@ import math
 
 import numpy as np
 
-GAS, INTERFACE, LIQUID = 0, 1, 2
+GAS, INTERFACE, LIQUID, SOLID = 0, 1, 2, 3
+
+# Link order of the population buffers and wall tables at the library boundary:
+# rest, the six axis links, then the twelve diagonals; odd q has its opposite
+# at q + 1.
+LINKS = np.array([(0, 0, 0),
+                  (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+                  (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0),
+                  (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
+                  (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], dtype=np.int64)
 
 # offsets of the 18 nearest neighbours on the cubic lattice (|d|^2 = 1 or 2)
 _NEIGHBOURS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
@@ -63,6 +72,10 @@ class Workload:
     u: np.ndarray | None         # float64[3, N] or None (= at rest)
     fill: np.ndarray             # float64[N]
     meta: dict = dataclasses.field(default_factory=dict)
+    # solid walls: {"cells": int32[n] ascending non-solid cells next to a solid
+    # cell, "delta": float64[19, n] wall point x + delta c_p on link p,
+    # "uw": float64[3, 19, n] wall velocity}; None without solid cells
+    walls: dict | None = None
 
     def velocity(self) -> np.ndarray:
         if self.u is None:
@@ -200,6 +213,106 @@ def droplet(n: int = 32, radius: float = 8.0, sigma: float = 1e-3, tau: float = 
     rho3 = np.where(types3 == GAS, p.rho_gas, p.rho_gas + 6.0 * sigma / radius)
     return Workload(name="droplet", params=p, flags=types3.reshape(-1), rho=rho3.reshape(-1), u=None,
                     fill=fill3.reshape(-1), meta={"radius": radius, "sigma": sigma})
+
+
+def _skew_zeta(nx: int, nz: int, slope: float):
+    """Vertical offset zeta = z - slope x of the cell centres, in [0, nz)
+    ([nz, nx] array; the strips below are bands of zeta)."""
+    xc = np.arange(nx) + 0.5
+    zc = np.arange(nz) + 0.5
+    return np.mod(zc[:, None] - slope * xc[None, :], float(nz))
+
+
+def skew_strips(nx: int, ny: int, nz: int, slope: float, bands, p: Params):
+    """Bands of zeta = z - slope x (x, y, z periodic; slope * nx a multiple of
+    nz so that the bands close on themselves).  bands: consecutive
+    (upper edge, kind, tangential velocity) from zeta = 0 to nz, kind "solid"
+    or "fluid"; a solid band moves with its velocity along the tangent
+    t = (1, 0, slope)/|.|.  Returns the class field [nz, ny, nx] (fluid cells
+    LIQUID) and the wall table: for each fluid cell next to a solid cell and
+    each link p into a solid cell, the exact distance delta of the crossing of
+    the band edge along c_p and the wall's velocity."""
+    if abs(slope * nx / nz - round(slope * nx / nz)) > 1e-12:
+        raise ValueError("slope * nx must be a multiple of nz")
+    zeta = _skew_zeta(nx, nz, slope)
+    edges = [0.0] + [float(b[0]) for b in bands]
+    kind = np.empty((nz, nx), dtype=np.uint8)
+    band = np.empty((nz, nx), dtype=np.int64)
+    for i, (hi, k, _) in enumerate(bands):
+        sel = (zeta >= edges[i]) & (zeta < hi)
+        kind[sel] = SOLID if k == "solid" else LIQUID
+        band[sel] = i
+    types3 = np.broadcast_to(kind[:, None, :], (nz, ny, nx)).copy()
+    tang = np.array([1.0, 0.0, slope]) / np.hypot(1.0, slope)
+    flags = types3.reshape(-1)
+    N = nx * ny * nz
+    idx = np.arange(N)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    solid = flags == SOLID
+    near = np.zeros(N, dtype=bool)
+    for q in range(1, 19):
+        c = LINKS[q]
+        s_ = ((x + c[0]) % nx) + nx * (((y + c[1]) % ny) + ny * ((z + c[2]) % nz))
+        near |= solid[s_]
+    cells = np.nonzero(near & ~solid)[0].astype(np.int32)
+    n = cells.size
+    delta = np.full((19, n), 0.5)
+    uw = np.zeros((3, 19, n))
+    cx, cy, cz = x[cells], y[cells], z[cells]
+    zc = zeta[cz, cx]
+    bc = band[cz, cx]
+    for q in range(1, 19):
+        c = LINKS[q]
+        s_ = ((cx + c[0]) % nx) + nx * (((cy + c[1]) % ny) + ny * ((cz + c[2]) % nz))
+        hit = solid[s_]
+        if not hit.any():
+            continue
+        d = c[2] - slope * c[0]          # change of zeta along the link
+        up = d > 0
+        lo = np.array(edges)[bc]
+        hi_ = np.array(edges)[bc + 1]
+        dl = np.where(up, (hi_ - zc) / np.where(d != 0, d, 1.0), (lo - zc) / np.where(d != 0, d, 1.0))
+        nb = np.where(up, (bc + 1) % len(bands), (bc - 1) % len(bands))
+        vel = np.array([b[2] for b in bands])[nb]
+        delta[q, hit] = dl[hit]
+        for a in range(3):
+            uw[a, q, hit] = vel[hit] * tang[a]
+    return types3, {"cells": cells, "delta": delta, "uw": uw}, zeta
+
+
+def skew_couette(nz: int = 16, slope: float = 0.25, U: float = 1e-3, ny: int = 1, tau: float = 0.8,
+                 Lambda: float = 3.0 / 16.0, stokes: int = 1, bands=None) -> Workload:
+    """Plane Couette flow in a channel rotated by atan(slope) against the
+    lattice (section 4.2: CLI walls recover it exactly with the linear
+    equilibrium): two solid bands, the lower one moving with U along the
+    channel, the upper one at rest, two liquid layers between them; x, y, z
+    periodic, nx = nz / slope; at rest at t = 0.  meta["profile"](zeta) is the
+    steady tangential velocity."""
+    nx = int(round(nz / slope))
+    if bands is None:
+        bands = ((3.3, "solid", U), (8.6, "fluid", 0.0), (11.2, "solid", 0.0), (float(nz), "fluid", 0.0))
+    p = Params(nx=nx, ny=ny, nz=nz, periodic=(1, 1, 1), tau=tau, Lambda=Lambda, stokes=stokes)
+    types3, walls, zeta = skew_strips(nx, ny, nz, slope, bands, p)
+    edges = [0.0] + [float(b[0]) for b in bands]
+
+    def profile(zz):
+        out = np.full(np.shape(zz), np.nan)
+        for i, (hi, k, _) in enumerate(bands):
+            if k != "fluid":
+                continue
+            lo = edges[i]
+            ulo = bands[(i - 1) % len(bands)][2]
+            uhi = bands[(i + 1) % len(bands)][2]
+            sel = (zz >= lo) & (zz < hi)
+            out = np.where(sel, ulo + (uhi - ulo) * (zz - lo) / (hi - lo), out)
+        return out
+
+    N = p.n_cells
+    return Workload(name="skew_couette", params=p, flags=types3.reshape(-1), rho=np.ones(N), u=None,
+                    fill=np.where(types3.reshape(-1) == SOLID, 0.0, 1.0),
+                    meta={"slope": slope, "U": U, "zeta": np.broadcast_to(zeta[:, None, :], (nz, ny, nx)).reshape(-1),
+                          "tangent": np.array([1.0, 0.0, slope]) / np.hypot(1.0, slope), "profile": profile},
+                    walls=walls)
 
 
 # Named configurations (sizes of the measured workloads).
