@@ -39,7 +39,7 @@ SWEEP_KERNEL = {"fp64": "k_sweep<FormF64, 1, false>", "fp32": "k_sweep<FormF32, 
 
 def sweep_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fslbm_device.hpp", "fslbm_sweep.hip"):
+    for f in ("fslbm_device.hpp", "fslbm_internal.hpp", "fslbm_sweep.hip"):
         h.update(open(os.path.join(ROOT, "paper_1409_5645_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define FSLBM_ABI_VERSION 2
+#define FSLBM_ABI_VERSION 3
 
 typedef struct fslbm_ctx fslbm_ctx;
 
@@ -109,6 +109,11 @@ typedef struct {
                                -div n from the fill field's gradient and Hessian by central
                                differences over the D3Q19 neighbourhood; not supported by the
                                adjoint window */
+  int32_t plic;             /* 0 or 1.  1: the FSL rules (FSL, FSL_STRESS, FSL_SHEAR) take the
+                               link distance delta = d / (c_q . n) from the plane n.(x - x_node)
+                               = d that cuts the cell's fill fraction phi (PLIC, the second-order
+                               interface position asked for in section 5) instead of d = phi -
+                               1/2; not supported by the adjoint window */
 } fslbm_params;
 
 typedef struct {

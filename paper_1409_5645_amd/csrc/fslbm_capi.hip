@@ -114,6 +114,7 @@ fslbm_status check_params(const fslbm_params* p, std::string& why) {
   if (!(p->rho_gas > 0.0)) { why = "rho_gas must be positive"; return FSLBM_E_INVALID; }
   if (!(p->conv_eps >= 0.0)) { why = "conv_eps must be >= 0"; return FSLBM_E_INVALID; }
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be finite and >= 0"; return FSLBM_E_INVALID; }
+  if (p->plic != 0 && p->plic != 1) { why = "plic must be 0 or 1"; return FSLBM_E_INVALID; }
   for (int f = 0; f < 6; ++f)
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->wall_u[f][a])) { why = "wall_u must be finite"; return FSLBM_E_INVALID; }
@@ -173,6 +174,7 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
       if (!p.periodic[f / 2] && p.wall_u[f][a] != 0.0) com.moving = 1;
   for (int i = 0; i < 6; ++i) com.shear_b[i] = p.shear_b[i];
   com.sigma = p.sigma;
+  com.plic = p.plic ? 1 : 0;
   com.rho_gas = p.rho_gas;
   com.scale = std::ldexp(1.0f, p.fp16_scale_log2);
   com.inv_scale = std::ldexp(1.0f, -p.fp16_scale_log2);
@@ -651,6 +653,10 @@ fslbm_status window_checks(fslbm_ctx* c, int32_t T, int32_t K) {
   }
   if (c->p.sigma != 0.0) {
     c->last_error = "the adjoint window does not support surface tension";
+    return FSLBM_E_UNSUPPORTED;
+  }
+  if (c->p.plic) {
+    c->last_error = "the adjoint window does not support the PLIC interface position";
     return FSLBM_E_UNSUPPORTED;
   }
   return FSLBM_OK;

@@ -22,6 +22,7 @@ struct Common {
   double shear_b[6];       // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules 4, 5)
   double sigma;            // surface tension coefficient (0: none)
   double rho_gas;          // gas density rho_b (actual, not in storage convention)
+  int plic;                // FSL link distances from the PLIC plane instead of phi - 1/2
 };
 
 template <class R>

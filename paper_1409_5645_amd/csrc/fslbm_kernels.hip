@@ -171,7 +171,11 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
       nv[1] = -gy / nrm;
       nv[2] = -gz / nrm;
     }
-    const double dist = d.phix - 0.5;
+    double dist = d.phix - 0.5;
+    if constexpr (EXTRA && (RULE & 1) != 0) {
+      // FSL link distances from the plane that cuts the cell's fill (PLIC)
+      if (cm.plic && have_n) dist = plic_plane_offset(d.phix, nv);
+    }
     // ---- moments of time t from the own post-collision populations
     R rho_t, u_t[3];
     recover_moments<R, SH>(d.own, k, incomp, rho_t, u_t);
@@ -217,8 +221,8 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
 // registers, store.
 constexpr int IBLOCK = 64;  // interface-list kernels: one wavefront per block
 
-// EXTRA: moving walls or surface tension present (a separate instantiation, so
-// that the plain path keeps its registers).
+// EXTRA: moving walls, surface tension or the PLIC interface position present
+// (a separate instantiation, so that the plain path keeps its registers).
 template <class F, int RULE, bool REC = false, bool EXTRA = false>
 __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_iface(SweepArgs a) {
   using R = typename F::R;
@@ -688,7 +692,7 @@ static void iface_form(const StepLaunch& L, int rule) {
   // the interface count is on the device: enough one-wavefront blocks for
   // every cell up to IFACE_GRID * IBLOCK, grid-stride beyond
   const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
-  const bool extra = L.sweep.c.moving || L.sweep.c.sigma != 0.0;
+  const bool extra = L.sweep.c.moving || L.sweep.c.sigma != 0.0 || L.sweep.c.plic;
   if (L.sweep.rec_f) {
     // a window step (rules 0 and 1): the list is fixed and its length (rec_cap) known here
     const unsigned nbr = std::min<unsigned>(nb, (unsigned)((L.sweep.rec_cap + IBLOCK - 1) / IBLOCK));

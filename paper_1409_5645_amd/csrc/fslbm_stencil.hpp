@@ -98,6 +98,48 @@ __device__ __forceinline__ double curvature(const IfaceData<F>& d) {
   return (g2 * trH - gHg) / (g2 * gn);
 }
 
+// Second-order interface position (section 5): the offset d of the plane
+// n.(x - x_node) = d that leaves the fill fraction phi of the unit cell on the
+// liquid side, for a unit normal n.  The cut volume is the forward relation of
+// Scardovelli & Zaleski (J. Comput. Phys. 164, 2000): components sorted
+// s1 <= s2 <= s3 and scaled to sum 1, offset reflected into [0, 1/2], the
+// quotients over s1 in closed form so near-axis normals lose nothing to
+// cancellation.  The offset is found by bisection on [0, 1/2] (54 halvings
+// reach the spacing of doubles there).
+__device__ __forceinline__ double plic_lower_volume(double al, double s1, double s2, double s3) {
+  if (al <= s1) return (al * al * al) / (6.0 * s1 * s2 * s3);
+  const double w = 1.0 / (6.0 * s2 * s3);
+  const double base = 3.0 * al * (al - s1) + s1 * s1;
+  if (al <= s2) return base * w;
+  const double r2 = al - s2;
+  const double s12 = s1 + s2;
+  if (al <= s3) {
+    if (al <= s12) return (base - r2 * r2 * r2 / s1) * w;
+    return (al - 0.5 * s12) / s3;
+  }
+  const double r3 = al - s3;
+  return (base - (r2 * r2 * r2 + r3 * r3 * r3) / s1) * w;
+}
+
+__device__ __noinline__ double plic_plane_offset(double phi, const double (&nv)[3]) {
+  const double a = fabs(nv[0]), b = fabs(nv[1]), c = fabs(nv[2]);
+  const double sum = a + b + c;
+  const double lo3 = fmin(a, fmin(b, c)), hi3 = fmax(a, fmax(b, c));
+  const double inv = 1.0 / sum;
+  const double s1 = lo3 * inv, s3 = hi3 * inv, s2 = ((sum - lo3) - hi3) * inv;
+  const double v = fmin(fmax(phi, 0.0), 1.0);
+  const bool upper = v > 0.5;
+  const double t = upper ? 1.0 - v : v;
+  double lo = 0.0, hi = 0.5;
+  for (int it = 0; it < 54; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (plic_lower_volume(mid, s1, s2, s3) < t) lo = mid;
+    else hi = mid;
+  }
+  const double al = 0.5 * (lo + hi);
+  return sum * ((upper ? 1.0 - al : al) - 0.5);
+}
+
 // c_q . S . c_q for a symmetric S = [xx, yy, zz, xy, xz, yz]
 template <int q, class R>
 __device__ __forceinline__ R c_S_c(const R (&S)[6]) {

@@ -23,7 +23,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 GAS, INTERFACE, LIQUID = 0, 1, 2
 STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "DEVICE", 4: "UNSTABLE", 5: "INVARIANT", 6: "CAPACITY"}
 FIELDS = ("rho", "u", "phi", "flags", "f", "mass", "rho_c", "u_c")
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class FslbmError(RuntimeError):
@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("stokes", ctypes.c_int32), ("g", ctypes.c_double * 3), ("rho_gas", ctypes.c_double),
                 ("conv_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32), ("freeze", ctypes.c_int32),
                 ("wall_u", (ctypes.c_double * 3) * 6), ("shear_b", ctypes.c_double * 6),
-                ("sigma", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("plic", ctypes.c_int32)]
 
 
 class Buffers(ctypes.Structure):
@@ -99,7 +99,7 @@ def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13) -> Params:
                   ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*[float(v) for v in face])
                                                  for face in getattr(p, "wall_u", ((0.0, 0.0, 0.0),) * 6)]),
                   (ctypes.c_double * 6)(*[float(v) for v in getattr(p, "shear_b", (0.0,) * 6)]),
-                  float(getattr(p, "sigma", 0.0)))
+                  float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)))
 
 
 class Sim:

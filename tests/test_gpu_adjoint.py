@@ -239,6 +239,11 @@ def test_window_errors(fs, case):
     with pytest.raises(fs.FslbmError, match="UNSUPPORTED"):  # no adjoint of the curvature
         st_.window(5, 1)
     st_.close()
+    sp = fs.Sim(dataclasses.replace(p, plic=1), st["flags"], precision="fp64")
+    sp.set_state(st["f"], st["mass"], st["phi"])
+    with pytest.raises(fs.FslbmError, match="UNSUPPORTED"):  # no adjoint of the plane offset
+        sp.window(5, 1)
+    sp.close()
 
 
 def test_full_size_fp64_fd_and_fp32_error(fs):
