@@ -197,6 +197,34 @@ fslbm_status fslbm_timing(fslbm_ctx* c, int32_t enable, double* sweep_ms, int64_
  * work. */
 fslbm_status fslbm_set_forcing(fslbm_ctx* c, const double g[3], double rho_gas);
 
+/* Solid walls at arbitrary distances from the nodes (the rotated channels of
+ * section 4.2).  Cells of class 3 in the flags are solid: they hold no fluid,
+ * never convert, and are walls to their fluid neighbours (no mass exchange,
+ * the cell's own fill in the interface geometry).  A population pulled from a
+ * solid cell takes the linear-interpolation closure for the link p towards
+ * the wall point x + delta c_p: the closure of Eq. (closure) whose
+ * coefficients satisfy the fitting conditions of Eq. (fitting, cl1) with no
+ * pressure term and the wall momentum to first order (C = 0, a0 = 1):
+ *   f_q(x,t+1) = ft_p(x) + kappa (ft_p(x - c_p) - ft_q(x))
+ *                + 2/(1 + 2 delta) * 2 w_q (c_q . u_w) / c_s^2,
+ * kappa = (1 - 2 delta)/(1 + 2 delta), q = pbar, rho_w = 1; halfway
+ * bounce-back (delta = 1/2) where x - c_p is not a fluid cell.
+ *   n       number of listed cells;
+ *   cells   int32[n], device: every non-solid cell with a D3Q19 link into a
+ *           solid cell, strictly ascending, nothing else;
+ *   delta   double[19][n], device: delta[p*n + i] in (0, 1] for each link p
+ *           of cells[i] whose neighbour x + c_p is solid (other entries not
+ *           read);
+ *   wall_u  double[3][19][n], device: velocity of that wall point,
+ *           wall_u[(a*19 + p)*n + i] (finite).
+ * The arrays stay owned by the caller and are read by every later step: keep
+ * them alive and unchanged until the next call or fslbm_destroy.  The table
+ * is validated on the device (then synchronises the stream); FSLBM_E_INVALID
+ * names the first violation.  Required before fslbm_step when the flags hold
+ * solid cells; not supported by the adjoint window. */
+fslbm_status fslbm_set_walls(fslbm_ctx* c, int32_t n, const int32_t* cells, const double* delta,
+                             const double* wall_u);
+
 /* ---------------------------------------------------------------------------
  * Adjoint window: gradients through T steps with frozen cell classes.
  *

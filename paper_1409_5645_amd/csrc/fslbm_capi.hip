@@ -33,6 +33,11 @@ struct fslbm_ctx {
   double* reservoir;
   double* kappa = nullptr;  // surface tension only
   double* wall_t = nullptr; // moving-wall terms [6][19]
+  bool has_solid = false;   // the flags hold solid cells
+  const int32_t* wcells = nullptr;  // wall table (caller's device memory, fslbm_set_walls)
+  const double* wdelta = nullptr;
+  const double* wuw = nullptr;
+  int nwall = -1;           // -1: no table set
   double* acc;
   int32_t* err;
   int32_t* cnt;
@@ -274,6 +279,7 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return fail(dev_fail(c, e, "init sync"));
   if (herr & 1) { c->last_error = "unknown cell class in flags"; return fail(FSLBM_E_INVALID); }
   if (herr & 2) { c->last_error = "a liquid cell has a gas neighbour"; return fail(FSLBM_E_INVALID); }
+  c->has_solid = (herr & 4) != 0;
   *out = c;
   return FSLBM_OK;
 }
@@ -316,6 +322,10 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     c->last_error = "this rule needs tau != 1 (n+ is not recoverable from a fully relaxed state)";
     return FSLBM_E_UNSUPPORTED;
   }
+  if (c->has_solid && c->nwall < 0) {
+    c->last_error = "solid cells present: set their wall table with fslbm_set_walls first";
+    return FSLBM_E_INVALID;
+  }
   for (int32_t i = 0; i < n; ++i) {
     StepLaunch L{};
     const int a = c->cur, b = 1 - c->cur;
@@ -345,6 +355,10 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.u_out = nullptr;
     s.kappa = c->kappa;
     s.wall_t = c->wall_t;
+    s.wcells = c->wcells;
+    s.wdelta = c->wdelta;
+    s.wuw = c->wuw;
+    s.nwall = c->nwall > 0 ? c->nwall : 0;
     ConvArgs& v = L.conv;
     v.c = c->com;
     v.fout = c->f[b];
@@ -380,6 +394,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
       HIPCHK(c, hipEventRecord(c->events[c->events_used + 1], c->stream), "event record");
       c->events_used += 2;
     }
+    if (s.nwall > 0) HIPCHK(c, launch_wall(L, c->p.precision), "wall launch");
     if (c->kappa) HIPCHK(c, launch_curvature(L), "curvature launch");
     HIPCHK(c, launch_iface(L, c->p.precision, rule), "interface launch");
     if (!c->p.freeze) HIPCHK(c, launch_convert(L, c->p.precision), "conversion launch");
@@ -659,6 +674,10 @@ fslbm_status window_checks(fslbm_ctx* c, int32_t T, int32_t K) {
     c->last_error = "the adjoint window does not support the PLIC interface position";
     return FSLBM_E_UNSUPPORTED;
   }
+  if (c->has_solid) {
+    c->last_error = "the adjoint window does not support solid cells";
+    return FSLBM_E_UNSUPPORTED;
+  }
   return FSLBM_OK;
 }
 
@@ -744,6 +763,38 @@ hipError_t window_run(fslbm_window* w, int t0, int t1, bool forward_pass) {
 }  // namespace
 
 extern "C" {
+
+fslbm_status fslbm_set_walls(fslbm_ctx* c, int32_t n, const int32_t* cells, const double* delta,
+                             const double* wall_u) {
+  if (!c) return FSLBM_E_INVALID;
+  if (n < 0) { c->last_error = "n must be >= 0"; return FSLBM_E_INVALID; }
+  if (n > 0 && (!cells || !delta || !wall_u)) { c->last_error = "cells, delta or wall_u is NULL"; return FSLBM_E_INVALID; }
+  HIPCHK(c, launch_fill_i32(c->err, 1, 0, c->stream), "wall check init");
+  HIPCHK(c, launch_fill_i32(c->cnt + 3, 1, 0, c->stream), "wall check init");
+  HIPCHK(c, launch_check_walls(c->flags, c->com.grid, cells, n, delta, wall_u, c->err, c->cnt + 3, c->stream),
+         "wall check");
+  int32_t h[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(&h[0], c->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "wall check copy");
+  HIPCHK(c, hipMemcpyAsync(&h[1], c->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "wall check copy");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "wall check sync");
+  if (h[0] & 1) { c->last_error = "wall list: cell index out of range"; return FSLBM_E_INVALID; }
+  if (h[0] & 2) { c->last_error = "wall list: cells not strictly ascending"; return FSLBM_E_INVALID; }
+  if (h[0] & 4) { c->last_error = "wall list: a listed cell is solid"; return FSLBM_E_INVALID; }
+  if (h[0] & 32) { c->last_error = "wall list: a listed cell has no link into a solid cell"; return FSLBM_E_INVALID; }
+  if (h[0] & 8) { c->last_error = "wall distance outside (0, 1] on a link into a solid cell"; return FSLBM_E_INVALID; }
+  if (h[0] & 16) { c->last_error = "wall velocity not finite"; return FSLBM_E_INVALID; }
+  if (h[1] != n) {
+    c->last_error = "wall list must hold every non-solid cell next to a solid cell (" + std::to_string(h[1]) +
+                    " such cells, " + std::to_string(n) + " listed)";
+    return FSLBM_E_INVALID;
+  }
+  c->wcells = cells;
+  c->wdelta = delta;
+  c->wuw = wall_u;
+  c->nwall = n;
+  c->com.solid = n > 0 ? 1 : 0;
+  return FSLBM_OK;
+}
 
 fslbm_status fslbm_set_forcing(fslbm_ctx* c, const double g[3], double rho_gas) {
   if (!c) return FSLBM_E_INVALID;

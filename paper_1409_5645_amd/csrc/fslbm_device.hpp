@@ -29,7 +29,7 @@ constexpr double W3D[Q] = {3.0 * (1.0 / 3.0),  3.0 * (1.0 / 18.0), 3.0 * (1.0 / 
                            3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0),
                            3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0), 3.0 * (1.0 / 36.0)};
 
-enum : uint8_t { GAS = 0, IFACE = 1, LIQ = 2 };
+enum : uint8_t { GAS = 0, IFACE = 1, LIQ = 2, SOLID = 3 };  // SOLID: obstacle, never converted
 
 // ---------------------------------------------------------------- forms
 // R: compute type; S: storage type.  Shifted forms store g_q = f_q - w_q, so

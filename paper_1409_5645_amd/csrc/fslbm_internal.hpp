@@ -23,6 +23,7 @@ struct Common {
   double sigma;            // surface tension coefficient (0: none)
   double rho_gas;          // gas density rho_b (actual, not in storage convention)
   int plic;                // FSL link distances from the PLIC plane instead of phi - 1/2
+  int solid;               // solid cells present (SweepArgs carries their wall table)
 };
 
 template <class R>
@@ -72,6 +73,13 @@ struct SweepArgs {
   int rec_cap;
   double* kappa;  // surface tension: 3 sigma kappa per listed interface cell (list order)
   const double* wall_t;  // moving walls: [6 faces][19 links] bounce-back terms 2 w_q (c_q.u_w)/c_s^2
+  // solid walls: ascending list of the non-solid cells next to a solid cell,
+  // per listed cell i and link p the wall distance delta[p*nwall + i] and
+  // velocity uw[(a*19 + p)*nwall + i] of the wall point x + delta c_p
+  const int32_t* wcells;
+  const double* wdelta;
+  const double* wuw;
+  int nwall;
 };
 
 struct ConvArgs {
@@ -171,6 +179,9 @@ hipError_t launch_convert(const StepLaunch& L, int precision);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, void* stream);
 hipError_t launch_fill_f64(double* p, size_t n, double v, void* stream);
 hipError_t launch_check_flags(const uint8_t* flags, const Grid& g, int32_t* err, void* stream);
+hipError_t launch_wall(const StepLaunch& L, int precision);
+hipError_t launch_check_walls(const uint8_t* flags, const Grid& g, const int32_t* cells, int n, const double* delta,
+                              const double* uw, int32_t* err, int32_t* count, void* stream);
 hipError_t launch_set_equilibrium(const InitArgs& a, int precision, const double* rho, const double* u,
                                   const double* fill, void* stream);
 hipError_t launch_set_state(const InitArgs& a, int precision, const double* f, const double* mass,

@@ -276,6 +276,25 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
     }
     d.m = a.mass_in[idx];
     d.phix = a.phi_in[idx];
+    if constexpr (EXTRA) {
+      if (a.c.solid) {
+        // solid pull sources (class SOLID, inside the grid): the cell's own fill
+        // for the geometry, the wall closure for the populations
+        uint32_t sm = 0, up = 0;
+#define FSLBM_ISOLID(q)                                                       \
+  if (d.ty[q] == WALL_CLASS && pull_source<q>(g, n) >= 0) sm |= 1u << q;      \
+  if (d.ty[q] == LIQ || d.ty[q] == IFACE) up |= 1u << q;
+        FSLBM_LINKS(FSLBM_ISOLID)
+#undef FSLBM_ISOLID
+        if (sm) {
+          const int slot = wall_slot(a.wcells, a.nwall, idx);
+          if (slot >= 0) solid_links<R>(d.f, d.own, sm, up, slot, a.nwall, a.wdelta, a.wuw);
+#pragma unroll
+          for (int q = 1; q < Q; ++q)
+            if ((sm >> q) & 1u) d.ph[q] = d.phix;
+        }
+      }
+    }
     if constexpr (REC) {
       // what the adjoint of this step needs at this cell, in list order
       using RR = typename F::R;
@@ -349,6 +368,12 @@ __global__ __launch_bounds__(IBLOCK) void k_curvature(SweepArgs a) {
   }
     FSLBM_LINKS(FSLBM_CLOAD)
 #undef FSLBM_CLOAD
+    if (a.c.solid) {
+      // a solid source is a wall: the cell's own fill
+#pragma unroll
+      for (int q = 1; q < Q; ++q)
+        if (d.ty[q] == WALL_CLASS) d.ph[q] = d.phix;
+    }
     a.kappa[i] = 3.0 * a.c.sigma * curvature(d);
   }
 }
@@ -367,7 +392,7 @@ __device__ void init_new_from_gas(const ConvArgs& a, int c) {
 #pragma unroll
   for (int q = 1; q < Q; ++q) {
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-    if (s < 0 || a.flags[s] == GAS) continue;
+    if (s < 0 || a.flags[s] == GAS || a.flags[s] == SOLID) continue;
     rs = rs + a.aux_rho[s];
     us0 = us0 + a.aux_u[s];
     us1 = us1 + a.aux_u[(size_t)g.N + s];
@@ -516,10 +541,11 @@ __global__ __launch_bounds__(BLOCK) void k_check_flags(const uint8_t* flags, Gri
   const int idx = blockIdx.x * BLOCK + threadIdx.x;
   if (idx >= g.N) return;
   const uint8_t t = flags[idx];
-  if (t > LIQ) {
+  if (t > SOLID) {
     atomicOr(err, 1);
     return;
   }
+  if (t == SOLID) atomicOr(err, 4);  // solid cells present
   if (t != LIQ) return;
   int x, y, z;
   coords(g, idx, x, y, z);
@@ -540,6 +566,13 @@ __global__ __launch_bounds__(BLOCK) void k_set_equilibrium(InitArgs a, const dou
   const uint8_t t = a.flags[idx];
   if (t == GAS) return;
   const size_t N = a.c.grid.N;
+  if (t == SOLID) {
+    // obstacles hold no fluid: zero populations (never read by the step)
+    S* fz = reinterpret_cast<S*>(a.f);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fz[(size_t)q * N + idx] = S(0);
+    return;
+  }
   const Consts<R>& k = pick_consts<R>(a.c);
   const double r = rho[idx];
   R uu[3] = {(R)u[idx], (R)u[N + idx], (R)u[2 * N + idx]};
@@ -571,6 +604,11 @@ __global__ __launch_bounds__(BLOCK) void k_set_state(InitArgs a, const double* f
   const size_t N = a.c.grid.N;
   const Consts<R>& k = pick_consts<R>(a.c);
   S* fo = reinterpret_cast<S*>(a.f);
+  if (t == SOLID) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fo[(size_t)q * N + idx] = S(0);
+    return;
+  }
   R fl[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -603,7 +641,7 @@ __global__ __launch_bounds__(BLOCK) void k_fields(FieldArgs a) {
   const S* fi = reinterpret_cast<const S*>(a.f);
   const Consts<R>& k = pick_consts<R>(a.c);
   if (a.flags_out) a.flags_out[idx] = t;
-  if (a.phi_out) a.phi_out[idx] = t == LIQ ? 1.0 : (t == GAS ? 0.0 : a.phi[idx]);
+  if (a.phi_out) a.phi_out[idx] = t == LIQ ? 1.0 : (t == IFACE ? a.phi[idx] : 0.0);
   if (a.mass_out) a.mass_out[idx] = t == IFACE ? a.mass[idx] : 0.0;
   if (a.rhoc_out) a.rhoc_out[idx] = t == IFACE ? a.aux_rho[idx] : 0.0;
   if (a.uc_out)
@@ -614,15 +652,16 @@ __global__ __launch_bounds__(BLOCK) void k_fields(FieldArgs a) {
   if (a.f_out) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
-      a.f_out[(size_t)q * N + idx] = t == GAS ? 0.0 : (SH ? (double)fl[q] + WD[q] : (double)fl[q]);
+      a.f_out[(size_t)q * N + idx] = (t == GAS || t == SOLID) ? 0.0 : (SH ? (double)fl[q] + WD[q] : (double)fl[q]);
   }
   if (a.rho_out || a.u_out) {
     R rs, uu[3];
     recover_moments<R, SH>(fl, k, a.c.incomp, rs, uu);
     const double r = SH ? 1.0 + (double)rs : (double)rs;
-    if (a.rho_out) a.rho_out[idx] = t == GAS ? 0.0 : r;
+    const bool fluid = t == LIQ || t == IFACE;
+    if (a.rho_out) a.rho_out[idx] = fluid ? r : 0.0;
     if (a.u_out)
-      for (int d = 0; d < 3; ++d) a.u_out[d * N + idx] = t == GAS ? 0.0 : (double)uu[d];
+      for (int d = 0; d < 3; ++d) a.u_out[d * N + idx] = fluid ? (double)uu[d] : 0.0;
   }
 }
 
@@ -639,7 +678,7 @@ __global__ __launch_bounds__(BLOCK) void k_stats(StatArgs a) {
   const S* fi = reinterpret_cast<const S*>(a.f);
   for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < a.c.grid.N; idx += gridDim.x * BLOCK) {
     const uint8_t t = a.flags[idx];
-    if (t == GAS) continue;
+    if (t == GAS || t == SOLID) continue;
     double r = 0.0;
     for (int q = 0; q < Q; ++q) r = r + (double)F::load(fi + (size_t)q * a.c.grid.N + idx, a.c.inv_scale);
     if (F::shifted) r = 1.0 + r;
@@ -692,7 +731,7 @@ static void iface_form(const StepLaunch& L, int rule) {
   // the interface count is on the device: enough one-wavefront blocks for
   // every cell up to IFACE_GRID * IBLOCK, grid-stride beyond
   const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
-  const bool extra = L.sweep.c.moving || L.sweep.c.sigma != 0.0 || L.sweep.c.plic;
+  const bool extra = L.sweep.c.moving || L.sweep.c.sigma != 0.0 || L.sweep.c.plic || L.sweep.c.solid;
   if (L.sweep.rec_f) {
     // a window step (rules 0 and 1): the list is fixed and its length (rec_cap) known here
     const unsigned nbr = std::min<unsigned>(nb, (unsigned)((L.sweep.rec_cap + IBLOCK - 1) / IBLOCK));
@@ -719,6 +758,132 @@ static void convert_form(const StepLaunch& L) {
   k_commit<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
   k_share<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
   k_gather<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
+}
+
+// Liquid cells next to solid cells (the wall list; interface cells there are
+// done by k_iface, gas cells need nothing): the sweep has written them with
+// values pulled from solid cells, so this kernel redoes their step after it:
+// pull (halfway bounce-back at wall faces, the wall closure on solid links),
+// TRT collision, store.  One cell per thread.
+template <class F>
+__global__ __launch_bounds__(IBLOCK) void k_wall(SweepArgs a) {
+  using R = typename F::R;
+  using S = typename F::S;
+  constexpr bool SH = F::shifted;
+  const Grid g = a.c.grid;
+  const S* __restrict__ fin = reinterpret_cast<const S*>(a.fin);
+  S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
+  const size_t N = (size_t)g.N;
+  const float isc = a.c.inv_scale;
+  const Consts<R>& k = pick_consts<R>(a.c);
+  const bool incomp = a.c.incomp, stokes = a.c.stokes;
+  for (int i = blockIdx.x * IBLOCK + threadIdx.x; i < a.nwall; i += gridDim.x * IBLOCK) {
+    const int idx = a.wcells[i];
+    if (a.flags[idx] != LIQ) continue;
+    Nbr n;
+    coords(g, idx, n.x, n.y, n.z);
+    n.xm = step_axis(n.x, -1, g.nx, g.px);
+    n.xp = step_axis(n.x, 1, g.nx, g.px);
+    n.ym = step_axis(n.y, -1, g.ny, g.py);
+    n.yp = step_axis(n.y, 1, g.ny, g.py);
+    n.zm = step_axis(n.z, -1, g.nz, g.pz);
+    n.zp = step_axis(n.z, 1, g.nz, g.pz);
+    R f[Q], own[Q];
+    uint32_t sm = 0, up = 0;
+    f[0] = F::load(fin + idx, isc);
+    own[0] = f[0];
+#define FSLBM_WLOAD(q)                                                                     \
+  {                                                                                        \
+    const int s = pull_source<q>(g, n);                                                    \
+    const size_t off = s >= 0 ? (size_t)q * N + (size_t)s : (size_t)OPP[q] * N + idx;      \
+    f[q] = F::load(fin + off, isc);                                                        \
+    own[q] = F::load(fin + (size_t)q * N + idx, isc);                                      \
+    const uint8_t ts = s >= 0 ? a.flags[s] : WALL_CLASS;                                   \
+    if (s >= 0 && ts == SOLID) sm |= 1u << q;                                              \
+    if (ts == LIQ || ts == IFACE) up |= 1u << q;                                           \
+  }
+    FSLBM_LINKS(FSLBM_WLOAD)
+#undef FSLBM_WLOAD
+    if (a.c.moving) {
+#define FSLBM_WWALLU(q)                                                                        \
+  {                                                                                            \
+    const double t = wall_term<q>(a.wall_t, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp);               \
+    if (t != 0.0) f[q] = f[q] + (R)t;                                                          \
+  }
+      FSLBM_LINKS(FSLBM_WWALLU)
+#undef FSLBM_WWALLU
+    }
+    solid_links<R>(f, own, sm, up, i, a.nwall, a.wdelta, a.wuw);
+    R rho_s, u[3];
+    if constexpr (sizeof(R) == 4)
+      collide_f32<SH>(f, k, incomp, stokes, rho_s, u);
+    else
+      collide<R, SH>(f, k, incomp, stokes, rho_s, u);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, f[q], a.c.scale);
+  }
+}
+
+hipError_t launch_wall(const StepLaunch& L, int precision) {
+  if (L.sweep.nwall <= 0) return hipSuccess;
+  const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.nwall + IBLOCK - 1) / IBLOCK));
+  hipStream_t st = (hipStream_t)L.stream;
+  if (precision == 0) k_wall<FormF64><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  else if (precision == 1) k_wall<FormF32><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  else k_wall<FormF16><<<nb, IBLOCK, 0, st>>>(L.sweep);
+  return hipGetLastError();
+}
+
+// Wall table checks: cells ascending, in range, not solid, each with a link
+// into a solid cell whose distance is in (0, 1] and velocity finite (err bits
+// 1, 2, 4, 32, 8, 16); count[0] += the number of non-solid cells with a link
+// into a solid cell (k_count_walls), to be compared with n.
+__global__ __launch_bounds__(BLOCK) void k_check_walls(const uint8_t* flags, Grid g, const int32_t* cells, int n,
+                                                       const double* delta, const double* uw, int32_t* err) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int idx = cells[i];
+  if (idx < 0 || idx >= g.N) {
+    atomicOr(err, 1);
+    return;
+  }
+  if (i > 0 && cells[i - 1] >= idx) atomicOr(err, 2);
+  if (flags[idx] == SOLID) atomicOr(err, 4);
+  int x, y, z;
+  coords(g, idx, x, y, z);
+  bool any = false;
+  for (int q = 1; q < Q; ++q) {
+    const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
+    if (s < 0 || flags[s] != SOLID) continue;
+    any = true;
+    const double d = delta[(size_t)q * n + i];
+    if (!(d > 0.0 && d <= 1.0)) atomicOr(err, 8);
+    for (int c = 0; c < 3; ++c)
+      if (!isfinite(uw[((size_t)c * Q + q) * n + i])) atomicOr(err, 16);
+  }
+  if (!any) atomicOr(err, 32);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_count_walls(const uint8_t* flags, Grid g, int32_t* count) {
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= g.N || flags[idx] == SOLID) return;
+  int x, y, z;
+  coords(g, idx, x, y, z);
+  for (int q = 1; q < Q; ++q) {
+    const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
+    if (s >= 0 && flags[s] == SOLID) {
+      atomicAdd(count, 1);
+      return;
+    }
+  }
+}
+
+hipError_t launch_check_walls(const uint8_t* flags, const Grid& g, const int32_t* cells, int n, const double* delta,
+                              const double* uw, int32_t* err, int32_t* count, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (n > 0) k_check_walls<<<blocks_for(n), BLOCK, 0, st>>>(flags, g, cells, n, delta, uw, err);
+  k_count_walls<<<blocks_for(g.N), BLOCK, 0, st>>>(flags, g, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_curvature(const StepLaunch& L) {

@@ -26,7 +26,7 @@ __device__ __forceinline__ int pull_source(const Grid& g, const Nbr& n) {
   return ((sx | sy | sz) < 0) ? -1 : sx + g.nx * (sy + g.ny * sz);
 }
 
-constexpr uint8_t WALL_CLASS = 3;  // class recorded for a pull source beyond a wall
+constexpr uint8_t WALL_CLASS = 3;  // class recorded for a pull source beyond a wall (= SOLID)
 
 // Neighbourhood of one interface cell, loaded in a single pass (all loads
 // independent, so the cell costs one memory round trip, not a chain of them).
@@ -96,6 +96,52 @@ __device__ __forceinline__ double curvature(const IfaceData<F>& d) {
   for (int a = 0; a < 3; ++a) gHg = gHg + g[a] * ((H[a][0] * g[0] + H[a][1] * g[1]) + H[a][2] * g[2]);
   const double gn = sqrt(g2);
   return (g2 * trH - gHg) / (g2 * gn);
+}
+
+// Slot of a cell in the ascending wall list (binary search), -1 if absent.
+__device__ __forceinline__ int wall_slot(const int32_t* __restrict__ cells, int n, int idx) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cells[mid] < idx) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && cells[lo] == idx) ? lo : -1;
+}
+
+// Solid walls of the rotated channels (section 4.2).  Link q whose pull source
+// x - c_q is a solid cell (bit q of `solid`): with p = qbar the link towards
+// the wall point x + delta c_p, the closure f_q(x,t+1) = a0 ft_p(x) +
+// a0bar ft_q(x) + a1 ft_p(x - c_p) + f^b of Eq. (closure) with the fitting
+// conditions alpha_+ = 0 and beta_+ / lambda_+ = alpha_- delta (Eq. fitting,
+// cl1; momentum of the wall matched to first order, no pressure term), C = 0
+// and a0 = 1: kappa = (1 - 2 delta)/(1 + 2 delta), a1 = kappa, a0bar = -kappa,
+// f^b = -4/(1 + 2 delta) e-_p(u_w), i.e. 2/(1 + 2 delta) times the halfway
+// bounce-back term 2 w_q (c_q . u_w)/c_s^2 (rho_w = 1).  ft_p(x - c_p) is the
+// value pulled along p; where its source is not a fluid cell (bit p of `up`
+// clear) the link takes halfway bounce-back.  f[p] of a fluid source is never
+// modified here, so the links can be done in any order.
+template <class R>
+__device__ __forceinline__ void solid_links(R (&f)[Q], const R (&own)[Q], uint32_t solid, uint32_t up, int slot,
+                                            int nw, const double* __restrict__ delta,
+                                            const double* __restrict__ uw) {
+#define FSLBM_SOLID(q)                                                                                  \
+  if ((solid >> q) & 1u) {                                                                              \
+    constexpr int p = OPP[q];                                                                           \
+    const double dl = delta[(size_t)p * nw + slot];                                                     \
+    const double u0 = uw[(size_t)p * nw + slot];                                                        \
+    const double u1 = uw[((size_t)Q + p) * nw + slot];                                                  \
+    const double u2 = uw[((size_t)2 * Q + p) * nw + slot];                                              \
+    const double bb = 6.0 * WD[q] * ((CX[q] * u0 + CY[q] * u1) + CZ[q] * u2);                            \
+    if ((up >> p) & 1u) {                                                                               \
+      const double kap = (1.0 - 2.0 * dl) / (1.0 + 2.0 * dl);                                           \
+      f[q] = (own[p] + (R)kap * (f[p] - own[q])) + (R)(bb * (2.0 / (1.0 + 2.0 * dl)));                  \
+    } else {                                                                                            \
+      f[q] = own[p] + (R)bb;                                                                            \
+    }                                                                                                   \
+  }
+  FSLBM_LINKS(FSLBM_SOLID)
+#undef FSLBM_SOLID
 }
 
 // Second-order interface position (section 5): the offset d of the plane

@@ -49,7 +49,7 @@ class Buffers(ctypes.Structure):
 
 
 EXPORTS = ("fslbm_workspace_size", "fslbm_init", "fslbm_set_equilibrium", "fslbm_set_state", "fslbm_step",
-           "fslbm_fields", "fslbm_stats", "fslbm_conversions", "fslbm_timing", "fslbm_set_forcing",
+           "fslbm_fields", "fslbm_stats", "fslbm_conversions", "fslbm_timing", "fslbm_set_forcing", "fslbm_set_walls",
            "fslbm_window_workspace_size", "fslbm_window_forward", "fslbm_window_backward", "fslbm_window_info",
            "fslbm_window_destroy", "fslbm_destroy", "fslbm_last_error")
 
@@ -75,6 +75,7 @@ def lib():
         L.fslbm_conversions.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(i32)), i32, ctypes.POINTER(i32)]
         L.fslbm_timing.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
         L.fslbm_set_forcing.argtypes = [vp, dp, ctypes.c_double]
+        L.fslbm_set_walls.argtypes = [vp, i32, vp, vp, vp]
         L.fslbm_window_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.fslbm_window_forward.argtypes = [vp, i32, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.fslbm_window_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, dp]
@@ -156,7 +157,25 @@ class Sim:
     def from_workload(cls, w, precision="fp64", **kw):
         s = cls(w.params, w.flags, precision=precision, **kw)
         s.set_equilibrium(w.rho, w.velocity(), w.fill)
+        walls = getattr(w, "walls", None)
+        if walls is not None:
+            s.set_walls(walls["cells"], walls.get("delta"), walls.get("uw"))
         return s
+
+    def set_walls(self, cells, delta=None, uw=None):
+        """Wall table of the solid cells (class 3): ascending non-solid cells
+        next to a solid cell, delta[19, n] (default 1/2) and uw[3, 19, n]
+        (default 0).  The device copies are kept by this object."""
+        torch = self.torch
+        c = np.ascontiguousarray(cells, dtype=np.int32)
+        n = c.size
+        d = np.full((19, n), 0.5) if delta is None else np.asarray(delta, dtype=np.float64).reshape(19, n)
+        v = np.zeros((3, 19, n)) if uw is None else np.asarray(uw, dtype=np.float64).reshape(3, 19, n)
+        self._walls = (torch.as_tensor(c).to(self.device), self._dev(d), self._dev(v))
+        torch.cuda.synchronize(self.device)
+        ct, dt, vt = self._walls
+        self._check(lib().fslbm_set_walls(self.ctx, n, ct.data_ptr() if n else None, dt.data_ptr() if n else None,
+                                          vt.data_ptr() if n else None), self.ctx)
 
     # ---------------------------------------------------------------- API
     def set_equilibrium(self, rho, u, fill):

@@ -315,6 +315,61 @@ def skew_couette(nz: int = 16, slope: float = 0.25, U: float = 1e-3, ny: int = 1
                     walls=walls)
 
 
+def add_plane_obstacle(w: Workload, normal, offset: float, velocity=(0.0, 0.0, 0.0), name=None) -> Workload:
+    """Make every cell whose centre x_c has normal . x_c < offset solid (a
+    half-space obstacle, e.g. an inclined ramp), and build the wall table with
+    the exact distance of each link's crossing of the plane and the obstacle's
+    velocity.  Cells next to the obstacle keep their class; their fill and
+    density are unchanged."""
+    p = w.params
+    nx, ny, nz = p.nx, p.ny, p.nz
+    nrm = np.asarray(normal, dtype=np.float64)
+    N = p.n_cells
+    idx = np.arange(N)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    xc = np.stack([x + 0.5, y + 0.5, z + 0.5]).astype(np.float64)
+    side = nrm @ xc - offset                     # < 0 inside the obstacle
+    flags = w.flags.copy()
+    flags[side < 0.0] = SOLID
+    solid = flags == SOLID
+    dims = (nx, ny, nz)
+
+    def nb(c):
+        cc = [x + c[0], y + c[1], z + c[2]]
+        ok = np.ones(N, dtype=bool)
+        for a in range(3):
+            if p.periodic[a]:
+                cc[a] = cc[a] % dims[a]
+            else:
+                ok &= (cc[a] >= 0) & (cc[a] < dims[a])
+                cc[a] = np.clip(cc[a], 0, dims[a] - 1)
+        return cc[0] + nx * (cc[1] + ny * cc[2]), ok
+
+    near = np.zeros(N, dtype=bool)
+    for q in range(1, 19):
+        s_, ok = nb(LINKS[q])
+        near |= ok & solid[s_]
+    cells = np.nonzero(near & ~solid)[0].astype(np.int32)
+    n = cells.size
+    delta = np.full((19, n), 0.5)
+    uw = np.zeros((3, 19, n))
+    for q in range(1, 19):
+        s_, ok = nb(LINKS[q])
+        hit = (ok & solid[s_])[cells]
+        if not hit.any():
+            continue
+        f0 = side[cells]
+        f1 = f0 + nrm @ LINKS[q].astype(np.float64)
+        delta[q, hit] = (f0 / (f0 - f1))[hit]
+        for a in range(3):
+            uw[a, q, hit] = velocity[a]
+    rho = np.where(solid, 1.0, w.rho)
+    fill = np.where(solid, 0.0, w.fill)
+    u = None if w.u is None else np.where(solid[None, :], 0.0, w.u)
+    return Workload(name=name or (w.name + "_obstacle"), params=p, flags=flags, rho=rho, u=u, fill=fill,
+                    meta=dict(w.meta), walls={"cells": cells, "delta": delta, "uw": uw})
+
+
 # Named configurations (sizes of the measured workloads).
 def config(name: str, seed: int = 0) -> Workload:
     if name == "channel":

@@ -384,3 +384,83 @@ def test_plic_reduced_precision(fs, oracle_mod, precision, tol):
     err = np.abs(g["u"][:, act] - uo[:, act]).max() / np.abs(uo[:, act]).max()
     _say(precision, "plic sloshing u rel err", err, "flag mismatches", int((g["flags"] != o.flags()).sum()))
     assert err < tol
+
+
+def _ramp_tank(**kw):
+    w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
+    w = W.add_plane_obstacle(w, (-0.3, 1.0, 0.12), 3.1, velocity=(2e-4, 6e-5, 0.0))  # along the ramp
+    return _with(w, **kw) if kw else w
+
+
+def test_skew_couette_walls_parity(fs, oracle_mod):
+    """Couette flow in a channel rotated by atan(1/4) between solid bands
+    (linear-interpolation wall closure, exact wall distances): FP64 against
+    the oracle over 300 steps from rest."""
+    w = W.skew_couette()
+    _say("case skew couette")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(3):
+        o.step(100, 1)
+        s.step(100, 1)
+        _compare(o, s, f"skew couette step {100 * (it + 1)}")
+
+
+@pytest.mark.parametrize("rule,extra", [(1, {}), (0, {}), (3, {}), (5, {}), (1, {"plic": 1, "sigma": 1e-3}),
+                                        (1, {"wall_u": _MOVING})])
+def test_solid_ramp_tank_parity(fs, oracle_mod, rule, extra):
+    """A converting sloshing tank over an inclined moving solid ramp: interface
+    and liquid cells next to solid cells, conversions along the ramp, with the
+    plain and the EXTRA interface kernel (moving wall faces, PLIC and surface
+    tension): classes and lists bit-exact, populations within 1e-12."""
+    w = _ramp_tank(**extra)
+    _say(f"case ramp tank rule {rule} {sorted(extra)}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(60):
+        o.step(1, rule)
+        s.step(1, rule)
+        if it % 10 == 9:
+            _compare(o, s, f"ramp step {it + 1}")
+    st = s.stats()
+    assert st["total_mass"] == pytest.approx(o.total_mass(), rel=1e-12)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp16s", 2e-2)])
+def test_skew_couette_reduced_precision(fs, oracle_mod, precision, tol):
+    """The rotated Couette flow in the FP32 and FP16-storage forms (the FP16
+    form on its two-cells sweep: x periodic, even rows) against the FP64
+    oracle after 600 steps: velocity error relative to the wall speed."""
+    w = W.skew_couette()
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    o.step(600, 1)
+    s.step(600, 1)
+    _, uo = o.macro()
+    ug = s.fields(("u",))["u"]
+    fl = w.flags == W.LIQUID
+    err = np.abs(ug[:, fl] - uo[:, fl]).max() / w.meta["U"]
+    _say(precision, "skew couette u err / U", err)
+    assert err < tol
+
+
+def test_wall_table_errors(fs):
+    w = _ramp_tank()
+    s = fs.Sim(w.params, w.flags)
+    s.set_equilibrium(w.rho, w.velocity(), w.fill)
+    with pytest.raises(fs.FslbmError, match="fslbm_set_walls"):
+        s.step(1, 1)
+    c, d, u = w.walls["cells"], w.walls["delta"], w.walls["uw"]
+    with pytest.raises(fs.FslbmError, match="every non-solid cell"):
+        s.set_walls(c[1:], d[:, 1:], u[:, :, 1:])
+    with pytest.raises(fs.FslbmError, match="ascending"):
+        s.set_walls(c[::-1], d[:, ::-1], u[:, :, ::-1])
+    bad = d.copy()
+    bad[d != 0.5] = 0.0
+    with pytest.raises(fs.FslbmError, match="outside"):
+        s.set_walls(c, bad, u)
+    s.set_walls(c, d, u)
+    with pytest.raises(fs.FslbmError, match="UNSUPPORTED"):
+        s.window(3, 1)
+    s.step(2, 1)
+    s.close()
