@@ -109,11 +109,14 @@ typedef struct {
                                -div n from the fill field's gradient and Hessian by central
                                differences over the D3Q19 neighbourhood; not supported by the
                                adjoint window */
-  int32_t plic;             /* 0 or 1.  1: the FSL rules (FSL, FSL_STRESS, FSL_SHEAR) take the
+  int32_t plic;             /* 0, 1 or 2.  1: the FSL rules (FSL, FSL_STRESS, FSL_SHEAR) take the
                                link distance delta = d / (c_q . n) from the plane n.(x - x_node)
                                = d that cuts the cell's fill fraction phi (PLIC, the second-order
                                interface position asked for in section 5) instead of d = phi -
-                               1/2; not supported by the adjoint window */
+                               1/2.  2: the same with the normal from height functions (3 x 3
+                               columns of 7 cells along the dominant axis, exact for planes of
+                               slope <= 1) where every column is complete, else the central-
+                               difference normal.  Not supported by the adjoint window */
 } fslbm_params;
 
 typedef struct {

@@ -81,6 +81,8 @@ def lib():
         L.ref_boundary_shear.argtypes = [dp, dp, ctypes.c_double, dp]
         L.ref_curvature.restype = ctypes.c_double
         L.ref_curvature.argtypes = [dp]
+        L.ref_interface_normal.restype = ctypes.c_int
+        L.ref_interface_normal.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp]
         L.ref_set_walls.restype = ctypes.c_int
         L.ref_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp]
         L.ref_cut_volume.restype = ctypes.c_double
@@ -151,6 +153,12 @@ class Oracle:
         if walls is not None:
             o.set_walls(walls["cells"], walls.get("delta"), walls.get("uw"))
         return o
+
+    def interface_normal(self, cell: int, rule: int = FSL):
+        """Normal (towards the gas) the step uses at an interface cell, or None."""
+        out = np.zeros(3)
+        ok = lib().ref_interface_normal(self._h, int(cell), int(rule), _dptr(out))
+        return out if ok else None
 
     def set_walls(self, cells, delta=None, uw=None):
         """Wall table of the solid cells: ascending non-solid cells next to a

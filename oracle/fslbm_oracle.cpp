@@ -221,6 +221,13 @@ double ref_curvature(const double* v27) {
 
 // PLIC: volume of the unit cube below m.x = a (m_i >= 0), and the plane offset
 // d from the cell centre (n unit, liquid below) that cuts the fraction phi.
+// The interface normal the step would use at a cell for a rule (towards the
+// gas); returns 0 where there is none.
+int ref_interface_normal(void* hp, int cell, int rule, double* n3) {
+  auto* h = static_cast<Handle*>(hp);
+  return h->sim.interface_normal(cell, rule, n3) ? 1 : 0;
+}
+
 double ref_cut_volume(const double* m3, double a) { return fsref::Oracle<double>::cut_volume(m3, a); }
 double ref_plic_offset(double phi, const double* n3) { return fsref::Oracle<double>::plic_offset(phi, n3); }
 

@@ -71,7 +71,8 @@ struct Params {
   double wall_u[6][3]; // velocity of the wall faces x-, x+, y-, y+, z-, z+
   double shear_b[6];   // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules with bit 2)
   double sigma;        // surface tension coefficient (0: none)
-  int plic;            // FSL link distance from the PLIC plane (nonzero) or phi - 1/2
+  int plic;            // FSL link distance: 0 phi - 1/2; 1 the PLIC plane; 2 the PLIC
+                       // plane with the height-function normal where available
 };
 
 // ---------------------------------------------------------------------------
@@ -590,6 +591,101 @@ struct Oracle {
     return phi[s];
   }
 
+  // Interface normal n = -grad(phi)/|grad(phi)| (towards the gas) by central
+  // differences over the six axis neighbours (a wall or solid: the cell's own
+  // fill).  False (n = 0) where the gradient vanishes.
+  bool cd_normal(int x, int y, int z, const T& phix, T nvec[3]) const {
+    T grad[3];
+    for (int a = 0; a < 3; ++a) {
+      int d[3] = {0, 0, 0};
+      d[a] = 1;
+      int sp = neighbor(x, y, z, d[0], d[1], d[2]);
+      int sm = neighbor(x, y, z, -d[0], -d[1], -d[2]);
+      T vp = sp < 0 ? phix : phi_of(sp);
+      T vm = sm < 0 ? phix : phi_of(sm);
+      grad[a] = T(0.5) * (vp - vm);
+    }
+    T nrm2 = (grad[0] * grad[0] + grad[1] * grad[1]) + grad[2] * grad[2];
+    for (int a = 0; a < 3; ++a) nvec[a] = T(0.0);
+    if (!(nrm2 > T(0.0))) return false;
+    using std::sqrt;  // the dual-number sqrt is found by argument lookup
+    T nrm = sqrt(nrm2);
+    for (int a = 0; a < 3; ++a) nvec[a] = -grad[a] / nrm;
+    return true;
+  }
+
+  // cell at offset d (periodic wrap, any |d|); -1 beyond a wall face or solid
+  int stencil_cell(int x, int y, int z, const int d[3]) const {
+    int c[3] = {x + d[0], y + d[1], z + d[2]};
+    int n[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (c[a] < 0 || c[a] >= n[a]) {
+        if (!p.periodic[a]) return -1;
+        c[a] = ((c[a] % n[a]) + n[a]) % n[a];
+      }
+    }
+    int s = c[0] + p.nx * (c[1] + p.ny * c[2]);
+    return type[s] == SOLID ? -1 : s;
+  }
+
+  // Height-function normal.  Along the axis a where the given normal is
+  // largest, the fill of the 3 x 3 columns of 7 cells around the cell sums to
+  // the height of the liquid in each column; when every column is complete
+  // (fill 1 at its liquid end, fill 0 at its gas end, no wall or solid in it)
+  // the surface height H is known on the 3 x 3 columns, and with
+  // central differences H_1, H_2 across the columns the normal towards the gas
+  // is (s e_a - H_1 e_1 - H_2 e_2)/|.|, s the side of the gas along a.  Exact
+  // for a plane whose slope against a is at most 1.  Leaves nvec unchanged
+  // (and returns false) where a column is not complete.
+  bool hf_normal(int x, int y, int z, T nvec[3]) const {
+    int a = 0;
+    for (int b = 1; b < 3; ++b) {
+      T ab = nvec[b] < T(0.0) ? -nvec[b] : nvec[b];
+      T aa = nvec[a] < T(0.0) ? -nvec[a] : nvec[a];
+      if (ab > aa) a = b;
+    }
+    const int sg = nvec[a] > T(0.0) ? 1 : -1;
+    const int e1 = (a + 1) % 3, e2 = (a + 2) % 3;
+    T h[3][3];
+    for (int i = -1; i <= 1; ++i)
+      for (int j = -1; j <= 1; ++j) {
+        T sum = T(0.0);
+        for (int k = -3; k <= 3; ++k) {
+          int d[3];
+          d[a] = k;
+          d[e1] = i;
+          d[e2] = j;
+          int s = stencil_cell(x, y, z, d);
+          if (s < 0) return false;
+          T v = phi_of(s);
+          if (k == -3 * sg && !(v >= T(1.0))) return false;
+          if (k == 3 * sg && !(v <= T(0.0))) return false;
+          sum = sum + v;
+        }
+        h[i + 1][j + 1] = sum;
+      }
+    T h1 = T(0.5) * (h[2][1] - h[0][1]);
+    T h2 = T(0.5) * (h[1][2] - h[1][0]);
+    T v[3];
+    v[a] = T((double)sg);
+    v[e1] = -h1;
+    v[e2] = -h2;
+    T nrm2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+    using std::sqrt;
+    T nrm = sqrt(nrm2);
+    for (int b = 0; b < 3; ++b) nvec[b] = v[b] / nrm;
+    return true;
+  }
+
+  // The normal a step uses at an interface cell for a rule (for tests).
+  bool interface_normal(int cell, int rule, T nvec[3]) const {
+    int x, y, z;
+    coords(cell, x, y, z);
+    bool ok = cd_normal(x, y, z, phi[cell], nvec);
+    if (p.plic == 2 && ok && (rule & 1)) hf_normal(x, y, z, nvec);
+    return ok;
+  }
+
   // ------------------------------------------------------------ one step
   std::vector<T> ftn;  // second population buffer (pull scheme ping-pong)
 
@@ -697,24 +793,11 @@ struct Oracle {
         // ---- S2 interface geometry: normal from the fill-level gradient
         // (central differences over the six axis neighbours), surface plane
         // at signed distance phi - 1/2 from the node along the normal.
-        T grad[3];
-        for (int a = 0; a < 3; ++a) {
-          int d[3] = {0, 0, 0};
-          d[a] = 1;
-          int sp = neighbor(x, y, z, d[0], d[1], d[2]);
-          int sm = neighbor(x, y, z, -d[0], -d[1], -d[2]);
-          T vp = sp < 0 ? phix : phi_of(sp);
-          T vm = sm < 0 ? phix : phi_of(sm);
-          grad[a] = T(0.5) * (vp - vm);
-        }
-        T nrm2 = (grad[0] * grad[0] + grad[1] * grad[1]) + grad[2] * grad[2];
-        bool have_normal = nrm2 > T(0.0);
-        T nvec[3] = {T(0.0), T(0.0), T(0.0)};
-        if (have_normal) {
-          using std::sqrt;  // the dual-number sqrt is found by argument lookup
-          T nrm = sqrt(nrm2);
-          for (int a = 0; a < 3; ++a) nvec[a] = -grad[a] / nrm;
-        }
+        T nvec[3];
+        const bool have_normal = cd_normal(x, y, z, phix, nvec);
+        // second-order reconstruction (section 5): the FSL rules may take the
+        // normal from height functions where their columns are complete
+        if (p.plic == 2 && have_normal && (rule & 1)) hf_normal(x, y, z, nvec);
         T dist = phix - T(0.5);
         // second-order interface position (section 5): the plane that cuts the
         // cell's fill fraction with the normal n (PLIC) instead of phi - 1/2

@@ -119,7 +119,7 @@ fslbm_status check_params(const fslbm_params* p, std::string& why) {
   if (!(p->rho_gas > 0.0)) { why = "rho_gas must be positive"; return FSLBM_E_INVALID; }
   if (!(p->conv_eps >= 0.0)) { why = "conv_eps must be >= 0"; return FSLBM_E_INVALID; }
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be finite and >= 0"; return FSLBM_E_INVALID; }
-  if (p->plic != 0 && p->plic != 1) { why = "plic must be 0 or 1"; return FSLBM_E_INVALID; }
+  if (p->plic < 0 || p->plic > 2) { why = "plic must be 0, 1 or 2"; return FSLBM_E_INVALID; }
   for (int f = 0; f < 6; ++f)
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->wall_u[f][a])) { why = "wall_u must be finite"; return FSLBM_E_INVALID; }
@@ -179,7 +179,7 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
       if (!p.periodic[f / 2] && p.wall_u[f][a] != 0.0) com.moving = 1;
   for (int i = 0; i < 6; ++i) com.shear_b[i] = p.shear_b[i];
   com.sigma = p.sigma;
-  com.plic = p.plic ? 1 : 0;
+  com.plic = p.plic;
   com.rho_gas = p.rho_gas;
   com.scale = std::ldexp(1.0f, p.fp16_scale_log2);
   com.inv_scale = std::ldexp(1.0f, -p.fp16_scale_log2);

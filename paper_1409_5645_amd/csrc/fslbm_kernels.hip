@@ -127,7 +127,9 @@ __device__ __forceinline__ void boundary_shear(const IfaceData<F>& d, const Nbr&
 template <class F, int RULE, bool EXTRA>
 __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& cm, typename F::R& rho_s,
                                                 typename F::R (&u)[3], const Nbr& nb,
-                                                const typename F::S* __restrict__ fin, double drho) {
+                                                const typename F::S* __restrict__ fin, double drho,
+                                                const uint8_t* __restrict__ flags = nullptr,
+                                                const double* __restrict__ phi = nullptr) {
   using R = typename F::R;
   constexpr bool SH = F::shifted;
   const Consts<R>& k = pick_consts<R>(cm);
@@ -173,7 +175,9 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
     }
     double dist = d.phix - 0.5;
     if constexpr (EXTRA && (RULE & 1) != 0) {
-      // FSL link distances from the plane that cuts the cell's fill (PLIC)
+      // FSL link distances from the plane that cuts the cell's fill (PLIC),
+      // with the height-function normal where its columns are complete
+      if (cm.plic == 2 && have_n) hf_normal(cm.grid, nb.x, nb.y, nb.z, flags, phi, nv);
       if (cm.plic && have_n) dist = plic_plane_offset(d.phix, nv);
     }
     // ---- moments of time t from the own post-collision populations
@@ -312,7 +316,7 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
     // ---- phase 2: interface treatment and collision
     R rho_s, u[3];
     const double drho = (EXTRA && a.c.sigma != 0.0) ? a.kappa[i] : 0.0;
-    const double m_new = iface_compute<F, RULE, EXTRA>(d, a.c, rho_s, u, n, fin, drho);
+    const double m_new = iface_compute<F, RULE, EXTRA>(d, a.c, rho_s, u, n, fin, drho, a.flags, a.phi_in);
     // ---- phase 3: populations, fill level and classification (FP64 bookkeeping)
 #pragma unroll
     for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, d.f[q], a.c.scale);

@@ -167,6 +167,66 @@ __device__ __forceinline__ double plic_lower_volume(double al, double s1, double
   return (base - (r2 * r2 * r2 + r3 * r3 * r3) / s1) * w;
 }
 
+// Height-function normal of an interface cell (the second-order
+// reconstruction of section 5 for the FSL link distance).  Along the axis a
+// of the largest component of the central-difference normal nv (lowest axis
+// on ties), the fills of the 3 x 3 columns of 7 cells around the cell are
+// summed (liquid 1, gas 0, interface its fill; a wall face or a solid cell in
+// a column leaves nv as it is).  With every column complete (fill >= 1 at the
+// liquid end, <= 0 at the gas end) the sums are the surface heights, and nv
+// becomes (s e_a - H_1 e_1 - H_2 e_2)/|.| with central differences H_1, H_2
+// across the columns and s the side of the gas along a.  Exact for a plane
+// whose slope against a is at most 1.
+__device__ __noinline__ void hf_normal(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
+                                       const double* __restrict__ phi, double (&nv)[3]) {
+  int a = 0;
+  if (fabs(nv[1]) > fabs(nv[a])) a = 1;
+  if (fabs(nv[2]) > fabs(nv[a])) a = 2;
+  const int sg = nv[a] > 0.0 ? 1 : -1;
+  const int e1 = a == 2 ? 0 : a + 1, e2 = a == 0 ? 2 : (a == 1 ? 0 : 1);
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  const int p3[3] = {g.px, g.py, g.pz};
+  const int c0[3] = {x, y, z};
+  double h[3][3];
+  for (int i = -1; i <= 1; ++i)
+    for (int j = -1; j <= 1; ++j) {
+      double sum = 0.0;
+      for (int k = -3; k <= 3; ++k) {
+        int d[3];
+        d[a] = k;
+        d[e1] = i;
+        d[e2] = j;
+        int cc[3];
+        for (int b = 0; b < 3; ++b) {
+          int v = c0[b] + d[b];
+          if (v < 0 || v >= n3[b]) {
+            if (!p3[b]) return;
+            v = ((v % n3[b]) + n3[b]) % n3[b];
+          }
+          cc[b] = v;
+        }
+        const int s = cc[0] + g.nx * (cc[1] + g.ny * cc[2]);
+        const uint8_t t = flags[s];
+        if (t == SOLID) return;
+        const double v = t == LIQ ? 1.0 : (t == GAS ? 0.0 : phi[s]);
+        if (k == -3 * sg && !(v >= 1.0)) return;
+        if (k == 3 * sg && !(v <= 0.0)) return;
+        sum = sum + v;
+      }
+      h[i + 1][j + 1] = sum;
+    }
+  const double h1 = 0.5 * (h[2][1] - h[0][1]);
+  const double h2 = 0.5 * (h[1][2] - h[1][0]);
+  double v[3];
+  v[a] = (double)sg;
+  v[e1] = -h1;
+  v[e2] = -h2;
+  const double nrm = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+  nv[0] = v[0] / nrm;
+  nv[1] = v[1] / nrm;
+  nv[2] = v[2] / nrm;
+}
+
 __device__ __noinline__ double plic_plane_offset(double phi, const double (&nv)[3]) {
   const double a = fabs(nv[0]), b = fabs(nv[1]), c = fabs(nv[2]);
   const double sum = a + b + c;

@@ -370,6 +370,58 @@ def add_plane_obstacle(w: Workload, normal, offset: float, velocity=(0.0, 0.0, 0
                     meta=dict(w.meta), walls={"cells": cells, "delta": delta, "uw": uw})
 
 
+def _area_below_line(slope: float, c: float, i: int, k: int) -> float:
+    """Exact area of the unit square [i, i+1] x [k, k+1] below z = slope x + c
+    (the clipped height is piecewise linear in x: trapezoids between kinks)."""
+    def h(x):
+        return min(max(slope * x + c - k, 0.0), 1.0)
+    pts = [float(i), float(i + 1)]
+    if slope != 0.0:
+        pts += [xb for xb in ((k - c) / slope, (k + 1 - c) / slope) if i < xb < i + 1]
+    pts.sort()
+    return sum(0.5 * (h(a) + h(b)) * (b - a) for a, b in zip(pts[:-1], pts[1:]))
+
+
+def skew_film(H: float = 8.0, slope: float = 0.25, tau: float = 2.0, g0: float = 1e-4, H0: float = 4.0,
+              Lambda: float = 0.25, plic: int = 0, wall: float = 3.3) -> Workload:
+    """Gravity-driven film on a wall rotated by atan(slope) against the lattice
+    (the rotated planar film flow of section 4.3): a solid band below
+    zeta = z - slope x = wall, a liquid film of normal thickness H above it,
+    gas beyond; x, y, z periodic (nx = nz / slope, ny = 1); gravity
+    g0 (H0/H)^3 along the wall (constant Reynolds number).  Exact fills of the
+    plane surface; uniform density.  meta["profile"](n) is the steady
+    half-Poiseuille velocity along the wall at normal distance n."""
+    ca = 1.0 / np.hypot(1.0, slope)
+    hz = H / ca
+    nz = int(np.ceil(wall + hz + max(6.0, hz))) + 1
+    nx = int(round(nz / slope))
+    g = g0 * (H0 / H) ** 3
+    t = np.array([1.0, 0.0, slope]) * ca
+    p = Params(nx=nx, ny=1, nz=nz, periodic=(1, 1, 1), tau=tau, Lambda=Lambda, g=tuple(g * t), plic=plic)
+    types3, walls, zeta = skew_strips(nx, 1, nz, slope, ((wall, "solid", 0.0), (float(nz), "fluid", 0.0)), p)
+    solid = types3[:, 0, :] == SOLID
+    fill = np.zeros((nz, nx))
+    for k in range(nz):
+        for i in range(nx):
+            if solid[k, i] or zeta[k, i] < wall:
+                continue
+            base = (k + 0.5 - slope * (i + 0.5)) - zeta[k, i]      # the periodic image of the bands
+            fill[k, i] = _area_below_line(slope, wall + hz + base, i, k)
+    cls = np.where(fill >= 1.0, LIQUID, np.where(fill <= 0.0, GAS, INTERFACE)).astype(np.uint8)
+    cls[solid] = SOLID
+    t3 = cls[:, None, :].copy()
+    promote = (t3 == LIQUID) & _shift_any(t3 == GAS, p.periodic)
+    t3[promote] = INTERFACE
+    N = p.n_cells
+    nu = (tau - 0.5) / 3.0
+    zflat = np.broadcast_to(zeta[:, None, :], (nz, 1, nx)).reshape(-1)
+    return Workload(name="skew_film", params=p, flags=t3.reshape(-1), rho=np.full(N, p.rho_gas), u=None,
+                    fill=fill[:, None, :].reshape(-1), walls=walls,
+                    meta={"H": H, "slope": slope, "g": g, "nu": nu, "tangent": t,
+                          "normal_dist": (zflat - wall) * ca,
+                          "profile": lambda n, Hr=H: g / nu * (Hr * n - n * n / 2.0)})
+
+
 # Named configurations (sizes of the measured workloads).
 def config(name: str, seed: int = 0) -> Workload:
     if name == "channel":

@@ -46,7 +46,7 @@ def test_workspace_size_and_param_validation(libpath):
     assert L.fslbm_workspace_size(ctypes.byref(cp), ctypes.byref(ws)) == 0
     assert ws.value >= 76 * 10 * 12 * 14
     for field, bad in (("tau", 0.5), ("magic", 0.0), ("precision", 7), ("nx", 0), ("abi_version", 99),
-                       ("fp16_scale_log2", 40), ("rho_gas", -1.0), ("plic", 2), ("sigma", -1.0)):
+                       ("fp16_scale_log2", 40), ("rho_gas", -1.0), ("plic", 3), ("sigma", -1.0)):
         cp2 = fslbm.make_params(p)
         setattr(cp2, field, bad)
         assert L.fslbm_workspace_size(ctypes.byref(cp2), ctypes.byref(ws)) == 1, field

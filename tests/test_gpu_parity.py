@@ -342,16 +342,16 @@ def test_surface_tension_reduced_precision(fs, oracle_mod, precision, tol):
     assert d < tol
 
 
-@pytest.mark.parametrize("rule", [1, 3, 5, 0])
-def test_plic_interface_position_parity(fs, oracle_mod, rule):
+@pytest.mark.parametrize("rule,plic", [(1, 1), (3, 1), (5, 1), (0, 1), (1, 2), (3, 2)])
+def test_plic_interface_position_parity(fs, oracle_mod, rule, plic):
     """FSL link distances from the plane cutting each interface cell's fill
     (PLIC) on a converting tank with moving walls, then with surface tension
     on a droplet: classes and lists bit-exact, populations within 1e-12
     against the oracle (the plane offset comes from separate root finders, so
     the last bits may differ).  Rule 0 (FSK) has no link distance: unchanged."""
     w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
-    w = _with(w, plic=1, wall_u=_MOVING, shear_b=(1e-4, -2e-4, 5e-5, 3e-4, -1e-4, 2e-4))
-    _say(f"case plic tank rule {rule}")
+    w = _with(w, plic=plic, wall_u=_MOVING, shear_b=(1e-4, -2e-4, 5e-5, 3e-4, -1e-4, 2e-4))
+    _say(f"case plic {plic} tank rule {rule}")
     o = oracle_mod.Oracle.from_workload(w)
     s = fs.Sim.from_workload(w)
     for it in range(60):
@@ -359,8 +359,8 @@ def test_plic_interface_position_parity(fs, oracle_mod, rule):
         s.step(1, rule)
         if it % 10 == 9:
             _compare(o, s, f"plic tank step {it + 1}")
-    w = _with(W.droplet(n=20, radius=6.0, sigma=1e-3), plic=1)
-    _say(f"case plic droplet rule {rule}")
+    w = _with(W.droplet(n=20, radius=6.0, sigma=1e-3), plic=plic)
+    _say(f"case plic {plic} droplet rule {rule}")
     o = oracle_mod.Oracle.from_workload(w)
     s = fs.Sim.from_workload(w)
     for it in range(2):
@@ -464,3 +464,18 @@ def test_wall_table_errors(fs):
         s.window(3, 1)
     s.step(2, 1)
     s.close()
+
+
+@pytest.mark.parametrize("rule,plic", [(1, 2), (1, 1), (0, 0), (3, 2)])
+def test_rotated_film_parity(fs, oracle_mod, rule, plic):
+    """Film on a wall rotated by atan(1/4) (solid band, interpolated wall
+    closure, plane free surface where the height-function normal applies):
+    FP64 against the oracle over 200 steps."""
+    w = W.skew_film(H=6.0, plic=plic)
+    _say(f"case rotated film rule {rule} plic {plic}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(4):
+        o.step(50, rule)
+        s.step(50, rule)
+        _compare(o, s, f"rotated film step {50 * (it + 1)}")

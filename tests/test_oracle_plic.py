@@ -164,3 +164,80 @@ def test_plic_changes_fsl_on_curved_surfaces_and_conserves_mass(oracle_mod):
     assert abs((o.total_mass() + o.reservoir()) / M0 - 1.0) < 1e-13
     ref = _run(oracle_mod, _with(w, plic=0), 1, 20)
     assert np.abs(o.populations() - ref.populations()).max() > 1e-8
+
+
+def _plane_box(n_true, c, nx=9, ny=9, nz=13, plic=2):
+    """Walled box cut by the plane n.x = c (n towards the gas, x the position
+    in cell units from the box corner): exact fill fractions by quadrature,
+    classes from the fills (liquid next to gas promoted to interface)."""
+    p = W.Params(nx=nx, ny=ny, nz=nz, plic=plic)
+    N = p.n_cells
+    m = np.abs(n_true)
+    fill = np.zeros(N)
+    idx = np.arange(N)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    for cell in range(N):
+        # liquid where n.(corner + u) < c; reflect axes with n_a < 0 so that m >= 0
+        corner = np.array([x[cell], y[cell], z[cell]], dtype=float)
+        a = c - n_true @ corner - np.minimum(n_true, 0.0).sum()
+        fill[cell] = 0.0 if a <= 0 else (1.0 if a >= m.sum() else _quad_volume(m, a))
+    types3 = np.where(fill >= 1.0, W.LIQUID, np.where(fill <= 0.0, W.GAS, W.INTERFACE)).astype(np.uint8)
+    t3 = types3.reshape(nz, ny, nx)
+    prom = (t3 == W.LIQUID) & W._shift_any(t3 == W.GAS, p.periodic)
+    t3[prom] = W.INTERFACE
+    return W.Workload("plane", p, t3.reshape(-1), np.ones(N), None, fill), (x, y, z)
+
+
+def test_height_function_normal_exact_for_planes(oracle_mod):
+    """Inclined planes (slopes up to 0.9 against the dominant axis, any
+    orientation): wherever the height function applies (all 3 x 3 columns of
+    7 cells complete inside the box; elsewhere the normal stays the
+    central-difference one, bit for bit) it equals the plane's normal to
+    1e-12, and the PLIC offset from it puts the plane where it is; the
+    central-difference normal is off by degrees."""
+    rng = np.random.default_rng(21)
+    exact_total = 0
+    for trial in range(4):
+        axis = trial % 3
+        v = rng.uniform(-0.9, 0.9, size=3)
+        v[axis] = 1.0 if rng.random() < 0.5 else -1.0
+        n_true = v / np.linalg.norm(v)
+        centre = np.array([4.5, 4.5, 6.5])
+        centre[axis] = [4.5, 4.5, 6.5][axis] + rng.uniform(-0.5, 0.5)
+        c = n_true @ centre
+        w, (x, y, z) = _plane_box(n_true, c)
+        o = oracle_mod.Oracle.from_workload(w)
+        o1 = oracle_mod.Oracle.from_workload(dataclasses.replace(w, params=dataclasses.replace(w.params, plic=1)))
+        worst_cd = 0.0
+        for cell in np.nonzero(w.flags == W.INTERFACE)[0]:
+            if not (0.0 < w.fill[cell] < 1.0):
+                continue
+            nh = o.interface_normal(int(cell), 1)
+            ncd = o1.interface_normal(int(cell), 1)
+            if nh is None or np.array_equal(nh, ncd):
+                continue
+            pos = np.array([x[cell], y[cell], z[cell]])
+            assert np.abs(nh - n_true).max() < 1e-12, (trial, cell, nh, n_true)
+            d = oracle_mod.plic_offset(w.fill[cell], nh)
+            assert d == pytest.approx(c - n_true @ (pos + 0.5), abs=1e-11)
+            worst_cd = max(worst_cd, np.degrees(np.arccos(min(1.0, ncd @ n_true))))
+            exact_total += 1
+        assert worst_cd > 1.0
+    assert exact_total >= 60
+
+
+def test_height_function_falls_back_and_leaves_fsk(oracle_mod):
+    """FSK and plic = 1 keep the central-difference normal; a cell whose
+    columns leave the box keeps it too."""
+    n_true = np.array([0.3, -0.2, 1.0])
+    n_true /= np.linalg.norm(n_true)
+    w, (x, y, z) = _plane_box(n_true, n_true @ np.array([4.5, 4.5, 6.2]))
+    o2 = oracle_mod.Oracle.from_workload(w)
+    o1 = oracle_mod.Oracle.from_workload(dataclasses.replace(w, params=dataclasses.replace(w.params, plic=1)))
+    for cell in np.nonzero(w.flags == W.INTERFACE)[0][:40]:
+        a, b = o2.interface_normal(int(cell), 0), o1.interface_normal(int(cell), 1)
+        assert np.array_equal(a, b)
+    edge = [c for c in np.nonzero((w.flags == W.INTERFACE) & (x == 0))[0]]
+    assert edge
+    for cell in edge:
+        assert np.array_equal(o2.interface_normal(int(cell), 1), o1.interface_normal(int(cell), 1))
