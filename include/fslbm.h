@@ -6,14 +6,21 @@
  *   - D3Q19 two-relaxation-time stream/collide, Eq. (lbe1), (lbe2), with the
  *     equilibria Eq. (eqEven), (eqOdd) and the body force through
  *     u_eq = U - F/lambda_- (section 2.1);
- *   - halfway bounce-back at every non-periodic domain face (section 4.3);
+ *   - halfway bounce-back at every non-periodic domain face (section 4.3),
+ *     with the momentum of moving faces (section 4.1), and solid cells with
+ *     the linear-interpolation wall closure at any wall distance (section 4.2,
+ *     fslbm_set_walls);
  *   - reconstruction of every population that streams in from a gas cell by the
  *     general linear closure Eq. (closure) with the FSK row of Table 1 (the rule
  *     of Eq. (koerner)) or the FSL row (Eq. (fsli1)-(fsli4), alpha_+ = 1), with
- *     S^b = 0 (section 3.4);
+ *     S^b = 0 or with the boundary shear term D of Eq. (bterm) taken from the
+ *     bulk or prescribed (sections 3.3, 3.4; the rule argument of fslbm_step);
+ *     optionally the Laplace pressure P_b - sigma kappa (Eq. freeboundary) and
+ *     the PLIC interface position for the FSL link distance (section 5);
  *   - mass exchange, fill-level update and interface <-> liquid / gas cell
  *     conversion with excess-mass redistribution (the interface tracking of the
- *     free-surface LBM that section 2.3 describes and section 4.4 cites).
+ *     free-surface LBM that section 2.3 describes and section 4.4 cites);
+ *   - the adjoint of windows of such steps with frozen cell classes.
  *
  * Memory: every device buffer is allocated by the caller (e.g. as torch
  * tensors) and borrowed by the library until fslbm_destroy; the library never

@@ -58,6 +58,20 @@ def test_workspace_size_and_param_validation(libpath):
     assert b"NULL" in L.fslbm_last_error(None)
 
 
+def test_size_limit(libpath):
+    """Population offsets are 32-bit: 19 N must stay below 2^32 (N up to
+    226,050,910 cells); a larger lattice is rejected before any device work."""
+    from paper_1409_5645_amd import fslbm, workloads as W
+    L = fslbm.lib()
+    ws = ctypes.c_size_t()
+    ok = fslbm.make_params(W.Params(nx=1024, ny=1024, nz=215))     # 225,443,840 cells
+    assert L.fslbm_workspace_size(ctypes.byref(ok), ctypes.byref(ws)) == 0
+    assert ws.value > 0
+    big = fslbm.make_params(W.Params(nx=1024, ny=1024, nz=216))    # 226,492,416 cells
+    assert L.fslbm_workspace_size(ctypes.byref(big), ctypes.byref(ws)) == 1
+    assert b"2^32" in L.fslbm_last_error(None)
+
+
 def test_binding_fails_loudly_without_gpu(libpath):
     import torch
     if torch.cuda.is_available():

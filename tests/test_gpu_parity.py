@@ -479,3 +479,29 @@ def test_rotated_film_parity(fs, oracle_mod, rule, plic):
         o.step(50, rule)
         s.step(50, rule)
         _compare(o, s, f"rotated film step {50 * (it + 1)}")
+
+
+def test_all_gas_and_enclosed_liquid(fs, oracle_mod):
+    """Edge cases: a lattice of gas only (nothing to do, zero mass); a single
+    liquid cell enclosed in solid cells (every link a wall link, the wall-cell
+    kernel only) stays at rest, bit-exact against the oracle."""
+    p = W.Params(nx=7, ny=5, nz=3, periodic=(1, 1, 1))
+    N = p.n_cells
+    s = fs.Sim(p, np.zeros(N, dtype=np.uint8))
+    s.set_equilibrium(np.ones(N), np.zeros((3, N)), np.zeros(N))
+    s.step(3, 1)
+    st = s.stats()
+    assert st["total_mass"] == 0.0 and s.conversions()["F"].size == 0
+    s.close()
+    flags = np.full(N, W.SOLID, dtype=np.uint8)
+    c = 3 + 7 * (2 + 5 * 1)
+    flags[c] = W.LIQUID
+    w = W.Workload("enclosed", p, flags, np.full(N, 1.001), None, (flags == W.LIQUID).astype(float),
+                   walls={"cells": np.array([c], dtype=np.int32), "delta": np.full((19, 1), 0.3),
+                          "uw": np.zeros((3, 19, 1))})
+    o = oracle_mod.Oracle.from_workload(w)
+    g = fs.Sim.from_workload(w)
+    o.step(5, 1)
+    g.step(5, 1)
+    _compare(o, g, "enclosed cell")
+    assert g.stats()["total_mass"] == pytest.approx(1.001, rel=1e-14)
