@@ -213,6 +213,28 @@ def adjoint_leg(log, T=400, config="slosh128"):
             "fp32_grad_err_vs_fp64": err, "forms": out}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def device_facts(torch) -> dict:
+    """Name, compute units, memory and clocks of device 0 as the runtime reports them."""
+    pr = torch.cuda.get_device_properties(0)
+    facts = {"name": pr.name, "compute_units": pr.multi_processor_count,
+             "memory_gib": round(pr.total_memory / 2 ** 30, 1)}
+    for key in ("gcnArchName", "clock_rate", "memory_clock_rate", "l2_cache_size"):
+        v = getattr(pr, key, None)
+        if v is not None:
+            facts[key] = v
+    return facts
+
+
 def cpu_baseline(w_full, log, budget_s=12.0, rule=1):
     """The serial FP64 oracle on a z-slab of the same tank (same x-y profile,
     walls on all faces), timed on one host core."""
@@ -235,6 +257,7 @@ def cpu_baseline(w_full, log, budget_s=12.0, rule=1):
     mlups = n_act * n / dt / 1e6
     log(f"[cpu oracle] {n} steps of {p.nx}x{p.ny}x{nz}: {mlups:.2f} MLUPS")
     return {"value": mlups, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "cpu": f"{cpu_model()}, {os.cpu_count()} logical cores present, 1 used",
             "sample": f"{n} {RULE_NAME[rule]} steps (after 1 untimed) of a {p.nx}x{p.ny}x{nz} z-slab of the same tank "
                       f"({n_act} active cells), serial FP64 oracle, 1 thread"}
 
@@ -309,6 +332,7 @@ def main():
                    "cells": w.params.n_cells, "active_cells": r["active_cells"], "form": head},
         "roofline": roof,
         "forms": results,
+        "device": device_facts(torch),
     }
     if not args.no_adjoint:
         line["adjoint"] = adjoint_leg(log)
