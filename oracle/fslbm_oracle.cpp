@@ -268,6 +268,14 @@ int ref_window_dual(const ref_params* rp, const uint8_t* flags, const double* ft
   try {
     auto s = std::make_unique<Oracle<Dual>>();
     s->set_params(to_params(rp));
+    // the derivative is exact for the rules without a D term and without the
+    // options whose arithmetic it does not follow (the PLIC root finder) or
+    // that need a wall table (solid cells)
+    if (rule != fsref::FSK && rule != fsref::FSL) throw std::runtime_error("dual window: rules 0 and 1 only");
+    if (s->p.plic) throw std::runtime_error("dual window: no PLIC interface position");
+    if (s->p.sigma != 0.0) throw std::runtime_error("dual window: no surface tension");
+    for (size_t i = 0; i < (size_t)s->N; ++i)
+      if (flags[i] == fsref::SOLID) throw std::runtime_error("dual window: no solid cells");
     const int N = s->N;
     // seed the parameter directions: rho_b, g and the constants derived from g
     s->rho_b.d = drho_b;

@@ -154,3 +154,22 @@ def test_linear_term_alone(oracle_mod, case):
                                                     T, 1, df0=d, f_weight=fw)[1]
     lin, full, inter = run(None, None, a), run(ut, pt, a), run(ut, pt, None)
     assert abs(lin - (full - inter)) <= 1e-9 * (abs(full) + abs(inter))
+
+
+def test_dual_window_refuses_what_it_does_not_differentiate(oracle_mod, case):
+    """The exact derivative covers rules 0 and 1 without PLIC, surface tension
+    or solid cells (as the GPU window does); anything else is refused."""
+    import dataclasses
+    p, st, ut, pt, rng = case
+    args = (st["flags"], st["f"], st["mass"], st["phi"], ut, pt, 2)
+    for rule in (2, 3, 4, 5):
+        with pytest.raises(ValueError, match="rules 0 and 1"):
+            oracle_mod.window_dual(p, *args, rule)
+    with pytest.raises(ValueError, match="PLIC"):
+        oracle_mod.window_dual(dataclasses.replace(p, plic=1), *args, 1)
+    with pytest.raises(ValueError, match="surface tension"):
+        oracle_mod.window_dual(dataclasses.replace(p, sigma=1e-3), *args, 1)
+    fl = st["flags"].copy()
+    fl[0] = W.SOLID
+    with pytest.raises(ValueError, match="solid"):
+        oracle_mod.window_dual(p, fl, *args[1:], 1)
