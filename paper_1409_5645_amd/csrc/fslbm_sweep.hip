@@ -34,7 +34,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   const int row = (int)blockIdx.x / a.cpr;
   const int chunk = (int)blockIdx.x - row * a.cpr;
   const int y = row % g.ny, z = row / g.ny;
-  const int x = chunk * BLOCK + (int)threadIdx.x;
+  const int x = chunk * (int)blockDim.x + (int)threadIdx.x;
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
   const int lane = (int)threadIdx.x & 63;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   const int row = (int)blockIdx.x / a.cpr;
   const int chunk = (int)blockIdx.x - row * a.cpr;
   const int y = row % g.ny, z = row / g.ny;
-  const int x0 = (chunk * BLOCK + (int)threadIdx.x) * 2;
+  const int x0 = (chunk * (int)blockDim.x + (int)threadIdx.x) * 2;
   const bool valid = x0 < g.nx;
   const int xl = valid ? x0 : 0;  // in-bounds pair for lanes past the row end
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
                             row_of(yp, z),  rbase,         row_of(ym, z),
                             row_of(yp, zm), row_of(y, zm), row_of(ym, zm)};
   // first column of the wavefront (uniform over it; readfirstlane says so) and after it
-  const int wx0 = __builtin_amdgcn_readfirstlane((chunk * BLOCK + ((int)threadIdx.x & ~63)) * 2);
+  const int wx0 = __builtin_amdgcn_readfirstlane((chunk * (int)blockDim.x + ((int)threadIdx.x & ~63)) * 2);
   const int wend = wx0 + 128;
   const bool row_end = xl + 2 == g.nx;  // last pair of the row (its right neighbour is past the row)
   const unsigned N2 = 2u * (unsigned)g.N;  // bytes per population plane
@@ -272,26 +272,30 @@ static void sweep_form(const StepLaunch& L) {
   hipStream_t st = (hipStream_t)L.stream;
   SweepArgs a = L.sweep;
   const Grid& g = a.c.grid;
-  a.cpr = (g.nx + BLOCK - 1) / BLOCK;
+  // whole wavefronts, no more than a row needs (short rows would idle lanes)
+  const int threads = std::min(BLOCK, 64 * ((g.nx + 63) / 64));
+  a.cpr = (g.nx + threads - 1) / threads;
   const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
   if (a.u_out && a.c.incomp && !a.c.stokes)
-    k_sweep<F, 1, true><<<nb, BLOCK, 0, st>>>(a);
+    k_sweep<F, 1, true><<<nb, threads, 0, st>>>(a);
   else if (a.c.incomp && !a.c.stokes)
-    k_sweep<F, 1><<<nb, BLOCK, 0, st>>>(a);
+    k_sweep<F, 1><<<nb, threads, 0, st>>>(a);
   else
-    k_sweep<F, 0><<<nb, BLOCK, 0, st>>>(a);
+    k_sweep<F, 0><<<nb, threads, 0, st>>>(a);
 }
 
 static void sweep_h2(const StepLaunch& L) {
   hipStream_t st = (hipStream_t)L.stream;
   SweepArgs a = L.sweep;
   const Grid& g = a.c.grid;
-  a.cpr = (g.nx + 2 * BLOCK - 1) / (2 * BLOCK);
+  // whole wavefronts of cell pairs, no more than a row needs
+  const int threads = std::min(BLOCK, 64 * ((g.nx + 127) / 128));
+  a.cpr = (g.nx + 2 * threads - 1) / (2 * threads);
   const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
   if (a.c.incomp && !a.c.stokes)
-    k_sweep_h2<1><<<nb, BLOCK, 0, st>>>(a);
+    k_sweep_h2<1><<<nb, threads, 0, st>>>(a);
   else
-    k_sweep_h2<0><<<nb, BLOCK, 0, st>>>(a);
+    k_sweep_h2<0><<<nb, threads, 0, st>>>(a);
 }
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule) {
