@@ -260,8 +260,10 @@ typedef struct fslbm_window fslbm_window;
  * default) for the current cell classes of c.  Synchronises. */
 fslbm_status fslbm_window_workspace_size(fslbm_ctx* c, int32_t T, int32_t K, size_t* bytes);
 
-/* Forward pass: T steps with rule FSK or FSL (the _STRESS rules are
- * FSLBM_E_UNSUPPORTED here) from the current state of c,
+/* Forward pass: T steps with rule FSK or FSL (the rules with a D term, surface
+ * tension, the PLIC option and solid cells are FSLBM_E_UNSUPPORTED here; the
+ * FP16 storage form, the compressible equilibrium and the Stokes equilibrium
+ * too) from the current state of c,
  * conversions disabled, storing checkpoints in the workspace (device memory,
  * 256-byte aligned, at least fslbm_window_workspace_size bytes).  On return the
  * state of c is that of time T (read it with fslbm_fields) and *out is the
