@@ -505,3 +505,39 @@ def test_all_gas_and_enclosed_liquid(fs, oracle_mod):
     g.step(5, 1)
     _compare(o, g, "enclosed cell")
     assert g.stats()["total_mass"] == pytest.approx(1.001, rel=1e-14)
+
+
+@pytest.mark.parametrize("rule,model", [(1, "compressible"), (0, "compressible"), (3, "compressible"),
+                                        (1, "stokes"), (1, "compressible+stokes")])
+def test_equilibrium_variants_parity(fs, oracle_mod, rule, model):
+    """The general equilibrium paths (rho_0 = rho, and the Stokes form without
+    the quadratic term), which the sweep takes in its runtime-model variant, on
+    a converting tank: classes and lists bit-exact, populations within 1e-12."""
+    w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
+    kw = {"incompressible": 0 if "compressible" in model else 1, "stokes": 1 if "stokes" in model else 0}
+    w = _with(w, **kw)
+    _say(f"case equilibrium {model} rule {rule}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(60):
+        o.step(1, rule)
+        s.step(1, rule)
+        if it % 10 == 9:
+            _compare(o, s, f"{model} step {it + 1}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp16s", 5e-2)])
+def test_compressible_reduced_precision(fs, oracle_mod, precision, tol):
+    """rho_0 = rho in the shifted FP32 and scaled FP16 forms (the collision
+    rebuilds rho_0 from the stored deviation) against the FP64 oracle."""
+    w = _with(W.sloshing(40, 24, 12, depth=11.0, amp=3.0, seed=4, gy=-4e-4, tau=0.6), incompressible=0)
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    o.step(100, 1)
+    s.step(100, 1)
+    _, uo = o.macro()
+    g = s.fields(("u", "flags"))
+    act = (o.flags() == W.LIQUID) & (g["flags"] == W.LIQUID)
+    err = np.abs(g["u"][:, act] - uo[:, act]).max() / np.abs(uo[:, act]).max()
+    _say(precision, "compressible sloshing u rel err", err, "flag mismatches", int((g["flags"] != o.flags()).sum()))
+    assert err < tol
