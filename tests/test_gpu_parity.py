@@ -541,3 +541,21 @@ def test_compressible_reduced_precision(fs, oracle_mod, precision, tol):
     err = np.abs(g["u"][:, act] - uo[:, act]).max() / np.abs(uo[:, act]).max()
     _say(precision, "compressible sloshing u rel err", err, "flag mismatches", int((g["flags"] != o.flags()).sum()))
     assert err < tol
+
+
+def test_wall_table_defaults_parity(fs, oracle_mod):
+    """A wall table given by its cells only (every wall halfway, walls at rest)
+    on the converting ramp tank: bit-exact against the oracle with the same
+    defaults, and mass conserved to rounding (halfway walls conserve mass)."""
+    w = _ramp_tank()
+    w = W.Workload(w.name, w.params, w.flags, w.rho, w.u, w.fill, meta=w.meta, walls={"cells": w.walls["cells"]})
+    _say("case ramp tank, default wall table")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    M0 = s.stats()["total_mass"]
+    for it in range(40):
+        o.step(1, 1)
+        s.step(1, 1)
+        if it % 10 == 9:
+            _compare(o, s, f"default walls step {it + 1}")
+    assert abs(s.stats()["total_mass"] / M0 - 1.0) < 1e-13  # includes the reservoir
