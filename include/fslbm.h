@@ -123,7 +123,10 @@ typedef struct {
                                1/2.  2: the same with the normal from height functions (3 x 3
                                columns of 7 cells along the dominant axis, exact for planes of
                                slope <= 1) where every column is complete, else the central-
-                               difference normal.  Not supported by the adjoint window */
+                               difference normal; with sigma != 0 the Laplace pressure then also
+                               takes the height-function curvature of the same columns (any
+                               rule), else the central-difference one.  Not supported by the
+                               adjoint window */
 } fslbm_params;
 
 typedef struct {

@@ -81,6 +81,8 @@ def lib():
         L.ref_boundary_shear.argtypes = [dp, dp, ctypes.c_double, dp]
         L.ref_curvature.restype = ctypes.c_double
         L.ref_curvature.argtypes = [dp]
+        L.ref_interface_curvature.restype = ctypes.c_double
+        L.ref_interface_curvature.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.ref_interface_normal.restype = ctypes.c_int
         L.ref_interface_normal.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp]
         L.ref_set_walls.restype = ctypes.c_int
@@ -153,6 +155,10 @@ class Oracle:
         if walls is not None:
             o.set_walls(walls["cells"], walls.get("delta"), walls.get("uw"))
         return o
+
+    def interface_curvature(self, cell: int) -> float:
+        """Curvature kappa = -div n the step uses at an interface cell."""
+        return float(lib().ref_interface_curvature(self._h, int(cell)))
 
     def interface_normal(self, cell: int, rule: int = FSL):
         """Normal (towards the gas) the step uses at an interface cell, or None."""

@@ -228,6 +228,10 @@ int ref_interface_normal(void* hp, int cell, int rule, double* n3) {
   return h->sim.interface_normal(cell, rule, n3) ? 1 : 0;
 }
 
+double ref_interface_curvature(void* hp, int cell) {
+  return static_cast<Handle*>(hp)->sim.interface_curvature(cell);
+}
+
 double ref_cut_volume(const double* m3, double a) { return fsref::Oracle<double>::cut_volume(m3, a); }
 double ref_plic_offset(double phi, const double* n3) { return fsref::Oracle<double>::plic_offset(phi, n3); }
 

@@ -72,7 +72,8 @@ struct Params {
   double shear_b[6];   // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules with bit 2)
   double sigma;        // surface tension coefficient (0: none)
   int plic;            // FSL link distance: 0 phi - 1/2; 1 the PLIC plane; 2 the PLIC
-                       // plane with the height-function normal where available
+                       // plane with the height-function normal, and the height-function
+                       // curvature, where their columns are complete
 };
 
 // ---------------------------------------------------------------------------
@@ -628,25 +629,20 @@ struct Oracle {
     return type[s] == SOLID ? -1 : s;
   }
 
-  // Height-function normal.  Along the axis a where the given normal is
-  // largest, the fill of the 3 x 3 columns of 7 cells around the cell sums to
-  // the height of the liquid in each column; when every column is complete
-  // (fill 1 at its liquid end, fill 0 at its gas end, no wall or solid in it)
-  // the surface height H is known on the 3 x 3 columns, and with
-  // central differences H_1, H_2 across the columns the normal towards the gas
-  // is (s e_a - H_1 e_1 - H_2 e_2)/|.|, s the side of the gas along a.  Exact
-  // for a plane whose slope against a is at most 1.  Leaves nvec unchanged
-  // (and returns false) where a column is not complete.
-  bool hf_normal(int x, int y, int z, T nvec[3]) const {
-    int a = 0;
+  // Column heights of the height function: along the axis a where nvec is
+  // largest (lowest axis on ties), h[i+1][j+1] = the fill summed over the 7
+  // cells of the column at offsets i, j across a; sg is the side of the gas
+  // along a.  False where a column is not complete (fill 1 at its liquid end,
+  // 0 at its gas end, no wall or solid in it).
+  bool hf_heights(int x, int y, int z, const T nvec[3], T h[3][3], int& a, int& sg) const {
+    a = 0;
     for (int b = 1; b < 3; ++b) {
       T ab = nvec[b] < T(0.0) ? -nvec[b] : nvec[b];
       T aa = nvec[a] < T(0.0) ? -nvec[a] : nvec[a];
       if (ab > aa) a = b;
     }
-    const int sg = nvec[a] > T(0.0) ? 1 : -1;
+    sg = nvec[a] > T(0.0) ? 1 : -1;
     const int e1 = (a + 1) % 3, e2 = (a + 2) % 3;
-    T h[3][3];
     for (int i = -1; i <= 1; ++i)
       for (int j = -1; j <= 1; ++j) {
         T sum = T(0.0);
@@ -664,6 +660,19 @@ struct Oracle {
         }
         h[i + 1][j + 1] = sum;
       }
+    return true;
+  }
+
+  // Height-function normal: with the surface height H known on the 3 x 3
+  // columns and central differences H_1, H_2 across them, the normal towards
+  // the gas is (s e_a - H_1 e_1 - H_2 e_2)/|.|.  Exact for a plane whose slope
+  // against a is at most 1.  Leaves nvec unchanged (and returns false) where a
+  // column is not complete.
+  bool hf_normal(int x, int y, int z, T nvec[3]) const {
+    T h[3][3];
+    int a, sg;
+    if (!hf_heights(x, y, z, nvec, h, a, sg)) return false;
+    const int e1 = (a + 1) % 3, e2 = (a + 2) % 3;
     T h1 = T(0.5) * (h[2][1] - h[0][1]);
     T h2 = T(0.5) * (h[1][2] - h[1][0]);
     T v[3];
@@ -675,6 +684,55 @@ struct Oracle {
     T nrm = sqrt(nrm2);
     for (int b = 0; b < 3; ++b) nvec[b] = v[b] / nrm;
     return true;
+  }
+
+  // Height-function curvature (the second-order reconstruction applied to
+  // kappa of Eq. freeboundary): with the axis from the central-difference
+  // normal and the 3 x 3 column heights, kappa = -div n = [H_11 (1 + H_2^2) +
+  // H_22 (1 + H_1^2) - 2 H_12 H_1 H_2] / (1 + H_1^2 + H_2^2)^(3/2), central
+  // differences throughout (a sphere of radius R has kappa = -2/R).  False
+  // where there is no normal or a column is not complete.
+  bool hf_curvature(int x, int y, int z, const T& phix, T& kappa) const {
+    T n[3], h[3][3];
+    int a, sg;
+    if (!cd_normal(x, y, z, phix, n)) return false;
+    if (!hf_heights(x, y, z, n, h, a, sg)) return false;
+    T h1 = T(0.5) * (h[2][1] - h[0][1]);
+    T h2 = T(0.5) * (h[1][2] - h[1][0]);
+    T h11 = (h[2][1] - T(2.0) * h[1][1]) + h[0][1];
+    T h22 = (h[1][2] - T(2.0) * h[1][1]) + h[1][0];
+    T h12 = T(0.25) * (((h[2][2] - h[2][0]) - h[0][2]) + h[0][0]);
+    T q = (T(1.0) + h1 * h1) + h2 * h2;
+    using std::sqrt;
+    T num = (h11 * (T(1.0) + h2 * h2) + h22 * (T(1.0) + h1 * h1)) - T(2.0) * ((h12 * h1) * h2);
+    kappa = num / (q * sqrt(q));
+    return true;
+  }
+
+  // The curvature a step uses at an interface cell (for tests): the
+  // central-difference kappa of the 3 x 3 x 3 fill block, or the
+  // height-function kappa with plic = 2 where its columns are complete; 0
+  // without a normal.
+  T interface_curvature(int cell) const {
+    int x, y, z;
+    coords(cell, x, y, z);
+    T n[3];
+    const T phix = phi[cell];
+    if (!cd_normal(x, y, z, phix, n)) return T(0.0);
+    T v[3][3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int cc = 0; cc < 3; ++cc) {
+          v[a][b][cc] = T(0.0);
+          int nz_ = (a != 1) + (b != 1) + (cc != 1);
+          if (nz_ == 0) { v[a][b][cc] = phix; continue; }
+          if (nz_ == 3) continue;
+          int sN = neighbor(x, y, z, a - 1, b - 1, cc - 1);
+          v[a][b][cc] = sN < 0 ? phix : phi_of(sN);
+        }
+    T kap = curvature(v);
+    if (p.plic == 2) hf_curvature(x, y, z, phix, kap);
+    return kap;
   }
 
   // The normal a step uses at an interface cell for a rule (for tests).
@@ -818,7 +876,9 @@ struct Oracle {
                 int sN = neighbor(x, y, z, a - 1, b - 1, cc - 1);
                 v[a][b][cc] = sN < 0 ? phix : phi_of(sN);
               }
-          rho_bc = rho_b - T(3.0 * p.sigma) * curvature(v);
+          T kap = curvature(v);
+          if (p.plic == 2) hf_curvature(x, y, z, phix, kap);
+          rho_bc = rho_b - T(3.0 * p.sigma) * kap;
         }
 
         // ---- S3 reconstruction of every population streaming in from gas.

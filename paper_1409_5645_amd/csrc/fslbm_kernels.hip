@@ -346,7 +346,8 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
 
 // Laplace-pressure correction of each listed interface cell (surface tension):
 // kappa[i] = 3 sigma kappa, with kappa = -div n from the fill seen over the
-// D3Q19 neighbourhood (Eq. freeboundary; see curvature).  Runs between the
+// D3Q19 neighbourhood (Eq. freeboundary; see curvature), or with plic = 2 from
+// the height function where its columns are complete.  Runs between the
 // sweep (which builds the list) and k_iface, only when sigma != 0.
 __global__ __launch_bounds__(IBLOCK) void k_curvature(SweepArgs a) {
   const Grid g = a.c.grid;
@@ -378,7 +379,21 @@ __global__ __launch_bounds__(IBLOCK) void k_curvature(SweepArgs a) {
       for (int q = 1; q < Q; ++q)
         if (d.ty[q] == WALL_CLASS) d.ph[q] = d.phix;
     }
-    a.kappa[i] = 3.0 * a.c.sigma * curvature(d);
+    double kap = curvature(d);
+    if (a.c.plic == 2) {
+      // height-function curvature where the columns along the axis of the
+      // central-difference normal are complete
+      const double gx = 0.5 * (phi_seen(d, 2) - phi_seen(d, 1));
+      const double gy = 0.5 * (phi_seen(d, 4) - phi_seen(d, 3));
+      const double gz = 0.5 * (phi_seen(d, 6) - phi_seen(d, 5));
+      const double nrm2 = (gx * gx + gy * gy) + gz * gz;
+      if (nrm2 > 0.0) {
+        const double nrm = sqrt(nrm2);
+        const double nv[3] = {-gx / nrm, -gy / nrm, -gz / nrm};
+        hf_curvature(g, n.x, n.y, n.z, a.flags, a.phi_in, nv, kap);
+      }
+    }
+    a.kappa[i] = 3.0 * a.c.sigma * kap;
   }
 }
 

@@ -167,27 +167,24 @@ __device__ __forceinline__ double plic_lower_volume(double al, double s1, double
   return (base - (r2 * r2 * r2 + r3 * r3 * r3) / s1) * w;
 }
 
-// Height-function normal of an interface cell (the second-order
-// reconstruction of section 5 for the FSL link distance).  Along the axis a
-// of the largest component of the central-difference normal nv (lowest axis
-// on ties), the fills of the 3 x 3 columns of 7 cells around the cell are
-// summed (liquid 1, gas 0, interface its fill; a wall face or a solid cell in
-// a column leaves nv as it is).  With every column complete (fill >= 1 at the
-// liquid end, <= 0 at the gas end) the sums are the surface heights, and nv
-// becomes (s e_a - H_1 e_1 - H_2 e_2)/|.| with central differences H_1, H_2
-// across the columns and s the side of the gas along a.  Exact for a plane
-// whose slope against a is at most 1.
-__device__ __noinline__ void hf_normal(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
-                                       const double* __restrict__ phi, double (&nv)[3]) {
-  int a = 0;
+// Height-function columns of an interface cell (the second-order
+// reconstruction of section 5).  Along the axis a of the largest component of
+// the central-difference normal nv (lowest axis on ties), the fills of the
+// 3 x 3 columns of 7 cells around the cell are summed (liquid 1, gas 0,
+// interface its fill).  With every column complete (fill >= 1 at the liquid
+// end, <= 0 at the gas end, no wall face or solid cell in it) the sums h are
+// the surface heights; sg is the side of the gas along a.  False otherwise.
+__device__ __forceinline__ bool hf_heights(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
+                                           const double* __restrict__ phi, const double (&nv)[3],
+                                           double (&h)[3][3], int& a, int& sg) {
+  a = 0;
   if (fabs(nv[1]) > fabs(nv[a])) a = 1;
   if (fabs(nv[2]) > fabs(nv[a])) a = 2;
-  const int sg = nv[a] > 0.0 ? 1 : -1;
+  sg = nv[a] > 0.0 ? 1 : -1;
   const int e1 = a == 2 ? 0 : a + 1, e2 = a == 0 ? 2 : (a == 1 ? 0 : 1);
   const int n3[3] = {g.nx, g.ny, g.nz};
   const int p3[3] = {g.px, g.py, g.pz};
   const int c0[3] = {x, y, z};
-  double h[3][3];
   for (int i = -1; i <= 1; ++i)
     for (int j = -1; j <= 1; ++j) {
       double sum = 0.0;
@@ -200,21 +197,34 @@ __device__ __noinline__ void hf_normal(const Grid& g, int x, int y, int z, const
         for (int b = 0; b < 3; ++b) {
           int v = c0[b] + d[b];
           if (v < 0 || v >= n3[b]) {
-            if (!p3[b]) return;
+            if (!p3[b]) return false;
             v = ((v % n3[b]) + n3[b]) % n3[b];
           }
           cc[b] = v;
         }
         const int s = cc[0] + g.nx * (cc[1] + g.ny * cc[2]);
         const uint8_t t = flags[s];
-        if (t == SOLID) return;
+        if (t == SOLID) return false;
         const double v = t == LIQ ? 1.0 : (t == GAS ? 0.0 : phi[s]);
-        if (k == -3 * sg && !(v >= 1.0)) return;
-        if (k == 3 * sg && !(v <= 0.0)) return;
+        if (k == -3 * sg && !(v >= 1.0)) return false;
+        if (k == 3 * sg && !(v <= 0.0)) return false;
         sum = sum + v;
       }
       h[i + 1][j + 1] = sum;
     }
+  return true;
+}
+
+// Height-function normal: with central differences H_1, H_2 of the column
+// heights across the axis a, nv becomes (s e_a - H_1 e_1 - H_2 e_2)/|.|, s the
+// side of the gas.  Exact for a plane whose slope against a is at most 1.
+// Leaves nv as it is where a column is not complete.
+__device__ __noinline__ void hf_normal(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
+                                       const double* __restrict__ phi, double (&nv)[3]) {
+  double h[3][3];
+  int a, sg;
+  if (!hf_heights(g, x, y, z, flags, phi, nv, h, a, sg)) return;
+  const int e1 = a == 2 ? 0 : a + 1, e2 = a == 0 ? 2 : (a == 1 ? 0 : 1);
   const double h1 = 0.5 * (h[2][1] - h[0][1]);
   const double h2 = 0.5 * (h[1][2] - h[1][0]);
   double v[3];
@@ -225,6 +235,26 @@ __device__ __noinline__ void hf_normal(const Grid& g, int x, int y, int z, const
   nv[0] = v[0] / nrm;
   nv[1] = v[1] / nrm;
   nv[2] = v[2] / nrm;
+}
+
+// Height-function curvature for the Laplace pressure of Eq. (freeboundary):
+// kappa = -div n = [H_11 (1 + H_2^2) + H_22 (1 + H_1^2) - 2 H_12 H_1 H_2] /
+// (1 + H_1^2 + H_2^2)^(3/2) with central differences of the column heights (a
+// sphere of radius R: -2/R).  Leaves kappa as it is where a column is not
+// complete.
+__device__ __noinline__ void hf_curvature(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
+                                          const double* __restrict__ phi, const double (&nv)[3], double& kappa) {
+  double h[3][3];
+  int a, sg;
+  if (!hf_heights(g, x, y, z, flags, phi, nv, h, a, sg)) return;
+  const double h1 = 0.5 * (h[2][1] - h[0][1]);
+  const double h2 = 0.5 * (h[1][2] - h[1][0]);
+  const double h11 = (h[2][1] - 2.0 * h[1][1]) + h[0][1];
+  const double h22 = (h[1][2] - 2.0 * h[1][1]) + h[1][0];
+  const double h12 = 0.25 * (((h[2][2] - h[2][0]) - h[0][2]) + h[0][0]);
+  const double q = (1.0 + h1 * h1) + h2 * h2;
+  const double num = (h11 * (1.0 + h2 * h2) + h22 * (1.0 + h1 * h1)) - 2.0 * ((h12 * h1) * h2);
+  kappa = num / (q * sqrt(q));
 }
 
 __device__ __noinline__ double plic_plane_offset(double phi, const double (&nv)[3]) {

@@ -325,6 +325,34 @@ def test_surface_tension_parity(fs, oracle_mod, rule):
             _compare(o, s, f"tank step {it + 1}")
 
 
+@pytest.mark.parametrize("rule", [1, 0, 3])
+def test_height_function_curvature_parity(fs, oracle_mod, rule):
+    """Surface tension with plic = 2 (height-function curvature where the
+    columns are complete, central differences elsewhere) on a droplet, a
+    tank with moving walls and a tank over a solid ramp (columns that meet
+    the ramp fall back): bit-exact against the oracle, and different from the
+    central-difference curvature."""
+    cases = []
+    w = W.droplet(n=20, radius=6.0, sigma=1e-3)
+    cases.append(("droplet", _with(w, plic=2), 3, 40))
+    w = W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6)
+    cases.append(("tank", _with(w, sigma=2e-3, wall_u=_MOVING, plic=2), 4, 10))
+    w = W.add_plane_obstacle(W.sloshing(37, 24, 10, depth=11.0, amp=3.0, seed=11, gy=-4e-4, tau=0.6),
+                             (-0.3, 1.0, 0.12), 3.1)
+    cases.append(("ramp tank", _with(w, sigma=2e-3, plic=2), 4, 10))
+    for name, w, reps, k in cases:
+        _say(f"case {name} sigma plic 2 rule {rule}")
+        o = oracle_mod.Oracle.from_workload(w)
+        s = fs.Sim.from_workload(w)
+        for it in range(reps):
+            o.step(k, rule)
+            s.step(k, rule)
+            _compare(o, s, f"{name} step {k * (it + 1)}")
+        cd = oracle_mod.Oracle.from_workload(_with(w, plic=0 if rule == 0 else 1))
+        cd.step(reps * k, rule)
+        assert np.abs(cd.populations() - o.populations()).max() > 1e-9
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("fp16s", 5e-2)])
 def test_surface_tension_reduced_precision(fs, oracle_mod, precision, tol):
     """Laplace pressure of a droplet in the FP32 and FP16-storage forms against

@@ -71,3 +71,91 @@ def test_droplet_laplace_pressure(oracle_mod):
     assert abs(dp6b / dp6 / 2.0 - 1.0) < 0.05
     dp0, _ = _laplace(oracle_mod, 6.0, 20, 0.0, steps=200)
     assert abs(dp0) < 1e-12
+
+
+def _hf_split(oracle_mod, w):
+    """kappa at the interface cells with 0 < fill < 1 with the height
+    function on (plic = 2) and off: (cells, kappa_hf, kappa_cd, where the
+    height function applied)."""
+    import dataclasses
+    o2 = oracle_mod.Oracle.from_workload(dataclasses.replace(w, params=dataclasses.replace(w.params, plic=2)))
+    o0 = oracle_mod.Oracle.from_workload(dataclasses.replace(w, params=dataclasses.replace(w.params, plic=0)))
+    cells = np.nonzero((w.flags == W.INTERFACE) & (w.fill > 0.0) & (w.fill < 1.0))[0]
+    k2 = np.array([o2.interface_curvature(int(c)) for c in cells])
+    k0 = np.array([o0.interface_curvature(int(c)) for c in cells])
+    return cells, k2, k0, k2 != k0
+
+
+def test_height_function_curvature_of_planes_is_zero(oracle_mod):
+    """Inclined planes with exact cut fills: wherever the 3 x 3 columns of
+    7 cells are complete the column heights are linear in the column offset,
+    so the height-function kappa vanishes to rounding; the central-difference
+    kappa of the same fills does not (the fill is not a linear field across
+    the interface)."""
+    from test_oracle_plic import _plane_box
+    rng = np.random.default_rng(5)
+    applied = 0
+    for trial in range(3):
+        v = rng.uniform(-0.8, 0.8, size=3)
+        v[trial] = 1.0
+        n_true = v / np.linalg.norm(v)
+        w, _ = _plane_box(n_true, n_true @ np.array([4.5, 4.5, 6.4]), plic=2)
+        _, k2, k0, hf = _hf_split(oracle_mod, w)
+        assert np.abs(k2[hf]).max() < 1e-12
+        assert np.abs(k0).max() > 0.05
+        applied += hf.sum()
+    assert applied >= 40
+
+
+@pytest.mark.parametrize("R", [6.0, 10.0])
+def test_height_function_curvature_of_drops_and_bubbles(oracle_mod, R):
+    """A drop (liquid inside) and a bubble (liquid outside) of radius R off
+    the lattice nodes, fills from 16^3 samples per cell: where the height
+    function applies (most cells) kappa is -2/R (+2/R for the bubble) to a
+    few percent, while the central-difference kappa of the same one-cell-wide
+    fill layer is off by more than half at the median; elsewhere the
+    central-difference kappa stays, bit for bit."""
+    import dataclasses
+    n = int(2 * R + 10)
+    drop = W.droplet(n=n, radius=R, sub=16)
+    bubble = dataclasses.replace(drop, fill=1.0 - drop.fill, flags=np.where(
+        drop.flags == W.INTERFACE, W.INTERFACE, np.where(drop.flags == W.LIQUID, W.GAS, W.LIQUID)).astype(np.uint8))
+    for w, exact in ((drop, -2.0 / R), (bubble, 2.0 / R)):
+        _, k2, k0, hf = _hf_split(oracle_mod, w)
+        assert hf.mean() > 0.5
+        err = np.abs(k2[hf] / exact - 1.0)
+        assert np.median(err) < 0.02
+        assert np.percentile(err, 90) < 0.05
+        assert err.max() < 0.3
+        assert np.median(np.abs(k0 / exact - 1.0)) > 0.5
+        assert np.array_equal(k2[~hf], k0[~hf])
+
+
+def test_height_function_curvature_of_a_cylinder(oracle_mod):
+    """A liquid cylinder of radius 8 along y: where the height function
+    applies kappa = -1/R to a few percent (one principal curvature: the
+    truncation error of the central differences weighs twice as much as on a
+    sphere of the same radius)."""
+    import dataclasses
+    R, n = 8.0, 26
+    drop = W.droplet(n=n, radius=R, sub=16)
+    p = drop.params
+    idx = np.arange(p.n_cells)
+    x, z = idx % n, idx // (n * n)
+    fill = np.zeros(p.n_cells)
+    k = (np.arange(16) + 0.5) / 16
+    cx, cz = n / 2 + 0.1, n / 2 + 0.37
+    for a in k:
+        for b in k:
+            fill += ((x + a - cx) ** 2 + (z + b - cz) ** 2 <= R * R)
+    fill /= 256.0
+    t = np.where(fill >= 1.0, W.LIQUID, np.where(fill <= 0.0, W.GAS, W.INTERFACE)).astype(np.uint8).reshape(n, n, n)
+    prom = (t == W.LIQUID) & W._shift_any(t == W.GAS, p.periodic)
+    t[prom] = W.INTERFACE
+    w = dataclasses.replace(drop, flags=t.reshape(-1), fill=fill)
+    _, k2, k0, hf = _hf_split(oracle_mod, w)
+    assert hf.mean() > 0.5
+    err = np.abs(k2[hf] * R + 1.0)
+    assert np.median(err) < 0.05
+    assert np.percentile(err, 90) < 0.1
+    assert np.median(np.abs(k0 * R + 1.0)) > 0.5
