@@ -125,8 +125,10 @@ typedef struct {
                                slope <= 1) where every column is complete, else the central-
                                difference normal; with sigma != 0 the Laplace pressure then also
                                takes the height-function curvature of the same columns (any
-                               rule), else the central-difference one.  Not supported by the
-                               adjoint window */
+                               rule), where they are not complete the mean of those of the
+                               D3Q19 interface neighbours that have one, else the central-
+                               difference one (the workspace then holds 8 N more bytes).  Not
+                               supported by the adjoint window */
 } fslbm_params;
 
 typedef struct {

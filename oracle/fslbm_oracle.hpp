@@ -72,8 +72,8 @@ struct Params {
   double shear_b[6];   // prescribed S^b [xx, yy, zz, xy, xz, yz] (rules with bit 2)
   double sigma;        // surface tension coefficient (0: none)
   int plic;            // FSL link distance: 0 phi - 1/2; 1 the PLIC plane; 2 the PLIC
-                       // plane with the height-function normal, and the height-function
-                       // curvature, where their columns are complete
+                       // plane with the height-function normal where its columns are
+                       // complete, and the height-function curvature (own or borrowed)
 };
 
 // ---------------------------------------------------------------------------
@@ -709,10 +709,48 @@ struct Oracle {
     return true;
   }
 
+  // Height-function kappa of an interface cell with a normal (false where
+  // it has none or a column is not complete).
+  bool hf_kappa_at(int cell, T& kappa) const {
+    if (type[cell] != INTERFACE) return false;
+    int x, y, z;
+    coords(cell, x, y, z);
+    return hf_curvature(x, y, z, phi[cell], kappa);
+  }
+
+  // The curvature with plic = 2: the cell's own height-function kappa; where
+  // its columns are not complete, the mean of the height-function kappa of
+  // its D3Q19 interface neighbours that have one (summed in link order);
+  // without such a neighbour kcd, the central-difference kappa.  A cell
+  // next to complete columns lies on the same stretch of surface, and the
+  // central-difference kappa of the raw fills is biased by the fill itself
+  // (of the wrong sign at small fills), so borrowing keeps the mean of kappa
+  // over the surface.  hf(c, k): hf_kappa_at of cell c (computed or looked up).
+  template <class HF>
+  T hf_or_borrowed(int x, int y, int z, int cell, const T& kcd, const HF& hf) const {
+    T k;
+    if (hf(cell, k)) return k;
+    T sum = T(0.0);
+    int cnt = 0;
+    for (int q = 1; q < Q; ++q) {
+      int s = neighbor(x, y, z, CV[q][0], CV[q][1], CV[q][2]);
+      if (s < 0 || !hf(s, k)) continue;
+      sum = sum + k;
+      ++cnt;
+    }
+    return cnt ? sum / T((double)cnt) : kcd;
+  }
+
+  void hf_kappa_field(std::vector<uint8_t>& have, std::vector<T>& khf) const {
+    have.assign(N, 0);
+    khf.assign(N, T(0.0));
+    for (int c = 0; c < N; ++c) have[c] = hf_kappa_at(c, khf[c]) ? 1 : 0;
+  }
+
   // The curvature a step uses at an interface cell (for tests): the
-  // central-difference kappa of the 3 x 3 x 3 fill block, or the
-  // height-function kappa with plic = 2 where its columns are complete; 0
-  // without a normal.
+  // central-difference kappa of the D3Q19 fill block, or with plic = 2 the
+  // height-function kappa, own or borrowed (hf_or_borrowed); 0 without a
+  // normal.
   T interface_curvature(int cell) const {
     int x, y, z;
     coords(cell, x, y, z);
@@ -731,7 +769,7 @@ struct Oracle {
           v[a][b][cc] = sN < 0 ? phix : phi_of(sN);
         }
     T kap = curvature(v);
-    if (p.plic == 2) hf_curvature(x, y, z, phix, kap);
+    if (p.plic == 2) kap = hf_or_borrowed(x, y, z, cell, kap, [this](int c, T& k) { return hf_kappa_at(c, k); });
     return kap;
   }
 
@@ -752,6 +790,10 @@ struct Oracle {
     ftn.resize((size_t)Q * N);
     std::vector<T> massn = mass;
     std::vector<T> phin = phi;
+    // height-function kappa of every interface cell at time t (plic = 2)
+    std::vector<uint8_t> hf_have;
+    std::vector<T> hf_k;
+    if (p.sigma != 0.0 && p.plic == 2) hf_kappa_field(hf_have, hf_k);
 
     for (int cell = 0; cell < N; ++cell) {
       if (type[cell] == GAS || type[cell] == SOLID) continue;
@@ -877,7 +919,12 @@ struct Oracle {
                 v[a][b][cc] = sN < 0 ? phix : phi_of(sN);
               }
           T kap = curvature(v);
-          if (p.plic == 2) hf_curvature(x, y, z, phix, kap);
+          if (p.plic == 2)
+            kap = hf_or_borrowed(x, y, z, cell, kap, [&](int c, T& k) {
+              if (!hf_have[c]) return false;
+              k = hf_k[c];
+              return true;
+            });
           rho_bc = rho_b - T(3.0 * p.sigma) * kap;
         }
 

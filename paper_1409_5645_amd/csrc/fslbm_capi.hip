@@ -32,6 +32,7 @@ struct fslbm_ctx {
   int32_t* counters;    // 2 sets of NCOUNT
   double* reservoir;
   double* kappa = nullptr;  // surface tension only
+  double* khf = nullptr;    // surface tension with plic = 2 only
   double* wall_t = nullptr; // moving-wall terms [6][19]
   bool has_solid = false;   // the flags hold solid cells
   const int32_t* wcells = nullptr;  // wall table (caller's device memory, fslbm_set_walls)
@@ -57,7 +58,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, wall_t, kappa, total;
+  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, wall_t, kappa, khf, total;
 };
 
 // Moving-wall bounce-back terms per face (x-, x+, y-, y+, z-, z+) and link:
@@ -77,8 +78,9 @@ void wall_table(const fslbm_params& p, double out[6 * Q]) {
     }
 }
 
-// kappa: with surface tension, one Laplace-pressure correction per listed cell
-Layout layout(size_t N, bool kappa) {
+// kappa: with surface tension, one Laplace-pressure correction per listed cell;
+// hf: with surface tension and plic = 2, the height-function kappa per cell
+Layout layout(size_t N, bool kappa, bool hf) {
   Layout L{};
   size_t o = 0;
   L.aux_rho = o;
@@ -101,6 +103,8 @@ Layout layout(size_t N, bool kappa) {
   o = align_up(o + 8 * 6 * Q);
   L.kappa = o;
   if (kappa) o = align_up(o + 8 * N);
+  L.khf = o;
+  if (kappa && hf) o = align_up(o + 8 * N);
   L.total = o;
   return L;
 }
@@ -209,7 +213,7 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes) {
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!bytes) { g_init_error = "bytes is NULL"; return FSLBM_E_INVALID; }
-  *bytes = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0).total;
+  *bytes = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2).total;
   return FSLBM_OK;
 }
 
@@ -223,7 +227,7 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
     return FSLBM_E_INVALID;
   }
   const size_t N = (size_t)p->nx * p->ny * p->nz;
-  const Layout L = layout(N, p->sigma != 0.0);
+  const Layout L = layout(N, p->sigma != 0.0, p->plic == 2);
   if (b->workspace_bytes < L.total) { g_init_error = "workspace too small"; return FSLBM_E_INVALID; }
   if (((uintptr_t)b->workspace) % ALIGN) { g_init_error = "workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
 
@@ -249,6 +253,7 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   c->counters = (int32_t*)(w + L.counters);
   c->reservoir = (double*)(w + L.scalars);
   if (p->sigma != 0.0) c->kappa = (double*)(w + L.kappa);
+  if (p->sigma != 0.0 && p->plic == 2) c->khf = (double*)(w + L.khf);
   c->wall_t = (double*)(w + L.wall_t);
   {
     double tab[6 * Q];
@@ -354,6 +359,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.pairs = c->pairs;
     s.u_out = nullptr;
     s.kappa = c->kappa;
+    s.khf = c->khf;
     s.wall_t = c->wall_t;
     s.wcells = c->wcells;
     s.wdelta = c->wdelta;

@@ -72,6 +72,7 @@ struct SweepArgs {
   double* rec_rho;
   int rec_cap;
   double* kappa;  // surface tension: 3 sigma kappa per listed interface cell (list order)
+  double* khf;    // surface tension with plic = 2: height-function kappa per cell (NaN: none)
   const double* wall_t;  // moving walls: [6 faces][19 links] bounce-back terms 2 w_q (c_q.u_w)/c_s^2
   // solid walls: ascending list of the non-solid cells next to a solid cell,
   // per listed cell i and link p the wall distance delta[p*nwall + i] and
@@ -174,7 +175,7 @@ struct AdjArgs {
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
 hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
-hipError_t launch_curvature(const StepLaunch& L);
+hipError_t launch_curvature(const StepLaunch& L);  // one or (plic = 2) two list kernels
 hipError_t launch_convert(const StepLaunch& L, int precision);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, void* stream);
 hipError_t launch_fill_f64(double* p, size_t n, double v, void* stream);

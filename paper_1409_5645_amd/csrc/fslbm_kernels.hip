@@ -379,10 +379,13 @@ __global__ __launch_bounds__(IBLOCK) void k_curvature(SweepArgs a) {
       for (int q = 1; q < Q; ++q)
         if (d.ty[q] == WALL_CLASS) d.ph[q] = d.phix;
     }
-    double kap = curvature(d);
+    const double kap = curvature(d);
     if (a.c.plic == 2) {
-      // height-function curvature where the columns along the axis of the
-      // central-difference normal are complete
+      // height-function kappa where the columns along the axis of the
+      // central-difference normal are complete (NaN otherwise) for
+      // k_curvature_hf, which also takes the final value; kappa[i] keeps the
+      // central-difference kappa for cells with no height-function kappa near
+      double khf = __builtin_nan("");
       const double gx = 0.5 * (phi_seen(d, 2) - phi_seen(d, 1));
       const double gy = 0.5 * (phi_seen(d, 4) - phi_seen(d, 3));
       const double gz = 0.5 * (phi_seen(d, 6) - phi_seen(d, 5));
@@ -390,8 +393,45 @@ __global__ __launch_bounds__(IBLOCK) void k_curvature(SweepArgs a) {
       if (nrm2 > 0.0) {
         const double nrm = sqrt(nrm2);
         const double nv[3] = {-gx / nrm, -gy / nrm, -gz / nrm};
-        hf_curvature(g, n.x, n.y, n.z, a.flags, a.phi_in, nv, kap);
+        hf_curvature(g, n.x, n.y, n.z, a.flags, a.phi_in, nv, khf);
       }
+      a.khf[idx] = khf;
+      a.kappa[i] = kap;
+    } else {
+      a.kappa[i] = 3.0 * a.c.sigma * kap;
+    }
+  }
+}
+
+// Height-function curvature with plic = 2, after k_curvature: a listed cell
+// takes its own height-function kappa; where its columns are not complete,
+// the mean of those of its D3Q19 interface neighbours that have one (summed
+// in link order: the neighbours lie on the same stretch of surface, while the
+// central-difference kappa of the raw fills is biased by the fill itself);
+// with no such neighbour the central-difference kappa.  kappa[i] = 3 sigma
+// kappa.  Every interface cell is listed, so khf holds this step's value at
+// every interface neighbour.
+__global__ __launch_bounds__(IBLOCK) void k_curvature_hf(SweepArgs a) {
+  const Grid g = a.c.grid;
+  const int n_i = a.counters[C_I];
+  for (int i = blockIdx.x * IBLOCK + threadIdx.x; i < n_i; i += gridDim.x * IBLOCK) {
+    const int idx = a.listI[i];
+    double kap = a.khf[idx];
+    if (isnan(kap)) {
+      int x, y, z;
+      coords(g, idx, x, y, z);
+      double sum = 0.0;
+      int cnt = 0;
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
+        if (s < 0 || a.flags[s] != IFACE) continue;
+        const double v = a.khf[s];
+        if (isnan(v)) continue;
+        sum = sum + v;
+        ++cnt;
+      }
+      kap = cnt ? sum / (double)cnt : a.kappa[i];
     }
     a.kappa[i] = 3.0 * a.c.sigma * kap;
   }
@@ -908,6 +948,7 @@ hipError_t launch_check_walls(const uint8_t* flags, const Grid& g, const int32_t
 hipError_t launch_curvature(const StepLaunch& L) {
   const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
   k_curvature<<<nb, IBLOCK, 0, (hipStream_t)L.stream>>>(L.sweep);
+  if (L.sweep.c.plic == 2) k_curvature_hf<<<nb, IBLOCK, 0, (hipStream_t)L.stream>>>(L.sweep);
   return hipGetLastError();
 }
 
