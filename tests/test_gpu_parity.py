@@ -353,11 +353,13 @@ def test_height_function_curvature_parity(fs, oracle_mod, rule):
         assert np.abs(cd.populations() - o.populations()).max() > 1e-9
 
 
+@pytest.mark.parametrize("plic", [0, 2])
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("fp16s", 5e-2)])
-def test_surface_tension_reduced_precision(fs, oracle_mod, precision, tol):
+def test_surface_tension_reduced_precision(fs, oracle_mod, precision, tol, plic):
     """Laplace pressure of a droplet in the FP32 and FP16-storage forms against
-    the FP64 oracle (pressure jump relative to 2 sigma / R after 300 steps)."""
-    w = W.droplet(n=20, radius=6.0, sigma=1e-3)
+    the FP64 oracle (pressure jump relative to 2 sigma / R after 300 steps),
+    with the central-difference and the height-function curvature."""
+    w = _with(W.droplet(n=20, radius=6.0, sigma=1e-3), plic=plic)
     o = oracle_mod.Oracle.from_workload(w)
     s = fs.Sim.from_workload(w, precision=precision)
     o.step(300, 1)
