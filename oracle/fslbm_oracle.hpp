@@ -718,7 +718,9 @@ struct Oracle {
     return hf_curvature(x, y, z, phi[cell], kappa);
   }
 
-  // The curvature with plic = 2: the cell's own height-function kappa; where
+  // The curvature of the Laplace pressure (Eq. freeboundary) with plic = 2,
+  // the second-order reconstruction asked for in section 5 applied to kappa:
+  // the cell's own height-function kappa; where
   // its columns are not complete, the mean of the height-function kappa of
   // its D3Q19 interface neighbours that have one (summed in link order);
   // without such a neighbour kcd, the central-difference kappa.  A cell
