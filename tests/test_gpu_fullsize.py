@@ -161,11 +161,12 @@ def test_slosh512_reduced_precision_subbox_step(fs, oracle_mod, precision):
     benchmark times: after 20 GPU steps, one more GPU step against one FP64
     oracle step from the same (decoded) state on a sub-box around the
     surface.  Every population is within the rounding of its form: the FP32
-    form computes and stores the shifted population g = f - w in FP32
-    (|error| <= 1e-6); the FP16 form stores 2^12 g in binary16, so the result
-    is within half an ulp, 2^-11 |g|, plus the FP32 arithmetic.  Classes agree
-    and interface masses (FP64 bookkeeping of FP32 exchanges) are within
-    1e-5."""
+    form computes and stores the shifted population g = f - w in FP32, whose
+    terms are of the size of g and of the density deviation (a few 1e-4 to
+    1e-3 here), so |error| <= 2e-9; the FP16 form stores 2^12 g in binary16,
+    so the result is within half an ulp, at most 2^-11 |g| (subnormals
+    included), plus the same FP32 arithmetic.  Classes agree and interface
+    masses (FP64 bookkeeping of FP32 exchanges) are within 1e-5."""
     w = W.config("slosh512", seed=0)
     p = w.params
     nx, ny, nz = p.nx, p.ny, p.nz
@@ -201,7 +202,7 @@ def test_slosh512_reduced_precision_subbox_step(fs, oracle_mod, precision):
     act = flo[inner] != W.GAS
     a, b = gf[(slice(None),) + inner][:, act], fo[(slice(None),) + inner][:, act]
     gq = np.abs(b - WQ[:, None])
-    tol = (2.0 ** -11 * gq + 1e-6) if precision == "fp16s" else np.full(gq.shape, 1e-6)
+    tol = (2.0 ** -11 * gq + 2e-9) if precision == "fp16s" else np.full(gq.shape, 2e-9)
     ratio = np.abs(a - b) / tol
     _say(precision, "sub-box max |err|", np.abs(a - b).max(), "max err / bound", ratio.max(), "max |g|", gq.max(),
          "active compared", int(act.sum()))
