@@ -488,38 +488,42 @@ __device__ void init_new_from_liquid(const ConvArgs& a, int c) {
   a.aux_rho[c] = r;
 }
 
+// One thread per (converted cell, link): a cell's 18 neighbours are handled by
+// 18 threads, so the work of a step is not the longest serial chain of one
+// cell's new neighbours.  Which thread wins a new cell's epoch mark does not
+// change the result (its initialisation reads only pre-conversion classes).
 template <class F>
 __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
   const int nF = a.counters[C_F], nE = a.counters[C_E];
   const Grid& g = a.c.grid;
-  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < nF + nE; i += gridDim.x * BLOCK) {
-    const int c = i < nF ? a.listF[i] : a.listE[i - nF];
+  // 18 N < 19 N < 2^32 (the lattice limit): the pair index fits in 32 unsigned bits
+  const unsigned total = (unsigned)(nF + nE) * (unsigned)(Q - 1);
+  for (unsigned i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += gridDim.x * BLOCK) {
+    const int e = (int)(i / (unsigned)(Q - 1));
+    const int q = 1 + (int)(i - (unsigned)e * (unsigned)(Q - 1));
+    const int c = e < nF ? a.listF[e] : a.listE[e - nF];
     int x, y, z;
     coords(g, c, x, y, z);
-    if (i < nF) {
-      for (int q = 1; q < Q; ++q) {
-        const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-        if (s < 0 || a.flags[s] != GAS) continue;
-        if (atomicExch(&a.new_epoch[s], a.step) != a.step) {
-          a.listNI[atomicAdd(&a.counters[C_NI], 1)] = s;
-          init_new_from_gas<F>(a, s);
-        }
+    const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
+    if (e < nF) {
+      if (s < 0 || a.flags[s] != GAS) continue;
+      if (atomicExch(&a.new_epoch[s], a.step) != a.step) {
+        a.listNI[atomicAdd(&a.counters[C_NI], 1)] = s;
+        init_new_from_gas<F>(a, s);
       }
     } else {
+      // E' = E minus N(F): every thread of the cell takes the same decision
       bool protect = false;
-      for (int q = 1; q < Q; ++q) {
-        const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-        if (s >= 0 && a.f_epoch[s] == a.step) protect = true;
+      for (int p = 1; p < Q; ++p) {
+        const int t = neighbor(g, x, y, z, CX[p], CY[p], CZ[p]);
+        if (t >= 0 && a.f_epoch[t] == a.step) protect = true;
       }
       if (protect) continue;
-      a.listEP[atomicAdd(&a.counters[C_EP], 1)] = c;
-      for (int q = 1; q < Q; ++q) {
-        const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-        if (s < 0 || a.flags[s] != LIQ) continue;
-        if (atomicExch(&a.new_epoch[s], a.step) != a.step) {
-          a.listNL[atomicAdd(&a.counters[C_NL], 1)] = s;
-          init_new_from_liquid<F>(a, s);
-        }
+      if (q == 1) a.listEP[atomicAdd(&a.counters[C_EP], 1)] = c;
+      if (s < 0 || a.flags[s] != LIQ) continue;
+      if (atomicExch(&a.new_epoch[s], a.step) != a.step) {
+        a.listNL[atomicAdd(&a.counters[C_NL], 1)] = s;
+        init_new_from_liquid<F>(a, s);
       }
     }
   }
@@ -543,29 +547,37 @@ __global__ __launch_bounds__(BLOCK) void k_commit(ConvArgs a) {
   }
 }
 
+// One thread per (converted cell, link), as in k_mark: every thread of a cell
+// counts its eligible neighbours; the link-1 thread divides the excess (or
+// hands it to the reservoir) and marks the cell, each thread lists its own
+// receiver.
 __global__ __launch_bounds__(BLOCK) void k_share(ConvArgs a) {
   const int nF = a.counters[C_F], nEP = a.counters[C_EP];
   const Grid& g = a.c.grid;
-  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < nF + nEP; i += gridDim.x * BLOCK) {
-    const int c = i < nF ? a.listF[i] : a.listEP[i - nF];
+  // 18 N < 19 N < 2^32 (the lattice limit): the pair index fits in 32 unsigned bits
+  const unsigned total = (unsigned)(nF + nEP) * (unsigned)(Q - 1);
+  for (unsigned i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += gridDim.x * BLOCK) {
+    const int e = (int)(i / (unsigned)(Q - 1));
+    const int q = 1 + (int)(i - (unsigned)e * (unsigned)(Q - 1));
+    const int c = e < nF ? a.listF[e] : a.listEP[e - nF];
     int x, y, z;
     coords(g, c, x, y, z);
     int n_elig = 0;
-    for (int q = 1; q < Q; ++q) {
-      const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-      if (s >= 0 && a.flags[s] == IFACE) ++n_elig;
+    for (int p = 1; p < Q; ++p) {
+      const int t = neighbor(g, x, y, z, CX[p], CY[p], CZ[p]);
+      if (t >= 0 && a.flags[t] == IFACE) ++n_elig;
     }
     if (n_elig == 0) {
-      atomicAdd(a.reservoir, a.mass[c]);
+      if (q == 1) atomicAdd(a.reservoir, a.mass[c]);
       continue;
     }
-    a.mass[c] = a.mass[c] / (double)n_elig;
-    a.conv_epoch[c] = a.step;
-    for (int q = 1; q < Q; ++q) {
-      const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-      if (s < 0 || a.flags[s] != IFACE) continue;
-      if (atomicExch(&a.recv_epoch[s], a.step) != a.step) a.listR[atomicAdd(&a.counters[C_R], 1)] = s;
+    if (q == 1) {
+      a.mass[c] = a.mass[c] / (double)n_elig;
+      a.conv_epoch[c] = a.step;
     }
+    const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
+    if (s < 0 || a.flags[s] != IFACE) continue;
+    if (atomicExch(&a.recv_epoch[s], a.step) != a.step) a.listR[atomicAdd(&a.counters[C_R], 1)] = s;
   }
 }
 
