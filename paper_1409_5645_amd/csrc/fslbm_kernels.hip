@@ -514,6 +514,7 @@ __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
     } else {
       // E' = E minus N(F): every thread of the cell takes the same decision
       bool protect = false;
+#pragma unroll
       for (int p = 1; p < Q; ++p) {
         const int t = neighbor(g, x, y, z, CX[p], CY[p], CZ[p]);
         if (t >= 0 && a.f_epoch[t] == a.step) protect = true;
@@ -563,6 +564,7 @@ __global__ __launch_bounds__(BLOCK) void k_share(ConvArgs a) {
     int x, y, z;
     coords(g, c, x, y, z);
     int n_elig = 0;
+#pragma unroll
     for (int p = 1; p < Q; ++p) {
       const int t = neighbor(g, x, y, z, CX[p], CY[p], CZ[p]);
       if (t >= 0 && a.flags[t] == IFACE) ++n_elig;
@@ -589,6 +591,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(ConvArgs a) {
     int x, y, z;
     coords(g, r, x, y, z);
     double m = a.mass[r];
+#pragma unroll
     for (int q = 1; q < Q; ++q) {
       const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
       if (s >= 0 && a.conv_epoch[s] == a.step) m = m + a.mass[s];
