@@ -265,7 +265,7 @@ def cpu_baseline(w_full, log, budget_s=12.0, rule=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=5000)  # the run length of the tank configurations
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="fp64,fp32,fp16s")
     ap.add_argument("--config", default="slosh512")
@@ -331,6 +331,7 @@ def main():
                                f"tau {w.params.tau}, g_y {w.params.g[1]:g}",
                    "cells": w.params.n_cells, "active_cells": r["active_cells"], "form": head},
         "roofline": roof,
+        "err_after_steps": args.warmup + args.steps,  # errors vs FP64 compare the final states
         "forms": results,
         "device": device_facts(torch),
     }
