@@ -335,11 +335,10 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? 4 : 1) void k_
     a.aux_u[N + idx] = (double)u[1];
     a.aux_u[2 * N + idx] = (double)u[2];
     if (!a.freeze) {
-      if (m_new > a.thr_hi * rho) {
-        a.f_epoch[idx] = a.step;
-        a.listF[atomicAdd(&a.counters[C_F], 1)] = idx;
-      }
-      if (m_new < a.thr_lo * rho) a.listE[atomicAdd(&a.counters[C_E], 1)] = idx;
+      const bool filled = m_new > a.thr_hi * rho;
+      if (filled) a.f_epoch[idx] = a.step;
+      wave_append(filled, &a.counters[C_F], a.listF, idx);
+      wave_append(m_new < a.thr_lo * rho, &a.counters[C_E], a.listE, idx);
     }
   }
 }
@@ -506,11 +505,9 @@ __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
     coords(g, c, x, y, z);
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
     if (e < nF) {
-      if (s < 0 || a.flags[s] != GAS) continue;
-      if (atomicExch(&a.new_epoch[s], a.step) != a.step) {
-        a.listNI[atomicAdd(&a.counters[C_NI], 1)] = s;
-        init_new_from_gas<F>(a, s);
-      }
+      const bool win = s >= 0 && a.flags[s] == GAS && atomicExch(&a.new_epoch[s], a.step) != a.step;
+      wave_append(win, &a.counters[C_NI], a.listNI, s);
+      if (win) init_new_from_gas<F>(a, s);
     } else {
       // E' = E minus N(F): every thread of the cell takes the same decision
       bool protect = false;
@@ -520,12 +517,10 @@ __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
         if (t >= 0 && a.f_epoch[t] == a.step) protect = true;
       }
       if (protect) continue;
-      if (q == 1) a.listEP[atomicAdd(&a.counters[C_EP], 1)] = c;
-      if (s < 0 || a.flags[s] != LIQ) continue;
-      if (atomicExch(&a.new_epoch[s], a.step) != a.step) {
-        a.listNL[atomicAdd(&a.counters[C_NL], 1)] = s;
-        init_new_from_liquid<F>(a, s);
-      }
+      wave_append(q == 1, &a.counters[C_EP], a.listEP, c);
+      const bool win = s >= 0 && a.flags[s] == LIQ && atomicExch(&a.new_epoch[s], a.step) != a.step;
+      wave_append(win, &a.counters[C_NL], a.listNL, s);
+      if (win) init_new_from_liquid<F>(a, s);
     }
   }
 }
@@ -579,7 +574,7 @@ __global__ __launch_bounds__(BLOCK) void k_share(ConvArgs a) {
     }
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
     if (s < 0 || a.flags[s] != IFACE) continue;
-    if (atomicExch(&a.recv_epoch[s], a.step) != a.step) a.listR[atomicAdd(&a.counters[C_R], 1)] = s;
+    wave_append(atomicExch(&a.recv_epoch[s], a.step) != a.step, &a.counters[C_R], a.listR, s);
   }
 }
 

@@ -40,6 +40,20 @@ struct IfaceData {
   double m, phix;
 };
 
+// Append value to list for every active lane with pred set, with one atomic
+// per wavefront: the lowest such lane reserves the slots, each lane writes at
+// its rank among them (lanes that have left the branch take no part).
+__device__ __forceinline__ void wave_append(bool pred, int32_t* counter, int32_t* list, int32_t value) {
+  const unsigned long long b = __ballot(pred);
+  if (b == 0ull) return;
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((long long)b) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(b));
+  base = __shfl(base, leader);
+  if (pred) list[base + __popcll(b & ((1ull << lane) - 1ull))] = value;
+}
+
 template <class F>
 __device__ __forceinline__ double phi_seen(const IfaceData<F>& d, int q) {
   // fill level seen from the cell: liquid 1, gas 0, interface its fill,
