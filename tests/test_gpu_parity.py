@@ -353,6 +353,28 @@ def test_height_function_curvature_parity(fs, oracle_mod, rule):
         assert np.abs(cd.populations() - o.populations()).max() > 1e-9
 
 
+@pytest.mark.parametrize("rule", [1, 0])
+def test_falling_droplet_conversion_burst_parity(fs, oracle_mod, rule):
+    """A droplet of radius 7 falling under strong gravity onto the floor of a
+    box walled in y: the splash converts tens of cells per step (filled,
+    emptied and protected cells, new interface cells from gas and from
+    liquid side by side).  Classes, lists, masses and populations against the
+    oracle every 20 steps over 200."""
+    w = W.droplet(n=24, radius=7.0, sigma=0.0, offset=(0.1, 3.23, 0.37))
+    w = _with(w, g=(0.0, -1e-3, 0.0), periodic=(1, 0, 1))
+    _say(f"case falling droplet rule {rule}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    most = 0
+    for it in range(10):
+        for _ in range(20):
+            o.step(1, rule)
+            s.step(1, rule)
+            most = max(most, sum(len(v) for v in o.lists().values()))
+        _compare(o, s, f"falling droplet step {20 * (it + 1)}")
+    assert most >= 60
+
+
 @pytest.mark.parametrize("plic", [0, 2])
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("fp16s", 5e-2)])
 def test_surface_tension_reduced_precision(fs, oracle_mod, precision, tol, plic):
