@@ -353,16 +353,18 @@ def test_height_function_curvature_parity(fs, oracle_mod, rule):
         assert np.abs(cd.populations() - o.populations()).max() > 1e-9
 
 
-@pytest.mark.parametrize("rule", [1, 0])
-def test_falling_droplet_conversion_burst_parity(fs, oracle_mod, rule):
+@pytest.mark.parametrize("rule,sigma,plic", [(1, 0.0, 0), (0, 0.0, 0), (1, 2e-3, 2), (3, 2e-3, 2)])
+def test_falling_droplet_conversion_burst_parity(fs, oracle_mod, rule, sigma, plic):
     """A droplet of radius 7 falling under strong gravity onto the floor of a
     box walled in y: the splash converts tens of cells per step (filled,
     emptied and protected cells, new interface cells from gas and from
-    liquid side by side).  Classes, lists, masses and populations against the
-    oracle every 20 steps over 200."""
-    w = W.droplet(n=24, radius=7.0, sigma=0.0, offset=(0.1, 3.23, 0.37))
-    w = _with(w, g=(0.0, -1e-3, 0.0), periodic=(1, 0, 1))
-    _say(f"case falling droplet rule {rule}")
+    liquid side by side), also with surface tension and the height-function
+    curvature (interface cells borrowing the curvature of neighbours that
+    change class from step to step).  Classes, lists, masses and populations
+    against the oracle every 20 steps over 200."""
+    w = W.droplet(n=24, radius=7.0, sigma=sigma, offset=(0.1, 3.23, 0.37))
+    w = _with(w, g=(0.0, -1e-3, 0.0), periodic=(1, 0, 1), plic=plic)
+    _say(f"case falling droplet rule {rule} sigma {sigma} plic {plic}")
     o = oracle_mod.Oracle.from_workload(w)
     s = fs.Sim.from_workload(w)
     most = 0
