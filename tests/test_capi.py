@@ -58,6 +58,27 @@ def test_workspace_size_and_param_validation(libpath):
     assert b"NULL" in L.fslbm_last_error(None)
 
 
+def test_workspace_grows_for_curvature_arrays(libpath):
+    """The workspace holds one 8-byte value per cell (256-byte aligned) for the
+    surface-tension correction when sigma != 0, and one more for the
+    height-function curvature when plic = 2 as well, as the header states."""
+    from paper_1409_5645_amd import fslbm, workloads as W
+    L = fslbm.lib()
+    N = 10 * 12 * 14
+    pad = (8 * N + 255) // 256 * 256
+
+    def size(**kw):
+        cp = fslbm.make_params(W.Params(nx=10, ny=12, nz=14, **kw))
+        ws = ctypes.c_size_t()
+        assert L.fslbm_workspace_size(ctypes.byref(cp), ctypes.byref(ws)) == 0
+        return ws.value
+
+    base = size()
+    assert size(plic=2) == base
+    assert size(sigma=1e-3) == base + pad
+    assert size(sigma=1e-3, plic=1) == base + pad
+    assert size(sigma=1e-3, plic=2) == base + 2 * pad
+
 def test_size_limit(libpath):
     """Population offsets are 32-bit: 19 N must stay below 2^32 (N up to
     226,050,910 cells); a larger lattice is rejected before any device work."""
