@@ -270,6 +270,8 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,fp16s")
     ap.add_argument("--config", default="slosh512")
     ap.add_argument("--rule", type=int, default=1)
+    ap.add_argument("--sigma", type=float, default=0.0)  # surface tension (0: none)
+    ap.add_argument("--plic", type=int, default=0)  # interface position / height functions (0, 1, 2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -290,6 +292,9 @@ def main():
         build.build()
     t0 = time.time()
     w = W.config(args.config, seed=0)
+    if args.sigma != 0.0 or args.plic != 0:
+        import dataclasses
+        w = dataclasses.replace(w, params=dataclasses.replace(w.params, sigma=args.sigma, plic=args.plic))
     log(f"workload {w.name} {w.params.nx}x{w.params.ny}x{w.params.nz} generated in {time.time() - t0:.1f}s "
         f"{w.counts()}")
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
@@ -328,7 +333,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"sloshing tank {w.params.nx}x{w.params.ny}x{w.params.nz} "
                                f"(depth {w.meta['depth']:g}, amplitude {w.meta['amp']:g}, seed 0), {RULE_NAME[args.rule]} rule, "
-                               f"tau {w.params.tau}, g_y {w.params.g[1]:g}",
+                               f"tau {w.params.tau}, g_y {w.params.g[1]:g}"
+                               + (f", sigma {w.params.sigma:g}" if w.params.sigma else "")
+                               + (f", plic {w.params.plic}" if w.params.plic else ""),
                    "cells": w.params.n_cells, "active_cells": r["active_cells"], "form": head},
         "roofline": roof,
         "err_after_steps": args.warmup + args.steps,  # errors vs FP64 compare the final states

@@ -233,7 +233,7 @@ __device__ __forceinline__ bool hf_heights(const Grid& g, int x, int y, int z, c
 // heights across the axis a, nv becomes (s e_a - H_1 e_1 - H_2 e_2)/|.|, s the
 // side of the gas.  Exact for a plane whose slope against a is at most 1.
 // Leaves nv as it is where a column is not complete.
-__device__ __noinline__ void hf_normal(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
+__device__ __forceinline__ void hf_normal(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
                                        const double* __restrict__ phi, double (&nv)[3]) {
   double h[3][3];
   int a, sg;
@@ -256,7 +256,7 @@ __device__ __noinline__ void hf_normal(const Grid& g, int x, int y, int z, const
 // (1 + H_1^2 + H_2^2)^(3/2) with central differences of the column heights (a
 // sphere of radius R: -2/R).  Leaves kappa as it is where a column is not
 // complete.
-__device__ __noinline__ void hf_curvature(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
+__device__ __forceinline__ void hf_curvature(const Grid& g, int x, int y, int z, const uint8_t* __restrict__ flags,
                                           const double* __restrict__ phi, const double (&nv)[3], double& kappa) {
   double h[3][3];
   int a, sg;
@@ -271,7 +271,7 @@ __device__ __noinline__ void hf_curvature(const Grid& g, int x, int y, int z, co
   kappa = num / (q * sqrt(q));
 }
 
-__device__ __noinline__ double plic_plane_offset(double phi, const double (&nv)[3]) {
+__device__ __forceinline__ double plic_plane_offset(double phi, const double (&nv)[3]) {
   const double a = fabs(nv[0]), b = fabs(nv[1]), c = fabs(nv[2]);
   const double sum = a + b + c;
   const double lo3 = fmin(a, fmin(b, c)), hi3 = fmax(a, fmax(b, c));
