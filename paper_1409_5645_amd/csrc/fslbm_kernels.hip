@@ -228,7 +228,7 @@ constexpr int IBLOCK = 64;  // interface-list kernels: one wavefront per block
 // EXTRA: moving walls, surface tension or the PLIC interface position present
 // (a separate instantiation, so that the plain path keeps its registers).
 template <class F, int RULE, bool REC = false, bool EXTRA = false>
-__global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? (EXTRA ? 3 : 4) : 1) void k_iface(SweepArgs a) {
+__global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? ((EXTRA || (RULE & 2)) ? 3 : 4) : 1) void k_iface(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
   constexpr bool SH = F::shifted;
