@@ -681,3 +681,30 @@ def test_wall_table_defaults_parity(fs, oracle_mod):
         if it % 10 == 9:
             _compare(o, s, f"default walls step {it + 1}")
     assert abs(s.stats()["total_mass"] / M0 - 1.0) < 1e-13  # includes the reservoir
+
+
+@pytest.mark.parametrize("case,rule", [("extension", 3), ("extension_fsk", 2), ("tilted", 3), ("tilted", 2)])
+def test_normal_stress_exact_states_parity(fs, oracle_mod, case, rule):
+    """The exact free-surface states of the D-term pins (planar extension under
+    a flat surface with S_nn != 0; in-surface shear under a 45-degree surface)
+    through one frozen FP64 step of the library: equal to the oracle and, at
+    every interior interface cell, to the exact populations (section 3.4)."""
+    from tests.test_oracle_stress import _extension_case, _interior_interface, _tilted_case
+    if case.startswith("extension"):
+        level = 11.0 if case == "extension_fsk" else 10.83
+        w, f, st = _extension_case(oracle_mod, level, 1e-3, -1e-5)
+        p, cells = w.params, _interior_interface(w)
+    else:
+        p, f, st, inner, _ = _tilted_case(oracle_mod, 1e-3)
+        cells = np.nonzero(inner & (st["flags"] == W.INTERFACE))[0]
+    _say(f"case {case} rule={rule} {p.nx}x{p.ny}x{p.nz}")
+    o = oracle_mod.Oracle(p, state=st)
+    o.set_freeze(True)
+    o.step(1, rule)
+    s = fs.Sim(p, st["flags"], precision="fp64", freeze=True)
+    s.set_state(st["f"], st["mass"], st["phi"])
+    s.step(1, rule)
+    _compare(o, s, f"{case} rule {rule}", lists=False)
+    g = s.fields(("f",))["f"]
+    assert np.abs(g[:, cells] - f[:, cells]).max() < 1e-15
+    s.close()

@@ -153,3 +153,217 @@ def test_stress_term_changes_a_sheared_surface(oracle_mod):
     fa, fb = a.populations(), b.populations()
     assert np.abs(fa - fb).max() > 1e-9
     assert abs(b.total_mass() + b.reservoir() - M0) / M0 < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Exact free-surface state with a normal viscous stress (section 3.4).
+#
+# Under a flat surface with normal +y, the planar extension u = (a (x - x0),
+# -a (y - y0), 0) has S = diag(a, -a, 0): d_n j_n = S_nn = -a != 0, and d_t j_n +
+# d_n j_t = 0 (Eq. proj2 holds).  With the linear (Stokes) equilibrium and a
+# uniform body force the lattice Boltzmann step has an exact steady solution
+# for linear velocity and pressure fields: substituting f = e + n into the
+# stream/collide step, every Taylor series stops after its first term and the
+# non-equilibrium is exactly Eq. (nqp), n+_q = (1/lambda_+)(w_q/c_s^2) c_q c_q : S,
+# n-_q = 0 (the force balances the pressure gradient), so the post-collision
+# populations are
+#     ft_q = w_q rho + (w_q/c_s^2) c_q.(u + g/2) + (1 + lambda_+) n+_q.
+# The free-surface condition Eq. (proj1) with sigma = 0 fixes the gas pressure
+# the step must be given: P(eta) - P_b = 2 nu S_nn, i.e. rho_b = rho(eta) -
+# 2 Lambda_+ S_nn.  With those, one step of a consistent rule must give back the
+# same populations at every interface cell whose neighbourhood is the exact
+# state, including every population it rebuilds from gas: Eq. (sli) then holds
+# term by term (its left side is rho - 3 Lambda_+ c c : S and the right side
+# rho_b - 3 Lambda_+ c c : S^b, so S^b_nn must be S_nn / 3).  Setting the normal
+# entry to 0 or to S_nn, or dropping the D term, breaks it.
+# ---------------------------------------------------------------------------
+
+def _extension_case(mod, level, a, gy, tau=0.8, rule=None):
+    nx, ny, nz = 12, 16, 12
+    w = W.pool(nx=nx, ny=ny, nz=nz, level=level, gy=gy, tau=tau, Lambda=3.0 / 16.0)
+    p = w.params
+    p.stokes = 1
+    lp = -1.0 / tau
+    Lp = tau - 0.5
+    N = nx * ny * nz
+    idx = np.arange(N)
+    x, y, z = idx % nx + 0.5, (idx // nx) % ny + 0.5, idx // (nx * ny) + 0.5
+    u = np.stack([a * (x - 6.0), -a * (y - 3.0), np.zeros(N)])
+    S = np.zeros((3, 3))
+    S[0, 0], S[1, 1] = a, -a
+    g = np.array(p.g)
+    cS = np.einsum("qa,ab,qb->q", C, S, C)
+    f = (W_Q[:, None] * w.rho[None, :] + 3.0 * W_Q[:, None] * (C @ (u + 0.5 * g[:, None]))
+         + ((1.0 + lp) / lp) * 3.0 * W_Q[:, None] * cS[:, None])
+    f[:, w.flags == W.GAS] = 0.0
+    p.rho_gas = p.rho_gas - 2.0 * Lp * S[1, 1]     # Eq. (proj1), sigma = 0
+    state = {"flags": w.flags, "f": f, "mass": w.fill * w.rho, "phi": w.fill}
+    return w, f, state
+
+
+def _interior_interface(w):
+    nx, ny, nz = w.params.nx, w.params.ny, w.params.nz
+    idx = np.arange(nx * ny * nz)
+    x, z = idx % nx, idx // (nx * ny)
+    return np.nonzero((w.flags == W.INTERFACE) & (x >= 1) & (x <= nx - 2) & (z >= 1) & (z <= nz - 2))[0]
+
+
+def test_extension_state_is_exact_in_the_bulk(oracle_mod):
+    """The constructed state is a steady solution away from the walls: with
+    a = 0 it is the oracle's own hydrostatic initial state, and with a != 0 one
+    step leaves every liquid cell whose neighbours are not wall-adjacent
+    unchanged (so any mismatch at interface cells is the boundary rule's)."""
+    w, f, st = _extension_case(oracle_mod, 10.5, 0.0, -1e-5)
+    o = oracle_mod.Oracle(w.params, w.flags, w.rho, None, w.fill)
+    act = w.flags != W.GAS
+    assert np.abs(o.populations()[:, act] - f[:, act]).max() < 1e-15
+    w, f, st = _extension_case(oracle_mod, 10.5, 1e-3, -1e-5)
+    o = oracle_mod.Oracle(w.params, state=st)
+    o.set_freeze(True)
+    o.step(1, oracle_mod.FSL_STRESS)
+    nx, ny, nz = w.params.nx, w.params.ny, w.params.nz
+    idx = np.arange(nx * ny * nz)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    inner = (w.flags == W.LIQUID) & (x >= 1) & (x <= nx - 2) & (z >= 1) & (z <= nz - 2) & (y >= 1)
+    assert np.abs(o.populations()[:, inner] - f[:, inner]).max() < 1e-15
+
+
+@pytest.mark.parametrize("rule,level,gy", [("FSL_STRESS", 10.5, -1e-5), ("FSL_STRESS", 10.83, -1e-5),
+                                           ("FSK_STRESS", 11.0, -1e-5), ("FSK_STRESS", 10.3, 0.0),
+                                           ("FSL_STRESS", 10.3, 0.0)])
+def test_normal_stress_rule_exact_under_extension(oracle_mod, rule, level, gy):
+    """Eq. (sli) with S^b from the bulk and S^b_nn = S_nn/3 reproduces the exact
+    extensional free-surface state on every rebuilt link (section 3.4, Table 1
+    column D, Eq. proj1, proj2).  FSL places the surface at its fill (any fill
+    with gravity), FSK half a link beyond the node (gravity needs fill 1 there);
+    without gravity the pressure is uniform and the surface position drops out."""
+    w, f, st = _extension_case(oracle_mod, level, 1e-3, gy)
+    o = oracle_mod.Oracle(w.params, state=st)
+    o.set_freeze(True)
+    o.step(1, getattr(oracle_mod, rule))
+    cells = _interior_interface(w)
+    assert cells.size == 100
+    err = np.abs(o.populations()[:, cells] - f[:, cells]).max()
+    assert err < 1e-15, err
+
+
+def test_normal_stress_needs_the_d_term(oracle_mod):
+    """The same state under the rules with D = 0: the normal viscous stress of
+    Eq. (proj1) is not imposed (section 3.4: D = 0 is consistent with Eq.
+    (proj2) only), so the rebuilt links miss by Lambda_+ (w_q/c_s^2) S_nn times
+    their alpha_+ -- resolved here far above round-off."""
+    for rule, level in (("FSL", 10.5), ("FSK", 11.0)):
+        w, f, st = _extension_case(oracle_mod, level, 1e-3, -1e-5)
+        o = oracle_mod.Oracle(w.params, state=st)
+        o.set_freeze(True)
+        o.step(1, getattr(oracle_mod, rule))
+        cells = _interior_interface(w)
+        assert np.abs(o.populations()[:, cells] - f[:, cells]).max() > 1e-6
+
+
+def test_boundary_shear_comes_from_the_bulk_neighbour(oracle_mod):
+    """S is extrapolated from the bulk (section 3.4), order zero, from the
+    liquid neighbour whose link points most directly into the liquid (reading
+    D1): here the cell below.  Disturb the even populations of links 1, 2 (+e)
+    and 5, 6 (-e) of one interface cell and of its four diagonal liquid
+    neighbours below: density and momentum are unchanged, the shear rate read
+    from those cells is not (S_xx up, S_zz down), and none of the disturbed
+    populations streams into the interface cell.  Its step stays exact only if
+    S comes from the cell straight below."""
+    w, f, st = _extension_case(oracle_mod, 10.83, 1e-3, -1e-5)
+    nx, ny = w.params.nx, w.params.ny
+    cell = lambda i, j, k: i + nx * (j + ny * k)
+    c0 = cell(5, 10, 6)
+    assert w.flags[c0] == W.INTERFACE and w.flags[cell(5, 9, 6)] == W.LIQUID
+    f = st["f"].copy()
+    e = 2e-4
+    for c in (c0, cell(4, 9, 6), cell(6, 9, 6), cell(5, 9, 5), cell(5, 9, 7)):
+        f[1, c] += e
+        f[2, c] += e
+        f[5, c] -= e
+        f[6, c] -= e
+    st = dict(st, f=f)
+    o = oracle_mod.Oracle(w.params, state=st)
+    o.set_freeze(True)
+    o.step(1, oracle_mod.FSL_STRESS)
+    _, fe, _ = _extension_case(oracle_mod, 10.83, 1e-3, -1e-5)
+    err = np.abs(o.populations()[:, c0] - fe[:, c0]).max()
+    assert err < 1e-15, err
+
+
+# A plane surface at 45 degrees, x + y = c, gas above (normal n = (1, 1, 0)/sqrt 2),
+# under a linear field whose shear lies in the surface, S = a (t1 t1^T - t2 t2^T)
+# with t1 = (1, -1, 0)/sqrt 2, t2 = z: S n = 0, so Eq. (proj1) and (proj2) hold
+# with P = P_b and the surface is a stream surface.  With uniform pressure the
+# exact state does not depend on where the closure places the surface, so the
+# rebuilt links must be exact whatever the staircase of fills; S^b keeps the
+# tangential block, and the D term is needed (c c : S != 0 on the tilted links).
+
+def _tilted_case(mod, a, tau=0.8):
+    nx, ny, nz, c = 14, 14, 8, 14.0
+    N = nx * ny * nz
+    idx = np.arange(N)
+    i, j, k = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    s = c - i - j                                   # offset of the line above the lower-left corner
+    fill = np.where(s <= 0, 0.0, np.where(s <= 1, 0.5 * s * s, np.where(s <= 2, 1 - 0.5 * (2 - s) ** 2, 1.0)))
+    flags = np.where(fill <= 0, W.GAS, np.where(s >= 3, W.LIQUID, W.INTERFACE)).astype(np.uint8)
+    p = W.Params(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 0), tau=tau, Lambda=3.0 / 16.0, stokes=1)
+    lp = -1.0 / tau
+    t1 = np.array([1.0, -1.0, 0.0]) / math.sqrt(2.0)
+    t2 = np.array([0.0, 0.0, 1.0])
+    S = a * (np.outer(t1, t1) - np.outer(t2, t2))
+    X = np.stack([i + 0.5 - 7.0, j + 0.5 - 7.0, k + 0.5 - 4.0])
+    u = S @ X
+    cS = np.einsum("qa,ab,qb->q", C, S, C)
+    f = W_Q[:, None] + 3.0 * W_Q[:, None] * (C @ u) + ((1.0 + lp) / lp) * 3.0 * W_Q[:, None] * cS[:, None]
+    f[:, flags == W.GAS] = 0.0
+    state = {"flags": flags, "f": f, "mass": fill, "phi": fill}
+    inner = (i >= 1) & (i <= nx - 2) & (j >= 1) & (j <= ny - 2) & (k >= 1) & (k <= nz - 2)
+    return p, f, state, inner, (i, j, k)
+
+
+@pytest.mark.parametrize("rule", ["FSL_STRESS", "FSK_STRESS"])
+def test_stress_rule_exact_on_tilted_surface(oracle_mod, rule):
+    p, f, st, inner, _ = _tilted_case(oracle_mod, 1e-3)
+    o = oracle_mod.Oracle(p, state=st)
+    o.set_freeze(True)
+    o.step(1, getattr(oracle_mod, rule))
+    cells = np.nonzero(inner & (st["flags"] == W.INTERFACE))[0]
+    assert cells.size > 100
+    err = np.abs(o.populations()[:, cells] - f[:, cells]).max()
+    assert err < 1e-15, err
+    for rule0 in ("FSL", "FSK"):
+        o = oracle_mod.Oracle(p, state=st)
+        o.set_freeze(True)
+        o.step(1, getattr(oracle_mod, rule0))
+        assert np.abs(o.populations()[:, cells] - f[:, cells]).max() > 1e-6
+
+
+def test_bulk_neighbour_on_tilted_surface(oracle_mod):
+    """On the 45-degree surface the liquid neighbour whose link points most
+    directly into the liquid is the diagonal x - (1, 1, 0), not the first
+    liquid link in link order (x - e_x): disturb the even populations of the
+    cell's other liquid neighbours and of the cell itself (density and momentum
+    kept, no disturbed population streams into the cell); its step stays exact."""
+    p, f0, st, inner, (i, j, k) = _tilted_case(oracle_mod, 1e-3)
+    nx, ny = p.nx, p.ny
+    cell = lambda a, b, c: a + nx * (b + ny * c)
+    c0 = cell(6, 6, 4)                               # on the band of fill 1 (i + j = c - 2)
+    assert st["flags"][c0] == W.INTERFACE and st["phi"][c0] == 1.0
+    assert st["flags"][cell(5, 5, 4)] == W.LIQUID and st["flags"][cell(5, 6, 4)] == W.LIQUID
+    f = st["f"].copy()
+    e = 2e-4
+    # pairs (3,4) and (5,6) of x - e_x; (1,2) and (5,6) of x - e_y; of the cell
+    # itself (3,4) and (5,6); of x - e_x -+ e_z (3,4) and (1,2)
+    for c, (p1, p2) in ((cell(5, 6, 4), (3, 5)), (cell(6, 5, 4), (1, 5)), (c0, (3, 5)),
+                        (cell(5, 6, 3), (3, 1)), (cell(5, 6, 5), (3, 1)), (cell(6, 5, 3), (1, 3)),
+                        (cell(6, 5, 5), (1, 3))):
+        f[p1, c] += e
+        f[p1 + 1, c] += e
+        f[p2, c] -= e
+        f[p2 + 1, c] -= e
+    o = oracle_mod.Oracle(p, state=dict(st, f=f))
+    o.set_freeze(True)
+    o.step(1, oracle_mod.FSL_STRESS)
+    err = np.abs(o.populations()[:, c0] - f0[:, c0]).max()
+    assert err < 1e-15, err
