@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define FSLBM_ABI_VERSION 3
+#define FSLBM_ABI_VERSION 4
 
 typedef struct fslbm_ctx fslbm_ctx;
 
@@ -59,8 +59,9 @@ typedef enum {
   FSLBM_E_INVALID = 1,      /* bad argument, size or cell-class pattern */
   FSLBM_E_UNSUPPORTED = 2,  /* valid but not supported (e.g. FSL at tau = 1) */
   FSLBM_E_DEVICE = 3,       /* HIP runtime error */
-  FSLBM_E_UNSTABLE = 4,     /* NaN or non-positive density found by fslbm_stats */
-  FSLBM_E_INVARIANT = 5,    /* a liquid cell touches a gas cell */
+  FSLBM_E_UNSTABLE = 4,     /* a health check found a NaN, a non-positive density or |u| > u_max */
+  FSLBM_E_INVARIANT = 5,    /* a health check found a liquid cell next to a gas cell or an
+                                unknown cell class */
   FSLBM_E_CAPACITY = 6      /* an output array is too small */
 } fslbm_status;
 
@@ -129,6 +130,12 @@ typedef struct {
                                D3Q19 interface neighbours that have one, else the central-
                                difference one (the workspace then holds 8 N more bytes).  Not
                                supported by the adjoint window */
+  int32_t check_every;      /* health check every K steps of fslbm_step (0: none; the
+                               environment variable FSLBM_CHECK_EVERY overrides it): after every
+                               K-th step the library checks every fluid cell and synchronises
+                               (see fslbm_step) */
+  double u_max;             /* |u| bound of the health check (lattice units, >= 0; 0 selects 0.4,
+                               below the lattice speed of sound 1/sqrt 3) */
 } fslbm_params;
 
 typedef struct {
@@ -167,7 +174,12 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
 
 /* Enqueue n time steps with one of the FSLBM_RULE_* rules.  Every rule but
  * FSK with tau = 1 is FSLBM_E_UNSUPPORTED (n+ cannot be recovered from the
- * post-collision state).  Asynchronous. */
+ * post-collision state).  Asynchronous, except with a health check
+ * (params.check_every = K > 0): after every step whose count of steps done
+ * is a multiple of K the health check of fslbm_stats runs and the call waits
+ * for it; on failure it returns FSLBM_E_UNSTABLE or FSLBM_E_INVARIANT (the
+ * message names the count of bad cells and the step) and enqueues no further
+ * step of this call. */
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule);
 
 /* Field export into caller device buffers.  mask selects fields by bit; dst[i]
@@ -187,8 +199,12 @@ fslbm_status fslbm_fields(fslbm_ctx* c, uint32_t mask, void* const* dst);
  * sum over interface cells of m + reservoir (double).  counts: [0] filled,
  * [1] emptied, [2] emptied and converted, [3] new interface from gas, [4] new
  * interface from liquid (all of the last step), [5] interface cells now,
- * [6] liquid cells now, [7] steps done.  Returns FSLBM_E_UNSTABLE if a
- * non-gas cell has a NaN or non-positive density.  Synchronises. */
+ * [6] liquid cells now, [7] steps done.  Health check of the current state
+ * (the interface tracking keeps a layer of interface cells between liquid and
+ * gas, section 2.3): FSLBM_E_INVARIANT if a cell class is unknown or a liquid
+ * cell has a gas cell among its 18 neighbours; else FSLBM_E_UNSTABLE if a
+ * liquid or interface cell has a NaN or non-positive density or a velocity
+ * |u| above params.u_max (all outputs are still written).  Synchronises. */
 fslbm_status fslbm_stats(fslbm_ctx* c, double* total_mass, double* reservoir, int64_t counts[8]);
 
 /* Conversion lists of the last step into host arrays, ascending cell index:

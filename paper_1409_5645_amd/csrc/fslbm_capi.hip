@@ -48,6 +48,8 @@ struct fslbm_ctx {
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
   int pairs = 1;  // FP16 sweep with two cells per lane (FSLBM_FP16_PAIRS=0 disables)
+  int check_every = 0;  // health check after every K-th step (0: none)
+  double u_max2 = 0.16; // square of the |u| bound of the health check
 };
 
 namespace {
@@ -97,8 +99,8 @@ Layout layout(size_t N, bool kappa, bool hf) {
   }
   L.counters = o;
   o = align_up(o + 2 * NCOUNT * sizeof(int32_t));
-  L.scalars = o;  // reservoir, acc, err(int), cnt[4] (int)
-  o = align_up(o + 2 * sizeof(double) + 8 * sizeof(int32_t));
+  L.scalars = o;  // reservoir, acc, err(int), cnt[8] (int)
+  o = align_up(o + 2 * sizeof(double) + 16 * sizeof(int32_t));
   L.wall_t = o;
   o = align_up(o + 8 * 6 * Q);
   L.kappa = o;
@@ -124,6 +126,8 @@ fslbm_status check_params(const fslbm_params* p, std::string& why) {
   if (!(p->conv_eps >= 0.0)) { why = "conv_eps must be >= 0"; return FSLBM_E_INVALID; }
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be finite and >= 0"; return FSLBM_E_INVALID; }
   if (p->plic < 0 || p->plic > 2) { why = "plic must be 0, 1 or 2"; return FSLBM_E_INVALID; }
+  if (p->check_every < 0) { why = "check_every must be >= 0"; return FSLBM_E_INVALID; }
+  if (!(p->u_max >= 0.0) || !std::isfinite(p->u_max)) { why = "u_max must be finite and >= 0"; return FSLBM_E_INVALID; }
   for (int f = 0; f < 6; ++f)
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->wall_u[f][a])) { why = "wall_u must be finite"; return FSLBM_E_INVALID; }
@@ -243,6 +247,12 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   c->phi[1] = b->phi[1];
   c->stream = (hipStream_t)b->stream;
   if (const char* e = std::getenv("FSLBM_FP16_PAIRS")) c->pairs = std::atoi(e) != 0;
+  c->check_every = p->check_every;
+  if (const char* e = std::getenv("FSLBM_CHECK_EVERY")) c->check_every = std::max(0, std::atoi(e));
+  {
+    const double um = p->u_max > 0.0 ? p->u_max : 0.4;
+    c->u_max2 = um * um;
+  }
   char* w = (char*)b->workspace;
   c->aux_rho = (double*)(w + L.aux_rho);
   c->aux_u = (double*)(w + L.aux_u);
@@ -275,7 +285,7 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   for (int i = 0; i < 4; ++i)
     if ((e = launch_fill_i32(*ep[i], N, -1, st)) != hipSuccess) return fail(dev_fail(c, e, "init epochs"));
   if ((e = launch_fill_i32(c->counters, 2 * NCOUNT, 0, st)) != hipSuccess) return fail(dev_fail(c, e, "init counters"));
-  if ((e = launch_fill_i32(c->err, 5, 0, st)) != hipSuccess) return fail(dev_fail(c, e, "init scalars"));
+  if ((e = launch_fill_i32(c->err, 16, 0, st)) != hipSuccess) return fail(dev_fail(c, e, "init scalars"));
   if ((e = launch_fill_f64(c->reservoir, 2, 0.0, st)) != hipSuccess) return fail(dev_fail(c, e, "init scalars"));
   if ((e = launch_check_flags(c->flags, c->com.grid, c->err, st)) != hipSuccess) return fail(dev_fail(c, e, "check flags"));
   int32_t herr = 0;
@@ -318,6 +328,50 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
   HIPCHK(c, hipStreamSynchronize(c->stream), "set_state sync");
   return FSLBM_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Health check and totals of the current state: mass sum (FP64), counts and
+// failing cells (k_stats).  Synchronises.  Returns FSLBM_E_INVARIANT or
+// FSLBM_E_UNSTABLE (with the message set) if a check fails.
+fslbm_status health(fslbm_ctx* c, double sc[2], int32_t cn[8], int32_t last[NCOUNT]) {
+  HIPCHK(c, launch_fill_f64(c->acc, 1, 0.0, c->stream), "stats init");
+  HIPCHK(c, launch_fill_i32(c->cnt, 8, 0, c->stream), "stats init");
+  StatArgs a;
+  a.c = c->com;
+  a.f = c->f[c->cur];
+  a.flags = c->flags;
+  a.mass = c->mass;
+  a.acc = c->acc;
+  a.cnt = c->cnt;
+  a.u_max2 = c->u_max2;
+  HIPCHK(c, launch_stats(a, c->p.precision, c->stream), "stats");
+  HIPCHK(c, hipMemcpyAsync(sc, c->reservoir, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "stats copy");
+  HIPCHK(c, hipMemcpyAsync(cn, c->cnt, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "stats copy");
+  for (int i = 0; i < NCOUNT; ++i) last[i] = 0;
+  if (c->step > 0)
+    HIPCHK(c, hipMemcpyAsync(last, c->counters + ((c->step - 1) & 1) * NCOUNT, NCOUNT * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->stream), "stats copy");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "stats sync");
+  const std::string at = " (after " + std::to_string(c->step) + " steps)";
+  if (cn[5] != 0) {
+    c->last_error = std::to_string(cn[5]) + " cells break the cell-class rule (unknown class, or a liquid cell next "
+                    "to a gas cell)" + at;
+    return FSLBM_E_INVARIANT;
+  }
+  if (cn[1] != 0 || cn[4] != 0) {
+    c->last_error = std::to_string(cn[1]) + " cells with NaN or non-positive density, " + std::to_string(cn[4]) +
+                    " cells with |u| above " + std::to_string(std::sqrt(c->u_max2)) + " or NaN" + at;
+    return FSLBM_E_UNSTABLE;
+  }
+  return FSLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
   if (!c) return FSLBM_E_INVALID;
@@ -406,6 +460,12 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     if (!c->p.freeze) HIPCHK(c, launch_convert(L, c->p.precision), "conversion launch");
     c->cur = b;
     c->step += 1;
+    if (c->check_every > 0 && c->step % c->check_every == 0) {
+      double sc[2];
+      int32_t cn[8], last[NCOUNT];
+      const fslbm_status hs = health(c, sc, cn, last);
+      if (hs != FSLBM_OK) return hs;
+    }
   }
   return FSLBM_OK;
 }
@@ -441,25 +501,10 @@ fslbm_status fslbm_fields(fslbm_ctx* c, uint32_t mask, void* const* dst) {
 
 fslbm_status fslbm_stats(fslbm_ctx* c, double* total_mass, double* reservoir, int64_t counts[8]) {
   if (!c) return FSLBM_E_INVALID;
-  HIPCHK(c, launch_fill_f64(c->acc, 1, 0.0, c->stream), "stats init");
-  HIPCHK(c, launch_fill_i32(c->cnt, 4, 0, c->stream), "stats init");
-  StatArgs a;
-  a.c = c->com;
-  a.f = c->f[c->cur];
-  a.flags = c->flags;
-  a.mass = c->mass;
-  a.acc = c->acc;
-  a.cnt = c->cnt;
-  HIPCHK(c, launch_stats(a, c->p.precision, c->stream), "stats");
-  double sc[2];
-  int32_t cn[4];
-  int32_t last[NCOUNT] = {0};
-  HIPCHK(c, hipMemcpyAsync(sc, c->reservoir, sizeof(sc), hipMemcpyDeviceToHost, c->stream), "stats copy");
-  HIPCHK(c, hipMemcpyAsync(cn, c->cnt, sizeof(cn), hipMemcpyDeviceToHost, c->stream), "stats copy");
-  if (c->step > 0)
-    HIPCHK(c, hipMemcpyAsync(last, c->counters + ((c->step - 1) & 1) * NCOUNT, sizeof(last), hipMemcpyDeviceToHost,
-                             c->stream), "stats copy");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "stats sync");
+  double sc[2] = {0.0, 0.0};
+  int32_t cn[8] = {0}, last[NCOUNT] = {0};
+  const fslbm_status hs = health(c, sc, cn, last);
+  if (hs == FSLBM_E_DEVICE) return hs;
   if (total_mass) *total_mass = sc[1] + sc[0];
   if (reservoir) *reservoir = sc[0];
   if (counts) {
@@ -472,11 +517,7 @@ fslbm_status fslbm_stats(fslbm_ctx* c, double* total_mass, double* reservoir, in
     counts[6] = cn[0];
     counts[7] = c->step;
   }
-  if (cn[1] != 0) {
-    c->last_error = std::to_string(cn[1]) + " cells with NaN or non-positive density";
-    return FSLBM_E_UNSTABLE;
-  }
-  return FSLBM_OK;
+  return hs;
 }
 
 fslbm_status fslbm_conversions(fslbm_ctx* c, int32_t* const* out, int32_t cap, int32_t n_out[5]) {

@@ -187,9 +187,6 @@ __device__ __forceinline__ void collide(R f[Q], const Consts<R>& k, bool incomp,
 
 // The same collision for the FP32 forms, written with fused multiply-adds (the
 // reduced-precision forms are not reproduced bit for bit, so the contraction
-// that saves issue slots is taken here and only here).
-// The same collision for the FP32 forms, written with fused multiply-adds (the
-// reduced-precision forms are not reproduced bit for bit, so the contraction
 // that saves issue slots is taken here and only here).  With SCALED, f holds
 // populations in units of 1/sc (the FP16 storage scale), which the collision is
 // linear in except for the quadratic equilibrium term and the velocity; sc is

@@ -141,7 +141,12 @@ struct StatArgs {
   const uint8_t* flags;
   const double* mass;
   double* acc;    // [0] mass sum
-  int32_t* cnt;   // [0] liquid cells, [1] bad cells, [2] interface cells
+  // [0] liquid cells, [1] cells with a NaN or non-positive density, [2]
+  // interface cells, [3] unused here, [4] cells with |u| above the bound (or
+  // a NaN velocity), [5] cells breaking the class rule (unknown class, or a
+  // liquid cell next to a gas cell)
+  int32_t* cnt;
+  double u_max2;  // square of the |u| bound
 };
 
 // One reverse step t+1 -> t of a window with frozen cell classes.

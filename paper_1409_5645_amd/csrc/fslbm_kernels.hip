@@ -734,24 +734,53 @@ __global__ __launch_bounds__(BLOCK) void k_fields(FieldArgs a) {
   }
 }
 
-// total mass and health check: block partial sums into acc[0]; counts of
-// liquid cells into cnt[0], bad cells into cnt[1], interface cells into cnt[2]
+// Total mass and health check: block partial sums of the mass into acc[0];
+// counts of liquid and interface cells, and of the cells that fail a check
+// (see StatArgs::cnt).  The mass sum is FP64 in every form.
 template <class F>
 __global__ __launch_bounds__(BLOCK) void k_stats(StatArgs a) {
+  using R = typename F::R;
   using S = typename F::S;
+  constexpr bool SH = F::shifted;
   __shared__ double sm[BLOCK / 64];
   __shared__ int sl[BLOCK / 64];
   __shared__ int si[BLOCK / 64];
   double v = 0.0;
   int nl = 0, ni = 0;
   const S* fi = reinterpret_cast<const S*>(a.f);
-  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < a.c.grid.N; idx += gridDim.x * BLOCK) {
+  const Grid& g = a.c.grid;
+  const Consts<R>& k = pick_consts<R>(a.c);
+  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < g.N; idx += gridDim.x * BLOCK) {
     const uint8_t t = a.flags[idx];
+    if (t > SOLID) {
+      atomicAdd(&a.cnt[5], 1);
+      continue;
+    }
     if (t == GAS || t == SOLID) continue;
+    if (t == LIQ) {
+      // the layer rule: no liquid cell has a gas cell among its 18 neighbours
+      int x, y, z;
+      coords(g, idx, x, y, z);
+      bool gas_near = false;
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
+        if (s >= 0 && a.flags[s] == GAS) gas_near = true;
+      }
+      if (gas_near) atomicAdd(&a.cnt[5], 1);
+    }
+    R fl[Q];
     double r = 0.0;
-    for (int q = 0; q < Q; ++q) r = r + (double)F::load(fi + (size_t)q * a.c.grid.N + idx, a.c.inv_scale);
+    for (int q = 0; q < Q; ++q) {
+      fl[q] = F::load(fi + (size_t)q * g.N + idx, a.c.inv_scale);
+      r = r + (double)fl[q];
+    }
     if (F::shifted) r = 1.0 + r;
     if (!(r > 0.0) || !isfinite(r)) atomicAdd(&a.cnt[1], 1);
+    R rs, u[3];
+    recover_moments<R, SH>(fl, k, a.c.incomp, rs, u);
+    const double usq = ((double)u[0] * (double)u[0] + (double)u[1] * (double)u[1]) + (double)u[2] * (double)u[2];
+    if (!(usq <= a.u_max2)) atomicAdd(&a.cnt[4], 1);
     if (t == LIQ) {
       v += r;
       nl += 1;

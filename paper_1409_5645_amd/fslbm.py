@@ -23,7 +23,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 GAS, INTERFACE, LIQUID = 0, 1, 2
 STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "DEVICE", 4: "UNSTABLE", 5: "INVARIANT", 6: "CAPACITY"}
 FIELDS = ("rho", "u", "phi", "flags", "f", "mass", "rho_c", "u_c")
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class FslbmError(RuntimeError):
@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
                 ("stokes", ctypes.c_int32), ("g", ctypes.c_double * 3), ("rho_gas", ctypes.c_double),
                 ("conv_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32), ("freeze", ctypes.c_int32),
                 ("wall_u", (ctypes.c_double * 3) * 6), ("shear_b", ctypes.c_double * 6),
-                ("sigma", ctypes.c_double), ("plic", ctypes.c_int32)]
+                ("sigma", ctypes.c_double), ("plic", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("u_max", ctypes.c_double)]
 
 
 class Buffers(ctypes.Structure):
@@ -91,8 +92,9 @@ def lib():
     return _lib
 
 
-def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13) -> Params:
-    """C parameter block from a workloads.Params."""
+def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13, check_every=0, u_max=0.0) -> Params:
+    """C parameter block from a workloads.Params (check_every, u_max: the
+    health check of fslbm_step; 0 = none / the default bound)."""
     return Params(ABI_VERSION, p.nx, p.ny, p.nz, (ctypes.c_int32 * 3)(*[int(v) for v in p.periodic]),
                   int(precision), float(p.tau), float(p.Lambda), int(p.incompressible), int(p.stokes),
                   (ctypes.c_double * 3)(*[float(v) for v in p.g]), float(p.rho_gas), float(p.eps),
@@ -100,14 +102,14 @@ def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13) -> Params:
                   ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*[float(v) for v in face])
                                                  for face in getattr(p, "wall_u", ((0.0, 0.0, 0.0),) * 6)]),
                   (ctypes.c_double * 6)(*[float(v) for v in getattr(p, "shear_b", (0.0,) * 6)]),
-                  float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)))
+                  float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)), int(check_every), float(u_max))
 
 
 class Sim:
     """One simulation on a GPU.  Buffers are torch tensors on `device`."""
 
     def __init__(self, params, flags, precision="fp64", device="cuda:0", stream=None, freeze=False,
-                 fp16_scale_log2=13):
+                 fp16_scale_log2=13, check_every=0, u_max=0.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fslbm needs a GPU (torch.cuda.is_available() is False)")
@@ -117,7 +119,7 @@ class Sim:
         self.params = params
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.N = N = params.nx * params.ny * params.nz
-        self.cp = make_params(params, self.precision, freeze, fp16_scale_log2)
+        self.cp = make_params(params, self.precision, freeze, fp16_scale_log2, check_every, u_max)
         ws = ctypes.c_size_t()
         self._check(L.fslbm_workspace_size(ctypes.byref(self.cp), ctypes.byref(ws)), None)
         dt = {FP64: torch.float64, FP32: torch.float32, FP16S: torch.float16}[self.precision]

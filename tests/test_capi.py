@@ -46,7 +46,8 @@ def test_workspace_size_and_param_validation(libpath):
     assert L.fslbm_workspace_size(ctypes.byref(cp), ctypes.byref(ws)) == 0
     assert ws.value >= 76 * 10 * 12 * 14
     for field, bad in (("tau", 0.5), ("magic", 0.0), ("precision", 7), ("nx", 0), ("abi_version", 99),
-                       ("fp16_scale_log2", 40), ("rho_gas", -1.0), ("plic", 3), ("sigma", -1.0)):
+                       ("fp16_scale_log2", 40), ("rho_gas", -1.0), ("plic", 3), ("sigma", -1.0),
+                       ("check_every", -1), ("u_max", -1.0), ("u_max", float("inf"))):
         cp2 = fslbm.make_params(p)
         setattr(cp2, field, bad)
         assert L.fslbm_workspace_size(ctypes.byref(cp2), ctypes.byref(ws)) == 1, field
@@ -101,3 +102,26 @@ def test_binding_fails_loudly_without_gpu(libpath):
     w = W.channel(nx=2, nz=2)
     with pytest.raises(RuntimeError):
         fslbm.Sim.from_workload(w)
+
+
+def test_parameter_block_layout_matches_header(tmp_path):
+    """The ctypes mirrors of fslbm_params and fslbm_buffers have the size and
+    field offsets the C compiler gives the header's structs."""
+    import subprocess
+    from paper_1409_5645_amd import fslbm
+    fields = [f for f, _ in fslbm.Params._fields_]
+    bfields = [f for f, _ in fslbm.Buffers._fields_]
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "fslbm.h"', "int main(void) {",
+            'printf("%zu\\n", sizeof(fslbm_params));']
+    prog += [f'printf("%zu\\n", offsetof(fslbm_params, {f}));' for f in fields]
+    prog += ['printf("%zu\\n", sizeof(fslbm_buffers));']
+    prog += [f'printf("%zu\\n", offsetof(fslbm_buffers, {f}));' for f in bfields]
+    prog += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(fslbm.Params)] + [getattr(fslbm.Params, f).offset for f in fields]
+    want += [ctypes.sizeof(fslbm.Buffers)] + [getattr(fslbm.Buffers, f).offset for f in bfields]
+    assert got == want
