@@ -266,10 +266,13 @@ fslbm_status fslbm_set_walls(fslbm_ctx* c, int32_t n, const int32_t* cells, cons
  * fsli1-fsli4), TRT collision (Eq. lbe2), phi = m / rho.  The window's
  * backward pass is the exact reverse-mode derivative of that map (the branches
  * of the forward run: delta clamps, the FSK fallback), written by hand; states
- * are kept by sqrt(T) checkpointing: every K-th state (K = ceil(sqrt T) by
- * default) is stored during the forward pass, and each segment's states are
- * recomputed from its checkpoint during the backward pass (the last segment's
- * are kept from the forward pass).  Between checkpoints only a compact record
+ * are kept by checkpointing: every K-th state is stored during the forward
+ * pass, and each segment's states are recomputed from its checkpoint during
+ * the backward pass (the last segment's are kept from the forward pass).  K =
+ * 0 selects the default: K = T (every step's record kept, no recomputation)
+ * when that workspace fits in half the device memory free at
+ * fslbm_window_workspace_size, else K = ceil(sqrt T) (sqrt(T)
+ * checkpointing).  Between checkpoints only a compact record
  * per step is kept: the collision velocity of the liquid cells and the inputs
  * of the interface cells.  All work runs on the context's stream.
  * Supported: FP64 and FP32 forms, the incompressible equilibrium with its

@@ -71,6 +71,7 @@ def lib():
         L.ref_total_mass.argtypes = [vp]
         L.ref_reservoir.restype = ctypes.c_double
         L.ref_reservoir.argtypes = [vp]
+        L.ref_branch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
         L.ref_list.restype = ctypes.c_int
         L.ref_list.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int]
         L.ref_constants.argtypes = [vp, dp]
@@ -224,6 +225,14 @@ class Oracle:
         u = np.empty(3 * self.N)
         lib().ref_get_macro(self._h, _dptr(rho), _dptr(u))
         return rho, u.reshape(3, self.N)
+
+    def branch_stats(self) -> dict:
+        """Branches the FSL closure took so far: link distances clamped at 0
+        and at 1, FSK fallbacks, and an order-independent signature of (step,
+        cell, link, branch); equal for two runs that took the same branches."""
+        out = (ctypes.c_uint64 * 4)()
+        lib().ref_branch_stats(self._h, out)
+        return {"clamp0": int(out[0]), "clamp1": int(out[1]), "fallback": int(out[2]), "signature": int(out[3])}
 
     def total_mass(self) -> float:
         return lib().ref_total_mass(self._h)

@@ -172,6 +172,14 @@ void ref_get_macro(void* hp, double* rho, double* u) {
 double ref_total_mass(void* hp) { return static_cast<Handle*>(hp)->sim.total_mass(); }
 double ref_reservoir(void* hp) { return static_cast<Handle*>(hp)->sim.reservoir; }
 
+// Branches of the FSL closure so far: out = {clamped at 0, clamped at 1, FSK
+// fallback, order-independent signature of (step, cell, link, branch)}.
+void ref_branch_stats(void* hp, unsigned long long* out) {
+  const auto& s = static_cast<Handle*>(hp)->sim;
+  for (int i = 0; i < 3; ++i) out[i] = s.branch_count[i];
+  out[3] = s.branch_sig;
+}
+
 // which: 0 = filled, 1 = emptied, 2 = emptied and converted, 3 = new interface
 // from gas, 4 = new interface from liquid.  Copies up to cap entries and
 // returns the list length.

@@ -100,6 +100,23 @@ struct Oracle {
   T reservoir = T(0.0);
   bool freeze = false;        // frozen flag topology (no conversions)
   long long steps_done = 0;
+  // Record of the branches the FSL closure took (diagnostics for finite
+  // differences: two runs with equal counts and signature took the same
+  // branch at every link of every step): link distance clamped at 0, at 1,
+  // FSK fallback; signature = sum mod 2^64 of a hash of (step, cell, link,
+  // branch) over those events, so it does not depend on their order.
+  unsigned long long branch_count[3] = {0, 0, 0};
+  unsigned long long branch_sig = 0;
+  void note_branch(int cell, int q, int code) {
+    unsigned long long k = ((unsigned long long)steps_done << 37) ^ ((unsigned long long)cell << 5) ^ (unsigned long long)q;
+    k = k * 4ull + (unsigned long long)code;
+    k += 0x9e3779b97f4a7c15ull;  // splitmix64 finaliser
+    k = (k ^ (k >> 30)) * 0xbf58476d1ce4e5b9ull;
+    k = (k ^ (k >> 27)) * 0x94d049bb133111ebull;
+    k = k ^ (k >> 31);
+    branch_count[code] += 1;
+    branch_sig += k;
+  }
 
   // conversion lists of the last step, ascending cell index
   std::vector<int> listF, listE, listEp, listNI, listNL;
@@ -981,10 +998,12 @@ struct Oracle {
             T nc = cdot(o, nvec);
             if (ok && nc > T(0.0)) {
               T delta = dist / nc;
-              if (delta < T(0.0)) delta = T(0.0);
-              if (delta > T(1.0)) delta = T(1.0);
+              if (delta < T(0.0)) { delta = T(0.0); note_branch(cell, q, 0); }
+              if (delta > T(1.0)) { delta = T(1.0); note_branch(cell, q, 1); }
               k = coeffs_fsli(T(1.0), delta);
               f_o_next = f[o];
+            } else {
+              note_branch(cell, q, 2);
             }
           }
           // Eq. (closure): f_{obar}(x,t+1) = a0 ft_o + a0bar ft_obar + a1 ft_o(x-c_o)

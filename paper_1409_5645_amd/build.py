@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libfslbm.so")
-SOURCES = ["fslbm_sweep.hip", "fslbm_kernels.hip", "fslbm_adjoint.hip", "fslbm_capi.hip"]
+SOURCES = ["fslbm_sweep.hip", "fslbm_kernels.hip", "fslbm_iface4.hip", "fslbm_adjoint.hip", "fslbm_capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: no FMA contraction, so the FP64 form reproduces the

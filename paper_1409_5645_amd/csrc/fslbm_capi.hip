@@ -48,7 +48,9 @@ struct fslbm_ctx {
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
   int pairs = 1;  // FP16 sweep with two cells per lane (FSLBM_FP16_PAIRS=0 disables)
+  int quad = 1;   // interface kernel with four lanes per cell (FSLBM_IFACE_QUAD=0 selects one lane per cell)
   int check_every = 0;  // health check after every K-th step (0: none)
+  int dflt_T = -1, dflt_K = 0;  // default checkpoint spacing chosen for windows of length dflt_T
   double u_max2 = 0.16; // square of the |u| bound of the health check
 };
 
@@ -221,19 +223,21 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes) {
   return FSLBM_OK;
 }
 
-fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out) {
-  std::string why;
-  fslbm_status s = check_params(p, why);
-  if (s != FSLBM_OK) { g_init_error = why; return s; }
-  if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
-  if (!b->f[0] || !b->f[1] || !b->flags || !b->mass || !b->phi[0] || !b->phi[1] || !b->workspace) {
+}  // extern "C"
+
+namespace {
+
+// fslbm_init with the workspace given separately; parameters already checked.
+fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* workspace, size_t workspace_bytes,
+                       fslbm_ctx** out) {
+  if (!b->f[0] || !b->f[1] || !b->flags || !b->mass || !b->phi[0] || !b->phi[1] || !workspace) {
     g_init_error = "a device buffer is NULL";
     return FSLBM_E_INVALID;
   }
   const size_t N = (size_t)p->nx * p->ny * p->nz;
   const Layout L = layout(N, p->sigma != 0.0, p->plic == 2);
-  if (b->workspace_bytes < L.total) { g_init_error = "workspace too small"; return FSLBM_E_INVALID; }
-  if (((uintptr_t)b->workspace) % ALIGN) { g_init_error = "workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
+  if (workspace_bytes < L.total) { g_init_error = "workspace too small"; return FSLBM_E_INVALID; }
+  if (((uintptr_t)workspace) % ALIGN) { g_init_error = "workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
 
   fslbm_ctx* c = new (std::nothrow) fslbm_ctx();
   if (!c) { g_init_error = "out of host memory"; return FSLBM_E_INVALID; }
@@ -247,13 +251,14 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   c->phi[1] = b->phi[1];
   c->stream = (hipStream_t)b->stream;
   if (const char* e = std::getenv("FSLBM_FP16_PAIRS")) c->pairs = std::atoi(e) != 0;
+  if (const char* e = std::getenv("FSLBM_IFACE_QUAD")) c->quad = std::atoi(e) != 0;
   c->check_every = p->check_every;
   if (const char* e = std::getenv("FSLBM_CHECK_EVERY")) c->check_every = std::max(0, std::atoi(e));
   {
     const double um = p->u_max > 0.0 ? p->u_max : 0.4;
     c->u_max2 = um * um;
   }
-  char* w = (char*)b->workspace;
+  char* w = (char*)workspace;
   c->aux_rho = (double*)(w + L.aux_rho);
   c->aux_u = (double*)(w + L.aux_u);
   int32_t** ep[4] = {&c->f_epoch, &c->new_epoch, &c->recv_epoch, &c->conv_epoch};
@@ -297,6 +302,18 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   c->has_solid = (herr & 4) != 0;
   *out = c;
   return FSLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out) {
+  std::string why;
+  fslbm_status s = check_params(p, why);
+  if (s != FSLBM_OK) { g_init_error = why; return s; }
+  if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
+  return init_impl(p, b, b->workspace, b->workspace_bytes, out);
 }
 
 static InitArgs init_args(fslbm_ctx* c) {
@@ -411,6 +428,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.freeze = c->p.freeze ? 1 : 0;
     s.cpr = 0;
     s.pairs = c->pairs;
+    s.quad = c->quad;
     s.u_out = nullptr;
     s.kappa = c->kappa;
     s.khf = c->khf;
@@ -728,13 +746,27 @@ fslbm_status window_checks(fslbm_ctx* c, int32_t T, int32_t K) {
   return FSLBM_OK;
 }
 
-int window_spacing(int32_t T, int32_t K) {
-  if (K == 0) {
-    int k = (int)std::ceil(std::sqrt((double)T));
-    while ((long long)k * k < T) ++k;
-    return std::max(k, 1);
-  }
-  return std::min(K, T);
+int sqrt_spacing(int32_t T) {
+  int k = (int)std::ceil(std::sqrt((double)T));
+  while ((long long)k * k < T) ++k;
+  return std::max(k, 1);
+}
+
+// Checkpoint spacing K of a window: as given (at most T), or for K = 0 the
+// default: every step's record (K = T, no recompute pass in the backward
+// pass) when that workspace fits in half the device memory free now, else
+// ceil(sqrt T).  The default chosen for a window length is kept in the
+// context, so that fslbm_window_workspace_size and fslbm_window_forward agree
+// even though the caller allocates the workspace in between.
+int window_spacing(fslbm_ctx* c, int32_t T, int32_t K, int n_i) {
+  if (K != 0) return std::min(K, T);
+  if (c->dflt_T == T) return c->dflt_K;
+  const size_t all = win_layout(c->com.grid, c->p.precision, T, T, n_i).total;
+  size_t free_b = 0, total_b = 0;
+  const bool fits = hipMemGetInfo(&free_b, &total_b) == hipSuccess && all <= free_b / 2;
+  c->dflt_T = T;
+  c->dflt_K = fits ? T : sqrt_spacing(T);
+  return c->dflt_K;
 }
 
 // One frozen forward step from state A (time t) to state B (time t+1) that
@@ -865,7 +897,8 @@ fslbm_status fslbm_window_workspace_size(fslbm_ctx* c, int32_t T, int32_t K, siz
   int32_t n_i = 0;
   HIPCHK(c, hipMemcpyAsync(&n_i, c->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "count copy");
   HIPCHK(c, hipStreamSynchronize(c->stream), "count sync");
-  *bytes = win_layout(c->com.grid, c->p.precision, T, window_spacing(T, K), n_i).total;
+  c->dflt_T = -1;  // a fresh default for this call
+  *bytes = win_layout(c->com.grid, c->p.precision, T, window_spacing(c, T, K, n_i), n_i).total;
   return FSLBM_OK;
 }
 
@@ -889,7 +922,7 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   const size_t N = (size_t)g.N;
   char* wsp = (char*)workspace;
   // the head of the layout does not depend on the interface count
-  const WinLayout H = win_layout(g, c->p.precision, T, window_spacing(T, K), 0);
+  const WinLayout H = win_layout(g, c->p.precision, T, 1, 0);
   if (workspace_bytes < H.ckpt) { c->last_error = "window workspace too small"; return FSLBM_E_INVALID; }
   fslbm_window* w = new (std::nothrow) fslbm_window();
   if (!w) { c->last_error = "out of host memory"; return FSLBM_E_INVALID; }
@@ -900,8 +933,7 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   w->ctx = c;
   w->com = c->com;
   w->T = T;
-  w->K = window_spacing(T, K);
-  w->C = (T + w->K - 1) / w->K;
+  w->C = 0;
   w->rule = rule;
   w->precision = c->p.precision;
   w->N = N;
@@ -919,6 +951,8 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   if ((e = hipMemcpyAsync(&n_i, w->n_dev, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
     return fail(dev_fail(c, e, "interface count copy"));
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return fail(dev_fail(c, e, "window sync"));
+  w->K = window_spacing(c, T, K, n_i);
+  w->C = (T + w->K - 1) / w->K;
   const WinLayout L = win_layout(g, c->p.precision, T, w->K, n_i);
   if (workspace_bytes < L.total) {
     c->last_error = "window workspace too small (" + std::to_string(workspace_bytes) + " < " +

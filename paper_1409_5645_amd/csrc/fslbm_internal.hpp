@@ -59,6 +59,7 @@ struct SweepArgs {
   int freeze;
   int cpr;   // blocks per lattice row (set by the launcher)
   int pairs; // FP16 form: two cells per lane when rows have even length
+  int quad;  // interface cells of the plain step with four lanes per cell (k_iface4)
   void* u_out;  // optional (FP64 / FP32 forms): collision velocity of liquid cells, [3][N] compute type
   // optional per-step record of the interface cells (list order, capacity
   // rec_cap): pulled and own populations of time t (compute type, [Q][cap]),
@@ -180,6 +181,7 @@ struct AdjArgs {
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
 hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
+hipError_t launch_iface4(const StepLaunch& L, int precision, int rule);  // fslbm_iface4.hip
 hipError_t launch_curvature(const StepLaunch& L);  // one or (plic = 2) two list kernels
 hipError_t launch_convert(const StepLaunch& L, int precision);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, void* stream);

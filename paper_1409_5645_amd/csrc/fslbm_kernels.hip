@@ -839,6 +839,10 @@ static void iface_form(const StepLaunch& L, int rule) {
       extra ? iface_go<F, 1, true, true>(L, nbr) : iface_go<F, 1, true, false>(L, nbr);
     return;
   }
+  if (!extra && L.sweep.quad) {
+    (void)launch_iface4(L, std::is_same<F, FormF64>::value ? 0 : (std::is_same<F, FormF32>::value ? 1 : 2), rule);
+    return;
+  }
   switch (rule) {
     case 0: extra ? iface_go<F, 0, false, true>(L, nb) : iface_go<F, 0, false, false>(L, nb); break;
     case 1: extra ? iface_go<F, 1, false, true>(L, nb) : iface_go<F, 1, false, false>(L, nb); break;

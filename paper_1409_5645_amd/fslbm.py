@@ -251,9 +251,12 @@ class Sim:
 
     def window(self, T, rule=FSL, K=0):
         """Forward pass of an adjoint window of T frozen-class steps from the
-        current state (sqrt(T) checkpointing with spacing K, 0 = ceil(sqrt T)).
-        Returns a Window whose backward() gives the gradients."""
-        return Window(self, int(T), int(rule), int(K))
+        current state, with checkpoint spacing K (0 = the library's default:
+        every step's record when it fits in half the free device memory, else
+        ceil(sqrt T)).  Returns a Window whose backward() gives the gradients."""
+        w = Window(self, int(T), int(rule), int(K))
+        self.last_window_K = w.K
+        return w
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -9,9 +9,12 @@ populations, u = (j - g) + g/2, in torch.
 
 Bars: FP64 directional derivatives within 1e-6 relative of the oracle's dual
 numbers (the two compute the same derivative in different orders, so agreement
-is expected near 1e-12); within 1e-5 of FP64 central differences (O(h^2)
-truncation and rounding of the loss); the checkpoint spacing does not change
-the result (bit for bit).  FP32: error against the FP64 gradient stated.
+is expected near 1e-12), at the adjoint's own configuration (128 x 96 x 128,
+T = 400) against golden values written by an oracle-only script; within 1e-6
+of FP64 central differences whose steps the oracle's branch record shows on
+one branch (h^2 truncation and rounding of the loss lie far below); the
+checkpoint spacing does not change the result (bit for bit).  FP32: error
+against the FP64 gradient stated.
 """
 import dataclasses
 import math
@@ -152,9 +155,19 @@ def test_adjoint_only_interface_loss(fs, oracle_mod, case):
         assert math.isfinite(rel) and rel <= 1e-6
 
 
-def test_adjoint_vs_central_difference_fp64(fs, case):
-    """Central differences of the GPU's own FP64 forward window (steps small
-    enough that every run takes the same branches)."""
+def _branches(oracle_mod, p, st, f0, rho_b):
+    q = dataclasses.replace(p, rho_gas=rho_b)
+    o = oracle_mod.Oracle(q, state={"flags": st["flags"], "f": f0, "mass": st["mass"], "phi": st["phi"]})
+    o.set_freeze(True)
+    o.step(T, 1)
+    return o.branch_stats()
+
+
+def test_adjoint_vs_central_difference_fp64(fs, oracle_mod, case):
+    """Central differences of the GPU's own FP64 forward window, with steps
+    for which the oracle's branch record shows the +-h runs taking the base
+    run's branch at every link-distance clamp and FSK fallback: then the
+    difference is the derivative of one smooth branch and must agree to 1e-6."""
     import torch
     _say("case adjoint fp64 FSL vs GPU central differences")
     p, st, tg, dirs = case
@@ -172,26 +185,39 @@ def test_adjoint_vs_central_difference_fp64(fs, case):
         sim.close()
         return L
 
+    base = _branches(oracle_mod, p, st, st["f"], p.rho_gas)
     h = 1e-6
+    for sgn in (1, -1):
+        assert _branches(oracle_mod, p, st, st["f"] + sgn * h * dirs["f"], p.rho_gas) == base
     fd = (loss_at(st["f"] + h * dirs["f"], p.rho_gas) - loss_at(st["f"] - h * dirs["f"], p.rho_gas)) / (2 * h)
     ad = float((gr["f"] * dirs["f"]).sum())
     _say("  f0    adjoint", ad, "fd", fd, "rel", abs(ad - fd) / abs(fd))
-    assert math.isfinite(ad) and abs(ad - fd) <= 1e-5 * abs(fd)
+    assert math.isfinite(ad) and abs(ad - fd) <= 1e-6 * abs(fd)
     hr = 1e-5 * p.rho_gas
+    for sgn in (1, -1):
+        assert _branches(oracle_mod, p, st, st["f"], p.rho_gas + sgn * hr) == base
     fd = (loss_at(st["f"], p.rho_gas + hr) - loss_at(st["f"], p.rho_gas - hr)) / (2 * hr)
     ad = gr["P_b"] / 3.0
     _say("  rho_b adjoint", ad, "fd", fd, "rel", abs(ad - fd) / abs(fd))
-    assert math.isfinite(ad) and abs(ad - fd) <= 1e-5 * abs(fd)
+    assert math.isfinite(ad) and abs(ad - fd) <= 1e-6 * abs(fd)
 
 
 def test_checkpoint_spacing_does_not_change_the_gradient(fs, case):
     _say("case adjoint fp64 FSL: checkpoint spacings 1, 3, 20 and the default")
     ref = _gpu_grad(fs, case, 1)
-    for K in (1, 3, T):
+    for K in (1, 3, 5, T):
         gr = _gpu_grad(fs, case, 1, K=K)
         for k in ("f", "m", "phi", "g"):
             np.testing.assert_array_equal(gr[k], ref[k], err_msg=f"K={K} {k}")
         assert gr["P_b"] == ref["P_b"]
+    # the default keeps every step's record when that fits in memory (here it does)
+    p, st, _, _ = case
+    sim = fs.Sim(p, st["flags"])
+    sim.set_state(st["f"], st["mass"], st["phi"])
+    win = sim.window(T, 1)
+    assert win.K == T and win.checkpoints == 1
+    win.close()
+    sim.close()
 
 
 def test_fp32_gradient_error_stated(fs, case):
@@ -268,100 +294,128 @@ def test_window_errors(fs, case):
     sp.close()
 
 
-def test_full_size_fp64_fd_and_fp32_error(fs):
-    """128 x 96 x 128 sloshing tank, T = 400, loss against a seed-generated
-    target run (P_b, g scaled by 1 + 0.01 xi, f0 + 1e-4 w xi): FP64 adjoint
-    against FP64 central differences for rho_b and g_y; FP32 gradient error
-    against FP64 stated; cost of forward + backward against T plain steps."""
+def test_full_size_against_oracle_golden(fs, oracle_mod):
+    """Configuration of the adjoint at its own size: 128 x 96 x 128 sloshing
+    tank, T = 400 frozen FSL steps, loss against a seed-generated target run
+    (tests/golden/make_adjoint_slosh128.py, which calls only the oracle).
+
+    - The target run is repeated on the GPU in FP64 from the same seeded
+      inputs; its interface-cell velocities and fills must hash to the oracle's
+      (the GPU's FP64 window forward is the oracle's bit for bit).
+    - FP64 adjoint: L, dL/drho_b, dL/dg and the derivative along a seeded
+      direction of f0 within 1e-6 of the oracle's dual numbers (the same
+      derivative computed in a different order; measured near 1e-12).
+    - Central differences: along g_y a relative step of 1e-6 keeps every
+      link-distance clamp and FSK fallback on the base run's branch (the
+      oracle's branch record in the golden file), so the difference must agree
+      to 1e-6.  Along rho_b no step does: the record shows the +-h runs crossing
+      about 10^2..10^4 clamp decisions at h = 1e-7..1e-5 (the loss has kinks
+      everywhere along rho_b), so that difference is reported, not asserted.
+    - FP32 gradient error against FP64 stated; forward and backward timed."""
+    import hashlib
+    import json
+    import os
     import torch
-    w = W.config("slosh128", seed=0)
-    p = w.params
+    sys_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    gold = json.load(open(os.path.join(sys_path, "adjoint_slosh128.json")))
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_adjoint_slosh128",
+                                                  os.path.join(sys_path, "make_adjoint_slosh128.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    TT = gold["T"]
+    p, st = mk.base_case()                      # oracle initial state (no steps)
     N = p.n_cells
-    TT = 400
-    _say(f"case adjoint full size {p.nx}x{p.ny}x{p.nz} T={TT}")
-    rng = np.random.default_rng(7)
-    xi1, xi2 = rng.normal(size=2)
-    ref = fs.Sim.from_workload(w)
-    base = ref.fields(("f", "mass", "phi", "flags"), device=True)
-    ref.close()
-    iface = (base["flags"] == W.INTERFACE).cpu().numpy()
-    wq = torch.as_tensor(np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12), dtype=torch.float64,
-                         device=base["f"].device)
-    act = (base["flags"] != W.GAS).to(torch.float64)
-    tgt = fs.Sim(p, w.flags)
-    f_t = base["f"] + 1e-4 * wq[:, None] * torch.randn(base["f"].shape, dtype=torch.float64, device=base["f"].device,
-                                                       generator=torch.Generator(device=base["f"].device).manual_seed(7)) * act
-    tgt.set_state(f_t, base["mass"], base["phi"])
-    g_t = [v * (1 + 0.01 * xi2) for v in p.g]
-    tgt.set_forcing(g_t, p.rho_gas * (1 + 0.01 * xi1))
+    it = st["flags"] == W.INTERFACE
+    _say(f"case adjoint full size {p.nx}x{p.ny}x{p.nz} T={TT} ({int(it.sum())} interface cells)")
+    pt, f_t = mk.target_inputs(p, st)
+    tgt = fs.Sim(p, st["flags"])
+    tgt.set_state(f_t, st["mass"], st["phi"])
+    tgt.set_forcing(pt.g, pt.rho_gas)
     tgt.window(TT, 1)
-    out = tgt.fields(("u", "phi"), device=True)
-    tg = {"u": out["u"].cpu().numpy(), "phi": out["phi"].cpu().numpy()}
+    out = tgt.fields(("f", "phi"))
     tgt.close()
+    tg_u, tg_phi = mk.velocity(out["f"][:, it], pt.g), out["phi"][it]
+    tb = np.concatenate([tg_u.ravel(), tg_phi])
+    np.testing.assert_allclose(tg_u.sum(axis=1), gold["target"]["sum_u"], rtol=1e-12, atol=1e-15)
+    assert abs(float((tb ** 2).sum()) - gold["target"]["sumsq"]) <= 1e-12 * gold["target"]["sumsq"]
+    same_bits = hashlib.sha256(tb.tobytes()).hexdigest() == gold["target"]["sha256_u_phi"]
+    _say(f"  target run: same bits as the oracle's: {same_bits}")
+    assert same_bits
+    tg = {"u": np.zeros((3, N)), "phi": np.zeros(N)}
+    tg["u"][:, it] = tg_u
+    tg["phi"][it] = tg_phi
+    dvec = mk.f0_direction(p, st)
 
     def grad(precision):
-        sim = fs.Sim(p, w.flags, precision=precision)
-        leaf = lambda v: v.clone().detach().requires_grad_(True)  # noqa: E731
-        f0, m0, phi0 = leaf(base["f"]), leaf(base["mass"]), leaf(base["phi"])
-        P_b = torch.tensor(p.rho_gas / 3.0, dtype=torch.float64, device=sim.device, requires_grad=True)
-        g = torch.tensor(p.g, dtype=torch.float64, device=sim.device, requires_grad=True)
+        sim = fs.Sim(p, st["flags"], precision=precision)
+        dev = sim.device
+        leaf = lambda a: torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True)  # noqa: E731
+        f0, m0, phi0 = leaf(st["f"]), leaf(st["mass"]), leaf(st["phi"])
+        P_b = leaf(p.rho_gas / 3.0)
+        g = leaf(np.array(p.g, dtype=np.float64))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fT, mT, phiT = fs.window_apply(sim, TT, 1, f0, m0, phi0, P_b, g)
-        L = _loss(torch, fT, phiT, g, iface, tg, with_linear=False)
+        L = _loss(torch, fT, phiT, g, it, tg, with_linear=False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         L.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        sim.set_state(base["f"], base["mass"], base["phi"])
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        sim.window(TT, 1)  # forward pass alone (it includes the checkpoint writes)
-        torch.cuda.synchronize()
-        t4 = time.perf_counter()
+        out = {"L": float(L.detach()), "P_b": float(P_b.grad), "g": g.grad.cpu().numpy(),
+               "df": float((f0.grad.cpu().numpy() * dvec).sum()), "f": f0.grad.detach().clone(),
+               "t_fwd": t1 - t0, "t_bwd": t2 - t1}
         sim.close()
-        return {"L": float(L.detach()), "P_b": float(P_b.grad), "g": g.grad.cpu().numpy(), "f": f0.grad,
-                "t_fwd": t1 - t0, "t_bwd": t2 - t1, "t_fwd_only": t4 - t3}
+        return out
 
     g64 = grad("fp64")
-    _say(f"  fp64 L {g64['L']:.6e} dL/dP_b {g64['P_b']:.6e} dL/dg {g64['g']}  "
+    _say(f"  fp64 L {g64['L']:.10e} dL/dP_b {g64['P_b']:.10e} dL/dg {g64['g']}  "
          f"fwd {g64['t_fwd']*1e3:.1f} ms bwd {g64['t_bwd']*1e3:.1f} ms")
+    checks = [("L", g64["L"], gold["L"]), ("dL/drho_b", g64["P_b"] / 3.0, gold["dL_drho_b"]),
+              ("dL/df0.d", g64["df"], gold["dL_df0_along_direction"])]
+    checks += [(f"dL/dg_{a}", float(g64["g"][i]), gold["dL_dg"][i]) for i, a in enumerate("xyz")]
+    for name, got, want in checks:
+        rel = abs(got - want) / abs(want)
+        _say(f"  {name:10s} gpu {got:.12e} oracle {want:.12e} rel {rel:.2e}")
+        assert math.isfinite(rel) and rel <= 1e-6, name
 
     def loss_at(rho_b, gv):
-        sim = fs.Sim(p, w.flags, precision="fp64")
-        sim.set_state(base["f"], base["mass"], base["phi"])
+        sim = fs.Sim(p, st["flags"], precision="fp64")
+        sim.set_state(st["f"], st["mass"], st["phi"])
         sim.set_forcing(gv, rho_b)
         sim.window(TT, 1)
         out = sim.fields(("f", "phi"), device=True)
         L = float(_loss(torch, out["f"], out["phi"], torch.tensor(gv, dtype=torch.float64, device=sim.device),
-                        iface, tg, with_linear=False))
+                        it, tg, with_linear=False))
         sim.close()
         return L
 
-    # 400 steps over ~10^4 interface cells: a relative step of 1e-5 already moves
-    # some link distances across a clamp; 1e-7 keeps the runs on one branch and
-    # is far from rounding-limited (the loss is O(1e-2))
-    hr = 1e-7 * p.rho_gas
-    fd = (loss_at(p.rho_gas + hr, p.g) - loss_at(p.rho_gas - hr, p.g)) / (2 * hr)
-    ad = g64["P_b"] / 3.0
-    _say(f"  rho_b adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}")
-    assert abs(ad - fd) <= 1e-5 * abs(fd)
-    hg = 1e-7 * abs(p.g[1])
+    row = next(r for r in gold["fd"]["g_y"] if r["h_rel"] == 1e-6)
+    assert row["same_branches_as_base"]
+    hg = 1e-6 * abs(p.g[1])
     gp, gm = list(p.g), list(p.g)
     gp[1] += hg
     gm[1] -= hg
     fd = (loss_at(p.rho_gas, gp) - loss_at(p.rho_gas, gm)) / (2 * hg)
     ad = float(g64["g"][1])
-    _say(f"  g_y   adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}")
-    assert abs(ad - fd) <= 1e-5 * abs(fd)
+    _say(f"  g_y   adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e} (one branch)")
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    hr = 1e-6 * p.rho_gas
+    fd = (loss_at(p.rho_gas + hr, p.g) - loss_at(p.rho_gas - hr, p.g)) / (2 * hr)
+    ad = g64["P_b"] / 3.0
+    row = next(r for r in gold["fd"]["rho_b"] if r["h_rel"] == 1e-6)
+    _say(f"  rho_b adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e} (crosses "
+         f"{row['branches_plus']['clamp0'] - gold['base_branches']['clamp0']:+d} / "
+         f"{row['branches_minus']['clamp0'] - gold['base_branches']['clamp0']:+d} clamps; oracle fd rel "
+         f"{row['rel_err_vs_dual']:.2e})")
 
     g32 = grad("fp32")
     ef = float(torch.linalg.norm(g32["f"] - g64["f"]) / torch.linalg.norm(g64["f"]))
     eP = abs(g32["P_b"] - g64["P_b"]) / abs(g64["P_b"])
     eg = float(np.linalg.norm(g32["g"] - g64["g"]) / np.linalg.norm(g64["g"]))
     _say(f"  fp32 gradient error: f0 {ef:.2e}  P_b {eP:.2e}  g {eg:.2e}")
-    _say(f"  fp32 fwd {g32['t_fwd']*1e3:.1f} ms bwd {g32['t_bwd']*1e3:.1f} ms fwd-only {g32['t_fwd_only']*1e3:.1f} ms")
+    _say(f"  fp32 fwd {g32['t_fwd']*1e3:.1f} ms bwd {g32['t_bwd']*1e3:.1f} ms")
     assert math.isfinite(ef) and ef < 0.1
 
 
@@ -421,7 +475,7 @@ def test_many_interface_cells_fd_and_spacing(fs):
     ad = g2["P_b"] / 3.0
     _say(f"  rho_b adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}")
     assert abs(ad - fd) <= 1e-5 * abs(fd)
-    # a step of 1e-7 keeps the runs on one branch of every clamp (see the test above)
+    # over T = 4 steps a step of 1e-7 along f0 moves few link distances (measured agreement 7e-12)
     h = 1e-7
     fd = (loss_at(base["f"] + h * d, p.rho_gas) - loss_at(base["f"] - h * d, p.rho_gas)) / (2 * h)
     ad = g2["df"]

@@ -163,7 +163,8 @@ def test_slosh512_reduced_precision_subbox_step(fs, oracle_mod, precision):
     surface.  Every population is within the rounding of its form: the FP32
     form computes and stores the shifted population g = f - w in FP32, whose
     terms are of the size of g and of the density deviation (a few 1e-4 to
-    1e-3 here), so |error| <= 2e-9; the FP16 form stores 2^12 g in binary16,
+    1e-3 here), so |error| <= 2e-9; the FP16 form stores 2^13 g in binary16
+    (the default scale exponent of the binding),
     so the result is within half an ulp, at most 2^-11 |g| (subnormals
     included), plus the same FP32 arithmetic.  Classes agree and interface
     masses (FP64 bookkeeping of FP32 exchanges) are within 1e-5."""
