@@ -62,7 +62,7 @@ typedef enum {
   FSLBM_E_UNSTABLE = 4,     /* a health check found a NaN, a non-positive density or |u| > u_max */
   FSLBM_E_INVARIANT = 5,    /* a health check found a liquid cell next to a gas cell or an
                                 unknown cell class */
-  FSLBM_E_CAPACITY = 6      /* an output array is too small */
+  FSLBM_E_CAPACITY = 6      /* an output array, or the static workspace, is too small */
 } fslbm_status;
 
 /* Gas-side reconstruction rule (Table 1).  FSK and FSL use the boundary value
@@ -159,6 +159,26 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes);
  * short workspace.  Synchronises.  Populations are undefined until
  * fslbm_set_equilibrium or fslbm_set_state. */
 fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out);
+
+/* Size of the library's static workspace of fslbm_init_static (64 MiB per
+ * device: lattices whose fslbm_workspace_size is at most this, e.g. about
+ * 880,000 cells without surface tension). */
+#define FSLBM_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * fslbm_init, but b->workspace and b->workspace_bytes are ignored -- the
+ * context's workspace is an array of FSLBM_STATIC_WORKSPACE_BYTES inside the
+ * library on the current device, which each device that uses it holds until
+ * the process ends.  No device memory is allocated, by this call or by the
+ * calls on the context.  The caller still passes every other buffer.
+ * FSLBM_E_CAPACITY if fslbm_workspace_size exceeds the array.  One context
+ * per device may hold the array at a time: while one exists, a second call
+ * on the same device is FSLBM_E_INVALID (contexts sharing it would race);
+ * fslbm_destroy releases it.  The array keeps the contents of the previous
+ * context; everything a step needs cleared is cleared here, as by
+ * fslbm_init.  Synchronises. */
+fslbm_status fslbm_init_static(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out);
 
 /* Initial state from macroscopic fields (device pointers, double): rho[N],
  * u[3*N] (u[a*N + idx]) and fill[N].  Every non-gas cell gets the

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -50,6 +51,7 @@ struct fslbm_ctx {
   int pairs = 1;  // FP16 sweep with two cells per lane (FSLBM_FP16_PAIRS=0 disables)
   int quad = 1;   // interface kernel with four lanes per cell (FSLBM_IFACE_QUAD=0 selects one lane per cell)
   int check_every = 0;  // health check after every K-th step (0: none)
+  int static_device = -1;  // device whose static workspace this context holds (fslbm_init_static)
   int dflt_T = -1, dflt_K = 0;  // default checkpoint spacing chosen for windows of length dflt_T
   double u_max2 = 0.16; // square of the |u| bound of the health check
 };
@@ -227,7 +229,8 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes) {
 
 namespace {
 
-// fslbm_init with the workspace given separately; parameters already checked.
+// fslbm_init with the workspace given separately (the caller's buffer, or the
+// library's static array for fslbm_init_static); parameters already checked.
 fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* workspace, size_t workspace_bytes,
                        fslbm_ctx** out) {
   if (!b->f[0] || !b->f[1] || !b->flags || !b->mass || !b->phi[0] || !b->phi[1] || !workspace) {
@@ -304,6 +307,17 @@ fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* work
   return FSLBM_OK;
 }
 
+// The allocation-free workspace: one array per device, in the library's own
+// device memory from the load of the code object until the process ends.  Its
+// device address comes from hipGetSymbolAddress (once per device, with that
+// device current); the name itself is only a host-side stand-in.
+__device__ __align__(256) unsigned char scratch[FSLBM_STATIC_WORKSPACE_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+bool g_scratch_busy[MAX_DEVICES] = {};
+
 }  // namespace
 
 extern "C" {
@@ -314,6 +328,44 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
   return init_impl(p, b, b->workspace, b->workspace_bytes, out);
+}
+
+fslbm_status fslbm_init_static(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out) {
+  std::string why;
+  fslbm_status s = check_params(p, why);
+  if (s != FSLBM_OK) { g_init_error = why; return s; }
+  if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
+  const size_t need = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2).total;
+  if (need > (size_t)FSLBM_STATIC_WORKSPACE_BYTES) {
+    g_init_error = "the lattice needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                   std::to_string((size_t)FSLBM_STATIC_WORKSPACE_BYTES) + " of the static workspace";
+    return FSLBM_E_CAPACITY;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "current device");
+  if (dev < 0 || dev >= MAX_DEVICES) { g_init_error = "device index beyond the static workspace table"; return FSLBM_E_UNSUPPORTED; }
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_busy[dev]) {
+      g_init_error = "the static workspace of this device is held by another context (destroy it first)";
+      return FSLBM_E_INVALID;
+    }
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return dev_fail(nullptr, e, "static workspace address");
+      g_scratch_ptr[dev] = ptr;
+    }
+    ws = g_scratch_ptr[dev];
+    g_scratch_busy[dev] = true;
+  }
+  s = init_impl(p, b, ws, (size_t)FSLBM_STATIC_WORKSPACE_BYTES, out);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (s != FSLBM_OK) g_scratch_busy[dev] = false;
+  else (*out)->static_device = dev;
+  return s;
 }
 
 static InitArgs init_args(fslbm_ctx* c) {
@@ -586,6 +638,10 @@ fslbm_status fslbm_destroy(fslbm_ctx* c) {
   if (!c) return FSLBM_E_INVALID;
   hipError_t e = hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
+  if (c->static_device >= 0) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    g_scratch_busy[c->static_device] = false;
+  }
   delete c;
   return e == hipSuccess ? FSLBM_OK : FSLBM_E_DEVICE;
 }

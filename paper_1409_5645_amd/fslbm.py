@@ -49,7 +49,7 @@ class Buffers(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
 
 
-EXPORTS = ("fslbm_workspace_size", "fslbm_init", "fslbm_set_equilibrium", "fslbm_set_state", "fslbm_step",
+EXPORTS = ("fslbm_workspace_size", "fslbm_init", "fslbm_init_static", "fslbm_set_equilibrium", "fslbm_set_state", "fslbm_step",
            "fslbm_fields", "fslbm_stats", "fslbm_conversions", "fslbm_timing", "fslbm_set_forcing", "fslbm_set_walls",
            "fslbm_window_workspace_size", "fslbm_window_forward", "fslbm_window_backward", "fslbm_window_info",
            "fslbm_window_destroy", "fslbm_destroy", "fslbm_last_error")
@@ -68,6 +68,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.fslbm_workspace_size.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
         L.fslbm_init.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Buffers), ctypes.POINTER(vp)]
+        L.fslbm_init_static.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Buffers), ctypes.POINTER(vp)]
         L.fslbm_set_equilibrium.argtypes = [vp, vp, vp, vp]
         L.fslbm_set_state.argtypes = [vp, vp, vp, vp, ctypes.c_double]
         L.fslbm_step.argtypes = [vp, i32, i32]
@@ -109,7 +110,7 @@ class Sim:
     """One simulation on a GPU.  Buffers are torch tensors on `device`."""
 
     def __init__(self, params, flags, precision="fp64", device="cuda:0", stream=None, freeze=False,
-                 fp16_scale_log2=13, check_every=0, u_max=0.0):
+                 fp16_scale_log2=13, check_every=0, u_max=0.0, static_workspace=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fslbm needs a GPU (torch.cuda.is_available() is False)")
@@ -129,14 +130,18 @@ class Sim:
             self.flags_t = torch.as_tensor(np.ascontiguousarray(flags, dtype=np.uint8)).to(self.device)
             self.mass_t = torch.zeros(N, dtype=torch.float64, device=self.device)
             self.phi_t = [torch.zeros(N, dtype=torch.float64, device=self.device) for _ in range(2)]
-            self.ws = torch.empty(ws.value, dtype=torch.uint8, device=self.device)
-        assert self.ws.data_ptr() % 256 == 0
+            # static_workspace: the library's own array (fslbm_init_static), no workspace buffer
+            self.ws = None if static_workspace else torch.empty(ws.value, dtype=torch.uint8, device=self.device)
+        assert self.ws is None or self.ws.data_ptr() % 256 == 0
         b = Buffers((ctypes.c_void_p * 2)(self.f[0].data_ptr(), self.f[1].data_ptr()), self.flags_t.data_ptr(),
                     self.mass_t.data_ptr(), (ctypes.c_void_p * 2)(self.phi_t[0].data_ptr(), self.phi_t[1].data_ptr()),
-                    self.ws.data_ptr(), ws.value, self.stream.cuda_stream)
+                    None if self.ws is None else self.ws.data_ptr(), 0 if self.ws is None else ws.value,
+                    self.stream.cuda_stream)
         torch.cuda.synchronize(self.device)
         h = ctypes.c_void_p()
-        self._check(L.fslbm_init(ctypes.byref(self.cp), ctypes.byref(b), ctypes.byref(h)), None)
+        init = L.fslbm_init_static if static_workspace else L.fslbm_init
+        with torch.cuda.device(self.device):
+            self._check(init(ctypes.byref(self.cp), ctypes.byref(b), ctypes.byref(h)), None)
         self.ctx = h
 
     # ------------------------------------------------------------- helpers
