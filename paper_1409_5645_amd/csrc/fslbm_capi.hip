@@ -49,10 +49,22 @@ struct fslbm_ctx {
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
   int pairs = 1;  // FP16 sweep with two cells per lane (FSLBM_FP16_PAIRS=0 disables)
-  int quad = 1;   // interface kernel with four lanes per cell (FSLBM_IFACE_QUAD=0 selects one lane per cell)
+  int quad = 2;   // interface kernel: 2 four lanes per cell in XCD-aware order (FSLBM_IFACE_QUAD: 1 plain order, 0 one lane per cell)
   int check_every = 0;  // health check after every K-th step (0: none)
   int static_device = -1;  // device whose static workspace this context holds (fslbm_init_static)
   int dflt_T = -1, dflt_K = 0;  // default checkpoint spacing chosen for windows of length dflt_T
+  // Rows the sweep launches: every ext_every steps the extent of the fluid
+  // cells is measured on the device and copied into pinned host memory
+  // without a wait; a step launches only the rows within the latest extent
+  // that has arrived, widened by one cell per step since it was taken (the
+  // fluid region grows by at most one cell per step: new interface cells are
+  // neighbours of filled ones).  Off (every row) for fslbm_init_static.
+  int ext_every = 0;
+  int32_t* ext_dev = nullptr;        // workspace: the kernel's output
+  int32_t* ext_host = nullptr;       // pinned: two slots of 4 values
+  hipEvent_t ext_ev[2] = {nullptr, nullptr};
+  int ext_step[2] = {-1, -1};        // step whose flags each slot describes
+  int ext_pending = -1, ext_valid = -1;
   double u_max2 = 0.16; // square of the |u| bound of the health check
 };
 
@@ -64,7 +76,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, wall_t, kappa, khf, total;
+  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, extent, wall_t, kappa, khf, total;
 };
 
 // Moving-wall bounce-back terms per face (x-, x+, y-, y+, z-, z+) and link:
@@ -105,6 +117,8 @@ Layout layout(size_t N, bool kappa, bool hf) {
   o = align_up(o + 2 * NCOUNT * sizeof(int32_t));
   L.scalars = o;  // reservoir, acc, err(int), cnt[8] (int)
   o = align_up(o + 2 * sizeof(double) + 16 * sizeof(int32_t));
+  L.extent = o;
+  o = align_up(o + 4 * sizeof(int32_t));
   L.wall_t = o;
   o = align_up(o + 8 * 6 * Q);
   L.kappa = o;
@@ -254,7 +268,7 @@ fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* work
   c->phi[1] = b->phi[1];
   c->stream = (hipStream_t)b->stream;
   if (const char* e = std::getenv("FSLBM_FP16_PAIRS")) c->pairs = std::atoi(e) != 0;
-  if (const char* e = std::getenv("FSLBM_IFACE_QUAD")) c->quad = std::atoi(e) != 0;
+  if (const char* e = std::getenv("FSLBM_IFACE_QUAD")) c->quad = std::max(0, std::min(2, std::atoi(e)));
   c->check_every = p->check_every;
   if (const char* e = std::getenv("FSLBM_CHECK_EVERY")) c->check_every = std::max(0, std::atoi(e));
   {
@@ -270,6 +284,7 @@ fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* work
   for (int i = 0; i < 7; ++i) *ls[i] = (int32_t*)(w + L.lists[i]);
   c->counters = (int32_t*)(w + L.counters);
   c->reservoir = (double*)(w + L.scalars);
+  c->ext_dev = (int32_t*)(w + L.extent);
   if (p->sigma != 0.0) c->kappa = (double*)(w + L.kappa);
   if (p->sigma != 0.0 && p->plic == 2) c->khf = (double*)(w + L.khf);
   c->wall_t = (double*)(w + L.wall_t);
@@ -327,7 +342,22 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
-  return init_impl(p, b, b->workspace, b->workspace_bytes, out);
+  s = init_impl(p, b, b->workspace, b->workspace_bytes, out);
+  if (s != FSLBM_OK) return s;
+  fslbm_ctx* c = *out;
+  c->ext_every = 16;
+  if (const char* e = std::getenv("FSLBM_EXTENT_EVERY")) c->ext_every = std::max(0, std::atoi(e));
+  if (c->ext_every > 0) {
+    hipError_t e = hipHostMalloc((void**)&c->ext_host, 8 * sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ext_ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ext_ev[1], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      fslbm_destroy(c);
+      *out = nullptr;
+      return dev_fail(nullptr, e, "extent buffers");
+    }
+  }
+  return FSLBM_OK;
 }
 
 fslbm_status fslbm_init_static(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out) {
@@ -438,6 +468,48 @@ fslbm_status health(fslbm_ctx* c, double sc[2], int32_t cn[8], int32_t last[NCOU
   return FSLBM_OK;
 }
 
+// Rows the sweep of the next step launches (SweepArgs box), from the latest
+// fluid extent that has arrived; starts a new measurement every ext_every
+// steps.  No wait on the device.
+hipError_t sweep_box(fslbm_ctx* c, SweepArgs& s) {
+  s.box = 0;
+  if (c->ext_every <= 0) return hipSuccess;
+  if (c->ext_pending >= 0) {
+    const hipError_t q = hipEventQuery(c->ext_ev[c->ext_pending]);
+    if (q == hipSuccess) {
+      c->ext_valid = c->ext_pending;
+      c->ext_pending = -1;
+    } else if (q != hipErrorNotReady) {
+      return q;
+    }
+  }
+  if (c->ext_pending < 0 && (c->ext_valid < 0 || c->step - c->ext_step[c->ext_valid] >= c->ext_every)) {
+    const int slot = c->ext_valid == 0 ? 1 : 0;
+    hipError_t e = launch_extent(c->flags, c->com.grid, c->ext_dev, (void*)c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->ext_host + 4 * slot, c->ext_dev, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ext_ev[slot], c->stream);
+    if (e != hipSuccess) return e;
+    c->ext_step[slot] = c->step;
+    c->ext_pending = slot;
+  }
+  if (c->ext_valid < 0) return hipSuccess;
+  const Grid& g = c->com.grid;
+  const int32_t* ex = c->ext_host + 4 * c->ext_valid;
+  const int d = c->step - c->ext_step[c->ext_valid];
+  s.box = 1;
+  if (ex[1] < 0) {  // no fluid cell: one row (the sweep still resets the next counters)
+    s.by0 = s.bz0 = 0;
+    s.bny = s.bnz = 1;
+    return hipSuccess;
+  }
+  s.by0 = g.py ? 0 : std::max(0, ex[0] - d);
+  s.bny = g.py ? g.ny : std::min(g.ny - 1, ex[1] + d) - s.by0 + 1;
+  s.bz0 = g.pz ? 0 : std::max(0, ex[2] - d);
+  s.bnz = g.pz ? g.nz : std::min(g.nz - 1, ex[3] + d) - s.bz0 + 1;
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -489,6 +561,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.wdelta = c->wdelta;
     s.wuw = c->wuw;
     s.nwall = c->nwall > 0 ? c->nwall : 0;
+    HIPCHK(c, sweep_box(c, s), "extent");
     ConvArgs& v = L.conv;
     v.c = c->com;
     v.fout = c->f[b];
@@ -638,6 +711,9 @@ fslbm_status fslbm_destroy(fslbm_ctx* c) {
   if (!c) return FSLBM_E_INVALID;
   hipError_t e = hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : c->ext_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (c->ext_host) (void)hipHostFree(c->ext_host);
   if (c->static_device >= 0) {
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     g_scratch_busy[c->static_device] = false;

@@ -26,7 +26,8 @@ namespace fslbm {
 
 constexpr int QBLOCK = 256;               // threads per block
 constexpr int QCELLS = QBLOCK / QUAD;     // cells per block
-constexpr unsigned IFACE4_GRID = 16384;   // blocks at most (grid-stride beyond)
+constexpr unsigned IFACE4_GRID = 16384;   // blocks at most (grid-stride beyond); a multiple of NXCD
+constexpr int NXCD = 8;                   // XCDs of the device
 
 // owner lane, pair slot and half (0: the odd link 2p + 1, 1: the even one) of
 // link q >= 1: pair p = (q - 1) / 2 lives in lane p % 4, slot p / 4
@@ -206,8 +207,21 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     wq[s] = R(p < 3 ? WD[1] : WD[7]);
     w3[s] = R(p < 3 ? W3D[1] : W3D[7]);
   }
-  const int stride = (int)gridDim.x * QCELLS;
-  for (int i = (int)blockIdx.x * QCELLS + ((int)threadIdx.x >> 2); i < n_i; i += stride) {
+  // Chunks of QCELLS consecutive list entries.  Workgroups go to the eight
+  // XCDs round robin (workgroup b to XCD b mod 8); with a.quad == 2 the chunks
+  // are dealt so that each XCD takes one contiguous stretch of the list, whose
+  // cells share rows and so the lines of their neighbourhoods in that XCD's
+  // L2; else chunk b, b + grid, ...
+  const int nchunk = (n_i + QCELLS - 1) / QCELLS;
+  const bool xcd_order = a.quad == 2;
+  const int per = (nchunk + NXCD - 1) / NXCD;
+  const int k0 = xcd_order ? (int)blockIdx.x / NXCD : (int)blockIdx.x;
+  const int kstride = xcd_order ? (int)gridDim.x / NXCD : (int)gridDim.x;
+  const int kend = xcd_order ? per : nchunk;
+  for (int kk = k0; kk < kend; kk += kstride) {
+    const int chunk = xcd_order ? ((int)blockIdx.x % NXCD) * per + kk : kk;
+    const int i = chunk * QCELLS + ((int)threadIdx.x >> 2);
+    if (chunk >= nchunk || i >= n_i) continue;  // quad-uniform
     const int idx = a.listI[i];
     Nbr n;
     coords(g, idx, n.x, n.y, n.z);
@@ -557,7 +571,8 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
 
 template <class F, int RULE>
 static void iface4_go(const StepLaunch& L) {
-  const unsigned nb = std::min<unsigned>(IFACE4_GRID, (unsigned)((L.sweep.c.grid.N + QCELLS - 1) / QCELLS));
+  unsigned nb = std::min<unsigned>(IFACE4_GRID, (unsigned)((L.sweep.c.grid.N + QCELLS - 1) / QCELLS));
+  nb = (nb + NXCD - 1) / NXCD * NXCD;
   k_iface4<F, RULE><<<nb, QBLOCK, 0, (hipStream_t)L.stream>>>(L.sweep);
 }
 

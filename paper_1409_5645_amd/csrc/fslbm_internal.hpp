@@ -58,8 +58,11 @@ struct SweepArgs {
   int step;
   int freeze;
   int cpr;   // blocks per lattice row (set by the launcher)
+  // box of rows the sweep launches (box != 0): y in [by0, by0 + bny), z in
+  // [bz0, bz0 + bnz); every liquid cell lies inside it.  0: every row.
+  int box, by0, bny, bz0, bnz;
   int pairs; // FP16 form: two cells per lane when rows have even length
-  int quad;  // interface cells of the plain step with four lanes per cell (k_iface4)
+  int quad;  // interface cells of the plain step with four lanes per cell (k_iface4); 2: XCD-aware order
   void* u_out;  // optional (FP64 / FP32 forms): collision velocity of liquid cells, [3][N] compute type
   // optional per-step record of the interface cells (list order, capacity
   // rec_cap): pulled and own populations of time t (compute type, [Q][cap]),
@@ -180,6 +183,8 @@ struct AdjArgs {
 };
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
+// y and z extent of the fluid cells into ext = (ymin, ymax, zmin, zmax); (INT_MAX, -1, ...) if none
+hipError_t launch_extent(const uint8_t* flags, const Grid& g, int32_t* ext, void* stream);
 hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
 hipError_t launch_iface4(const StepLaunch& L, int precision, int rule);  // fslbm_iface4.hip
 hipError_t launch_curvature(const StepLaunch& L);  // one or (plic = 2) two list kernels

@@ -31,9 +31,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
 #pragma unroll
     for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
   }
-  const int row = (int)blockIdx.x / a.cpr;
-  const int chunk = (int)blockIdx.x - row * a.cpr;
-  const int y = row % g.ny, z = row / g.ny;
+  const int brow = (int)blockIdx.x / a.cpr;
+  const int chunk = (int)blockIdx.x - brow * a.cpr;
+  const int y = a.box ? a.by0 + brow % a.bny : brow % g.ny;
+  const int z = a.box ? a.bz0 + brow / a.bny : brow / g.ny;
+  const int row = y + g.ny * z;
   const int x = chunk * (int)blockDim.x + (int)threadIdx.x;
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
@@ -197,9 +199,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
 #pragma unroll
     for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
   }
-  const int row = (int)blockIdx.x / a.cpr;
-  const int chunk = (int)blockIdx.x - row * a.cpr;
-  const int y = row % g.ny, z = row / g.ny;
+  const int brow = (int)blockIdx.x / a.cpr;
+  const int chunk = (int)blockIdx.x - brow * a.cpr;
+  const int y = a.box ? a.by0 + brow % a.bny : brow % g.ny;
+  const int z = a.box ? a.bz0 + brow / a.bny : brow / g.ny;
+  const int row = y + g.ny * z;
   const int x0 = (chunk * (int)blockDim.x + (int)threadIdx.x) * 2;
   const bool valid = x0 < g.nx;
   const int xl = valid ? x0 : 0;  // in-bounds pair for lanes past the row end
@@ -266,6 +270,81 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   }
 }
 
+// Extent of the fluid (liquid and interface) cells in y and z: ext[0..3] =
+// (ymin, ymax, zmin, zmax), to be set to (INT_MAX, -1, INT_MAX, -1) before.
+// One block per z-slab walks the slab's flags with 16-byte loads; each
+// block contributes its extent with two atomics per axis.
+constexpr int EBLOCK = 256;
+__global__ __launch_bounds__(EBLOCK) void k_extent(const uint8_t* __restrict__ flags, Grid g, int32_t* ext) {
+  __shared__ int smin[EBLOCK / 64], smax[EBLOCK / 64];
+  const int z = (int)blockIdx.x;
+  const size_t slab = (size_t)g.nx * (size_t)g.ny;
+  const uint8_t* p = flags + slab * (size_t)z;
+  int ymin = 0x7fffffff, ymax = -1;
+  // 16-byte chunks of the slab; the slab start is 16-byte aligned when nx*ny
+  // is a multiple of 16, else bytes one by one
+  const bool vec = (slab % 16) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0;
+  if (vec) {
+    const uint4* p4 = reinterpret_cast<const uint4*>(p);
+    for (size_t c = threadIdx.x; c < slab / 16; c += EBLOCK) {
+      const uint4 v = p4[c];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t b = (w[k >> 2] >> (8 * (k & 3))) & 0xffu;
+        if (b == IFACE || b == LIQ) {
+          const int y = (int)((c * 16 + (size_t)k) / (size_t)g.nx);
+          ymin = min(ymin, y);
+          ymax = max(ymax, y);
+        }
+      }
+    }
+  } else {
+    for (size_t c = threadIdx.x; c < slab; c += EBLOCK) {
+      const uint8_t b = p[c];
+      if (b == IFACE || b == LIQ) {
+        const int y = (int)(c / (size_t)g.nx);
+        ymin = min(ymin, y);
+        ymax = max(ymax, y);
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    ymin = min(ymin, __shfl_down(ymin, o));
+    ymax = max(ymax, __shfl_down(ymax, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smin[threadIdx.x >> 6] = ymin;
+    smax[threadIdx.x >> 6] = ymax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < EBLOCK / 64; ++w) {
+      ymin = min(ymin, smin[w]);
+      ymax = max(ymax, smax[w]);
+    }
+    if (ymax >= 0) {
+      atomicMin(&ext[0], ymin);
+      atomicMax(&ext[1], ymax);
+      atomicMin(&ext[2], z);
+      atomicMax(&ext[3], z);
+    }
+  }
+}
+
+__global__ void k_extent_init(int32_t* ext) {
+  ext[0] = 0x7fffffff;
+  ext[1] = -1;
+  ext[2] = 0x7fffffff;
+  ext[3] = -1;
+}
+
+hipError_t launch_extent(const uint8_t* flags, const Grid& g, int32_t* ext, void* stream) {
+  k_extent_init<<<1, 1, 0, (hipStream_t)stream>>>(ext);
+  k_extent<<<(unsigned)g.nz, EBLOCK, 0, (hipStream_t)stream>>>(flags, g, ext);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ launchers
 template <class F>
 static void sweep_form(const StepLaunch& L) {
@@ -275,7 +354,7 @@ static void sweep_form(const StepLaunch& L) {
   // whole wavefronts, no more than a row needs (short rows would idle lanes)
   const int threads = std::min(BLOCK, 64 * ((g.nx + 63) / 64));
   a.cpr = (g.nx + threads - 1) / threads;
-  const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
+  const unsigned nb = (unsigned)a.cpr * (a.box ? (unsigned)a.bny * (unsigned)a.bnz : (unsigned)g.ny * (unsigned)g.nz);
   if (a.u_out && a.c.incomp && !a.c.stokes)
     k_sweep<F, 1, true><<<nb, threads, 0, st>>>(a);
   else if (a.c.incomp && !a.c.stokes)
@@ -291,7 +370,7 @@ static void sweep_h2(const StepLaunch& L) {
   // whole wavefronts of cell pairs, no more than a row needs
   const int threads = std::min(BLOCK, 64 * ((g.nx + 127) / 128));
   a.cpr = (g.nx + 2 * threads - 1) / (2 * threads);
-  const unsigned nb = (unsigned)a.cpr * (unsigned)g.ny * (unsigned)g.nz;
+  const unsigned nb = (unsigned)a.cpr * (a.box ? (unsigned)a.bny * (unsigned)a.bnz : (unsigned)g.ny * (unsigned)g.nz);
   if (a.c.incomp && !a.c.stokes)
     k_sweep_h2<1><<<nb, threads, 0, st>>>(a);
   else
