@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define FSLBM_ABI_VERSION 4
+#define FSLBM_ABI_VERSION 5
 
 typedef struct fslbm_ctx fslbm_ctx;
 
@@ -136,6 +136,11 @@ typedef struct {
                                (see fslbm_step) */
   double u_max;             /* |u| bound of the health check (lattice units, >= 0; 0 selects 0.4,
                                below the lattice speed of sound 1/sqrt 3) */
+  int32_t hold_fill;        /* nonzero: the fill levels and interface masses keep
+                               their values, so the surface stays where the caller put it (an
+                               interface position known exactly, as for the steady films of
+                               section 4.3); the cell classes are frozen as with freeze; the
+                               populations evolve as usual */
 } fslbm_params;
 
 typedef struct {
@@ -275,6 +280,22 @@ fslbm_status fslbm_set_forcing(fslbm_ctx* c, const double g[3], double rho_gas);
  * solid cells; not supported by the adjoint window. */
 fslbm_status fslbm_set_walls(fslbm_ctx* c, int32_t n, const int32_t* cells, const double* delta,
                              const double* wall_u);
+
+/* A prescribed surface plane for every interface cell (section 2.2: a
+ * boundary node x_b with boundary links meeting the surface at x_b + delta
+ * c_q, 0 <= delta <= 1), for surfaces whose position is known exactly (the
+ * steady films of section 4.3).  Requires params.hold_fill.  The FSL rules
+ * then take the link distances delta = offset / (n . c_o) (clamped to
+ * [0, 1]) and the rules with a D term the local basis from this plane
+ * instead of the fill field.
+ *   normal  double[3][N], device: unit normal towards the gas,
+ *           normal[a*N + idx] (read at interface cells);
+ *   offset  double[N], device: signed distance of the plane from the node
+ *           along the normal (positive: the node is on the liquid side).
+ * The arrays stay owned by the caller and are read by every later step; NULL
+ * removes the surface.  Not supported by the adjoint window.  No device
+ * work. */
+fslbm_status fslbm_set_surface(fslbm_ctx* c, const double* normal, const double* offset);
 
 /* ---------------------------------------------------------------------------
  * Adjoint window: gradients through T steps with frozen cell classes.

@@ -37,7 +37,7 @@ class _RefParams(ctypes.Structure):
                 ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
                 ("rho_gas", ctypes.c_double), ("eps", ctypes.c_double),
                 ("wall_u", ctypes.c_double * 18), ("shear_b", ctypes.c_double * 6),
-                ("sigma", ctypes.c_double), ("plic", ctypes.c_int)]
+                ("sigma", ctypes.c_double), ("plic", ctypes.c_int), ("hold", ctypes.c_int)]
 
 
 _lib = None
@@ -87,6 +87,7 @@ def lib():
         L.ref_interface_normal.restype = ctypes.c_int
         L.ref_interface_normal.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp]
         L.ref_set_walls.restype = ctypes.c_int
+        L.ref_set_surface.argtypes = [ctypes.c_void_p, dp, dp]
         L.ref_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp]
         L.ref_cut_volume.restype = ctypes.c_double
         L.ref_cut_volume.argtypes = [dp, ctypes.c_double]
@@ -111,7 +112,7 @@ def _params(p) -> _RefParams:
                       float(p.g[0]), float(p.g[1]), float(p.g[2]), float(p.rho_gas), float(p.eps),
                       (ctypes.c_double * 18)(*[float(v) for face in wall for v in face]),
                       (ctypes.c_double * 6)(*[float(v) for v in shear]),
-                      float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)))
+                      float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)), int(getattr(p, "hold", 0)))
 
 
 FSK, FSL = 0, 1
@@ -155,6 +156,9 @@ class Oracle:
         walls = getattr(w, "walls", None)
         if walls is not None:
             o.set_walls(walls["cells"], walls.get("delta"), walls.get("uw"))
+        surf = getattr(w, "surface", None)
+        if surf is not None:
+            o.set_surface(surf["normal"], surf["offset"])
         return o
 
     def interface_curvature(self, cell: int) -> float:
@@ -180,6 +184,16 @@ class Oracle:
                                  None if d is None else _dptr(d), None if v is None else _dptr(v))
         if rc != 0:
             raise RuntimeError("oracle wall table rejected: " + lib().ref_error(self._h).decode())
+
+    def set_surface(self, normal, offset):
+        """Prescribed surface plane of every interface cell: normal[3, N] (unit,
+        towards the gas) and offset[N] (signed distance of the plane from the
+        node along the normal); FSL link distances delta = offset / (n . c)."""
+        nn = np.ascontiguousarray(normal, dtype=np.float64).reshape(-1)
+        dd = np.ascontiguousarray(offset, dtype=np.float64).reshape(-1)
+        assert nn.size == 3 * self.N and dd.size == self.N
+        self._surf = (nn, dd)
+        lib().ref_set_surface(self._h, _dptr(nn), _dptr(dd))
 
     def __del__(self):
         h = getattr(self, "_h", None)

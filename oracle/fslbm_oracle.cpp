@@ -31,6 +31,7 @@ struct ref_params {
   double shear_b[6];  // prescribed S^b [xx, yy, zz, xy, xz, yz]
   double sigma;       // surface tension coefficient
   int plic;           // FSL link distance from the PLIC plane
+  int hold;           // fill levels and interface masses held
 };
 
 static Params to_params(const ref_params* r) {
@@ -55,6 +56,7 @@ static Params to_params(const ref_params* r) {
   for (int i = 0; i < 6; ++i) p.shear_b[i] = r->shear_b[i];
   p.sigma = r->sigma;
   p.plic = r->plic;
+  p.hold = r->hold;
   return p;
 }
 
@@ -103,6 +105,12 @@ int ref_set_walls(void* hp, int n, const int* cells, const double* delta, const 
     h->err = e.what();
     return -1;
   }
+}
+
+// Prescribed surface: normal[3 N] (unit, towards the gas) and offset[N] of the
+// plane from each interface cell's node.
+void ref_set_surface(void* hp, const double* normal, const double* offset) {
+  static_cast<Handle*>(hp)->sim.set_surface(normal, offset);
 }
 
 void ref_destroy(void* hp) { delete static_cast<Handle*>(hp); }
@@ -286,6 +294,7 @@ int ref_window_dual(const ref_params* rp, const uint8_t* flags, const double* ft
     if (rule != fsref::FSK && rule != fsref::FSL) throw std::runtime_error("dual window: rules 0 and 1 only");
     if (s->p.plic) throw std::runtime_error("dual window: no PLIC interface position");
     if (s->p.sigma != 0.0) throw std::runtime_error("dual window: no surface tension");
+    if (s->p.hold) throw std::runtime_error("dual window: no held fills");
     for (size_t i = 0; i < (size_t)s->N; ++i)
       if (flags[i] == fsref::SOLID) throw std::runtime_error("dual window: no solid cells");
     const int N = s->N;

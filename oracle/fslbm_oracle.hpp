@@ -74,6 +74,8 @@ struct Params {
   int plic;            // FSL link distance: 0 phi - 1/2; 1 the PLIC plane; 2 the PLIC
                        // plane with the height-function normal where its columns are
                        // complete, and the height-function curvature (own or borrowed)
+  int hold;            // nonzero: fill levels and interface masses keep their values (a
+                       // surface held at a known position; with frozen classes)
 };
 
 // ---------------------------------------------------------------------------
@@ -127,6 +129,10 @@ struct Oracle {
   // point x + delta c_p and the wall velocity, where x + c_p is solid.
   bool any_solid = false;
   std::vector<int> wall_cells;
+  // A prescribed surface (with held fills): for each interface cell the unit
+  // normal towards the gas, surf_n[a*N + cell], and the signed offset of the
+  // plane from the node along it, surf_d[cell]; empty if not set.
+  std::vector<double> surf_n, surf_d;
   std::vector<double> wall_delta;  // [19][n]
   std::vector<double> wall_uvel;   // [3][19][n]
 
@@ -199,6 +205,11 @@ struct Oracle {
   // The wall table: validated against the classes (every non-solid cell with
   // a link into a solid cell listed, nothing else; delta in (0, 1] on those
   // links).  NULL delta: 1/2 (halfway); NULL velocities: resting walls.
+  void set_surface(const double* n3, const double* d) {
+    surf_n.assign(n3, n3 + (size_t)3 * N);
+    surf_d.assign(d, d + (size_t)N);
+  }
+
   void set_walls(int n, const int* cells, const double* delta, const double* uvel) {
     std::vector<int> need;
     for (int cell = 0; cell < N; ++cell) {
@@ -913,7 +924,7 @@ struct Oracle {
         // (central differences over the six axis neighbours), surface plane
         // at signed distance phi - 1/2 from the node along the normal.
         T nvec[3];
-        const bool have_normal = cd_normal(x, y, z, phix, nvec);
+        bool have_normal = cd_normal(x, y, z, phix, nvec);
         // second-order reconstruction (section 5): the FSL rules may take the
         // normal from height functions where their columns are complete
         if (p.plic == 2 && have_normal && (rule & 1)) hf_normal(x, y, z, nvec);
@@ -921,6 +932,13 @@ struct Oracle {
         // second-order interface position (section 5): the plane that cuts the
         // cell's fill fraction with the normal n (PLIC) instead of phi - 1/2
         if (p.plic && have_normal && (rule & 1)) dist = plic_offset(phix, nvec);
+        // a prescribed surface: the given plane (section 2.2: the boundary
+        // link meets it at x_b + delta c_q)
+        if (!surf_d.empty()) {
+          for (int a = 0; a < 3; ++a) nvec[a] = T(surf_n[(size_t)a * N + cell]);
+          dist = T(surf_d[cell]);
+          have_normal = true;
+        }
 
         // Laplace pressure: the boundary term takes P_b - sigma kappa (Eq.
         // freeboundary), i.e. rho_b - 3 sigma kappa
@@ -1025,8 +1043,8 @@ struct Oracle {
 
       if (iface) {
         // ---- S6 fill level and classification
-        massn[cell] = m_new;
-        phin[cell] = m_new / rho;
+        massn[cell] = p.hold ? mass[cell] : m_new;
+        phin[cell] = p.hold ? phi[cell] : m_new / rho;
         rho_c[cell] = rho;
         for (int a = 0; a < 3; ++a) u_c[(size_t)a * N + cell] = u[a];
       }
@@ -1037,7 +1055,7 @@ struct Oracle {
     phi.swap(phin);
 
     listF.clear(); listE.clear(); listEp.clear(); listNI.clear(); listNL.clear();
-    if (!freeze) convert();
+    if (!freeze && !p.hold) convert();  // a held surface keeps its classes
     ++steps_done;
   }
 

@@ -40,6 +40,8 @@ struct fslbm_ctx {
   const double* wdelta = nullptr;
   const double* wuw = nullptr;
   int nwall = -1;           // -1: no table set
+  const double* surf_n = nullptr;   // prescribed surface (caller's device memory, fslbm_set_surface)
+  const double* surf_d = nullptr;
   double* acc;
   int32_t* err;
   int32_t* cnt;
@@ -549,7 +551,8 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.thr_hi = c->thr_hi;
     s.thr_lo = c->thr_lo;
     s.step = c->step;
-    s.freeze = c->p.freeze ? 1 : 0;
+    s.freeze = (c->p.freeze || c->p.hold_fill) ? 1 : 0;  // a held surface keeps its classes
+    s.hold = c->p.hold_fill ? 1 : 0;
     s.cpr = 0;
     s.pairs = c->pairs;
     s.quad = c->quad;
@@ -561,6 +564,8 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.wdelta = c->wdelta;
     s.wuw = c->wuw;
     s.nwall = c->nwall > 0 ? c->nwall : 0;
+    s.surf_n = c->surf_n;
+    s.surf_d = c->surf_d;
     HIPCHK(c, sweep_box(c, s), "extent");
     ConvArgs& v = L.conv;
     v.c = c->com;
@@ -600,7 +605,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     if (s.nwall > 0) HIPCHK(c, launch_wall(L, c->p.precision), "wall launch");
     if (c->kappa) HIPCHK(c, launch_curvature(L), "curvature launch");
     HIPCHK(c, launch_iface(L, c->p.precision, rule), "interface launch");
-    if (!c->p.freeze) HIPCHK(c, launch_convert(L, c->p.precision), "conversion launch");
+    if (!s.freeze) HIPCHK(c, launch_convert(L, c->p.precision), "conversion launch");
     c->cur = b;
     c->step += 1;
     if (c->check_every > 0 && c->step % c->check_every == 0) {
@@ -875,6 +880,10 @@ fslbm_status window_checks(fslbm_ctx* c, int32_t T, int32_t K) {
     c->last_error = "the adjoint window does not support solid cells";
     return FSLBM_E_UNSUPPORTED;
   }
+  if (c->p.hold_fill || c->com.surface) {
+    c->last_error = "the adjoint window does not support held fills or a prescribed surface";
+    return FSLBM_E_UNSUPPORTED;
+  }
   return FSLBM_OK;
 }
 
@@ -1004,6 +1013,23 @@ fslbm_status fslbm_set_walls(fslbm_ctx* c, int32_t n, const int32_t* cells, cons
   c->wuw = wall_u;
   c->nwall = n;
   c->com.solid = n > 0 ? 1 : 0;
+  return FSLBM_OK;
+}
+
+fslbm_status fslbm_set_surface(fslbm_ctx* c, const double* normal, const double* offset) {
+  if (!c) return FSLBM_E_INVALID;
+  if (!normal || !offset) {
+    c->surf_n = c->surf_d = nullptr;
+    c->com.surface = 0;
+    return FSLBM_OK;
+  }
+  if (!c->p.hold_fill) {
+    c->last_error = "a prescribed surface needs params.hold_fill (the surface must stay where it is given)";
+    return FSLBM_E_INVALID;
+  }
+  c->surf_n = normal;
+  c->surf_d = offset;
+  c->com.surface = 1;
   return FSLBM_OK;
 }
 

@@ -550,8 +550,8 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     const double rho = SH ? 1.0 + (double)rho_s : (double)rho_s;
     bool filled = false, emptied = false;
     if (lead) {
-      a.mass[idx] = m_new;
-      a.phi_out[idx] = m_new / rho;
+      a.mass[idx] = a.hold ? m_old : m_new;
+      a.phi_out[idx] = a.hold ? phix : m_new / rho;
       a.aux_rho[idx] = rho;
       a.aux_u[idx] = (double)u[0];
       a.aux_u[N + idx] = (double)u[1];

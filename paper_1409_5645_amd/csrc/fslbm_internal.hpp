@@ -24,6 +24,7 @@ struct Common {
   double rho_gas;          // gas density rho_b (actual, not in storage convention)
   int plic;                // FSL link distances from the PLIC plane instead of phi - 1/2
   int solid;               // solid cells present (SweepArgs carries their wall table)
+  int surface;             // a prescribed surface plane per interface cell (SweepArgs surf_n, surf_d)
 };
 
 template <class R>
@@ -57,6 +58,7 @@ struct SweepArgs {
   double thr_hi, thr_lo;
   int step;
   int freeze;
+  int hold;   // fill levels and interface masses held
   int cpr;   // blocks per lattice row (set by the launcher)
   // box of rows the sweep launches (box != 0): y in [by0, by0 + bny), z in
   // [bz0, bz0 + bnz); every liquid cell lies inside it.  0: every row.
@@ -81,6 +83,10 @@ struct SweepArgs {
   // solid walls: ascending list of the non-solid cells next to a solid cell,
   // per listed cell i and link p the wall distance delta[p*nwall + i] and
   // velocity uw[(a*19 + p)*nwall + i] of the wall point x + delta c_p
+  // prescribed surface: unit normal towards the gas [3][N] and plane offset
+  // from the node [N] of the interface cells (caller's device memory)
+  const double* surf_n;
+  const double* surf_d;
   const int32_t* wcells;
   const double* wdelta;
   const double* wuw;

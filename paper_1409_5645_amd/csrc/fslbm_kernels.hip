@@ -129,7 +129,9 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
                                                 typename F::R (&u)[3], const Nbr& nb,
                                                 const typename F::S* __restrict__ fin, double drho,
                                                 const uint8_t* __restrict__ flags = nullptr,
-                                                const double* __restrict__ phi = nullptr) {
+                                                const double* __restrict__ phi = nullptr,
+                                                const double* __restrict__ surf_n = nullptr,
+                                                const double* __restrict__ surf_d = nullptr) {
   using R = typename F::R;
   constexpr bool SH = F::shifted;
   const Consts<R>& k = pick_consts<R>(cm);
@@ -165,7 +167,7 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
     const double gy = 0.5 * (phi_seen(d, 4) - phi_seen(d, 3));
     const double gz = 0.5 * (phi_seen(d, 6) - phi_seen(d, 5));
     const double nrm2 = (gx * gx + gy * gy) + gz * gz;
-    const bool have_n = nrm2 > 0.0;
+    bool have_n = nrm2 > 0.0;
     double nv[3] = {0.0, 0.0, 0.0};
     if (have_n) {
       const double nrm = sqrt(nrm2);
@@ -179,6 +181,19 @@ __device__ __forceinline__ double iface_compute(IfaceData<F>& d, const Common& c
       // with the height-function normal where its columns are complete
       if (cm.plic == 2 && have_n) hf_normal(cm.grid, nb.x, nb.y, nb.z, flags, phi, nv);
       if (cm.plic && have_n) dist = plic_plane_offset(d.phix, nv);
+    }
+    if constexpr (EXTRA) {
+      // a prescribed surface: the given plane (section 2.2: each boundary link
+      // meets it at x_b + delta c_q)
+      if (cm.surface) {
+        const size_t ci = (size_t)nb.x + (size_t)cm.grid.nx * ((size_t)nb.y + (size_t)cm.grid.ny * (size_t)nb.z);
+        const size_t Nn = (size_t)cm.grid.N;
+        nv[0] = surf_n[ci];
+        nv[1] = surf_n[Nn + ci];
+        nv[2] = surf_n[2 * Nn + ci];
+        dist = surf_d[ci];
+        have_n = true;
+      }
     }
     // ---- moments of time t from the own post-collision populations
     R rho_t, u_t[3];
@@ -316,7 +331,8 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? ((EXTRA || (RU
     // ---- phase 2: interface treatment and collision
     R rho_s, u[3];
     const double drho = (EXTRA && a.c.sigma != 0.0) ? a.kappa[i] : 0.0;
-    const double m_new = iface_compute<F, RULE, EXTRA>(d, a.c, rho_s, u, n, fin, drho, a.flags, a.phi_in);
+    const double m_new = iface_compute<F, RULE, EXTRA>(d, a.c, rho_s, u, n, fin, drho, a.flags, a.phi_in, a.surf_n,
+                                                       a.surf_d);
     // ---- phase 3: populations, fill level and classification (FP64 bookkeeping)
 #pragma unroll
     for (int q = 0; q < Q; ++q) F::store(fout + (size_t)q * N + idx, d.f[q], a.c.scale);
@@ -328,8 +344,8 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? ((EXTRA || (RU
       for (int c = 0; c < 3; ++c) ru[(unsigned)c * cap + (unsigned)i] = u[c];
       a.rec_rho[i] = rho;
     }
-    a.mass[idx] = m_new;
-    a.phi_out[idx] = m_new / rho;
+    a.mass[idx] = a.hold ? d.m : m_new;
+    a.phi_out[idx] = a.hold ? d.phix : m_new / rho;
     a.aux_rho[idx] = rho;
     a.aux_u[idx] = (double)u[0];
     a.aux_u[N + idx] = (double)u[1];
@@ -829,7 +845,8 @@ static void iface_form(const StepLaunch& L, int rule) {
   // the interface count is on the device: enough one-wavefront blocks for
   // every cell up to IFACE_GRID * IBLOCK, grid-stride beyond
   const unsigned nb = std::min<unsigned>(IFACE_GRID, (unsigned)((L.sweep.c.grid.N + IBLOCK - 1) / IBLOCK));
-  const bool extra = L.sweep.c.moving || L.sweep.c.sigma != 0.0 || L.sweep.c.plic || L.sweep.c.solid;
+  const bool extra =
+      L.sweep.c.moving || L.sweep.c.sigma != 0.0 || L.sweep.c.plic || L.sweep.c.solid || L.sweep.c.surface;
   if (L.sweep.rec_f) {
     // a window step (rules 0 and 1): the list is fixed and its length (rec_cap) known here
     const unsigned nbr = std::min<unsigned>(nb, (unsigned)((L.sweep.rec_cap + IBLOCK - 1) / IBLOCK));

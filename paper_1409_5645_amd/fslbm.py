@@ -23,7 +23,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 GAS, INTERFACE, LIQUID = 0, 1, 2
 STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "DEVICE", 4: "UNSTABLE", 5: "INVARIANT", 6: "CAPACITY"}
 FIELDS = ("rho", "u", "phi", "flags", "f", "mass", "rho_c", "u_c")
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class FslbmError(RuntimeError):
@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("conv_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32), ("freeze", ctypes.c_int32),
                 ("wall_u", (ctypes.c_double * 3) * 6), ("shear_b", ctypes.c_double * 6),
                 ("sigma", ctypes.c_double), ("plic", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("u_max", ctypes.c_double)]
+                ("u_max", ctypes.c_double), ("hold_fill", ctypes.c_int32)]
 
 
 class Buffers(ctypes.Structure):
@@ -51,6 +51,7 @@ class Buffers(ctypes.Structure):
 
 EXPORTS = ("fslbm_workspace_size", "fslbm_init", "fslbm_init_static", "fslbm_set_equilibrium", "fslbm_set_state", "fslbm_step",
            "fslbm_fields", "fslbm_stats", "fslbm_conversions", "fslbm_timing", "fslbm_set_forcing", "fslbm_set_walls",
+           "fslbm_set_surface",
            "fslbm_window_workspace_size", "fslbm_window_forward", "fslbm_window_backward", "fslbm_window_info",
            "fslbm_window_destroy", "fslbm_destroy", "fslbm_last_error")
 
@@ -78,6 +79,7 @@ def lib():
         L.fslbm_timing.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
         L.fslbm_set_forcing.argtypes = [vp, dp, ctypes.c_double]
         L.fslbm_set_walls.argtypes = [vp, i32, vp, vp, vp]
+        L.fslbm_set_surface.argtypes = [vp, vp, vp]
         L.fslbm_window_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.fslbm_window_forward.argtypes = [vp, i32, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.fslbm_window_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, dp]
@@ -103,13 +105,14 @@ def make_params(p, precision=FP64, freeze=False, fp16_scale_log2=13, check_every
                   ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*[float(v) for v in face])
                                                  for face in getattr(p, "wall_u", ((0.0, 0.0, 0.0),) * 6)]),
                   (ctypes.c_double * 6)(*[float(v) for v in getattr(p, "shear_b", (0.0,) * 6)]),
-                  float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)), int(check_every), float(u_max))
+                  float(getattr(p, "sigma", 0.0)), int(getattr(p, "plic", 0)), int(check_every), float(u_max),
+                  int(getattr(p, "hold", 0)))
 
 
 class Sim:
     """One simulation on a GPU.  Buffers are torch tensors on `device`."""
 
-    def __init__(self, params, flags, precision="fp64", device="cuda:0", stream=None, freeze=False,
+    def __init__(self, params, flags, precision="fp64", device="cuda:0", stream=None, freeze=None,
                  fp16_scale_log2=13, check_every=0, u_max=0.0, static_workspace=False):
         import torch
         if not torch.cuda.is_available():
@@ -120,6 +123,8 @@ class Sim:
         self.params = params
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.N = N = params.nx * params.ny * params.nz
+        if freeze is None:  # a held surface implies frozen classes
+            freeze = bool(getattr(params, "hold", 0))
         self.cp = make_params(params, self.precision, freeze, fp16_scale_log2, check_every, u_max)
         ws = ctypes.c_size_t()
         self._check(L.fslbm_workspace_size(ctypes.byref(self.cp), ctypes.byref(ws)), None)
@@ -167,7 +172,19 @@ class Sim:
         walls = getattr(w, "walls", None)
         if walls is not None:
             s.set_walls(walls["cells"], walls.get("delta"), walls.get("uw"))
+        surf = getattr(w, "surface", None)
+        if surf is not None:
+            s.set_surface(surf["normal"], surf["offset"])
         return s
+
+    def set_surface(self, normal, offset):
+        """Prescribed surface plane of the interface cells: normal[3, N]
+        (unit, towards the gas) and offset[N] (plane offset from the node);
+        needs params.hold.  The device copies are kept by this object."""
+        self._surface = (self._dev(normal), self._dev(offset))
+        self.torch.cuda.synchronize(self.device)
+        self._check(lib().fslbm_set_surface(self.ctx, self._surface[0].data_ptr(), self._surface[1].data_ptr()),
+                    self.ctx)
 
     def set_walls(self, cells, delta=None, uw=None):
         """Wall table of the solid cells (class 3): ascending non-solid cells

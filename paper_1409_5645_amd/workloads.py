@@ -57,6 +57,7 @@ class Params:
     shear_b: tuple = (0.0,) * 6               # prescribed S^b [xx, yy, zz, xy, xz, yz]
     sigma: float = 0.0                        # surface tension coefficient
     plic: int = 0                             # FSL link distance from the PLIC plane
+    hold: int = 0                             # fill levels and interface masses held (with frozen classes)
 
     @property
     def n_cells(self) -> int:
@@ -76,6 +77,10 @@ class Workload:
     # cell, "delta": float64[19, n] wall point x + delta c_p on link p,
     # "uw": float64[3, 19, n] wall velocity}; None without solid cells
     walls: dict | None = None
+    # a prescribed surface (with params.hold): {"normal": float64[3, N] unit
+    # normal towards the gas, "offset": float64[N] signed distance of the plane
+    # from the node along it}, read at interface cells; None otherwise
+    surface: dict | None = None
 
     def velocity(self) -> np.ndarray:
         if self.u is None:
@@ -383,14 +388,21 @@ def _area_below_line(slope: float, c: float, i: int, k: int) -> float:
 
 
 def skew_film(H: float = 8.0, slope: float = 0.25, tau: float = 2.0, g0: float = 1e-4, H0: float = 4.0,
-              Lambda: float = 0.25, plic: int = 0, wall: float = 3.3) -> Workload:
+              Lambda: float = 0.25, plic: int = 0, wall: float = 3.3, surface: bool = False) -> Workload:
     """Gravity-driven film on a wall rotated by atan(slope) against the lattice
     (the rotated planar film flow of section 4.3): a solid band below
     zeta = z - slope x = wall, a liquid film of normal thickness H above it,
     gas beyond; x, y, z periodic (nx = nz / slope, ny = 1); gravity
     g0 (H0/H)^3 along the wall (constant Reynolds number).  Exact fills of the
     plane surface; uniform density.  meta["profile"](n) is the steady
-    half-Poiseuille velocity along the wall at normal distance n."""
+    half-Poiseuille velocity along the wall at normal distance n.
+
+    surface=True: the surface held at its exact plane (params.hold) and given
+    to the step (Workload.surface).  Cells are classed by where their node
+    lies: a node below the plane is fluid, and a fluid node with a D3Q19
+    neighbour beyond the plane is an interface (boundary) node -- the
+    boundary node of section 2.2, whose boundary links meet the plane at
+    0 <= delta <= 1."""
     ca = 1.0 / np.hypot(1.0, slope)
     hz = H / ca
     nz = int(np.ceil(wall + hz + max(6.0, hz))) + 1
@@ -407,16 +419,31 @@ def skew_film(H: float = 8.0, slope: float = 0.25, tau: float = 2.0, g0: float =
                 continue
             base = (k + 0.5 - slope * (i + 0.5)) - zeta[k, i]      # the periodic image of the bands
             fill[k, i] = _area_below_line(slope, wall + hz + base, i, k)
-    cls = np.where(fill >= 1.0, LIQUID, np.where(fill <= 0.0, GAS, INTERFACE)).astype(np.uint8)
-    cls[solid] = SOLID
+    if surface:
+        p = dataclasses.replace(p, hold=1)
+        below = (zeta < wall + hz) & ~solid            # node below the plane
+        cls = np.where(below, LIQUID, GAS).astype(np.uint8)
+        cls[solid] = SOLID
+        fill = np.where(below, np.maximum(fill, 0.5), 0.0)
+    else:
+        cls = np.where(fill >= 1.0, LIQUID, np.where(fill <= 0.0, GAS, INTERFACE)).astype(np.uint8)
+        cls[solid] = SOLID
     t3 = cls[:, None, :].copy()
     promote = (t3 == LIQUID) & _shift_any(t3 == GAS, p.periodic)
     t3[promote] = INTERFACE
+    if surface:
+        fill[(t3[:, 0, :] == LIQUID)] = 1.0
     N = p.n_cells
+    surf = None
+    if surface:
+        nrm = np.array([-slope, 0.0, 1.0]) * ca
+        off = (wall + hz - zeta) * ca                   # plane above the node: positive
+        surf = {"normal": np.repeat(nrm[:, None], N, axis=1),
+                "offset": np.broadcast_to(off[:, None, :], (nz, 1, nx)).reshape(-1).copy()}
     nu = (tau - 0.5) / 3.0
     zflat = np.broadcast_to(zeta[:, None, :], (nz, 1, nx)).reshape(-1)
     return Workload(name="skew_film", params=p, flags=t3.reshape(-1), rho=np.full(N, p.rho_gas), u=None,
-                    fill=fill[:, None, :].reshape(-1), walls=walls,
+                    fill=fill[:, None, :].reshape(-1), walls=walls, surface=surf,
                     meta={"H": H, "slope": slope, "g": g, "nu": nu, "tangent": t,
                           "normal_dist": (zflat - wall) * ca,
                           "profile": lambda n, Hr=H: g / nu * (Hr * n - n * n / 2.0)})

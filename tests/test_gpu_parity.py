@@ -746,3 +746,23 @@ def test_sweep_row_box_matches_full_sweep(fs, monkeypatch, precision, axis):
             assert np.array_equal(got[k], ref[k]), f"K={K}: {k}"
         for k in lref:
             np.testing.assert_array_equal(lists[k], lref[k], err_msg=f"K={K}: list {k}")
+
+
+@pytest.mark.parametrize("rule", [1, 0, 3])
+def test_held_surface_rotated_film_parity(fs, oracle_mod, rule):
+    """The rotated film with the surface held at its exact plane (prescribed
+    surface, held fills, CLI walls): FP64 populations equal to the oracle's,
+    classes and fills unchanged, every 100 steps over 300."""
+    w = W.skew_film(H=8.0, surface=True)
+    _say(f"case held-surface rotated film rule {rule}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w)
+    for it in range(3):
+        o.step(100, rule)
+        s.step(100, rule)
+        _compare(o, s, f"held film step {100 * (it + 1)}", lists=False)
+    g = s.fields(("flags", "phi"))
+    assert (g["flags"] == w.flags).all()
+    iface = w.flags == W.INTERFACE
+    assert np.array_equal(g["phi"][iface], w.fill[iface])
+    s.close()
