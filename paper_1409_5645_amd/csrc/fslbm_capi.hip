@@ -26,8 +26,7 @@ struct fslbm_ctx {
   int cur = 0;          // index of the buffers holding time t
   int step = 0;         // steps done (also the epoch stamp of the next step)
   // workspace carve-out
-  double* aux_rho;
-  double* aux_u;
+  double* aux;  // [N][4] collision density and velocity of interface cells
   int32_t *f_epoch, *new_epoch, *recv_epoch, *conv_epoch;
   int32_t *listF, *listE, *listEP, *listNI, *listNL, *listR, *listI;
   int32_t* counters;    // 2 sets of NCOUNT
@@ -78,7 +77,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t aux_rho, aux_u, epochs[4], lists[7], counters, scalars, extent, wall_t, kappa, khf, total;
+  size_t aux, epochs[4], lists[7], counters, scalars, extent, wall_t, kappa, khf, total;
 };
 
 // Moving-wall bounce-back terms per face (x-, x+, y-, y+, z-, z+) and link:
@@ -103,10 +102,8 @@ void wall_table(const fslbm_params& p, double out[6 * Q]) {
 Layout layout(size_t N, bool kappa, bool hf) {
   Layout L{};
   size_t o = 0;
-  L.aux_rho = o;
-  o = align_up(o + 8 * N);
-  L.aux_u = o;
-  o = align_up(o + 24 * N);
+  L.aux = o;
+  o = align_up(o + 32 * N);
   for (int i = 0; i < 4; ++i) {
     L.epochs[i] = o;
     o = align_up(o + 4 * N);
@@ -278,8 +275,7 @@ fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* work
     c->u_max2 = um * um;
   }
   char* w = (char*)workspace;
-  c->aux_rho = (double*)(w + L.aux_rho);
-  c->aux_u = (double*)(w + L.aux_u);
+  c->aux = (double*)(w + L.aux);
   int32_t** ep[4] = {&c->f_epoch, &c->new_epoch, &c->recv_epoch, &c->conv_epoch};
   for (int i = 0; i < 4; ++i) *ep[i] = (int32_t*)(w + L.epochs[i]);
   int32_t** ls[7] = {&c->listF, &c->listE, &c->listEP, &c->listNI, &c->listNL, &c->listR, &c->listI};
@@ -407,8 +403,7 @@ static InitArgs init_args(fslbm_ctx* c) {
   a.flags = c->flags;
   a.mass = c->mass;
   a.phi = c->phi[c->cur];
-  a.aux_rho = c->aux_rho;
-  a.aux_u = c->aux_u;
+  a.aux = c->aux;
   return a;
 }
 
@@ -540,8 +535,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.mass = c->mass;
     s.phi_in = c->phi[a];
     s.phi_out = c->phi[b];
-    s.aux_rho = c->aux_rho;
-    s.aux_u = c->aux_u;
+    s.aux = c->aux;
     s.f_epoch = c->f_epoch;
     s.listF = c->listF;
     s.listE = c->listE;
@@ -573,8 +567,7 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     v.flags = c->flags;
     v.mass = c->mass;
     v.phi_out = c->phi[b];
-    v.aux_rho = c->aux_rho;
-    v.aux_u = c->aux_u;
+    v.aux = c->aux;
     v.f_epoch = c->f_epoch;
     v.new_epoch = c->new_epoch;
     v.recv_epoch = c->recv_epoch;
@@ -631,8 +624,7 @@ fslbm_status fslbm_fields(fslbm_ctx* c, uint32_t mask, void* const* dst) {
   a.flags = c->flags;
   a.mass = c->mass;
   a.phi = c->phi[c->cur];
-  a.aux_rho = c->aux_rho;
-  a.aux_u = c->aux_u;
+  a.aux = c->aux;
   auto sel = [&](int bit) { return ((mask >> bit) & 1u) ? dst[bit] : nullptr; };
   a.rho_out = (double*)sel(0);
   a.u_out = (double*)sel(1);
@@ -777,7 +769,7 @@ struct fslbm_window {
   void* own = nullptr;
   double* phic = nullptr;
   double *part_sweep = nullptr, *part_iface = nullptr, *grads = nullptr;
-  double *aux_rho = nullptr, *aux_u = nullptr;  // recompute steps (the context's stay untouched)
+  double* aux = nullptr;  // recompute steps (the context's stays untouched)
   int32_t* counters = nullptr;
   int32_t* fixed_count = nullptr;  // counter set whose interface count is n_i (for the fixed list)
   int32_t* listI_fwd = nullptr;
@@ -792,7 +784,7 @@ struct WinLayout {
   size_t ckpt, state_bytes, st_m, st_phi;
   size_t hot[2], hot_m;
   size_t rec, rec_bytes, rc_f, rc_own, rc_phi, rc_m, rc_ui, rc_rho;
-  size_t ncls, nslot, lam[2], lam_m, lphi[2], own, phic, part_sweep, part_iface, grads, aux_rho, aux_u, counters,
+  size_t ncls, nslot, lam[2], lam_m, lphi[2], own, phic, part_sweep, part_iface, grads, aux, counters,
       fixed_count, listI_fwd;
   size_t total;
 };
@@ -848,8 +840,7 @@ WinLayout win_layout(const Grid& g, int precision, int T, int K, int n_i) {
   L.part_sweep = take(3 * 8 * (size_t)adj_sweep_slots(g));
   L.part_iface = take(4 * 8 * (size_t)adj_iface_blocks(n_i));
   L.grads = take(4 * 8);
-  L.aux_rho = take(8 * N);
-  L.aux_u = take(24 * N);
+  L.aux = take(32 * N);
   L.counters = take(2 * NCOUNT * sizeof(int32_t));
   L.fixed_count = take(NCOUNT * sizeof(int32_t));
   L.listI_fwd = take(4 * N);
@@ -928,8 +919,7 @@ hipError_t window_step(fslbm_window* w, const fslbm_window::State& A, const fslb
   s.phi_in = A.phi;
   s.phi_out = B.phi;
   // the forward pass leaves the context's collision moments at the final state
-  s.aux_rho = forward_pass ? c->aux_rho : w->aux_rho;
-  s.aux_u = forward_pass ? c->aux_u : w->aux_u;
+  s.aux = forward_pass ? c->aux : w->aux;
   s.f_epoch = c->f_epoch;
   s.listF = c->listF;
   s.listE = c->listE;
@@ -1145,8 +1135,7 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   w->part_sweep = (double*)(wsp + L.part_sweep);
   w->part_iface = (double*)(wsp + L.part_iface);
   w->grads = (double*)(wsp + L.grads);
-  w->aux_rho = (double*)(wsp + L.aux_rho);
-  w->aux_u = (double*)(wsp + L.aux_u);
+  w->aux = (double*)(wsp + L.aux);
   w->counters = (int32_t*)(wsp + L.counters);
   w->fixed_count = (int32_t*)(wsp + L.fixed_count);
   w->listI_fwd = (int32_t*)(wsp + L.listI_fwd);

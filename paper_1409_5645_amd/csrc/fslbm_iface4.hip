@@ -21,6 +21,7 @@
 #include "fslbm_stencil.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace fslbm {
 
@@ -132,9 +133,15 @@ __device__ __forceinline__ void quad_moments(const R (&A)[3], const R (&B)[3], R
 // u_b).  Both links of a pair share e+ (it depends on (c.u)^2) and n+ (on the
 // pair's sum); only the link with n.c_o > 0 can take the FSL row, so a pair
 // needs one FSL evaluation at most.
-template <class R, int RULE>
+// d . v for an integer direction and a geometry vector of type G
+template <class G>
+__device__ __forceinline__ G idot(const int (&d)[3], const G (&v)[3]) {
+  return ((G)d[0] * v[0] + (G)d[1] * v[1]) + (G)d[2] * v[2];
+}
+
+template <class R, int RULE, class G>
 __device__ __forceinline__ void rebuild_pair(R& fA, R& fB, R oA, R oB, bool gA, bool gB, const int (&d)[3], R w,
-                                             R w3, bool have_n, const double (&nv)[3], double dist, R rho_t,
+                                             R w3, bool have_n, const G (&nv)[3], G dist, R rho_t,
                                              R rho0_t, const R (&u_t)[3], R usq_t, const Consts<R>& k, bool incomp,
                                              bool stokes, const R (&Sb)[6], bool stress) {
   const R dR[3] = {R(d[0]), R(d[1]), R(d[2])};
@@ -154,14 +161,14 @@ __device__ __forceinline__ void rebuild_pair(R& fA, R& fB, R oA, R oB, bool gA, 
   }
   if constexpr ((RULE & 1) != 0) {
     // link A: o = B, c_o = -d, n.c_o = -(d.n); link B: o = A, n.c_o = d.n
-    const double dn = ddot(d, nv);
-    const bool useA = gA && !gB && have_n && -dn > 0.0;
-    const bool useB = gB && !gA && have_n && dn > 0.0;
+    const G dn = idot(d, nv);
+    const bool useA = gA && !gB && have_n && -dn > G(0.0);
+    const bool useB = gB && !gA && have_n && dn > G(0.0);
     if (useA || useB) {
-      const double nc = useA ? -dn : dn;
-      double dl = dist / nc;
-      if (dl < 0.0) dl = 0.0;
-      if (dl > 1.0) dl = 1.0;
+      const G nc = useA ? -dn : dn;
+      G dl = dist / nc;
+      if (dl < G(0.0)) dl = G(0.0);
+      if (dl > G(1.0)) dl = G(1.0);
       const R delta = (R)dl;
       const R own_o = useA ? oB : oA, own_q = useA ? oA : oB, f_o = useA ? fB0 : fA0;
       const R e_o_t = e_plus_w(w, cu, rho_t, rho0_t, incomp, stokes, usq_t);
@@ -185,6 +192,9 @@ template <class F, int RULE>
 __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
+  // the interface geometry (normal, link distances): FP64 in the FP64 form,
+  // FP32 in the FP32-arithmetic forms
+  using G = typename std::conditional<sizeof(R) == 8, double, float>::type;
   constexpr bool SH = F::shifted;
   const Grid g = a.c.grid;
   const int n_i = a.counters[C_I];
@@ -327,26 +337,24 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     if (gasmask) {
       // ---- interface geometry: n = -grad(phi)/|grad(phi)| by central
       // differences over the six axis neighbours (links 1..6: lanes 0, 1, 2, slot 0)
-      double psA = L.tA[0] == LIQ ? 1.0 : (L.tA[0] == GAS ? 0.0 : L.pA[0]);
-      double psB = L.tB[0] == LIQ ? 1.0 : (L.tB[0] == GAS ? 0.0 : L.pB[0]);
-      if (L.tA[0] == WALL_CLASS) psA = phix;
-      if (L.tB[0] == WALL_CLASS) psB = phix;
-      const double p1 = qbcast<0>(psA), p2 = qbcast<0>(psB);
-      const double p3 = qbcast<1>(psA), p4 = qbcast<1>(psB);
-      const double p5 = qbcast<2>(psA), p6 = qbcast<2>(psB);
-      const double gx = 0.5 * (p2 - p1);
-      const double gy = 0.5 * (p4 - p3);
-      const double gz = 0.5 * (p6 - p5);
-      const double nrm2 = (gx * gx + gy * gy) + gz * gz;
-      const bool have_n = nrm2 > 0.0;
-      double nv[3] = {0.0, 0.0, 0.0};
+      const G psA = L.tA[0] == LIQ ? G(1.0) : (L.tA[0] == GAS ? G(0.0) : (G)L.pA[0]);
+      const G psB = L.tB[0] == LIQ ? G(1.0) : (L.tB[0] == GAS ? G(0.0) : (G)L.pB[0]);
+      const G p1 = qbcast<0>(psA), p2 = qbcast<0>(psB);
+      const G p3 = qbcast<1>(psA), p4 = qbcast<1>(psB);
+      const G p5 = qbcast<2>(psA), p6 = qbcast<2>(psB);
+      const G gx = G(0.5) * (p2 - p1);
+      const G gy = G(0.5) * (p4 - p3);
+      const G gz = G(0.5) * (p6 - p5);
+      const G nrm2 = (gx * gx + gy * gy) + gz * gz;
+      const bool have_n = nrm2 > G(0.0);
+      G nv[3] = {G(0.0), G(0.0), G(0.0)};
       if (have_n) {
-        const double nrm = sqrt(nrm2);
+        const G nrm = sqrt(nrm2);
         nv[0] = -gx / nrm;
         nv[1] = -gy / nrm;
         nv[2] = -gz / nrm;
       }
-      const double dist = phix - 0.5;
+      const G dist = (G)phix - G(0.5);
       // ---- moments of time t from the own post-collision populations
       R rho_t, j_t[3], u_t[3];
       quad_moments(L.oA, L.oB, L.f0, rho_t, j_t, dI, nsl, sub);
@@ -368,9 +376,10 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
           // pull source of link kbar
           int best = -1, bx = 0, by = 0, bz = 0;
           double best_v = 0.0;
+          const double nvd[3] = {(double)nv[0], (double)nv[1], (double)nv[2]};
 #define FSLBM_QBULK(kk)                                                              \
   if ((liqmask >> OPP[kk]) & 1u) {                                                   \
-    const double cn = -cdot<kk>(nv);                                                 \
+    const double cn = -cdot<kk>(nvd);                                                \
     const double len2 = kk <= 6 ? 1.0 : 2.0;                                         \
     const double v = cn < 0.0 ? -(cn * cn) / len2 : (cn * cn) / len2;                \
     if (best < 0 || v > best_v) {                                                    \
@@ -447,18 +456,18 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
           Sd[4] = (double)(fs * M[4]);
           Sd[5] = (double)(fs * M[5]);
           // normal entry of the boundary value: n.S.n / 3; S^b = P S P + s_nn n n^T
-          const double ndg = (Sd[0] * (nv[0] * nv[0]) + Sd[1] * (nv[1] * nv[1])) + Sd[2] * (nv[2] * nv[2]);
-          const double nof = (Sd[3] * (nv[0] * nv[1]) + Sd[4] * (nv[0] * nv[2])) + Sd[5] * (nv[1] * nv[2]);
+          const double ndg = (Sd[0] * (nvd[0] * nvd[0]) + Sd[1] * (nvd[1] * nvd[1])) + Sd[2] * (nvd[2] * nvd[2]);
+          const double nof = (Sd[3] * (nvd[0] * nvd[1]) + Sd[4] * (nvd[0] * nvd[2])) + Sd[5] * (nvd[1] * nvd[2]);
           const double s_nn = (ndg + 2.0 * nof) / 3.0;
           double Sn[3];
-          Sn[0] = (Sd[0] * nv[0] + Sd[3] * nv[1]) + Sd[4] * nv[2];
-          Sn[1] = (Sd[3] * nv[0] + Sd[1] * nv[1]) + Sd[5] * nv[2];
-          Sn[2] = (Sd[4] * nv[0] + Sd[5] * nv[1]) + Sd[2] * nv[2];
-          const double kk = ((nv[0] * Sn[0] + nv[1] * Sn[1]) + nv[2] * Sn[2]) + s_nn;
+          Sn[0] = (Sd[0] * nvd[0] + Sd[3] * nvd[1]) + Sd[4] * nvd[2];
+          Sn[1] = (Sd[3] * nvd[0] + Sd[1] * nvd[1]) + Sd[5] * nvd[2];
+          Sn[2] = (Sd[4] * nvd[0] + Sd[5] * nvd[1]) + Sd[2] * nvd[2];
+          const double kk = ((nvd[0] * Sn[0] + nvd[1] * Sn[1]) + nvd[2] * Sn[2]) + s_nn;
           constexpr int IA[6] = {0, 1, 2, 0, 0, 1}, IB[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
           for (int c = 0; c < 6; ++c)
-            Sb[c] = (R)(((Sd[c] - Sn[IA[c]] * nv[IB[c]]) - nv[IA[c]] * Sn[IB[c]]) + kk * (nv[IA[c]] * nv[IB[c]]));
+            Sb[c] = (R)(((Sd[c] - Sn[IA[c]] * nvd[IB[c]]) - nvd[IA[c]] * Sn[IB[c]]) + kk * (nvd[IA[c]] * nvd[IB[c]]));
         }
       }
       if constexpr ((RULE & 4) != 0) {
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
         if (s < nsl) {
           const bool gA = (gasmask >> qa[s]) & 1u, gB = (gasmask >> (qa[s] + 1)) & 1u;
           if (gA || gB)
-            rebuild_pair<R, RULE>(L.fA[s], L.fB[s], L.oA[s], L.oB[s], gA, gB, dI[s], wq[s], w3[s], have_n, nv, dist,
+            rebuild_pair<R, RULE, G>(L.fA[s], L.fB[s], L.oA[s], L.oB[s], gA, gB, dI[s], wq[s], w3[s], have_n, nv, dist,
                                   rho_t, rho0_t, u_t, usq_t, k, incomp, stokes, Sb, stress);
         }
       }
@@ -552,10 +561,7 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     if (lead) {
       a.mass[idx] = a.hold ? m_old : m_new;
       a.phi_out[idx] = a.hold ? phix : m_new / rho;
-      a.aux_rho[idx] = rho;
-      a.aux_u[idx] = (double)u[0];
-      a.aux_u[N + idx] = (double)u[1];
-      a.aux_u[2 * (size_t)N + idx] = (double)u[2];
+      *reinterpret_cast<double4*>(a.aux + 4 * (size_t)idx) = make_double4(rho, (double)u[0], (double)u[1], (double)u[2]);
       if (!a.freeze) {
         filled = m_new > a.thr_hi * rho;
         emptied = m_new < a.thr_lo * rho;

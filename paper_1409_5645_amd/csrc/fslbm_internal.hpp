@@ -47,8 +47,9 @@ struct SweepArgs {
   double* mass;           // interface mass of time t+1
   const double* phi_in;
   double* phi_out;
-  double* aux_rho;
-  double* aux_u;
+  // collision density and velocity of the interface cells of the step, [N][4]
+  // (rho, u_x, u_y, u_z; 32 bytes per cell, one store)
+  double* aux;
   int32_t* f_epoch;
   int32_t* listF;
   int32_t* listE;
@@ -99,8 +100,7 @@ struct ConvArgs {
   uint8_t* flags;
   double* mass;
   double* phi_out;
-  double* aux_rho;
-  const double* aux_u;
+  double* aux;  // [N][4] as in SweepArgs
   int32_t* f_epoch;
   int32_t* new_epoch;
   int32_t* recv_epoch;
@@ -123,8 +123,9 @@ struct InitArgs {
   const uint8_t* flags;
   double* mass;
   double* phi;
-  double* aux_rho;
-  double* aux_u;
+  // collision density and velocity of the interface cells of the step, [N][4]
+  // (rho, u_x, u_y, u_z; 32 bytes per cell, one store)
+  double* aux;
 };
 
 struct FieldArgs {
@@ -133,8 +134,7 @@ struct FieldArgs {
   const uint8_t* flags;
   const double* mass;
   const double* phi;
-  const double* aux_rho;
-  const double* aux_u;
+  const double* aux;  // [N][4] as in SweepArgs
   double* rho_out;
   double* u_out;
   double* phi_out;

@@ -346,10 +346,7 @@ __global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? ((EXTRA || (RU
     }
     a.mass[idx] = a.hold ? d.m : m_new;
     a.phi_out[idx] = a.hold ? d.phix : m_new / rho;
-    a.aux_rho[idx] = rho;
-    a.aux_u[idx] = (double)u[0];
-    a.aux_u[N + idx] = (double)u[1];
-    a.aux_u[2 * N + idx] = (double)u[2];
+    *reinterpret_cast<double4*>(a.aux + 4 * (size_t)idx) = make_double4(rho, (double)u[0], (double)u[1], (double)u[2]);
     if (!a.freeze) {
       const bool filled = m_new > a.thr_hi * rho;
       if (filled) a.f_epoch[idx] = a.step;
@@ -467,10 +464,11 @@ __device__ void init_new_from_gas(const ConvArgs& a, int c) {
   for (int q = 1; q < Q; ++q) {
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
     if (s < 0 || a.flags[s] == GAS || a.flags[s] == SOLID) continue;
-    rs = rs + a.aux_rho[s];
-    us0 = us0 + a.aux_u[s];
-    us1 = us1 + a.aux_u[(size_t)g.N + s];
-    us2 = us2 + a.aux_u[2 * (size_t)g.N + s];
+    const double4 v = *reinterpret_cast<const double4*>(a.aux + 4 * (size_t)s);
+    rs = rs + v.x;
+    us0 = us0 + v.y;
+    us1 = us1 + v.z;
+    us2 = us2 + v.w;
     ++cnt;
   }
   const double rbar = rs / (double)cnt;
@@ -483,7 +481,7 @@ __device__ void init_new_from_gas(const ConvArgs& a, int c) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) F::store(fo + (size_t)q * g.N + c, out[q], a.c.scale);
   a.mass[c] = 0.0;
-  a.aux_rho[c] = rbar;
+  a.aux[4 * (size_t)c] = rbar;
 }
 
 template <class F>
@@ -500,7 +498,7 @@ __device__ void init_new_from_liquid(const ConvArgs& a, int c) {
     for (int q = 1; q < Q; ++q) r = r + (double)F::load(fo + (size_t)q * a.c.grid.N + c, a.c.inv_scale);
   }
   a.mass[c] = r;
-  a.aux_rho[c] = r;
+  a.aux[4 * (size_t)c] = r;
 }
 
 // One thread per (converted cell, link): a cell's 18 neighbours are handled by
@@ -548,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_commit(ConvArgs a) {
     if (i < nF) {
       const int c = a.listF[i];
       a.flags[c] = LIQ;
-      a.mass[c] = a.mass[c] - a.aux_rho[c];  // excess of a filled cell
+      a.mass[c] = a.mass[c] - a.aux[4 * (size_t)c];  // excess of a filled cell
     } else if (i < nF + nEP) {
       a.flags[a.listEP[i - nF]] = GAS;      // excess of an emptied cell: its mass
     } else if (i < nF + nEP + nNI) {
@@ -608,7 +606,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(ConvArgs a) {
       if (s >= 0 && a.conv_epoch[s] == a.step) m = m + a.mass[s];
     }
     a.mass[r] = m;
-    a.phi_out[r] = m / a.aux_rho[r];
+    a.phi_out[r] = m / a.aux[4 * (size_t)r];
   }
 }
 
@@ -669,10 +667,7 @@ __global__ __launch_bounds__(BLOCK) void k_set_equilibrium(InitArgs a, const dou
   if (t == IFACE) {
     a.phi[idx] = fill[idx];
     a.mass[idx] = fill[idx] * r;
-    a.aux_rho[idx] = r;
-    a.aux_u[idx] = u[idx];
-    a.aux_u[N + idx] = u[N + idx];
-    a.aux_u[2 * N + idx] = u[2 * N + idx];
+    *reinterpret_cast<double4*>(a.aux + 4 * idx) = make_double4(r, u[idx], u[N + idx], u[2 * N + idx]);
   }
 }
 
@@ -707,10 +702,8 @@ __global__ __launch_bounds__(BLOCK) void k_set_state(InitArgs a, const double* f
     recover_moments<R, SH>(fl, k, a.c.incomp, rs, uu);
     a.phi[idx] = fill[idx];
     a.mass[idx] = mass[idx];
-    a.aux_rho[idx] = SH ? 1.0 + (double)rs : (double)rs;
-    a.aux_u[idx] = uu[0];
-    a.aux_u[N + idx] = uu[1];
-    a.aux_u[2 * N + idx] = uu[2];
+    *reinterpret_cast<double4*>(a.aux + 4 * idx) =
+        make_double4(SH ? 1.0 + (double)rs : (double)rs, (double)uu[0], (double)uu[1], (double)uu[2]);
   }
 }
 
@@ -728,9 +721,9 @@ __global__ __launch_bounds__(BLOCK) void k_fields(FieldArgs a) {
   if (a.flags_out) a.flags_out[idx] = t;
   if (a.phi_out) a.phi_out[idx] = t == LIQ ? 1.0 : (t == IFACE ? a.phi[idx] : 0.0);
   if (a.mass_out) a.mass_out[idx] = t == IFACE ? a.mass[idx] : 0.0;
-  if (a.rhoc_out) a.rhoc_out[idx] = t == IFACE ? a.aux_rho[idx] : 0.0;
+  if (a.rhoc_out) a.rhoc_out[idx] = t == IFACE ? a.aux[4 * idx] : 0.0;
   if (a.uc_out)
-    for (int d = 0; d < 3; ++d) a.uc_out[d * N + idx] = t == IFACE ? a.aux_u[d * N + idx] : 0.0;
+    for (int d = 0; d < 3; ++d) a.uc_out[d * N + idx] = t == IFACE ? a.aux[4 * idx + 1 + d] : 0.0;
   R fl[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) fl[q] = F::load(fi + (size_t)q * N + idx, a.c.inv_scale);
