@@ -215,6 +215,8 @@ void make_constants(const fslbm_params& p, Common& com, double& thr_hi, double& 
   com.grid.px = p.periodic[0] ? 1 : 0;
   com.grid.py = p.periodic[1] ? 1 : 0;
   com.grid.pz = p.periodic[2] ? 1 : 0;
+  com.grid.rx = grid_recip(p.nx);
+  com.grid.ry = grid_recip(p.ny);
   thr_hi = 1.0 + p.conv_eps;
   thr_lo = -p.conv_eps;
 }

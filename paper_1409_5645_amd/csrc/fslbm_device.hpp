@@ -286,7 +286,13 @@ __device__ __forceinline__ void recover_moments(const R f[Q], const Consts<R>& k
 struct Grid {
   int nx, ny, nz, N;
   int px, py, pz;
+  unsigned rx, ry;  // floor(2^32 / nx), floor(2^32 / ny) (2^32 - 1 for 1): see coords
 };
+
+// floor(2^32 / d) for d >= 2, 2^32 - 1 for d = 1: the reciprocal coords divides by
+inline unsigned grid_recip(int d) {
+  return d <= 1 ? 0xffffffffu : (unsigned)(4294967296ull / (unsigned long long)d);
+}
 
 // coordinate one step along an axis; -1 if beyond a wall
 __device__ __forceinline__ int step_axis(int c, int d, int n, int per) {
@@ -305,11 +311,25 @@ __device__ __forceinline__ int neighbor(const Grid& g, int x, int y, int z, int 
   return sx + g.nx * (sy + g.ny * sz);
 }
 
+// n / d and n % d for 0 <= n < 2^31 with m = grid_recip(d): since
+// n / d - 1 < n m / 2^32 <= n / d, the high word of n m is the quotient or one
+// less, and one comparison of the remainder fixes it
+__device__ __forceinline__ unsigned divmod_recip(unsigned n, unsigned d, unsigned m, unsigned& r) {
+  unsigned q = __umulhi(n, m);
+  r = n - q * d;
+  if (r >= d) {
+    q += 1u;
+    r -= d;
+  }
+  return q;
+}
+
 __device__ __forceinline__ void coords(const Grid& g, int idx, int& x, int& y, int& z) {
-  x = idx % g.nx;
-  int r = idx / g.nx;
-  y = r % g.ny;
-  z = r / g.ny;
+  unsigned rx, ry;
+  const unsigned row = divmod_recip((unsigned)idx, (unsigned)g.nx, g.rx, rx);
+  z = (int)divmod_recip(row, (unsigned)g.ny, g.ry, ry);
+  x = (int)rx;
+  y = (int)ry;
 }
 
 }  // namespace fslbm

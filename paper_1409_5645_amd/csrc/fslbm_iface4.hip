@@ -166,7 +166,9 @@ __device__ __forceinline__ void rebuild_pair(R& fA, R& fB, R oA, R oB, bool gA, 
     const bool useB = gB && !gA && have_n && dn > G(0.0);
     if (useA || useB) {
       const G nc = useA ? -dn : dn;
-      G dl = dist / nc;
+      G dl;
+      if constexpr (sizeof(G) == 8) dl = dist / nc;
+      else dl = dist * __builtin_amdgcn_rcpf(nc);  // FP32 geometry: hardware reciprocal (1 ulp)
       if (dl < G(0.0)) dl = G(0.0);
       if (dl > G(1.0)) dl = G(1.0);
       const R delta = (R)dl;
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
   const int sub = (int)threadIdx.x & (QUAD - 1);
   const int nsl = sub == 0 ? 3 : 2;  // pair slots of this lane
   const bool lead = sub == 0;        // lane that stores the cell's scalars
-  int dI[3][3], qa[3];
+  int dI[3][3], qa[3], lo[3];
   R wq[3], w3[3];
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -216,6 +218,7 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     qa[s] = 2 * p + 1;
     wq[s] = R(p < 3 ? WD[1] : WD[7]);
     w3[s] = R(p < 3 ? W3D[1] : W3D[7]);
+    lo[s] = dI[s][0] + g.nx * (dI[s][1] + g.ny * dI[s][2]);  // index offset of direction d
   }
   // Chunks of QCELLS consecutive list entries.  Workgroups go to the eight
   // XCDs round robin (workgroup b to XCD b mod 8); with a.quad == 2 the chunks
@@ -235,22 +238,27 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     const int idx = a.listI[i];
     Nbr n;
     coords(g, idx, n.x, n.y, n.z);
-    n.xm = step_axis(n.x, -1, g.nx, g.px);
-    n.xp = step_axis(n.x, 1, g.nx, g.px);
-    n.ym = step_axis(n.y, -1, g.ny, g.py);
-    n.yp = step_axis(n.y, 1, g.ny, g.py);
-    n.zm = step_axis(n.z, -1, g.nz, g.pz);
-    n.zp = step_axis(n.z, 1, g.nz, g.pz);
-    // ---- loads.  Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q); beyond a wall
-    // halfway bounce-back f_q(x) = ft_qbar(x).  Link A (c = d) pulls from
-    // x - d, link B (c = -d) from x + d.
-    QuadLinks<R> L;
+    // ---- pull sources: link A (c = d) pulls from x - d, link B (c = -d)
+    // from x + d; -1 beyond a wall.  A cell off every face of the lattice
+    // (no wall, no periodic wrap around it) takes them as idx -/+ the offset of d.
+    int srcA[3], srcB[3];
+    const bool inner = (unsigned)(n.x - 1) < (unsigned)(g.nx - 2) && (unsigned)(n.y - 1) < (unsigned)(g.ny - 2) &&
+                       (unsigned)(n.z - 1) < (unsigned)(g.nz - 2);
+    if (inner) {
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      L.fA[s] = L.fB[s] = L.oA[s] = L.oB[s] = R(0.0);
-      L.tA[s] = L.tB[s] = GAS;
-      L.pA[s] = L.pB[s] = 0.0;
-      if (s < nsl) {
+      for (int s = 0; s < 3; ++s) {
+        srcA[s] = idx - lo[s];
+        srcB[s] = idx + lo[s];
+      }
+    } else {
+      n.xm = step_axis(n.x, -1, g.nx, g.px);
+      n.xp = step_axis(n.x, 1, g.nx, g.px);
+      n.ym = step_axis(n.y, -1, g.ny, g.py);
+      n.yp = step_axis(n.y, 1, g.ny, g.py);
+      n.zm = step_axis(n.z, -1, g.nz, g.pz);
+      n.zp = step_axis(n.z, 1, g.nz, g.pz);
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
         const int* d = dI[s];
         const int xa = d[0] == 1 ? n.xm : (d[0] == -1 ? n.xp : n.x);
         const int ya = d[1] == 1 ? n.ym : (d[1] == -1 ? n.yp : n.y);
@@ -258,8 +266,20 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
         const int xb = d[0] == 1 ? n.xp : (d[0] == -1 ? n.xm : n.x);
         const int yb = d[1] == 1 ? n.yp : (d[1] == -1 ? n.ym : n.y);
         const int zb = d[2] == 1 ? n.zp : (d[2] == -1 ? n.zm : n.z);
-        const int sa = ((xa | ya | za) < 0) ? -1 : xa + g.nx * (ya + g.ny * za);
-        const int sb = ((xb | yb | zb) < 0) ? -1 : xb + g.nx * (yb + g.ny * zb);
+        srcA[s] = ((xa | ya | za) < 0) ? -1 : xa + g.nx * (ya + g.ny * za);
+        srcB[s] = ((xb | yb | zb) < 0) ? -1 : xb + g.nx * (yb + g.ny * zb);
+      }
+    }
+    // ---- loads.  Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q); beyond a wall
+    // halfway bounce-back f_q(x) = ft_qbar(x).
+    QuadLinks<R> L;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      L.fA[s] = L.fB[s] = L.oA[s] = L.oB[s] = R(0.0);
+      L.tA[s] = L.tB[s] = GAS;
+      L.pA[s] = L.pB[s] = 0.0;
+      if (s < nsl) {
+        const int sa = srcA[s], sb = srcB[s];
         const unsigned qA = (unsigned)qa[s], qB = qA + 1u;
         const unsigned offA = sa >= 0 ? qA * N + (unsigned)sa : qB * N + (unsigned)idx;
         const unsigned offB = sb >= 0 ? qB * N + (unsigned)sb : qA * N + (unsigned)idx;
@@ -349,10 +369,18 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
       const bool have_n = nrm2 > G(0.0);
       G nv[3] = {G(0.0), G(0.0), G(0.0)};
       if (have_n) {
-        const G nrm = sqrt(nrm2);
-        nv[0] = -gx / nrm;
-        nv[1] = -gy / nrm;
-        nv[2] = -gz / nrm;
+        if constexpr (sizeof(G) == 8) {
+          const G nrm = sqrt(nrm2);
+          nv[0] = -gx / nrm;
+          nv[1] = -gy / nrm;
+          nv[2] = -gz / nrm;
+        } else {
+          // FP32 geometry: hardware reciprocal square root (1 ulp)
+          const G r = __builtin_amdgcn_rsqf(nrm2);
+          nv[0] = -gx * r;
+          nv[1] = -gy * r;
+          nv[2] = -gz * r;
+        }
       }
       const G dist = (G)phix - G(0.5);
       // ---- moments of time t from the own post-collision populations
