@@ -138,7 +138,10 @@ __device__ __forceinline__ uint32_t h_pack(float a, float b) {
 
 // Pull of the 19 populations of a lane's cell pair (see k_sweep_h2).  Phase 1
 // issues all loads (19 pairs, 10 wavefront-edge elements); phase 2 shifts and
-// selects, so no load waits on another link's data movement.
+// selects, so no load waits on another link's data movement.  A lane whose
+// two cells are gas loads no pair: no liquid cell pulls from a gas cell (the
+// interface layer lies between them), so its values reach only gas or
+// interface slots, which the sweep's results do not use.
 // All addresses are 32-bit byte offsets from the buffer start (the two-cells
 // form is used only while 19 N populations of 2 bytes stay below 2^32 bytes),
 // so the per-link source and edge offsets are a few 32-bit scalar operations
@@ -146,15 +149,17 @@ __device__ __forceinline__ uint32_t h_pack(float a, float b) {
 template <bool WALLS>
 __device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const char* __restrict__ fb,
                                           const Grid& g, unsigned N2, const unsigned (&srow2)[9], unsigned rbase2,
-                                          unsigned xl2, int wx0, int wend, bool row_end) {
+                                          unsigned xl2, int wx0, int wend, bool row_end, bool ld) {
   uint32_t p[Q], e[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) p[q] = 0u;
 #define FSLBM_LOAD2(q)                                                                            \
   {                                                                                               \
     const unsigned ro = srow2[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                     \
     const bool wall = WALLS && ro == WALL_ROW;                                                    \
     const unsigned own_qb = (unsigned)OPP[q] * N2 + rbase2;                                       \
     const unsigned src = wall ? own_qb : (unsigned)q * N2 + ro;                                   \
-    p[q] = *reinterpret_cast<const uint32_t*>(fb + (src + xl2));                                  \
+    if (ld) p[q] = *reinterpret_cast<const uint32_t*>(fb + (src + xl2));                          \
     if (CX[q] == 1) {                                                                             \
       const unsigned eo = wx0 > 0 ? src + 2u * (unsigned)(wx0 - 1)                                \
                                   : (g.px ? src + 2u * (unsigned)(g.nx - 1) : own_qb);            \
@@ -250,10 +255,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   bool wall_rows = false;
 #pragma unroll
   for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
+  const bool ld = tt[0] != GAS || tt[1] != GAS;  // lanes past the row end read as gas
   if (!wall_rows)
-    pull_pair<false>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end);
+    pull_pair<false>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
   else
-    pull_pair<true>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end);
+    pull_pair<true>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
 
   // ---- TRT collision, Eq. (lbe2), in storage units
   const Consts<float>& k = a.c.kf;
