@@ -242,8 +242,19 @@ constexpr int IBLOCK = 64;  // interface-list kernels: one wavefront per block
 
 // EXTRA: moving walls, surface tension or the PLIC interface position present
 // (a separate instantiation, so that the plain path keeps its registers).
+// Waves per SIMD the FP32-arithmetic forms are compiled for (the FP64 form
+// takes what it needs): 4 (128 VGPRs) for the plain FSK and FSL rules, 3 (168)
+// for the rules with a boundary shear and the EXTRA variants, 2 for the EXTRA
+// variant of FSL with a prescribed shear; each without spills.
+template <class F, int RULE, bool EXTRA>
+constexpr int iface_waves() {
+  if (sizeof(typename F::R) != 4) return 1;
+  if (EXTRA) return RULE == 5 ? 2 : 3;
+  return (RULE & 6) ? 3 : 4;
+}
+
 template <class F, int RULE, bool REC = false, bool EXTRA = false>
-__global__ __launch_bounds__(IBLOCK, sizeof(typename F::R) == 4 ? ((EXTRA || (RULE & 2)) ? 3 : 4) : 1) void k_iface(SweepArgs a) {
+__global__ __launch_bounds__(IBLOCK, (iface_waves<F, RULE, EXTRA>())) void k_iface(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
   constexpr bool SH = F::shifted;

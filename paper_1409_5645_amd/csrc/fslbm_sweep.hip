@@ -12,8 +12,14 @@ constexpr int BLOCK = 256;
 // Stream/collide sweep over liquid cells, one cell per lane; a block covers a
 // chunk of one lattice row, so the row, its y and z and the source rows of
 // every link are uniform (scalar) values.  Interface cells are appended to the
-// interface list (one atomic per wavefront) and updated by k_iface; gas cells
-// are skipped.
+// interface list (one atomic per wavefront) and updated by k_iface.  A
+// wavefront without liquid cells exits; in one with liquid cells every lane of
+// the row (but solid cells) pulls, collides and stores, so that its stores
+// cover whole cache lines: a partly written line costs the memory system more
+// than a whole one.  What it writes into gas and interface cells is not a
+// result: the interface kernel, which runs after this one, overwrites the
+// interface cells, and gas populations are never read (a cell that becomes
+// interface is initialised in full).
 //
 // Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q).  A source beyond a wall gives
 // halfway bounce-back f_q(x) = ft_qbar(x).  Every load is unconditional with a
@@ -51,7 +57,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
       if (t == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)(rbase + x);
     }
   }
-  if (t != LIQ) return;
+  if (__ballot(t == LIQ) == 0) return;
+  if (x >= g.nx || t == SOLID) return;
 
   // source rows (element offsets) of the nine (c_y, c_z) combinations
   const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
@@ -109,10 +116,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
   if constexpr (WITH_U) {
-    // collision velocity, kept for the adjoint of this step
-    R* __restrict__ uo = reinterpret_cast<R*>(a.u_out);
+    // collision velocity of the liquid cells, kept for the adjoint of this step
+    if (t == LIQ) {
+      R* __restrict__ uo = reinterpret_cast<R*>(a.u_out);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) uo[(unsigned)c * N + rbase + (unsigned)x] = u[c];
+      for (int c = 0; c < 3; ++c) uo[(unsigned)c * N + rbase + (unsigned)x] = u[c];
+    }
   }
 }
 
@@ -120,9 +129,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
 // populations of a pair are 4-byte aligned loads; the x-shifted neighbour comes
 // from the adjacent lane by a wavefront shift (DPP), and the one element beyond
 // the wavefront (or the row end: periodic wrap, or bounce-back at a wall) is a
-// broadcast load from a wavefront-uniform address.  Liquid cells only; a pair
-// store also covers an interface or gas partner (k_iface, which runs after this
-// kernel, writes interface cells; gas slots are never read).
+// broadcast load from a wavefront-uniform address.  As in k_sweep, a wavefront
+// with liquid cells stores every pair of the row (but pairs with a solid cell),
+// so that its stores cover whole cache lines; its results are those of the
+// liquid cells.
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i receives lane i-1
 constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i receives lane i+1
 
@@ -268,7 +278,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   float rho_s, u[3];
   collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
   collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
-  if (liq) {
+  if (valid && tt[0] != SOLID && tt[1] != SOLID) {
     char* __restrict__ fo = reinterpret_cast<char*>(a.fout);
     const unsigned o = 2u * (rbase + (unsigned)x0);
 #pragma unroll
