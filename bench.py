@@ -44,14 +44,17 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(form: str, n_act: float, n_cells: int):
+def traffic_for(form: str, n_cells: int):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
+    if it was taken on the current kernel source and a lattice of n_cells cells
+    (else None)."""
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("source_hash") != sweep_source_hash() or form not in d.get("forms", {}):
+        return None
+    if d.get("cells") != n_cells:
         return None
     return d["forms"][form].get("bytes_per_launch")
 
@@ -352,7 +355,7 @@ def main():
 
     head = HEADLINE if HEADLINE in results else forms[-1]
     r = results[head]
-    traffic = traffic_for(head, r["active_cells"], w.params.n_cells)
+    traffic = traffic_for(head, w.params.n_cells)
     roof = {"bound": "hbm", "achieved": r["sweep_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": SWEEP_KERNEL[head],

@@ -44,14 +44,15 @@ def test_error_norms():
 
 def test_traffic_lookup(tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
-    d = {"source_hash": "abc", "forms": {"fp16s": {"bytes_per_launch": 123.0}}}
+    d = {"source_hash": "abc", "cells": 1000, "forms": {"fp16s": {"bytes_per_launch": 123.0}}}
     (tmp_path / "profiles" / "sweep_traffic.json").write_text(json.dumps(d))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "sweep_source_hash", lambda: "abc")
-    assert bench.traffic_for("fp16s", 1.0, 1) == 123.0
-    assert bench.traffic_for("fp32", 1.0, 1) is None
+    assert bench.traffic_for("fp16s", 1000) == 123.0
+    assert bench.traffic_for("fp32", 1000) is None
+    assert bench.traffic_for("fp16s", 999) is None  # counters of another lattice
     monkeypatch.setattr(bench, "sweep_source_hash", lambda: "changed")
-    assert bench.traffic_for("fp16s", 1.0, 1) is None
+    assert bench.traffic_for("fp16s", 1000) is None
 
 
 def test_committed_counters_match_the_sweep_source():
@@ -59,6 +60,7 @@ def test_committed_counters_match_the_sweep_source():
     the benchmark line carries the measured traffic."""
     d = json.load(open(os.path.join(ROOT, "profiles", "sweep_traffic.json")))
     assert d["source_hash"] == bench.sweep_source_hash()
+    assert d["cells"] == 512 * 320 * 512
     for form in ("fp64", "fp32", "fp16s"):
         assert 1.0 <= d["forms"][form]["ratio_to_algorithmic"] < 1.1
     assert np.isclose(d["calibration"]["write_factor"], 1.0, atol=0.01)
