@@ -204,7 +204,12 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
  * is a multiple of K the health check of fslbm_stats runs and the call waits
  * for it; on failure it returns FSLBM_E_UNSTABLE or FSLBM_E_INVARIANT (the
  * message names the count of bad cells and the step) and enqueues no further
- * step of this call. */
+ * step of this call.  A context from fslbm_init also bounds how far the host
+ * may run ahead: the sweep launches only the rows within the fluid's extent,
+ * measured on the device every 16 steps and read back without a wait, and
+ * when the extent in use is 32 steps old the call waits for the next one
+ * (so the device has at most 32 steps queued).  The environment variable
+ * FSLBM_EXTENT_EVERY at init sets the 16 (0: every row, never a wait). */
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule);
 
 /* Field export into caller device buffers.  mask selects fields by bit; dst[i]

@@ -117,7 +117,7 @@ Layout layout(size_t N, bool kappa, bool hf) {
   L.scalars = o;  // reservoir, acc, err(int), cnt[8] (int)
   o = align_up(o + 2 * sizeof(double) + 16 * sizeof(int32_t));
   L.extent = o;
-  o = align_up(o + 4 * sizeof(int32_t));
+  o = align_up(o + EXT_BYTES);
   L.wall_t = o;
   o = align_up(o + 8 * 6 * Q);
   L.kappa = o;
@@ -309,6 +309,7 @@ fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* work
     if ((e = launch_fill_i32(*ep[i], N, -1, st)) != hipSuccess) return fail(dev_fail(c, e, "init epochs"));
   if ((e = launch_fill_i32(c->counters, 2 * NCOUNT, 0, st)) != hipSuccess) return fail(dev_fail(c, e, "init counters"));
   if ((e = launch_fill_i32(c->err, 16, 0, st)) != hipSuccess) return fail(dev_fail(c, e, "init scalars"));
+  if ((e = launch_extent_init(c->ext_dev, st)) != hipSuccess) return fail(dev_fail(c, e, "init extent"));
   if ((e = launch_fill_f64(c->reservoir, 2, 0.0, st)) != hipSuccess) return fail(dev_fail(c, e, "init scalars"));
   if ((e = launch_check_flags(c->flags, c->com.grid, c->err, st)) != hipSuccess) return fail(dev_fail(c, e, "check flags"));
   int32_t herr = 0;
@@ -468,13 +469,19 @@ fslbm_status health(fslbm_ctx* c, double sc[2], int32_t cn[8], int32_t last[NCOU
 }
 
 // Rows the sweep of the next step launches (SweepArgs box), from the latest
-// fluid extent that has arrived; starts a new measurement every ext_every
-// steps.  No wait on the device.
+// fluid extent that has arrived, widened by one cell per step since it was
+// measured; a new measurement (of the rows of this box) starts every
+// ext_every steps.  The host reads the extents back without waiting, except
+// that it lets the device fall at most 2 ext_every steps behind: when the
+// extent in use is that old and the next one has not arrived, it waits for
+// that one, so that the box stays within 2 ext_every cells of the fluid.
 hipError_t sweep_box(fslbm_ctx* c, SweepArgs& s) {
   s.box = 0;
   if (c->ext_every <= 0) return hipSuccess;
   if (c->ext_pending >= 0) {
-    const hipError_t q = hipEventQuery(c->ext_ev[c->ext_pending]);
+    hipError_t q = hipEventQuery(c->ext_ev[c->ext_pending]);
+    if (q == hipErrorNotReady && c->ext_valid >= 0 && c->step - c->ext_step[c->ext_valid] >= 2 * c->ext_every)
+      q = hipEventSynchronize(c->ext_ev[c->ext_pending]);
     if (q == hipSuccess) {
       c->ext_valid = c->ext_pending;
       c->ext_pending = -1;
@@ -482,9 +489,26 @@ hipError_t sweep_box(fslbm_ctx* c, SweepArgs& s) {
       return q;
     }
   }
+  const Grid& g = c->com.grid;
+  int by0 = 0, bny = g.ny, bz0 = 0, bnz = g.nz;
+  bool empty = false;
+  if (c->ext_valid >= 0) {
+    const int32_t* ex = c->ext_host + 4 * c->ext_valid;
+    const int d = c->step - c->ext_step[c->ext_valid];
+    if (ex[1] < 0) {
+      empty = true;  // no fluid cell
+    } else {
+      by0 = g.py ? 0 : std::max(0, ex[0] - d);
+      bny = g.py ? g.ny : std::min(g.ny - 1, ex[1] + d) - by0 + 1;
+      bz0 = g.pz ? 0 : std::max(0, ex[2] - d);
+      bnz = g.pz ? g.nz : std::min(g.nz - 1, ex[3] + d) - bz0 + 1;
+    }
+  }
   if (c->ext_pending < 0 && (c->ext_valid < 0 || c->step - c->ext_step[c->ext_valid] >= c->ext_every)) {
     const int slot = c->ext_valid == 0 ? 1 : 0;
-    hipError_t e = launch_extent(c->flags, c->com.grid, c->ext_dev, (void*)c->stream);
+    // the fluid of this step lies in this step's box (every row before the first extent)
+    hipError_t e = empty ? launch_extent(c->flags, g, 0, 1, 0, 1, c->ext_dev, (void*)c->stream)
+                         : launch_extent(c->flags, g, by0, bny, bz0, bnz, c->ext_dev, (void*)c->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->ext_host + 4 * slot, c->ext_dev, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ext_ev[slot], c->stream);
@@ -493,19 +517,16 @@ hipError_t sweep_box(fslbm_ctx* c, SweepArgs& s) {
     c->ext_pending = slot;
   }
   if (c->ext_valid < 0) return hipSuccess;
-  const Grid& g = c->com.grid;
-  const int32_t* ex = c->ext_host + 4 * c->ext_valid;
-  const int d = c->step - c->ext_step[c->ext_valid];
   s.box = 1;
-  if (ex[1] < 0) {  // no fluid cell: one row (the sweep still resets the next counters)
+  if (empty) {  // one row (the sweep still resets the next counters)
     s.by0 = s.bz0 = 0;
     s.bny = s.bnz = 1;
     return hipSuccess;
   }
-  s.by0 = g.py ? 0 : std::max(0, ex[0] - d);
-  s.bny = g.py ? g.ny : std::min(g.ny - 1, ex[1] + d) - s.by0 + 1;
-  s.bz0 = g.pz ? 0 : std::max(0, ex[2] - d);
-  s.bnz = g.pz ? g.nz : std::min(g.nz - 1, ex[3] + d) - s.bz0 + 1;
+  s.by0 = by0;
+  s.bny = bny;
+  s.bz0 = bz0;
+  s.bnz = bnz;
   return hipSuccess;
 }
 

@@ -190,7 +190,13 @@ struct AdjArgs {
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule);
 // y and z extent of the fluid cells into ext = (ymin, ymax, zmin, zmax); (INT_MAX, -1, ...) if none
-hipError_t launch_extent(const uint8_t* flags, const Grid& g, int32_t* ext, void* stream);
+// partial extents of k_extent (ext holds (1 + EXT_COPIES) lines of 32 int32:
+// the result in the first, the partials after it)
+constexpr int EXT_COPIES = 64;
+constexpr size_t EXT_BYTES = (size_t)(1 + EXT_COPIES) * 32 * sizeof(int32_t);
+hipError_t launch_extent_init(int32_t* ext, void* stream);
+hipError_t launch_extent(const uint8_t* flags, const Grid& g, int y0, int ny, int z0, int nz, int32_t* ext,
+                         void* stream);
 hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
 hipError_t launch_iface4(const StepLaunch& L, int precision, int rule);  // fslbm_iface4.hip
 hipError_t launch_curvature(const StepLaunch& L);  // one or (plic = 2) two list kernels

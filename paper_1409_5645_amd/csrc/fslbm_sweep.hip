@@ -287,77 +287,118 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
 }
 
 // Extent of the fluid (liquid and interface) cells in y and z: ext[0..3] =
-// (ymin, ymax, zmin, zmax), to be set to (INT_MAX, -1, INT_MAX, -1) before.
-// One block per z-slab walks the slab's flags with 16-byte loads; each
-// block contributes its extent with two atomics per axis.
+// (ymin, ymax, zmin, zmax).  Only the rows of the box [y0, y0 + ny) x
+// [z0, z0 + nz) are read (the caller knows the fluid lies inside it).  A lane
+// reads 16 flag bytes of a row (one 16-byte load where the row allows); each
+// block adds its extent to one of EXT_COPIES partial extents (one atomic per
+// value; spread over copies so that the blocks do not queue on one address),
+// and k_extent_final reduces the copies into ext[0..3] and resets them for the
+// next measurement (k_extent_init sets them once, when the context is made).
 constexpr int EBLOCK = 256;
-__global__ __launch_bounds__(EBLOCK) void k_extent(const uint8_t* __restrict__ flags, Grid g, int32_t* ext) {
-  __shared__ int smin[EBLOCK / 64], smax[EBLOCK / 64];
-  const int z = (int)blockIdx.x;
-  const size_t slab = (size_t)g.nx * (size_t)g.ny;
-  const uint8_t* p = flags + slab * (size_t)z;
-  int ymin = 0x7fffffff, ymax = -1;
-  // 16-byte chunks of the slab; the slab start is 16-byte aligned when nx*ny
-  // is a multiple of 16, else bytes one by one
-  const bool vec = (slab % 16) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0;
-  if (vec) {
-    const uint4* p4 = reinterpret_cast<const uint4*>(p);
-    for (size_t c = threadIdx.x; c < slab / 16; c += EBLOCK) {
-      const uint4 v = p4[c];
+constexpr int ECELLS = 16;
+constexpr int ESTRIDE = 32;  // int32 between partial extents: one 128-byte line each
+
+__device__ __forceinline__ void extent_reset(int32_t* e) {
+  e[0] = 0x7fffffff;
+  e[1] = -1;
+  e[2] = 0x7fffffff;
+  e[3] = -1;
+}
+
+__global__ void k_extent_init(int32_t* ext) {
+  extent_reset(ext + ESTRIDE * (1 + (int)threadIdx.x));  // one thread per partial extent
+}
+
+__global__ __launch_bounds__(EBLOCK) void k_extent(const uint8_t* __restrict__ flags, Grid g, int y0, int ny, int z0,
+                                                   int nz, int32_t* ext) {
+  __shared__ int sm[4][EBLOCK / 64];
+  const int lpr = (g.nx + ECELLS - 1) / ECELLS;
+  const int total = ny * nz * lpr;  // < N / 16 + ny nz < 2^31
+  int ymin = 0x7fffffff, ymax = -1, zmin = 0x7fffffff, zmax = -1;
+  for (int k = (int)blockIdx.x * EBLOCK + (int)threadIdx.x; k < total; k += (int)gridDim.x * EBLOCK) {
+    const int brow = k / lpr;
+    const int x0 = (k - brow * lpr) * ECELLS;
+    const int by = brow % ny;
+    const int y = y0 + by, z = z0 + (brow - by) / ny;
+    const size_t o = ((size_t)z * g.ny + (size_t)y) * (size_t)g.nx + (size_t)x0;
+    bool fluid = false;
+    if (x0 + ECELLS <= g.nx && (o & 15u) == 0u) {
+      const uint4 v = *reinterpret_cast<const uint4*>(flags + o);
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const uint32_t b = (w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-        if (b == IFACE || b == LIQ) {
-          const int y = (int)((c * 16 + (size_t)k) / (size_t)g.nx);
-          ymin = min(ymin, y);
-          ymax = max(ymax, y);
-        }
+      for (int j = 0; j < ECELLS; ++j) {
+        const uint32_t b = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        fluid = fluid || b == IFACE || b == LIQ;
       }
+    } else {
+      for (int j = 0; j < ECELLS && x0 + j < g.nx; ++j) fluid = fluid || flags[o + j] == IFACE || flags[o + j] == LIQ;
     }
-  } else {
-    for (size_t c = threadIdx.x; c < slab; c += EBLOCK) {
-      const uint8_t b = p[c];
-      if (b == IFACE || b == LIQ) {
-        const int y = (int)(c / (size_t)g.nx);
-        ymin = min(ymin, y);
-        ymax = max(ymax, y);
-      }
+    if (fluid) {
+      ymin = min(ymin, y);
+      ymax = max(ymax, y);
+      zmin = min(zmin, z);
+      zmax = max(zmax, z);
     }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    ymin = min(ymin, __shfl_down(ymin, o));
-    ymax = max(ymax, __shfl_down(ymax, o));
+  for (int off = 32; off > 0; off >>= 1) {
+    ymin = min(ymin, __shfl_down(ymin, off));
+    ymax = max(ymax, __shfl_down(ymax, off));
+    zmin = min(zmin, __shfl_down(zmin, off));
+    zmax = max(zmax, __shfl_down(zmax, off));
   }
   if ((threadIdx.x & 63) == 0) {
-    smin[threadIdx.x >> 6] = ymin;
-    smax[threadIdx.x >> 6] = ymax;
+    sm[0][threadIdx.x >> 6] = ymin;
+    sm[1][threadIdx.x >> 6] = ymax;
+    sm[2][threadIdx.x >> 6] = zmin;
+    sm[3][threadIdx.x >> 6] = zmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < EBLOCK / 64; ++w) {
-      ymin = min(ymin, smin[w]);
-      ymax = max(ymax, smax[w]);
+      ymin = min(ymin, sm[0][w]);
+      ymax = max(ymax, sm[1][w]);
+      zmin = min(zmin, sm[2][w]);
+      zmax = max(zmax, sm[3][w]);
     }
     if (ymax >= 0) {
-      atomicMin(&ext[0], ymin);
-      atomicMax(&ext[1], ymax);
-      atomicMin(&ext[2], z);
-      atomicMax(&ext[3], z);
+      int32_t* e = ext + ESTRIDE * (1 + (int)(blockIdx.x % EXT_COPIES));
+      atomicMin(&e[0], ymin);
+      atomicMax(&e[1], ymax);
+      atomicMin(&e[2], zmin);
+      atomicMax(&e[3], zmax);
     }
   }
 }
 
-__global__ void k_extent_init(int32_t* ext) {
-  ext[0] = 0x7fffffff;
-  ext[1] = -1;
-  ext[2] = 0x7fffffff;
-  ext[3] = -1;
+__global__ void k_extent_final(int32_t* ext) {
+  const int c = (int)threadIdx.x;  // EXT_COPIES threads: one wavefront
+  int v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = ext[ESTRIDE * (1 + c) + i];
+  extent_reset(ext + ESTRIDE * (1 + c));
+  for (int off = 32; off > 0; off >>= 1) {
+    v[0] = min(v[0], __shfl_down(v[0], off));
+    v[1] = max(v[1], __shfl_down(v[1], off));
+    v[2] = min(v[2], __shfl_down(v[2], off));
+    v[3] = max(v[3], __shfl_down(v[3], off));
+  }
+  if (c == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ext[i] = v[i];
 }
 
-hipError_t launch_extent(const uint8_t* flags, const Grid& g, int32_t* ext, void* stream) {
-  k_extent_init<<<1, 1, 0, (hipStream_t)stream>>>(ext);
-  k_extent<<<(unsigned)g.nz, EBLOCK, 0, (hipStream_t)stream>>>(flags, g, ext);
+hipError_t launch_extent_init(int32_t* ext, void* stream) {
+  static_assert(EXT_COPIES == 64, "k_extent_init and k_extent_final use one wavefront of EXT_COPIES lanes");
+  k_extent_init<<<1, EXT_COPIES, 0, (hipStream_t)stream>>>(ext);
+  return hipGetLastError();
+}
+
+hipError_t launch_extent(const uint8_t* flags, const Grid& g, int y0, int ny, int z0, int nz, int32_t* ext,
+                         void* stream) {
+  const long long total = (long long)ny * nz * ((g.nx + ECELLS - 1) / ECELLS);
+  const unsigned nb = (unsigned)std::max<long long>(1, std::min<long long>(4096, (total + EBLOCK - 1) / EBLOCK));
+  k_extent<<<nb, EBLOCK, 0, (hipStream_t)stream>>>(flags, g, y0, ny, z0, nz, ext);
+  k_extent_final<<<1, EXT_COPIES, 0, (hipStream_t)stream>>>(ext);
   return hipGetLastError();
 }
 
