@@ -471,15 +471,24 @@ __device__ void init_new_from_gas(const ConvArgs& a, int c) {
   coords(g, c, x, y, z);
   double rs = 0.0, us0 = 0.0, us1 = 0.0, us2 = 0.0;
   int cnt = 0;
+  // classes and auxiliary rows of all neighbours in one batch of loads (a
+  // neighbour beyond a wall reads the cell's own row and is skipped)
+  uint8_t tn[Q];
+  double4 vn[Q];
 #pragma unroll
   for (int q = 1; q < Q; ++q) {
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-    if (s < 0 || a.flags[s] == GAS || a.flags[s] == SOLID) continue;
-    const double4 v = *reinterpret_cast<const double4*>(a.aux + 4 * (size_t)s);
-    rs = rs + v.x;
-    us0 = us0 + v.y;
-    us1 = us1 + v.z;
-    us2 = us2 + v.w;
+    const int sc = s >= 0 ? s : c;
+    tn[q] = s >= 0 ? a.flags[sc] : (uint8_t)GAS;
+    vn[q] = *reinterpret_cast<const double4*>(a.aux + 4 * (size_t)sc);
+  }
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    if (tn[q] == GAS || tn[q] == SOLID) continue;
+    rs = rs + vn[q].x;
+    us0 = us0 + vn[q].y;
+    us1 = us1 + vn[q].z;
+    us2 = us2 + vn[q].w;
     ++cnt;
   }
   const double rbar = rs / (double)cnt;
@@ -611,11 +620,20 @@ __global__ __launch_bounds__(BLOCK) void k_gather(ConvArgs a) {
     int x, y, z;
     coords(g, r, x, y, z);
     double m = a.mass[r];
+    // marks and masses of all neighbours in one batch of loads, then the sum
+    // in link order (a neighbour beyond a wall reads the cell's own entries)
+    int ep[Q];
+    double mn[Q];
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
       const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-      if (s >= 0 && a.conv_epoch[s] == a.step) m = m + a.mass[s];
+      const int sc = s >= 0 ? s : r;
+      ep[q] = s >= 0 ? a.conv_epoch[sc] : -1;
+      mn[q] = a.mass[sc];
     }
+#pragma unroll
+    for (int q = 1; q < Q; ++q)
+      if (ep[q] == a.step) m = m + mn[q];
     a.mass[r] = m;
     a.phi_out[r] = m / a.aux[4 * (size_t)r];
   }
