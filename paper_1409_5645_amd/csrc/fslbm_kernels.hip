@@ -772,9 +772,83 @@ __global__ __launch_bounds__(BLOCK) void k_fields(FieldArgs a) {
   }
 }
 
+// Bits j + 1 of gas and liq for the cells x0 + j, j = -1 .. 16, of the row
+// starting at rbase (a cell beyond a wall sets no bit, beyond a periodic face
+// the wrapped one; positions past the row end set none, and the right
+// neighbour of the row's last cell is at bit nx - x0 + 1).  One 16-byte load
+// where the row allows.
+__device__ __forceinline__ void row_masks(const uint8_t* __restrict__ f, const Grid& g, unsigned rbase, int x0,
+                                          uint32_t& gas, uint32_t& liq) {
+  gas = liq = 0u;
+  const int n = min(16, g.nx - x0);  // cells of this chunk
+  if (n == 16 && ((rbase + (unsigned)x0) & 15u) == 0u) {
+    const uint4 v = *reinterpret_cast<const uint4*>(f + rbase + (unsigned)x0);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t b = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
+      gas |= (b == GAS ? 1u : 0u) << (j + 1);
+      liq |= (b == LIQ ? 1u : 0u) << (j + 1);
+    }
+  } else {
+    for (int j = 0; j < n; ++j) {
+      const uint8_t b = f[rbase + (unsigned)(x0 + j)];
+      gas |= (b == GAS ? 1u : 0u) << (j + 1);
+      liq |= (b == LIQ ? 1u : 0u) << (j + 1);
+    }
+  }
+  const int xl = x0 > 0 ? x0 - 1 : (g.px ? g.nx - 1 : -1);
+  if (xl >= 0 && f[rbase + (unsigned)xl] == GAS) gas |= 1u;
+  const int xr = x0 + n < g.nx ? x0 + n : (g.px ? 0 : -1);
+  if (xr >= 0 && f[rbase + (unsigned)xr] == GAS) gas |= 1u << (n + 1);
+}
+
+// The layer rule of the health check: liquid cells with a gas cell among
+// their 18 neighbours, added to cnt[5].  A lane takes 16 cells of a row and
+// the masks of its eight neighbour rows (the rows at y +- 1 or z +- 1 give
+// neighbours at x - 1, x, x + 1, the four diagonal rows only at x), one
+// 16-byte load per row.
+__global__ __launch_bounds__(BLOCK) void k_layer(const uint8_t* __restrict__ flags, Grid g, int32_t* cnt) {
+  __shared__ int sb[BLOCK / 64];
+  const int lpr = (g.nx + 15) / 16;
+  const int total = g.ny * g.nz * lpr;  // < N / 16 + ny nz < 2^31
+  int bad = 0;
+  for (int k = (int)blockIdx.x * BLOCK + (int)threadIdx.x; k < total; k += (int)gridDim.x * BLOCK) {
+    const int row = k / lpr;
+    const int x0 = (k - row * lpr) * 16;
+    const int y = row % g.ny, z = row / g.ny;
+    uint32_t gas, liq;
+    row_masks(flags, g, (unsigned)row * (unsigned)g.nx, x0, gas, liq);
+    if (liq == 0u) continue;
+    uint32_t near = (gas << 1) | (gas >> 1);
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (dy == 0 && dz == 0) continue;
+        const int ys = step_axis(y, dy, g.ny, g.py), zs = step_axis(z, dz, g.nz, g.pz);
+        if (ys < 0 || zs < 0) continue;
+        uint32_t gr, lr;
+        row_masks(flags, g, (unsigned)(ys + g.ny * zs) * (unsigned)g.nx, x0, gr, lr);
+        near |= (dy != 0 && dz != 0) ? gr : (gr | (gr << 1) | (gr >> 1));
+      }
+    }
+    bad += __popc(liq & near);
+  }
+  for (int o = 32; o > 0; o >>= 1) bad += __shfl_down(bad, o);
+  if ((threadIdx.x & 63) == 0) sb[threadIdx.x >> 6] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) t += sb[w];
+    if (t > 0) atomicAdd(&cnt[5], t);
+  }
+}
+
 // Total mass and health check: block partial sums of the mass into acc[0];
 // counts of liquid and interface cells, and of the cells that fail a check
-// (see StatArgs::cnt).  The mass sum is FP64 in every form.
+// (see StatArgs::cnt; the layer rule is k_layer's).  The mass sum is FP64 in
+// every form.
 template <class F>
 __global__ __launch_bounds__(BLOCK) void k_stats(StatArgs a) {
   using R = typename F::R;
@@ -795,18 +869,6 @@ __global__ __launch_bounds__(BLOCK) void k_stats(StatArgs a) {
       continue;
     }
     if (t == GAS || t == SOLID) continue;
-    if (t == LIQ) {
-      // the layer rule: no liquid cell has a gas cell among its 18 neighbours
-      int x, y, z;
-      coords(g, idx, x, y, z);
-      bool gas_near = false;
-#pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-        if (s >= 0 && a.flags[s] == GAS) gas_near = true;
-      }
-      if (gas_near) atomicAdd(&a.cnt[5], 1);
-    }
     R fl[Q];
     double r = 0.0;
     for (int q = 0; q < Q; ++q) {
@@ -1096,12 +1158,111 @@ hipError_t launch_fields(const FieldArgs& a, int precision, void* stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const StatArgs& a, int precision, void* stream) {
+// k_stats with 16 bytes of every population plane per lane: G = 16 / s cells
+// (8 in the FP16 form, whose 2-byte elements would otherwise take a load
+// instruction per element and per cell), for lattices whose N is a multiple
+// of G (the planes then start on 16-byte boundaries).  Same checks and sums
+// as k_stats, cell by cell.
+template <class F>
+__global__ __launch_bounds__(BLOCK) void k_stats_vec(StatArgs a) {
+  using R = typename F::R;
+  using S = typename F::S;
+  constexpr bool SH = F::shifted;
+  constexpr int G = 16 / (int)sizeof(S);
+  __shared__ double sm[BLOCK / 64];
+  __shared__ int sl[BLOCK / 64];
+  __shared__ int si[BLOCK / 64];
+  double v = 0.0;
+  int nl = 0, ni = 0;
+  const S* fi = reinterpret_cast<const S*>(a.f);
+  const Grid& g = a.c.grid;
+  const unsigned N = (unsigned)g.N;
+  const unsigned ng = N / (unsigned)G;
+  const Consts<R>& k = pick_consts<R>(a.c);
+  for (unsigned gi = blockIdx.x * BLOCK + threadIdx.x; gi < ng; gi += gridDim.x * BLOCK) {
+    const unsigned base = gi * (unsigned)G;
+    uint8_t t[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) t[c] = a.flags[base + (unsigned)c];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      if (t[c] > SOLID) atomicAdd(&a.cnt[5], 1);
+      any = any || t[c] == LIQ || t[c] == IFACE;
+    }
+    if (!any) continue;
+    uint4 vq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) vq[q] = *reinterpret_cast<const uint4*>(fi + ((size_t)q * N + base));
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      if (t[c] != LIQ && t[c] != IFACE) continue;
+      R fl[Q];
+      double r = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        fl[q] = F::load(reinterpret_cast<const S*>(&vq[q]) + c, a.c.inv_scale);
+        r = r + (double)fl[q];
+      }
+      if (F::shifted) r = 1.0 + r;
+      if (!(r > 0.0) || !isfinite(r)) atomicAdd(&a.cnt[1], 1);
+      R rs, u[3];
+      recover_moments<R, SH>(fl, k, a.c.incomp, rs, u);
+      const double usq = ((double)u[0] * (double)u[0] + (double)u[1] * (double)u[1]) + (double)u[2] * (double)u[2];
+      if (!(usq <= a.u_max2)) atomicAdd(&a.cnt[4], 1);
+      if (t[c] == LIQ) {
+        v += r;
+        nl += 1;
+      } else {
+        v += a.mass[base + (unsigned)c];
+        ni += 1;
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    v += __shfl_down(v, o);
+    nl += __shfl_down(nl, o);
+    ni += __shfl_down(ni, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sm[threadIdx.x >> 6] = v;
+    sl[threadIdx.x >> 6] = nl;
+    si[threadIdx.x >> 6] = ni;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    int cl = 0, ci = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) {
+      s += sm[w];
+      cl += sl[w];
+      ci += si[w];
+    }
+    atomicAdd(a.acc, s);
+    atomicAdd(&a.cnt[0], cl);
+    atomicAdd(&a.cnt[2], ci);
+  }
+}
+
+template <class F>
+static void stats_form(const StatArgs& a, hipStream_t s) {
+  constexpr int G = 16 / (int)sizeof(typename F::S);
   const unsigned nb = std::min<unsigned>(2048u, blocks_for(a.c.grid.N));
+  if (a.c.grid.N % G == 0)
+    k_stats_vec<F><<<std::min<unsigned>(2048u, blocks_for(a.c.grid.N / G)), BLOCK, 0, s>>>(a);
+  else
+    k_stats<F><<<nb, BLOCK, 0, s>>>(a);
+}
+
+hipError_t launch_stats(const StatArgs& a, int precision, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (precision == 0) k_stats<FormF64><<<nb, BLOCK, 0, s>>>(a);
-  else if (precision == 1) k_stats<FormF32><<<nb, BLOCK, 0, s>>>(a);
-  else k_stats<FormF16><<<nb, BLOCK, 0, s>>>(a);
+  if (precision == 0) stats_form<FormF64>(a, s);
+  else if (precision == 1) stats_form<FormF32>(a, s);
+  else stats_form<FormF16>(a, s);
+  const Grid& g = a.c.grid;
+  const long long lanes = (long long)g.ny * g.nz * ((g.nx + 15) / 16);
+  const unsigned nl = (unsigned)std::max<long long>(1, std::min<long long>(2048, (lanes + BLOCK - 1) / BLOCK));
+  k_layer<<<nl, BLOCK, 0, s>>>(a.flags, g, a.cnt);
   return hipGetLastError();
 }
 

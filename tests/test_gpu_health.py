@@ -21,7 +21,11 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _case():
+def _case(odd=False):
+    # odd: N = 25 * 17 * 5 is odd, so the statistics take their one-cell-per-lane
+    # kernel in every form (else the one with 16 bytes of each plane per lane)
+    if odd:
+        return W.sloshing(25, 17, 5, depth=8.0, amp=2.5, seed=2, gy=-4e-4, tau=0.6)
     return W.sloshing(24, 18, 6, depth=8.0, amp=2.5, seed=2, gy=-4e-4, tau=0.6)
 
 
@@ -29,10 +33,11 @@ def _first(flags, cls):
     return int(np.nonzero(flags == cls)[0][len(np.nonzero(flags == cls)[0]) // 2])
 
 
+@pytest.mark.parametrize("odd", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
-def test_nan_population_is_unstable(fs, oracle_mod, precision):
-    w = _case()
-    _say(f"case nan {precision}")
+def test_nan_population_is_unstable(fs, oracle_mod, precision, odd):
+    w = _case(odd)
+    _say(f"case nan {precision} odd={odd}")
     o = oracle_mod.Oracle.from_workload(w)
     f = o.populations().copy()
     c = _first(w.flags, W.LIQUID)
@@ -71,8 +76,9 @@ def test_fast_cell_is_unstable(fs):
     s.close()
 
 
-def test_liquid_next_to_gas_breaks_the_layer_rule(fs):
-    w = _case()
+@pytest.mark.parametrize("odd", [False, True])
+def test_liquid_next_to_gas_breaks_the_layer_rule(fs, odd):
+    w = _case(odd)
     _say("case layer rule")
     s = fs.Sim.from_workload(w)
     s.stats()
@@ -108,3 +114,68 @@ def test_checked_steps_equal_unchecked(fs):
     assert b.stats()["steps"] == 40
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("nx,periodic", [(37, (0, 0, 0)), (37, (1, 0, 1)), (64, (0, 0, 0)), (64, (1, 1, 1))])
+def test_layer_rule_count_matches_the_definition(fs, nx, periodic):
+    """The count of liquid cells with a gas cell among their 18 neighbours
+    (D3Q19 links; periodic faces wrap, walls give no neighbour), on a random
+    class field written into the caller's flag buffer, equals the count taken
+    straight from the definition with numpy: rows of 37 cells (chunks that
+    end inside a row, unaligned rows) and of 64 (16-byte loads)."""
+    w = W.sloshing(nx, 18, 6, depth=8.0, amp=2.5, seed=2, gy=-4e-4, tau=0.6, periodic=periodic)
+    _say(f"case layer count nx={nx} periodic={periodic}")
+    s = fs.Sim.from_workload(w)
+    rng = np.random.default_rng(5)
+    fl = rng.choice(np.array([W.GAS, W.INTERFACE, W.LIQUID], dtype=np.uint8), size=w.params.n_cells, p=[0.1, 0.3, 0.6])
+    f3 = fl.reshape(w.params.nz, w.params.ny, nx)
+    bad = np.zeros_like(f3, dtype=bool)
+    for q in range(1, 19):
+        cx, cy, cz = (int(v) for v in W.LINKS[q])
+        nb = f3
+        ok = np.ones_like(f3, dtype=bool)
+        for ax, (c, per) in enumerate(((cz, periodic[2]), (cy, periodic[1]), (cx, periodic[0]))):
+            if c == 0:
+                continue
+            nb = np.roll(nb, -c, axis=ax)
+            if not per:
+                idx = [slice(None)] * 3
+                idx[ax] = slice(-1, None) if c > 0 else slice(0, 1)
+                ok[tuple(idx)] = False
+        bad |= ok & (nb == W.GAS)
+    expect = int((bad & (f3 == W.LIQUID)).sum())
+    assert expect > 0
+    import torch
+    # every cell liquid at rest first, so that the populations are sound
+    # wherever the random field puts a fluid cell
+    N = w.params.n_cells
+    s.flags_t.fill_(W.LIQUID)
+    s.set_equilibrium(np.ones(N), np.zeros((3, N)), np.ones(N))
+    assert s.stats()["liquid"] == N
+    s.flags_t.copy_(torch.from_numpy(fl).to(s.flags_t.device))
+    with pytest.raises(fs.FslbmError, match="INVARIANT") as e:
+        s.stats()
+    assert f"{expect} cells break the cell-class rule" in str(e.value), (expect, str(e.value))
+    s.close()
+
+
+@pytest.mark.parametrize("odd", [False, True])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-6), ("fp16s", 1e-4)])
+def test_total_mass_of_both_statistics_kernels(fs, oracle_mod, precision, tol, odd):
+    """Total mass and class counts from fslbm_stats against the oracle at the
+    initial state, through the kernel with 16 bytes of each plane per lane
+    (N a multiple of 16 / s) and through the one-cell-per-lane kernel (odd N).
+    The reduced forms recompute the liquid density from their stored
+    populations, so they differ by the storage rounding."""
+    w = _case(odd)
+    _say(f"case stats mass {precision} odd={odd}")
+    o = oracle_mod.Oracle.from_workload(w)
+    s = fs.Sim.from_workload(w, precision=precision)
+    st = s.stats()
+    m0 = o.total_mass()
+    err = abs(st["total_mass"] - m0) / m0
+    _say(f"  total mass rel err {err:.2e}")
+    assert err <= tol
+    assert st["liquid"] == int((w.flags == W.LIQUID).sum())
+    assert st["interface"] == int((w.flags == W.INTERFACE).sum())
+    s.close()
