@@ -209,7 +209,10 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
  * measured on the device every 16 steps and read back without a wait, and
  * when the extent in use is 32 steps old the call waits for the next one
  * (so the device has at most 32 steps queued).  The environment variable
- * FSLBM_EXTENT_EVERY at init sets the 16 (0: every row, never a wait). */
+ * FSLBM_EXTENT_EVERY at init sets the 16 (0: every row, never a wait).  The
+ * classes change only through the steps: a caller that writes the flags
+ * buffer between steps calls fslbm_set_state or fslbm_set_equilibrium
+ * afterwards, which also make the next step measure the extent again. */
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule);
 
 /* Field export into caller device buffers.  mask selects fields by bit; dst[i]

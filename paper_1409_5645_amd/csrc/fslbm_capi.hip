@@ -399,6 +399,14 @@ fslbm_status fslbm_init_static(const fslbm_params* p, const fslbm_buffers* b, fs
   return s;
 }
 
+// A new state may put fluid anywhere: the next step measures the extent
+// again and launches every row until it has arrived (the stream is idle here,
+// so no copy into the host slots is still in flight).
+static void forget_extent(fslbm_ctx* c) {
+  c->ext_valid = -1;
+  c->ext_pending = -1;
+}
+
 static InitArgs init_args(fslbm_ctx* c) {
   InitArgs a;
   a.c = c->com;
@@ -415,6 +423,7 @@ fslbm_status fslbm_set_equilibrium(fslbm_ctx* c, const double* rho, const double
   if (!rho || !u || !fill) { c->last_error = "NULL field"; return FSLBM_E_INVALID; }
   HIPCHK(c, launch_set_equilibrium(init_args(c), c->p.precision, rho, u, fill, c->stream), "set_equilibrium");
   HIPCHK(c, hipStreamSynchronize(c->stream), "set_equilibrium sync");
+  forget_extent(c);
   return FSLBM_OK;
 }
 
@@ -425,6 +434,7 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
   HIPCHK(c, launch_set_state(init_args(c), c->p.precision, f, mass, fill, c->stream), "set_state");
   HIPCHK(c, launch_fill_f64(c->reservoir, 1, reservoir, c->stream), "set reservoir");
   HIPCHK(c, hipStreamSynchronize(c->stream), "set_state sync");
+  forget_extent(c);
   return FSLBM_OK;
 }
 

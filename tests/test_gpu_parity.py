@@ -806,3 +806,34 @@ def test_interface_kernel_layouts_agree(fs, monkeypatch, precision, tol, periodi
             _say(f"  quad {quad}: population difference {err:.3e}, mass {merr:.3e}")
             assert err <= tol
             assert merr <= 10 * tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16s"])
+def test_new_state_resets_the_row_box(fs, oracle_mod, precision):
+    """A context that has stepped a shallow tank (its row box then covers the
+    bottom rows only) and is given, through fslbm_set_state, a state with the
+    fluid far higher continues exactly as a new context started from that
+    state: the library measures the fluid's extent again instead of widening
+    the old one."""
+    shallow = W.sloshing(40, 64, 8, depth=5.0, amp=1.5, seed=3, gy=-4e-4, tau=0.6)
+    deep = W.sloshing(40, 64, 8, depth=52.0, amp=3.0, seed=4, gy=-4e-4, tau=0.6)
+    _say(f"case new state resets the row box {precision}")
+    o = oracle_mod.Oracle.from_workload(deep)
+    st = (o.populations(), o.mass(), o.phi())
+    a = fs.Sim(shallow.params, shallow.flags, precision=precision)
+    a.set_equilibrium(shallow.rho, shallow.velocity(), shallow.fill)
+    a.step(60, fs.FSL)
+    import torch
+    a.flags_t.copy_(torch.from_numpy(deep.flags).to(a.flags_t.device))
+    a.set_state(*st)
+    b = fs.Sim(deep.params, deep.flags, precision=precision)
+    b.set_state(*st)
+    a.step(40, fs.FSL)
+    b.step(40, fs.FSL)
+    ga, gb = a.fields(("f", "flags", "mass", "phi")), b.fields(("f", "flags", "mass", "phi"))
+    np.testing.assert_array_equal(ga["flags"], gb["flags"])
+    act = gb["flags"] != W.GAS
+    assert np.array_equal(ga["f"][:, act], gb["f"][:, act])
+    assert np.array_equal(ga["mass"], gb["mass"])
+    a.close()
+    b.close()
