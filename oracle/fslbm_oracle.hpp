@@ -12,7 +12,11 @@
 // directional derivatives (adjoint checks).  T = double is the FP64 oracle.
 //
 // Parity status per function is listed in the test files; every function here
-// is pinned by at least one closed form, invariant or special case.
+// is pinned by at least one closed form, invariant or special case, with one
+// exception.  Parity unpinned: the weight of the mass exchange between two
+// interface cells, (phi_x + phi_s) / 2 in step S4.  The paper leaves it to the
+// interface tracking it cites; any symmetric weight conserves mass and passes
+// every pin, so only the antisymmetry (mass conservation) is pinned.
 #pragma once
 
 #include <algorithm>
@@ -914,7 +918,7 @@ struct Oracle {
           if (type[s] == LIQUID) {
             dm = dm + diff;
           } else {
-            T wgt = T(0.5) * (phix + phi[s]);
+            T wgt = T(0.5) * (phix + phi[s]);  // parity unpinned (see the header)
             dm = dm + wgt * diff;
           }
         }
