@@ -9,12 +9,15 @@
 //   k_mark    E' = E minus N(F); new interface cells from gas next to filled
 //             cells (initialised from their interface neighbours) and from
 //             liquid next to E' cells.
-//   k_commit  new cell classes; excess of filled cells.
-//   k_share   excess split over interface neighbours; receiver list.
-//   k_gather  receivers add the shares in ascending link order; fill refresh.
+//   k_share   excess of the filled and E' cells split over the neighbours
+//             that are interface cells after the conversions; receiver list.
+//   k_gather  receivers add the shares in ascending link order; fill refresh;
+//             new cell classes.
 // Membership marks are step-stamped int arrays ("epochs"), so nothing needs to
 // be cleared between steps; list counters are double buffered by step parity
-// and the sweep of step t zeroes the set of step t+1.
+// and the sweep of step t zeroes the set of step t+1.  The cell classes keep
+// their values of time t until k_gather: k_share takes the classes after the
+// conversions from the marks (iface_after).
 #include "fslbm_device.hpp"
 #include "fslbm_internal.hpp"
 #include "fslbm_stencil.hpp"
@@ -521,6 +524,11 @@ __device__ void init_new_from_liquid(const ConvArgs& a, int c) {
   a.aux[4 * (size_t)c] = r;
 }
 
+// Mark of an E' cell in new_epoch: below every step stamp (>= 0) and the
+// initial -1, and distinct for every step.  E' cells are interface cells and
+// new_epoch's step stamps go to gas and liquid cells only.
+__device__ __forceinline__ int ep_stamp(int step) { return -2 - step; }
+
 // One thread per (converted cell, link): a cell's 18 neighbours are handled by
 // 18 threads, so the work of a step is not the longest serial chain of one
 // cell's new neighbours.  Which thread wins a new cell's epoch mark does not
@@ -551,6 +559,7 @@ __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
         if (t >= 0 && a.f_epoch[t] == a.step) protect = true;
       }
       if (protect) continue;
+      if (q == 1) a.new_epoch[c] = ep_stamp(a.step);
       wave_append(q == 1, &a.counters[C_EP], a.listEP, c);
       const bool win = s >= 0 && a.flags[s] == LIQ && atomicExch(&a.new_epoch[s], a.step) != a.step;
       wave_append(win, &a.counters[C_NL], a.listNL, s);
@@ -559,28 +568,21 @@ __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_commit(ConvArgs a) {
-  const int nF = a.counters[C_F], nEP = a.counters[C_EP], nNI = a.counters[C_NI], nNL = a.counters[C_NL];
-  const int tot = nF + nEP + nNI + nNL;
-  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < tot; i += gridDim.x * BLOCK) {
-    if (i < nF) {
-      const int c = a.listF[i];
-      a.flags[c] = LIQ;
-      a.mass[c] = a.mass[c] - a.aux[4 * (size_t)c];  // excess of a filled cell
-    } else if (i < nF + nEP) {
-      a.flags[a.listEP[i - nF]] = GAS;      // excess of an emptied cell: its mass
-    } else if (i < nF + nEP + nNI) {
-      a.flags[a.listNI[i - nF - nEP]] = IFACE;
-    } else {
-      a.flags[a.listNL[i - nF - nEP - nNI]] = IFACE;
-    }
-  }
+// Whether cell t is an interface cell after this step's conversions: a new
+// interface cell, or an interface cell of time t that neither filled nor is in
+// E'.  Three loads, no branch, so that a caller's 18 neighbours load in one
+// batch.
+__device__ __forceinline__ bool iface_after(const ConvArgs& a, int t) {
+  const int ne = a.new_epoch[t];
+  const int fe = a.f_epoch[t];
+  const uint8_t fl = a.flags[t];
+  return (ne == a.step) | ((fl == IFACE) & (fe != a.step) & (ne != ep_stamp(a.step)));
 }
 
 // One thread per (converted cell, link), as in k_mark: every thread of a cell
-// counts its eligible neighbours; the link-1 thread divides the excess (or
-// hands it to the reservoir) and marks the cell, each thread lists its own
-// receiver.
+// counts its eligible neighbours; the link-1 thread takes the excess (a filled
+// cell's mass minus its density, an emptied cell's mass), divides it (or hands
+// it to the reservoir) and marks the cell, each thread lists its own receiver.
 __global__ __launch_bounds__(BLOCK) void k_share(ConvArgs a) {
   const int nF = a.counters[C_F], nEP = a.counters[C_EP];
   const Grid& g = a.c.grid;
@@ -589,33 +591,55 @@ __global__ __launch_bounds__(BLOCK) void k_share(ConvArgs a) {
   for (unsigned i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += gridDim.x * BLOCK) {
     const int e = (int)(i / (unsigned)(Q - 1));
     const int q = 1 + (int)(i - (unsigned)e * (unsigned)(Q - 1));
-    const int c = e < nF ? a.listF[e] : a.listEP[e - nF];
+    const bool filled = e < nF;
+    const int c = filled ? a.listF[e] : a.listEP[e - nF];
     int x, y, z;
     coords(g, c, x, y, z);
     int n_elig = 0;
+    bool recv = false;
 #pragma unroll
     for (int p = 1; p < Q; ++p) {
       const int t = neighbor(g, x, y, z, CX[p], CY[p], CZ[p]);
-      if (t >= 0 && a.flags[t] == IFACE) ++n_elig;
-    }
-    if (n_elig == 0) {
-      if (q == 1) atomicAdd(a.reservoir, a.mass[c]);
-      continue;
+      const bool el = (t >= 0) & iface_after(a, t >= 0 ? t : c);
+      n_elig += el ? 1 : 0;
+      if (p == q) recv = el;
     }
     if (q == 1) {
-      a.mass[c] = a.mass[c] / (double)n_elig;
-      a.conv_epoch[c] = a.step;
+      const double ex = filled ? a.mass[c] - a.aux[4 * (size_t)c] : a.mass[c];
+      if (n_elig == 0) {
+        atomicAdd(a.reservoir, ex);
+        if (filled) a.mass[c] = ex;
+      } else {
+        a.mass[c] = ex / (double)n_elig;
+        a.conv_epoch[c] = a.step;
+      }
     }
+    if (!recv) continue;
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
-    if (s < 0 || a.flags[s] != IFACE) continue;
     wave_append(atomicExch(&a.recv_epoch[s], a.step) != a.step, &a.counters[C_R], a.listR, s);
   }
 }
 
+// Receivers (first nR threads) and the new cell classes (the rest).
 __global__ __launch_bounds__(BLOCK) void k_gather(ConvArgs a) {
   const int nR = a.counters[C_R];
+  const int nF = a.counters[C_F], nEP = a.counters[C_EP], nNI = a.counters[C_NI], nNL = a.counters[C_NL];
+  const int tot = nR + nF + nEP + nNI + nNL;
   const Grid& g = a.c.grid;
-  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < nR; i += gridDim.x * BLOCK) {
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < tot; i += gridDim.x * BLOCK) {
+    if (i >= nR) {
+      int j = i - nR;
+      if (j < nF) {
+        a.flags[a.listF[j]] = LIQ;
+      } else if ((j -= nF) < nEP) {
+        a.flags[a.listEP[j]] = GAS;
+      } else if ((j -= nEP) < nNI) {
+        a.flags[a.listNI[j]] = IFACE;
+      } else {
+        a.flags[a.listNL[j - nNI]] = IFACE;
+      }
+      continue;
+    }
     const int r = a.listR[i];
     int x, y, z;
     coords(g, r, x, y, z);
@@ -958,7 +982,6 @@ template <class F>
 static void convert_form(const StepLaunch& L) {
   hipStream_t st = (hipStream_t)L.stream;
   k_mark<F><<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
-  k_commit<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
   k_share<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
   k_gather<<<LIST_GRID, BLOCK, 0, st>>>(L.conv);
 }
