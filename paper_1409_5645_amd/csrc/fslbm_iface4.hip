@@ -273,31 +273,47 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     // ---- loads.  Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q); beyond a wall
     // halfway bounce-back f_q(x) = ft_qbar(x).
     QuadLinks<R> L;
+    // classes of the pull sources first: the value pulled from a gas source
+    // is replaced by the reconstruction and the fill of a source counts only
+    // where it is an interface cell, so those loads are made only where needed
+    // (a wall source takes the cell's own fill)
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      L.fA[s] = L.fB[s] = L.oA[s] = L.oB[s] = R(0.0);
       L.tA[s] = L.tB[s] = GAS;
-      L.pA[s] = L.pB[s] = 0.0;
+      if (s < nsl) {
+        const int sa = srcA[s], sb = srcB[s];
+        const uint8_t ta = a.flags[sa >= 0 ? sa : idx], tb = a.flags[sb >= 0 ? sb : idx];
+        L.tA[s] = sa >= 0 ? (int)ta : (int)WALL_CLASS;
+        L.tB[s] = sb >= 0 ? (int)tb : (int)WALL_CLASS;
+      }
+    }
+    const double m_old = a.mass_in[idx];
+    const double phix = a.phi_in[idx];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      L.oA[s] = L.oB[s] = R(0.0);
+      if (s < nsl) {
+        const unsigned qA = (unsigned)qa[s], qB = qA + 1u;
+        L.oA[s] = F::load(fin + (qA * N + (unsigned)idx), isc);
+        L.oB[s] = F::load(fin + (qB * N + (unsigned)idx), isc);
+      }
+    }
+    L.f0 = sub == 1 ? F::load(fin + (unsigned)idx, isc) : R(0.0);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      L.fA[s] = L.fB[s] = R(0.0);
+      L.pA[s] = L.pB[s] = phix;
       if (s < nsl) {
         const int sa = srcA[s], sb = srcB[s];
         const unsigned qA = (unsigned)qa[s], qB = qA + 1u;
         const unsigned offA = sa >= 0 ? qA * N + (unsigned)sa : qB * N + (unsigned)idx;
         const unsigned offB = sb >= 0 ? qB * N + (unsigned)sb : qA * N + (unsigned)idx;
-        L.fA[s] = F::load(fin + offA, isc);
-        L.fB[s] = F::load(fin + offB, isc);
-        L.oA[s] = F::load(fin + (qA * N + (unsigned)idx), isc);
-        L.oB[s] = F::load(fin + (qB * N + (unsigned)idx), isc);
-        const int ca = sa >= 0 ? sa : idx, cb = sb >= 0 ? sb : idx;
-        const uint8_t ta = a.flags[ca], tb = a.flags[cb];
-        L.tA[s] = sa >= 0 ? (int)ta : (int)WALL_CLASS;
-        L.tB[s] = sb >= 0 ? (int)tb : (int)WALL_CLASS;
-        L.pA[s] = a.phi_in[ca];
-        L.pB[s] = a.phi_in[cb];
+        if (L.tA[s] != GAS) L.fA[s] = F::load(fin + offA, isc);
+        if (L.tB[s] != GAS) L.fB[s] = F::load(fin + offB, isc);
+        if (L.tA[s] == IFACE) L.pA[s] = a.phi_in[sa];
+        if (L.tB[s] == IFACE) L.pB[s] = a.phi_in[sb];
       }
     }
-    L.f0 = sub == 1 ? F::load(fin + (unsigned)idx, isc) : R(0.0);
-    const double m_old = a.mass_in[idx];
-    const double phix = a.phi_in[idx];
 
     // ---- link classes of the cell (bit q: source of link q is gas / liquid /
     // takes part in the mass exchange), OR-combined over the quad
