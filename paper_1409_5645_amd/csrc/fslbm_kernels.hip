@@ -464,34 +464,47 @@ __global__ __launch_bounds__(IBLOCK) void k_curvature_hf(SweepArgs a) {
 }
 
 // ------------------------------------------------------------ conversions
-template <class F>
-__device__ void init_new_from_gas(const ConvArgs& a, int c) {
-  using R = typename F::R;
-  using S = typename F::S;
-  constexpr bool SH = F::shifted;
+// Classes and auxiliary rows of the 18 neighbours of a new interface cell c
+// from gas (a neighbour beyond a wall reads the cell's own row and counts as
+// gas).  Split from the arithmetic so that the loads can go out before the
+// thread knows that it initialises c.  Nothing here is written by k_mark: the
+// non-gas neighbours of a gas cell are interface cells (a liquid cell never
+// touches gas), and k_mark writes rows of new cells only.
+struct GasNbrs {
+  uint8_t tn[Q];
+  double4 vn[Q];
+};
+
+__device__ __forceinline__ void load_gas_nbrs(const ConvArgs& a, int c, GasNbrs& nb) {
   const Grid& g = a.c.grid;
   int x, y, z;
   coords(g, c, x, y, z);
-  double rs = 0.0, us0 = 0.0, us1 = 0.0, us2 = 0.0;
-  int cnt = 0;
-  // classes and auxiliary rows of all neighbours in one batch of loads (a
-  // neighbour beyond a wall reads the cell's own row and is skipped)
-  uint8_t tn[Q];
-  double4 vn[Q];
 #pragma unroll
   for (int q = 1; q < Q; ++q) {
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
     const int sc = s >= 0 ? s : c;
-    tn[q] = s >= 0 ? a.flags[sc] : (uint8_t)GAS;
-    vn[q] = *reinterpret_cast<const double4*>(a.aux + 4 * (size_t)sc);
+    nb.tn[q] = s >= 0 ? a.flags[sc] : (uint8_t)GAS;
+    nb.vn[q] = *reinterpret_cast<const double4*>(a.aux + 4 * (size_t)sc);
   }
+}
+
+// f = f^eq of the mean collision density and velocity of the non-gas
+// neighbours, mass 0.
+template <class F>
+__device__ void init_new_from_gas(const ConvArgs& a, int c, const GasNbrs& nb) {
+  using R = typename F::R;
+  using S = typename F::S;
+  constexpr bool SH = F::shifted;
+  const Grid& g = a.c.grid;
+  double rs = 0.0, us0 = 0.0, us1 = 0.0, us2 = 0.0;
+  int cnt = 0;
 #pragma unroll
   for (int q = 1; q < Q; ++q) {
-    if (tn[q] == GAS || tn[q] == SOLID) continue;
-    rs = rs + vn[q].x;
-    us0 = us0 + vn[q].y;
-    us1 = us1 + vn[q].z;
-    us2 = us2 + vn[q].w;
+    if (nb.tn[q] == GAS || nb.tn[q] == SOLID) continue;
+    rs = rs + nb.vn[q].x;
+    us0 = us0 + nb.vn[q].y;
+    us1 = us1 + nb.vn[q].z;
+    us2 = us2 + nb.vn[q].w;
     ++cnt;
   }
   const double rbar = rs / (double)cnt;
@@ -507,18 +520,18 @@ __device__ void init_new_from_gas(const ConvArgs& a, int c) {
   a.aux[4 * (size_t)c] = rbar;
 }
 
+// A new interface cell from liquid keeps its populations (of time t+1, written
+// by the sweep); m = rho.  The populations are loaded by the caller.
 template <class F>
-__device__ void init_new_from_liquid(const ConvArgs& a, int c) {
-  using S = typename F::S;
-  const S* fo = reinterpret_cast<const S*>(a.fout);
+__device__ void init_new_from_liquid(const ConvArgs& a, int c, const typename F::R (&fl)[Q]) {
   double r;
   if (F::shifted) {
     double s = 0.0;
-    for (int q = 0; q < Q; ++q) s = s + (double)F::load(fo + (size_t)q * a.c.grid.N + c, a.c.inv_scale);
+    for (int q = 0; q < Q; ++q) s = s + (double)fl[q];
     r = 1.0 + s;
   } else {
-    r = (double)F::load(fo + c, a.c.inv_scale);
-    for (int q = 1; q < Q; ++q) r = r + (double)F::load(fo + (size_t)q * a.c.grid.N + c, a.c.inv_scale);
+    r = (double)fl[0];
+    for (int q = 1; q < Q; ++q) r = r + (double)fl[q];
   }
   a.mass[c] = r;
   a.aux[4 * (size_t)c] = r;
@@ -535,8 +548,11 @@ __device__ __forceinline__ int ep_stamp(int step) { return -2 - step; }
 // change the result (its initialisation reads only pre-conversion classes).
 template <class F>
 __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
+  using R = typename F::R;
+  using S = typename F::S;
   const int nF = a.counters[C_F], nE = a.counters[C_E];
   const Grid& g = a.c.grid;
+  const S* fo = reinterpret_cast<const S*>(a.fout);
   // 18 N < 19 N < 2^32 (the lattice limit): the pair index fits in 32 unsigned bits
   const unsigned total = (unsigned)(nF + nE) * (unsigned)(Q - 1);
   for (unsigned i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += gridDim.x * BLOCK) {
@@ -546,10 +562,17 @@ __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
     int x, y, z;
     coords(g, c, x, y, z);
     const int s = neighbor(g, x, y, z, CX[q], CY[q], CZ[q]);
+    const uint8_t ts = s >= 0 ? a.flags[s] : (uint8_t)SOLID;
     if (e < nF) {
-      const bool win = s >= 0 && a.flags[s] == GAS && atomicExch(&a.new_epoch[s], a.step) != a.step;
+      // a gas neighbour: its initialisation data load with the claim
+      bool win = false;
+      GasNbrs nb;
+      if (ts == GAS) {
+        load_gas_nbrs(a, s, nb);
+        win = atomicExch(&a.new_epoch[s], a.step) != a.step;
+      }
       wave_append(win, &a.counters[C_NI], a.listNI, s);
-      if (win) init_new_from_gas<F>(a, s);
+      if (win) init_new_from_gas<F>(a, s, nb);
     } else {
       // E' = E minus N(F): every thread of the cell takes the same decision
       bool protect = false;
@@ -561,9 +584,16 @@ __global__ __launch_bounds__(BLOCK) void k_mark(ConvArgs a) {
       if (protect) continue;
       if (q == 1) a.new_epoch[c] = ep_stamp(a.step);
       wave_append(q == 1, &a.counters[C_EP], a.listEP, c);
-      const bool win = s >= 0 && a.flags[s] == LIQ && atomicExch(&a.new_epoch[s], a.step) != a.step;
+      // a liquid neighbour: its populations load with the claim
+      bool win = false;
+      R fl[Q];
+      if (ts == LIQ) {
+#pragma unroll
+        for (int p = 0; p < Q; ++p) fl[p] = F::load(fo + (size_t)p * g.N + s, a.c.inv_scale);
+        win = atomicExch(&a.new_epoch[s], a.step) != a.step;
+      }
       wave_append(win, &a.counters[C_NL], a.listNL, s);
-      if (win) init_new_from_liquid<F>(a, s);
+      if (win) init_new_from_liquid<F>(a, s, fl);
     }
   }
 }
