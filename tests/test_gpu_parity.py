@@ -375,14 +375,42 @@ def test_falling_droplet_conversion_burst_parity(fs, oracle_mod, rule, sigma, pl
     _say(f"case falling droplet rule {rule} sigma {sigma} plic {plic}")
     o = oracle_mod.Oracle.from_workload(w)
     s = fs.Sim.from_workload(w)
+    shape = (w.params.nz, w.params.ny, w.params.nx)
     most = 0
+    seen = dict(protected=0, new_from_gas=0, new_from_liquid=0, adjacent_emptied=0, adjacent_filled=0)
     for it in range(10):
         for _ in range(20):
             o.step(1, rule)
             s.step(1, rule)
-            most = max(most, sum(len(v) for v in o.lists().values()))
+            ls = o.lists()
+            most = max(most, sum(len(v) for v in ls.values()))
+            seen["protected"] += len(ls["E"]) - len(ls["E'"])
+            seen["new_from_gas"] += len(ls["NI"])
+            seen["new_from_liquid"] += len(ls["NL"])
+            seen["adjacent_emptied"] += _adjacent_pairs(ls["E'"], shape, (1, 0, 1))
+            seen["adjacent_filled"] += _adjacent_pairs(ls["F"], shape, (1, 0, 1))
         _compare(o, s, f"falling droplet step {20 * (it + 1)}")
     assert most >= 60
+    # the run holds every kind of conversion event the list kernels treat apart
+    # (E' cells and filled cells next to cells of their own kind are not
+    # receivers of each other's excess)
+    assert all(v > 0 for v in seen.values()), seen
+
+
+def _adjacent_pairs(cells, shape, periodic):
+    """Pairs of listed cells that are D3Q19 neighbours (periodic axes wrap)."""
+    nz, ny, nx = shape
+    c = np.asarray(cells, dtype=np.int64)
+    x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+    n = 0
+    for i in range(len(c) - 1):
+        d = []
+        for a, m, per in ((x, nx, periodic[0]), (y, ny, periodic[1]), (z, nz, periodic[2])):
+            da = np.abs(a[i] - a[i + 1:])
+            d.append(np.minimum(da, m - da) if per else da)
+        d2 = d[0] ** 2 + d[1] ** 2 + d[2] ** 2
+        n += int(np.count_nonzero((d2 >= 1) & (d2 <= 2)))
+    return n
 
 
 def _no_liquid_next_to_gas(flags, shape, periodic):
