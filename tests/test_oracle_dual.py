@@ -31,10 +31,28 @@ def case(oracle_mod):
     rng = np.random.default_rng(0)
     ut = rng.normal(0.0, 1e-3, (3, N))
     pt = rng.uniform(0.0, 1.0, N)
-    return w.params, st, ut, pt, rng
+    return w.params, st, ut, pt
 
 
 T = 20
+
+# The random directions of the tests below: slot k holds the shapes ("f": the
+# population array, "n": one value per cell) that test k draws.  Each test
+# replays the draws of seed 0 up to its own, so its directions do not depend on
+# which other tests ran before it in the same process.
+_DRAWS = [("f",), ("f",), ("n", "n"), ("n", "n"), ("f", "f"), ("f", "f"), ("f", "f")]
+
+
+def _rng(st, slot):
+    N = st["flags"].size
+    shape = {"f": st["f"].shape, "n": (N,)}
+    rng = np.random.default_rng(0)
+    rng.normal(0.0, 1e-3, (3, N))
+    rng.uniform(0.0, 1.0, N)
+    for k in range(slot):
+        for d in _DRAWS[k]:
+            rng.normal(0.0, 1.0, shape[d])
+    return rng
 
 
 def _L(oracle_mod, p, st, ut, pt, rule, f=None, m=None, phi=None):
@@ -45,7 +63,7 @@ def _L(oracle_mod, p, st, ut, pt, rule, f=None, m=None, phi=None):
 
 @pytest.mark.parametrize("rule", [0, 1])
 def test_value_part_is_the_fp64_oracle(oracle_mod, case, rule):
-    p, st, ut, pt, _ = case
+    p, st, ut, pt = case
     _, _, fin = oracle_mod.window_dual(p, st["flags"], st["f"], st["mass"], st["phi"], ut, pt, T, rule,
                                        drho_b=1.0, dg=[0.3, -1.0, 0.2], want_state=True)
     o = oracle_mod.Oracle(p, state=dict(st, reservoir=0.0))
@@ -60,7 +78,8 @@ def test_value_part_is_the_fp64_oracle(oracle_mod, case, rule):
 
 @pytest.mark.parametrize("rule", [0, 1])
 def test_populations_direction_vs_central_difference(oracle_mod, case, rule):
-    p, st, ut, pt, rng = case
+    p, st, ut, pt = case
+    rng = _rng(st, rule)
     d = rng.normal(0.0, 1.0, st["f"].shape) * (st["flags"] != W.GAS)
     _, dL = oracle_mod.window_dual(p, st["flags"], st["f"], st["mass"], st["phi"], ut, pt, T, rule, df0=d)
     h = 1e-6
@@ -71,7 +90,8 @@ def test_populations_direction_vs_central_difference(oracle_mod, case, rule):
 
 @pytest.mark.parametrize("rule", [0, 1])
 def test_mass_and_fill_direction_vs_central_difference(oracle_mod, case, rule):
-    p, st, ut, pt, rng = case
+    p, st, ut, pt = case
+    rng = _rng(st, 2 + rule)
     it = st["flags"] == W.INTERFACE
     dphi = rng.normal(0.0, 1.0, it.size) * it
     dm = rng.normal(0.0, 1.0, it.size) * it
@@ -85,7 +105,7 @@ def test_mass_and_fill_direction_vs_central_difference(oracle_mod, case, rule):
 
 @pytest.mark.parametrize("rule", [0, 1])
 def test_gas_density_vs_central_difference(oracle_mod, case, rule):
-    p, st, ut, pt, _ = case
+    p, st, ut, pt = case
     _, dL = oracle_mod.window_dual(p, st["flags"], st["f"], st["mass"], st["phi"], ut, pt, T, rule, drho_b=1.0)
     h = 1e-5 * p.rho_gas
     Lp = oracle_mod.window_dual(dataclasses.replace(p, rho_gas=p.rho_gas + h), st["flags"], st["f"], st["mass"],
@@ -99,7 +119,7 @@ def test_gas_density_vs_central_difference(oracle_mod, case, rule):
 @pytest.mark.parametrize("rule", [0, 1])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_body_force_vs_central_difference(oracle_mod, case, rule, axis):
-    p, st, ut, pt, _ = case
+    p, st, ut, pt = case
     dg = np.zeros(3)
     dg[axis] = 1.0
     _, dL = oracle_mod.window_dual(p, st["flags"], st["f"], st["mass"], st["phi"], ut, pt, T, rule, dg=dg)
@@ -116,7 +136,8 @@ def test_body_force_vs_central_difference(oracle_mod, case, rule, axis):
 
 
 def test_derivative_is_linear_in_the_direction(oracle_mod, case):
-    p, st, ut, pt, rng = case
+    p, st, ut, pt = case
+    rng = _rng(st, 4)
     act = st["flags"] != W.GAS
     d1 = rng.normal(0.0, 1.0, st["f"].shape) * act
     d2 = rng.normal(0.0, 1.0, st["f"].shape) * act
@@ -129,7 +150,8 @@ def test_derivative_is_linear_in_the_direction(oracle_mod, case):
 
 
 def test_linear_population_term_vs_central_difference(oracle_mod, case):
-    p, st, ut, pt, rng = case
+    p, st, ut, pt = case
+    rng = _rng(st, 5)
     act = st["flags"] != W.GAS
     a = rng.normal(0.0, 1.0, st["f"].shape) * act
     d = rng.normal(0.0, 1.0, st["f"].shape) * act
@@ -146,7 +168,8 @@ def test_linear_population_term_vs_central_difference(oracle_mod, case):
 def test_linear_term_alone(oracle_mod, case):
     """Without targets the loss is the linear functional alone: its derivative
     along d equals that of the full loss minus that of the interface term."""
-    p, st, ut, pt, rng = case
+    p, st, ut, pt = case
+    rng = _rng(st, 6)
     act = st["flags"] != W.GAS
     a = rng.normal(0.0, 1.0, st["f"].shape) * act
     d = rng.normal(0.0, 1.0, st["f"].shape) * act
@@ -160,7 +183,7 @@ def test_dual_window_refuses_what_it_does_not_differentiate(oracle_mod, case):
     """The exact derivative covers rules 0 and 1 without PLIC, surface tension
     or solid cells (as the GPU window does); anything else is refused."""
     import dataclasses
-    p, st, ut, pt, rng = case
+    p, st, ut, pt = case
     args = (st["flags"], st["f"], st["mass"], st["phi"], ut, pt, 2)
     for rule in (2, 3, 4, 5):
         with pytest.raises(ValueError, match="rules 0 and 1"):
