@@ -154,7 +154,9 @@ typedef struct {
   void* stream;             /* hipStream_t, or NULL for the null stream */
 } fslbm_buffers;
 
-/* Bytes of workspace a context with these parameters needs. */
+/* Bytes of workspace a context from fslbm_init with these parameters needs
+ * (including a cell -> list-entry map and a list-ordered population buffer of
+ * N/8 entries, at least 32768, for the interface-first step of fslbm_step). */
 fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes);
 
 /* Validate parameters and buffers, check the cell classes on the device (every
@@ -166,8 +168,9 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes);
 fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx** out);
 
 /* Size of the library's static workspace of fslbm_init_static (64 MiB per
- * device: lattices whose fslbm_workspace_size is at most this, e.g. about
- * 880,000 cells without surface tension). */
+ * device: about 880,000 cells without surface tension; a static context needs
+ * less than fslbm_workspace_size, as it always runs the interface kernel after
+ * the sweep). */
 #define FSLBM_STATIC_WORKSPACE_BYTES (64u << 20)
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -177,7 +180,7 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
  * library on the current device, which each device that uses it holds until
  * the process ends.  No device memory is allocated, by this call or by the
  * calls on the context.  The caller still passes every other buffer.
- * FSLBM_E_CAPACITY if fslbm_workspace_size exceeds the array.  One context
+ * FSLBM_E_CAPACITY if its workspace exceeds the array.  One context
  * per device may hold the array at a time: while one exists, a second call
  * on the same device is FSLBM_E_INVALID (contexts sharing it would race);
  * fslbm_destroy releases it.  The array keeps the contents of the previous
@@ -210,9 +213,14 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
  * when the extent in use is 32 steps old the call waits for the next one
  * (so the device has at most 32 steps queued).  The environment variable
  * FSLBM_EXTENT_EVERY at init sets the 16 (0: every row, never a wait).  The
- * classes change only through the steps: a caller that writes the flags
- * buffer between steps calls fslbm_set_state or fslbm_set_equilibrium
- * afterwards, which also make the next step measure the extent again. */
+ * plain step (no moving wall, surface tension, PLIC, solid cells or
+ * prescribed surface) runs the interface kernel before the sweep, which
+ * stores the interface populations with its whole rows; the results are the
+ * same bits as with the interface kernel after the sweep, which the
+ * environment variable FSLBM_REORDER=0 at init selects.  The classes change
+ * only through the steps: a caller that writes the flags buffer between steps
+ * calls fslbm_set_state or fslbm_set_equilibrium afterwards, which also make
+ * the next step measure the extent again and rebuild the interface list. */
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule);
 
 /* Field export into caller device buffers.  mask selects fields by bit; dst[i]

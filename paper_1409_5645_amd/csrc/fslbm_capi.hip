@@ -30,6 +30,15 @@ struct fslbm_ctx {
   int32_t *f_epoch, *new_epoch, *recv_epoch, *conv_epoch;
   int32_t *listF, *listE, *listEP, *listNI, *listNL, *listR, *listI;
   int32_t* counters;    // 2 sets of NCOUNT
+  // interface kernel before the sweep (the plain step with the four-lane
+  // interface kernel): cell -> list entry, the list-ordered populations the
+  // sweep stores, and whether listI / islot / the counter of the current step
+  // hold the list of the current state (else the step builds it first)
+  int32_t* islot = nullptr;
+  void* rbuf = nullptr;
+  int rcap = 0;
+  bool reorder = false;
+  bool list_ok = false;
   double* reservoir;
   double* kappa = nullptr;  // surface tension only
   double* khf = nullptr;    // surface tension with plic = 2 only
@@ -77,8 +86,13 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t aux, epochs[4], lists[7], counters, scalars, extent, wall_t, kappa, khf, total;
+  size_t aux, epochs[4], lists[7], counters, scalars, extent, wall_t, kappa, khf, islot, rbuf, rcap, total;
 };
+
+// Entries of the list-ordered population buffer of the interface-first step:
+// every cell on small lattices, else an eighth of them (at least 32768); an
+// interface list longer than that writes the rest straight into the cells.
+size_t rbuf_entries(size_t N) { return N <= 32768 ? N : std::max<size_t>(32768, N / 8); }
 
 // Moving-wall bounce-back terms per face (x-, x+, y-, y+, z-, z+) and link:
 // 2 w_q (c_q . u_w) / c_s^2 in FP64 (zero on periodic axes and for walls at
@@ -98,8 +112,10 @@ void wall_table(const fslbm_params& p, double out[6 * Q]) {
 }
 
 // kappa: with surface tension, one Laplace-pressure correction per listed cell;
-// hf: with surface tension and plic = 2, the height-function kappa per cell
-Layout layout(size_t N, bool kappa, bool hf) {
+// hf: with surface tension and plic = 2, the height-function kappa per cell;
+// reorder: room for the interface-first step (cell -> list entry, 19
+// populations of s bytes per list entry)
+Layout layout(size_t N, bool kappa, bool hf, size_t s, bool reorder) {
   Layout L{};
   size_t o = 0;
   L.aux = o;
@@ -124,6 +140,11 @@ Layout layout(size_t N, bool kappa, bool hf) {
   if (kappa) o = align_up(o + 8 * N);
   L.khf = o;
   if (kappa && hf) o = align_up(o + 8 * N);
+  L.rcap = reorder ? rbuf_entries(N) : 0;
+  L.islot = o;
+  if (reorder) o = align_up(o + 4 * N);
+  L.rbuf = o;
+  if (reorder) o = align_up(o + (size_t)Q * s * L.rcap);
   L.total = o;
   return L;
 }
@@ -236,7 +257,7 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes) {
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!bytes) { g_init_error = "bytes is NULL"; return FSLBM_E_INVALID; }
-  *bytes = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2).total;
+  *bytes = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2, storage_bytes(p->precision), true).total;
   return FSLBM_OK;
 }
 
@@ -247,13 +268,13 @@ namespace {
 // fslbm_init with the workspace given separately (the caller's buffer, or the
 // library's static array for fslbm_init_static); parameters already checked.
 fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* workspace, size_t workspace_bytes,
-                       fslbm_ctx** out) {
+                       bool reorder, fslbm_ctx** out) {
   if (!b->f[0] || !b->f[1] || !b->flags || !b->mass || !b->phi[0] || !b->phi[1] || !workspace) {
     g_init_error = "a device buffer is NULL";
     return FSLBM_E_INVALID;
   }
   const size_t N = (size_t)p->nx * p->ny * p->nz;
-  const Layout L = layout(N, p->sigma != 0.0, p->plic == 2);
+  const Layout L = layout(N, p->sigma != 0.0, p->plic == 2, storage_bytes(p->precision), reorder);
   if (workspace_bytes < L.total) { g_init_error = "workspace too small"; return FSLBM_E_INVALID; }
   if (((uintptr_t)workspace) % ALIGN) { g_init_error = "workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
 
@@ -288,6 +309,17 @@ fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* work
   if (p->sigma != 0.0) c->kappa = (double*)(w + L.kappa);
   if (p->sigma != 0.0 && p->plic == 2) c->khf = (double*)(w + L.khf);
   c->wall_t = (double*)(w + L.wall_t);
+  if (reorder) {
+    c->islot = (int32_t*)(w + L.islot);
+    c->rbuf = (void*)(w + L.rbuf);
+    c->rcap = (int)L.rcap;
+    // FSLBM_REORDER=0: the interface kernel after the sweep in every step;
+    // FSLBM_RCAP: fewer list entries in the population buffer (the rest are
+    // written straight into the cells)
+    c->reorder = true;
+    if (const char* e = std::getenv("FSLBM_REORDER")) c->reorder = std::atoi(e) != 0;
+    if (const char* e = std::getenv("FSLBM_RCAP")) c->rcap = std::max(0, std::min(c->rcap, std::atoi(e)));
+  }
   {
     double tab[6 * Q];
     wall_table(*p, tab);
@@ -343,7 +375,7 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
-  s = init_impl(p, b, b->workspace, b->workspace_bytes, out);
+  s = init_impl(p, b, b->workspace, b->workspace_bytes, true, out);
   if (s != FSLBM_OK) return s;
   fslbm_ctx* c = *out;
   c->ext_every = 16;
@@ -366,7 +398,8 @@ fslbm_status fslbm_init_static(const fslbm_params* p, const fslbm_buffers* b, fs
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
-  const size_t need = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2).total;
+  const size_t need =
+      layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2, storage_bytes(p->precision), false).total;
   if (need > (size_t)FSLBM_STATIC_WORKSPACE_BYTES) {
     g_init_error = "the lattice needs " + std::to_string(need) + " bytes of workspace, more than the " +
                    std::to_string((size_t)FSLBM_STATIC_WORKSPACE_BYTES) + " of the static workspace";
@@ -392,7 +425,7 @@ fslbm_status fslbm_init_static(const fslbm_params* p, const fslbm_buffers* b, fs
     ws = g_scratch_ptr[dev];
     g_scratch_busy[dev] = true;
   }
-  s = init_impl(p, b, ws, (size_t)FSLBM_STATIC_WORKSPACE_BYTES, out);
+  s = init_impl(p, b, ws, (size_t)FSLBM_STATIC_WORKSPACE_BYTES, false, out);
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   if (s != FSLBM_OK) g_scratch_busy[dev] = false;
   else (*out)->static_device = dev;
@@ -401,10 +434,12 @@ fslbm_status fslbm_init_static(const fslbm_params* p, const fslbm_buffers* b, fs
 
 // A new state may put fluid anywhere: the next step measures the extent
 // again and launches every row until it has arrived (the stream is idle here,
-// so no copy into the host slots is still in flight).
+// so no copy into the host slots is still in flight), and builds the
+// interface list of the new classes.
 static void forget_extent(fslbm_ctx* c) {
   c->ext_valid = -1;
   c->ext_pending = -1;
+  c->list_ok = false;
 }
 
 static InitArgs init_args(fslbm_ctx* c) {
@@ -593,6 +628,14 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     s.nwall = c->nwall > 0 ? c->nwall : 0;
     s.surf_n = c->surf_n;
     s.surf_d = c->surf_d;
+    // the plain step with the four-lane interface kernel runs it before the
+    // sweep (the other variants after it)
+    const bool extra = s.c.moving || s.c.sigma != 0.0 || s.c.plic || s.c.solid || s.c.surface;
+    const bool order = c->reorder && c->quad && !extra;
+    s.order = order ? 1 : 0;
+    s.islot = c->islot;
+    s.rbuf = c->rbuf;
+    s.rcap = c->rcap;
     HIPCHK(c, sweep_box(c, s), "extent");
     ConvArgs& v = L.conv;
     v.c = c->com;
@@ -614,7 +657,18 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
     v.counters = s.counters;
     v.reservoir = c->reservoir;
     v.step = c->step;
+    v.order = s.order;
+    v.listI = c->listI;
+    v.islot = c->islot;
+    v.counters_next = s.counters_next;
     L.stream = (void*)c->stream;
+    if (order) {
+      // the interface list of the current classes, when no step has left it
+      if (!c->list_ok)
+        HIPCHK(c, launch_list_append(c->flags, c->com.grid, s.counters + C_I, c->listI, c->islot, c->stream),
+               "interface list");
+      HIPCHK(c, launch_iface(L, c->p.precision, rule), "interface launch");
+    }
     if (c->timing) {
       while (c->events.size() < c->events_used + 2) {
         hipEvent_t ev;
@@ -628,10 +682,13 @@ fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule) {
       HIPCHK(c, hipEventRecord(c->events[c->events_used + 1], c->stream), "event record");
       c->events_used += 2;
     }
-    if (s.nwall > 0) HIPCHK(c, launch_wall(L, c->p.precision), "wall launch");
-    if (c->kappa) HIPCHK(c, launch_curvature(L), "curvature launch");
-    HIPCHK(c, launch_iface(L, c->p.precision, rule), "interface launch");
+    if (!order) {
+      if (s.nwall > 0) HIPCHK(c, launch_wall(L, c->p.precision), "wall launch");
+      if (c->kappa) HIPCHK(c, launch_curvature(L), "curvature launch");
+      HIPCHK(c, launch_iface(L, c->p.precision, rule), "interface launch");
+    }
     if (!s.freeze) HIPCHK(c, launch_convert(L, c->p.precision), "conversion launch");
+    c->list_ok = order;
     c->cur = b;
     c->step += 1;
     if (c->check_every > 0 && c->step % c->check_every == 0) {
@@ -1088,6 +1145,7 @@ fslbm_status fslbm_window_forward(fslbm_ctx* c, int32_t T, int32_t K, int32_t ru
   if (!c) return FSLBM_E_INVALID;
   if (!out || !workspace) { c->last_error = "out or workspace is NULL"; return FSLBM_E_INVALID; }
   if (((uintptr_t)workspace) % ALIGN) { c->last_error = "window workspace not 256-byte aligned"; return FSLBM_E_INVALID; }
+  c->list_ok = false;  // the window's steps keep their own lists; the next plain step rebuilds
   if (rule >= FSLBM_RULE_FSK_STRESS && rule <= FSLBM_RULE_FSL_SHEAR) {
     c->last_error = "the adjoint window supports the FSK and FSL rules (D = 0)";
     return FSLBM_E_UNSUPPORTED;

@@ -1,6 +1,9 @@
 // Interface cells of the step with four lanes per cell (a quad), for the
 // rules and forms of the plain step (no moving walls, surface tension, PLIC or
-// solid cells, no adjoint record; those take k_iface).
+// solid cells, no adjoint record; those take k_iface).  Run before the sweep
+// (SweepArgs::order), it takes the list the step before built and writes the
+// populations into a list-ordered buffer that the sweep stores with its rows,
+// instead of 19 scattered 2-, 4- or 8-byte stores per cell.
 //
 // The 18 moving links form 9 pairs of opposites (q, q + 1), q odd; lane s of
 // the quad owns pairs s and s + 4, lane 0 also pair 8 and lane 1 the rest
@@ -200,8 +203,14 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
   constexpr bool SH = F::shifted;
   const Grid g = a.c.grid;
   const int n_i = a.counters[C_I];
+  // before the sweep (order 1) this kernel opens the counters of the next step
+  if (a.order && blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < NCOUNT; ++c) a.counters_next[c] = 0;
+  }
   const S* __restrict__ fin = reinterpret_cast<const S*>(a.fin);
   S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
+  S* __restrict__ rbuf = reinterpret_cast<S*>(a.rbuf);
   const unsigned N = (unsigned)g.N;  // 19 N < 2^32 is checked at init
   const float isc = a.c.inv_scale;
   const Consts<R>& k = pick_consts<R>(a.c);
@@ -236,6 +245,9 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     const int i = chunk * QCELLS + ((int)threadIdx.x >> 2);
     if (chunk >= nchunk || i >= n_i) continue;  // quad-uniform
     const int idx = a.listI[i];
+    // the list of order 1 comes from the step before: an entry whose cell has
+    // since filled or emptied is skipped (quad-uniform)
+    if (a.order && a.flags[idx] != IFACE) continue;
     Nbr n;
     coords(g, idx, n.x, n.y, n.z);
     // ---- pull sources: link A (c = d) pulls from x - d, link B (c = -d)
@@ -590,16 +602,21 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
         L.fB[s] = __builtin_fmaf(-k.lm, nm, B0 + lpn);
       }
     }
-    // ---- stores: populations of the lane's links; the cell's scalars (FP64
-    // bookkeeping) and classification from lane 0
+    // ---- stores: populations of the lane's links (order 1: into list entry
+    // i of rbuf, which the sweep stores with its rows; past rcap, and in
+    // order 0, into the cell); the cell's scalars (FP64 bookkeeping) and
+    // classification from lane 0
+    const bool to_r = a.order && i < a.rcap;
+    S* const pb = to_r ? rbuf + i : fout + idx;
+    const unsigned ps = to_r ? (unsigned)a.rcap : N;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       if (s < nsl) {
-        F::store(fout + ((unsigned)qa[s] * N + (unsigned)idx), L.fA[s], a.c.scale);
-        F::store(fout + ((unsigned)(qa[s] + 1) * N + (unsigned)idx), L.fB[s], a.c.scale);
+        F::store(pb + (unsigned)qa[s] * ps, L.fA[s], a.c.scale);
+        F::store(pb + (unsigned)(qa[s] + 1) * ps, L.fB[s], a.c.scale);
       }
     }
-    if (sub == 1) F::store(fout + (unsigned)idx, L.f0, a.c.scale);
+    if (sub == 1) F::store(pb, L.f0, a.c.scale);
     const double rho = SH ? 1.0 + (double)rho_s : (double)rho_s;
     bool filled = false, emptied = false;
     if (lead) {

@@ -66,6 +66,18 @@ struct SweepArgs {
   int box, by0, bny, bz0, bnz;
   int pairs; // FP16 form: two cells per lane when rows have even length
   int quad;  // interface cells of the plain step with four lanes per cell (k_iface4); 2: XCD-aware order
+  // order != 0: the interface kernel runs before the sweep.  It takes the
+  // list of time t that the previous step built (listI, counters[C_I]; with
+  // holes where a cell has left the interface) and writes the populations of
+  // t+1 of list entry i to rbuf[q * rcap + i] (i < rcap; beyond that straight
+  // into fout).  The sweep then stores them with the rows it writes whole,
+  // lists the interface cells of time t for the next step (counters_next,
+  // islot: cell -> list entry) and leaves the counter zeroing to the
+  // interface kernel.
+  int order;
+  int32_t* islot;
+  void* rbuf;
+  int rcap;
   void* u_out;  // optional (FP64 / FP32 forms): collision velocity of liquid cells, [3][N] compute type
   // optional per-step record of the interface cells (list order, capacity
   // rec_cap): pulled and own populations of time t (compute type, [Q][cap]),
@@ -109,6 +121,12 @@ struct ConvArgs {
   int32_t* counters;
   double* reservoir;
   int step;
+  // order != 0 (SweepArgs::order): the new interface cells join the list of
+  // the next step (listI, counters_next[C_I], islot)
+  int order;
+  int32_t* listI;
+  int32_t* islot;
+  int32_t* counters_next;
 };
 
 struct StepLaunch {
@@ -201,6 +219,10 @@ hipError_t launch_iface(const StepLaunch& L, int precision, int rule);
 hipError_t launch_iface4(const StepLaunch& L, int precision, int rule);  // fslbm_iface4.hip
 hipError_t launch_curvature(const StepLaunch& L);  // one or (plic = 2) two list kernels
 hipError_t launch_convert(const StepLaunch& L, int precision);
+// interface cells of the current classes -> list, islot, *counter (a step with
+// the interface kernel first after a new state)
+hipError_t launch_list_append(const uint8_t* flags, const Grid& g, int32_t* counter, int32_t* list, int32_t* islot,
+                              void* stream);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, void* stream);
 hipError_t launch_fill_f64(double* p, size_t n, double v, void* stream);
 hipError_t launch_check_flags(const uint8_t* flags, const Grid& g, int32_t* err, void* stream);

@@ -3,9 +3,13 @@
 // Per time step t (stream order, no host synchronisation):
 //   k_sweep   (fslbm_sweep.hip) pull stream + bounce-back + TRT collision of
 //             the liquid cells; builds the interface-cell list.
-//   k_iface   interface cells: mass exchange, interface geometry, FSK/FSL
+//   k_iface   interface cells (k_iface4 in fslbm_iface4.hip for the plain
+//             step): mass exchange, interface geometry, FSK/FSL
 //             reconstruction, TRT collision, fill update and filled/emptied
 //             classification with list append.
+//   The plain step runs k_iface4 first, on the list the step before built,
+//   and k_sweep stores its populations (the interface-first order of
+//   SweepArgs::order).
 //   k_mark    E' = E minus N(F); new interface cells from gas next to filled
 //             cells (initialised from their interface neighbours) and from
 //             liquid next to E' cells.
@@ -15,7 +19,8 @@
 //             new cell classes.
 // Membership marks are step-stamped int arrays ("epochs"), so nothing needs to
 // be cleared between steps; list counters are double buffered by step parity
-// and the sweep of step t zeroes the set of step t+1.  The cell classes keep
+// and the sweep of step t (the interface kernel, when it runs first) zeroes
+// the set of step t+1.  The cell classes keep
 // their values of time t until k_gather: k_share takes the classes after the
 // conversions from the marks (iface_after).
 #include "fslbm_device.hpp"
@@ -650,7 +655,8 @@ __global__ __launch_bounds__(BLOCK) void k_share(ConvArgs a) {
   }
 }
 
-// Receivers (first nR threads) and the new cell classes (the rest).
+// Receivers (first nR threads) and the new cell classes (the rest; with the
+// interface kernel first, the new interface cells also join the next list).
 __global__ __launch_bounds__(BLOCK) void k_gather(ConvArgs a) {
   const int nR = a.counters[C_R];
   const int nF = a.counters[C_F], nEP = a.counters[C_EP], nNI = a.counters[C_NI], nNL = a.counters[C_NL];
@@ -658,15 +664,27 @@ __global__ __launch_bounds__(BLOCK) void k_gather(ConvArgs a) {
   const Grid& g = a.c.grid;
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < tot; i += gridDim.x * BLOCK) {
     if (i >= nR) {
-      int j = i - nR;
+      int j = i - nR, cell;
+      uint8_t cls;
       if (j < nF) {
-        a.flags[a.listF[j]] = LIQ;
+        cell = a.listF[j];
+        cls = LIQ;
       } else if ((j -= nF) < nEP) {
-        a.flags[a.listEP[j]] = GAS;
+        cell = a.listEP[j];
+        cls = GAS;
       } else if ((j -= nEP) < nNI) {
-        a.flags[a.listNI[j]] = IFACE;
+        cell = a.listNI[j];
+        cls = IFACE;
       } else {
-        a.flags[a.listNL[j - nNI]] = IFACE;
+        cell = a.listNL[j - nNI];
+        cls = IFACE;
+      }
+      a.flags[cell] = cls;
+      if (a.order) {
+        // a new interface cell joins the list of the next step
+        const bool join = cls == IFACE;
+        const int pos = wave_append_at(join, &a.counters_next[C_I], a.listI, cell);
+        if (join) a.islot[cell] = pos;
       }
       continue;
     }
@@ -691,6 +709,17 @@ __global__ __launch_bounds__(BLOCK) void k_gather(ConvArgs a) {
     a.mass[r] = m;
     a.phi_out[r] = m / a.aux[4 * (size_t)r];
   }
+}
+
+// The interface cells of the current classes into list and islot (cell -> list
+// entry), in wavefront order; *counter (zero before) becomes their number.  For
+// the first step with the interface kernel first after a new state.
+__global__ __launch_bounds__(BLOCK) void k_list_append(const uint8_t* __restrict__ flags, int N, int32_t* counter,
+                                                       int32_t* list, int32_t* islot) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const bool it = i < N && flags[i] == IFACE;
+  const int pos = wave_append_at(it, counter, list, i);
+  if (it) islot[i] = pos;
 }
 
 // --------------------------------------------------------- init / export
@@ -1153,6 +1182,14 @@ hipError_t launch_iface(const StepLaunch& L, int precision, int rule) {
   if (precision == 0) iface_form<FormF64>(L, rule);
   else if (precision == 1) iface_form<FormF32>(L, rule);
   else iface_form<FormF16>(L, rule);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_append(const uint8_t* flags, const Grid& g, int32_t* counter, int32_t* list, int32_t* islot,
+                              void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  k_fill_i32<<<1, BLOCK, 0, st>>>(counter, 1, 0);
+  k_list_append<<<blocks_for((size_t)g.N), BLOCK, 0, st>>>(flags, g.N, counter, list, islot);
   return hipGetLastError();
 }
 

@@ -40,6 +40,21 @@ struct IfaceData {
   double m, phix;
 };
 
+// As wave_append below, returning the list position of the lane's value (-1
+// where pred is false).
+__device__ __forceinline__ int wave_append_at(bool pred, int32_t* counter, int32_t* list, int32_t value) {
+  const unsigned long long b = __ballot(pred);
+  if (b == 0ull) return -1;
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((long long)b) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(b));
+  base = __shfl(base, leader);
+  const int pos = base + __popcll(b & ((1ull << lane) - 1ull));
+  if (pred) list[pos] = value;
+  return pred ? pos : -1;
+}
+
 // Append value to list for every active lane with pred set, with one atomic
 // per wavefront: the lowest such lane reserves the slots, each lane writes at
 // its rank among them (lanes that have left the branch take no part).

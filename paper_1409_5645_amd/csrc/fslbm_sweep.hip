@@ -12,14 +12,20 @@ constexpr int BLOCK = 256;
 // Stream/collide sweep over liquid cells, one cell per lane; a block covers a
 // chunk of one lattice row, so the row, its y and z and the source rows of
 // every link are uniform (scalar) values.  Interface cells are appended to the
-// interface list (one atomic per wavefront) and updated by k_iface.  A
-// wavefront without liquid cells exits; in one with liquid cells every lane of
-// the row (but solid cells) pulls, collides and stores, so that its stores
-// cover whole cache lines: a partly written line costs the memory system more
-// than a whole one.  What it writes into gas and interface cells is not a
-// result: the interface kernel, which runs after this one, overwrites the
-// interface cells, and gas populations are never read (a cell that becomes
-// interface is initialised in full).
+// interface list (one atomic per wavefront) and updated by the interface
+// kernel.  A wavefront without liquid cells exits; in one with liquid cells
+// every lane of the row (but solid cells) pulls, collides and stores, so that
+// its stores cover whole cache lines: a partly written line costs the memory
+// system more than a whole one.  What it writes into gas cells is not a
+// result (gas populations are never read; a cell that becomes interface is
+// initialised in full).  The interface cells take one of two orders:
+//   - order 0: the interface kernel runs after this one and overwrites them
+//     (a step with walls, surface tension, PLIC, solids or an adjoint record,
+//     or any step with FSLBM_REORDER=0);
+//   - order 1: the interface kernel ran before this one and left their
+//     populations in a list-ordered buffer; a wavefront with liquid or
+//     interface cells stores them with its whole row segment, and the list
+//     built here is that of the next step.
 //
 // Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q).  A source beyond a wall gives
 // halfway bounce-back f_q(x) = ft_qbar(x).  Every load is unconditional with a
@@ -33,7 +39,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   using S = typename F::S;
   constexpr bool SH = F::shifted;
   const Grid g = a.c.grid;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !a.order) {
 #pragma unroll
     for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
   }
@@ -45,19 +51,24 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   const int x = chunk * (int)blockDim.x + (int)threadIdx.x;
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
-  const int lane = (int)threadIdx.x & 63;
+  const bool it = t == IFACE;
+  // with the interface kernel first: the list entry of time t that holds this
+  // interface cell's populations of t+1 (read before the entry of the next
+  // list replaces it)
+  const int oslot = (a.order && it) ? a.islot[rbase + x] : -1;
   {
-    // interface cells -> list (wavefront-aggregated append)
-    const unsigned long long b = __ballot(t == IFACE);
-    if (b) {
-      const int leader = __ffsll((long long)b) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
-      base = __shfl(base, leader);
-      if (t == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)(rbase + x);
-    }
+    // interface cells -> list (of this step; with the interface kernel first,
+    // of the next step), wavefront-aggregated append
+    const int pos = wave_append_at(it, a.order ? &a.counters_next[C_I] : &a.counters[C_I], a.listI, (int)(rbase + x));
+    // the map is read at interface cells only; a wavefront with interface
+    // cells writes its whole segment of it (-1 elsewhere), so no line of it
+    // is left partly written
+    if (a.order && __ballot(it) != 0ull && x < g.nx) a.islot[rbase + x] = pos;
   }
-  if (__ballot(t == LIQ) == 0) return;
+  // a wavefront without liquid cells that holds interface cells (order 1)
+  // pulls nothing: it only stores their populations from the list buffer
+  const bool wliq = __ballot(t == LIQ) != 0ull;
+  if (!wliq && (!a.order || __ballot(it) == 0ull)) return;
   if (x >= g.nx || t == SOLID) return;
 
   // source rows (element offsets) of the nine (c_y, c_z) combinations
@@ -79,6 +90,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   // lane), so all 19 loads of a cell are in flight together.  F::load_raw
   // keeps the FP16 form in its storage units (the collision absorbs the scale).
   R f[Q];
+  R rho_s = R(0.0), u[3] = {R(0.0), R(0.0), R(0.0)};
+  if (wliq) {
 #define FSLBM_PULL(q)                                                                               \
   {                                                                                                 \
     const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                        \
@@ -87,34 +100,48 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
                                                     : (unsigned)q * N + ro + (unsigned)sx;          \
     f[q] = F::load_raw(fin + off);                                                                  \
   }
-  FSLBM_PULL(0)
-  FSLBM_LINKS(FSLBM_PULL)
+    FSLBM_PULL(0)
+    FSLBM_LINKS(FSLBM_PULL)
 #undef FSLBM_PULL
-  if (a.c.moving) {
-    // moving walls (uniform branch): halfway bounce-back gains 2 w_q (c_q . u_w) / c_s^2,
-    // in storage units for the FP16 form
-    const double su = F::scaled ? (double)a.c.scale : 1.0;
+    if (a.c.moving) {
+      // moving walls (uniform branch): halfway bounce-back gains 2 w_q (c_q . u_w) / c_s^2,
+      // in storage units for the FP16 form
+      const double su = F::scaled ? (double)a.c.scale : 1.0;
 #define FSLBM_WALLU(q)                                                         \
   {                                                                            \
     const double t = wall_term<q>(a.wall_t, xm, xp, ym, yp, zm, zp);           \
     if (t != 0.0) f[q] = f[q] + (R)(t * su);                                   \
   }
-    FSLBM_LINKS(FSLBM_WALLU)
+      FSLBM_LINKS(FSLBM_WALLU)
 #undef FSLBM_WALLU
-  }
+    }
 
-  // ---- TRT collision, Eq. (lbe2)
-  const Consts<R>& k = pick_consts<R>(a.c);
-  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
-  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
-  R rho_s, u[3];
-  if constexpr (sizeof(R) == 4)
-    collide_f32_scaled<SH, F::scaled>(f, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
-  else
-    collide<R, SH>(f, k, incomp, stokes, rho_s, u);
-  S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
+    // ---- TRT collision, Eq. (lbe2)
+    const Consts<R>& k = pick_consts<R>(a.c);
+    const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+    const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+    if constexpr (sizeof(R) == 4)
+      collide_f32_scaled<SH, F::scaled>(f, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+    else
+      collide<R, SH>(f, k, incomp, stokes, rho_s, u);
+  } else {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+    for (int q = 0; q < Q; ++q) f[q] = R(0.0);
+  }
+  S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
+  // an interface cell stores what the interface kernel computed for it (its
+  // list entry beyond rcap: written there directly, left alone here)
+  const bool from_r = a.order && it;
+  const bool keep = from_r && (unsigned)oslot >= (unsigned)a.rcap;
+  if (from_r && !keep) {
+    const S* __restrict__ rb = reinterpret_cast<const S*>(a.rbuf) + oslot;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = F::load_raw(rb + (unsigned)q * (unsigned)a.rcap);
+  }
+  if (!keep) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+  }
   if constexpr (WITH_U) {
     // collision velocity of the liquid cells, kept for the adjoint of this step
     if (t == LIQ) {
@@ -210,7 +237,7 @@ __device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const 
 template <int MODEL>
 __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   const Grid g = a.c.grid;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !a.order) {
 #pragma unroll
     for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
   }
@@ -225,21 +252,32 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint16_t fl2 = valid ? *reinterpret_cast<const uint16_t*>(a.flags + rbase + xl) : (uint16_t)0;
   const uint8_t tt[2] = {(uint8_t)(fl2 & 0xffu), (uint8_t)(fl2 >> 8)};
-  const int lane = (int)threadIdx.x & 63;
-  // interface cells -> list (wavefront-aggregated append, one cell of the pair at a time)
+  // with the interface kernel first: the list entries of time t that hold the
+  // populations of t+1 of the pair's interface cells (read before the entries
+  // of the next list replace them)
+  int oslot[2] = {-1, -1};
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const unsigned long long b = __ballot(tt[j] == IFACE);
-    if (b) {
-      const int leader = __ffsll((long long)b) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
-      base = __shfl(base, leader);
-      if (tt[j] == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)rbase + x0 + j;
-    }
-  }
+  for (int j = 0; j < 2; ++j)
+    if (a.order && tt[j] == IFACE) oslot[j] = a.islot[rbase + (unsigned)(x0 + j)];
+  // interface cells -> list (of this step; with the interface kernel first, of
+  // the next step), wavefront-aggregated append, one cell of the pair at a time
+  int pos[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    pos[j] = wave_append_at(tt[j] == IFACE, a.order ? &a.counters_next[C_I] : &a.counters[C_I], a.listI,
+                            (int)rbase + x0 + j);
+  // the map is read at interface cells only; a wavefront with interface cells
+  // writes its whole segment of it (-1 elsewhere, 8 bytes per pair), so no
+  // line of it is left partly written
+  if (a.order && __ballot(tt[0] == IFACE || tt[1] == IFACE) != 0ull && valid)
+    *reinterpret_cast<int2*>(a.islot + rbase + (unsigned)x0) = make_int2(pos[0], pos[1]);
   const bool liq = tt[0] == LIQ || tt[1] == LIQ;
-  if (__ballot(liq) == 0) return;  // lanes exchange data below: whole wavefronts only
+  const bool from_r0 = a.order && tt[0] == IFACE, from_r1 = a.order && tt[1] == IFACE;
+  // lanes exchange data below: whole wavefronts only.  A wavefront without
+  // liquid cells that holds interface cells (order 1) pulls nothing: it only
+  // stores their populations from the list buffer.
+  const bool wliq = __ballot(liq) != 0ull;
+  if (!wliq && __ballot(from_r0 || from_r1) == 0ull) return;
 
   const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
   const int zm = step_axis(z, -1, g.nz, g.pz), zp = step_axis(z, 1, g.nz, g.pz);
@@ -260,29 +298,55 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   for (int i = 0; i < 9; ++i) srow2[i] = srow[i] == WALL_ROW ? WALL_ROW : 2u * srow[i];
 
   float f0[Q], f1[Q];
-  // interior blocks (no source row beyond a y/z wall) take a select-only pull;
-  // the few blocks on the y/z faces take the general one
-  bool wall_rows = false;
+  if (wliq) {
+    // interior blocks (no source row beyond a y/z wall) take a select-only pull;
+    // the few blocks on the y/z faces take the general one
+    bool wall_rows = false;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
-  const bool ld = tt[0] != GAS || tt[1] != GAS;  // lanes past the row end read as gas
-  if (!wall_rows)
-    pull_pair<false>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
-  else
-    pull_pair<true>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
+    for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
+    const bool ld = tt[0] != GAS || tt[1] != GAS;  // lanes past the row end read as gas
+    if (!wall_rows)
+      pull_pair<false>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
+    else
+      pull_pair<true>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
 
-  // ---- TRT collision, Eq. (lbe2), in storage units
-  const Consts<float>& k = a.c.kf;
-  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
-  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
-  float rho_s, u[3];
-  collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
-  collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+    // ---- TRT collision, Eq. (lbe2), in storage units
+    const Consts<float>& k = a.c.kf;
+    const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+    const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+    float rho_s, u[3];
+    collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+    collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f0[q] = f1[q] = 0.0f;
+  }
   if (valid && tt[0] != SOLID && tt[1] != SOLID) {
+    // an interface cell stores what the interface kernel computed for it (its
+    // list entry beyond rcap: written there directly, left alone here)
+    const bool keep0 = from_r0 && (unsigned)oslot[0] >= (unsigned)a.rcap;
+    const bool keep1 = from_r1 && (unsigned)oslot[1] >= (unsigned)a.rcap;
+    const uint16_t* __restrict__ rb = reinterpret_cast<const uint16_t*>(a.rbuf);
+    const unsigned rc = (unsigned)a.rcap;
+    if (from_r0 && !keep0) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) f0[q] = h_one(rb[(unsigned)q * rc + (unsigned)oslot[0]]);
+    }
+    if (from_r1 && !keep1) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) f1[q] = h_one(rb[(unsigned)q * rc + (unsigned)oslot[1]]);
+    }
     char* __restrict__ fo = reinterpret_cast<char*>(a.fout);
     const unsigned o = 2u * (rbase + (unsigned)x0);
+    if (!keep0 && !keep1) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fo + ((unsigned)q * N2 + o)) = h_pack(f0[q], f1[q]);
+      for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fo + ((unsigned)q * N2 + o)) = h_pack(f0[q], f1[q]);
+    } else {
+      for (int q = 0; q < Q; ++q) {
+        if (!keep0) *reinterpret_cast<_Float16*>(fo + ((unsigned)q * N2 + o)) = (_Float16)f0[q];
+        if (!keep1) *reinterpret_cast<_Float16*>(fo + ((unsigned)q * N2 + o + 2u)) = (_Float16)f1[q];
+      }
+    }
   }
 }
 
