@@ -212,12 +212,13 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
  * measured on the device every 16 steps and read back without a wait, and
  * when the extent in use is 32 steps old the call waits for the next one
  * (so the device has at most 32 steps queued).  The environment variable
- * FSLBM_EXTENT_EVERY at init sets the 16 (0: every row, never a wait).  The
- * plain step (no moving wall, surface tension, PLIC, solid cells or
- * prescribed surface) runs the interface kernel before the sweep, which
- * stores the interface populations with its whole rows; the results are the
- * same bits as with the interface kernel after the sweep, which the
- * environment variable FSLBM_REORDER=0 at init selects.  The classes change
+ * FSLBM_EXTENT_EVERY at init sets the 16 (0: every row, never a wait).  In
+ * the FP32 and FP16 forms the plain step (no moving wall, surface tension,
+ * PLIC, solid cells or prescribed surface) runs the interface kernel before
+ * the sweep, which stores the interface populations with its whole rows; the
+ * results are the same bits as with the interface kernel after the sweep.
+ * The environment variable FSLBM_REORDER at init (0 / 1) selects either
+ * order for every form.  The classes change
  * only through the steps: a caller that writes the flags buffer between steps
  * calls fslbm_set_state or fslbm_set_equilibrium afterwards, which also make
  * the next step measure the extent again and rebuild the interface list. */

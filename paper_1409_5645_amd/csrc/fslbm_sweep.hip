@@ -20,8 +20,8 @@ constexpr int BLOCK = 256;
 // result (gas populations are never read; a cell that becomes interface is
 // initialised in full).  The interface cells take one of two orders:
 //   - order 0: the interface kernel runs after this one and overwrites them
-//     (a step with walls, surface tension, PLIC, solids or an adjoint record,
-//     or any step with FSLBM_REORDER=0);
+//     (the FP64 form, a step with walls, surface tension, PLIC, solids or an
+//     adjoint record, or any step with FSLBM_REORDER=0);
 //   - order 1: the interface kernel ran before this one and left their
 //     populations in a list-ordered buffer; a wavefront with liquid or
 //     interface cells stores them with its whole row segment, and the list
@@ -52,19 +52,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
   const bool it = t == IFACE;
-  // with the interface kernel first: the list entry of time t that holds this
-  // interface cell's populations of t+1 (read before the entry of the next
-  // list replaces it)
-  const int oslot = (a.order && it) ? a.islot[rbase + x] : -1;
-  {
-    // interface cells -> list (of this step; with the interface kernel first,
-    // of the next step), wavefront-aggregated append
-    const int pos = wave_append_at(it, a.order ? &a.counters_next[C_I] : &a.counters[C_I], a.listI, (int)(rbase + x));
-    // the map is read at interface cells only; a wavefront with interface
-    // cells writes its whole segment of it (-1 elsewhere), so no line of it
-    // is left partly written
-    if (a.order && __ballot(it) != 0ull && x < g.nx) a.islot[rbase + x] = pos;
-  }
+  // interface cells -> this step's list, wavefront-aggregated append (with
+  // the interface kernel first: the next step's list, after the collision)
+  if (!a.order) wave_append(it, &a.counters[C_I], a.listI, (int)(rbase + x));
   // a wavefront without liquid cells that holds interface cells (order 1)
   // pulls nothing: it only stores their populations from the list buffer
   const bool wliq = __ballot(t == LIQ) != 0ull;
@@ -129,9 +119,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
     for (int q = 0; q < Q; ++q) f[q] = R(0.0);
   }
   S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
+  // With the interface kernel first (a wavefront with interface cells has
+  // come this far, and every lane of the row but none past its end): the list
+  // entry of time t of an interface cell, then its entry in the next list.
+  // The map is read at interface cells only; a wavefront with interface cells
+  // writes its whole segment of it (-1 elsewhere), so no line of it is left
+  // partly written.
+  const bool from_r = a.order && it;
+  int oslot = -1;
+  if (a.order) {
+    if (it) oslot = a.islot[rbase + x];
+    const int pos = wave_append_at(it, &a.counters_next[C_I], a.listI, (int)(rbase + x));
+    if (__ballot(it) != 0ull) a.islot[rbase + x] = pos;
+  }
   // an interface cell stores what the interface kernel computed for it (its
   // list entry beyond rcap: written there directly, left alone here)
-  const bool from_r = a.order && it;
   const bool keep = from_r && (unsigned)oslot >= (unsigned)a.rcap;
   if (from_r && !keep) {
     const S* __restrict__ rb = reinterpret_cast<const S*>(a.rbuf) + oslot;
@@ -252,25 +254,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint16_t fl2 = valid ? *reinterpret_cast<const uint16_t*>(a.flags + rbase + xl) : (uint16_t)0;
   const uint8_t tt[2] = {(uint8_t)(fl2 & 0xffu), (uint8_t)(fl2 >> 8)};
-  // with the interface kernel first: the list entries of time t that hold the
-  // populations of t+1 of the pair's interface cells (read before the entries
-  // of the next list replace them)
-  int oslot[2] = {-1, -1};
+  // interface cells -> this step's list, wavefront-aggregated append, one
+  // cell of the pair at a time (with the interface kernel first: the next
+  // step's list, after the collision)
+  if (!a.order) {
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
-    if (a.order && tt[j] == IFACE) oslot[j] = a.islot[rbase + (unsigned)(x0 + j)];
-  // interface cells -> list (of this step; with the interface kernel first, of
-  // the next step), wavefront-aggregated append, one cell of the pair at a time
-  int pos[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-    pos[j] = wave_append_at(tt[j] == IFACE, a.order ? &a.counters_next[C_I] : &a.counters[C_I], a.listI,
-                            (int)rbase + x0 + j);
-  // the map is read at interface cells only; a wavefront with interface cells
-  // writes its whole segment of it (-1 elsewhere, 8 bytes per pair), so no
-  // line of it is left partly written
-  if (a.order && __ballot(tt[0] == IFACE || tt[1] == IFACE) != 0ull && valid)
-    *reinterpret_cast<int2*>(a.islot + rbase + (unsigned)x0) = make_int2(pos[0], pos[1]);
+    for (int j = 0; j < 2; ++j) wave_append(tt[j] == IFACE, &a.counters[C_I], a.listI, (int)rbase + x0 + j);
+  }
   const bool liq = tt[0] == LIQ || tt[1] == LIQ;
   const bool from_r0 = a.order && tt[0] == IFACE, from_r1 = a.order && tt[1] == IFACE;
   // lanes exchange data below: whole wavefronts only.  A wavefront without
@@ -320,6 +310,22 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   } else {
 #pragma unroll
     for (int q = 0; q < Q; ++q) f0[q] = f1[q] = 0.0f;
+  }
+  // With the interface kernel first (every wavefront with interface cells has
+  // come this far): the list entries of time t of the pair's interface cells,
+  // then their entries in the next list.  The map is read at interface cells
+  // only; a wavefront with interface cells writes its whole segment of it (-1
+  // elsewhere, 8 bytes per pair), so no line of it is left partly written.
+  int oslot[2] = {-1, -1};
+  if (a.order) {
+    int pos[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (tt[j] == IFACE) oslot[j] = a.islot[rbase + (unsigned)(x0 + j)];
+      pos[j] = wave_append_at(tt[j] == IFACE, &a.counters_next[C_I], a.listI, (int)rbase + x0 + j);
+    }
+    if (__ballot(from_r0 || from_r1) != 0ull && valid)
+      *reinterpret_cast<int2*>(a.islot + rbase + (unsigned)x0) = make_int2(pos[0], pos[1]);
   }
   if (valid && tt[0] != SOLID && tt[1] != SOLID) {
     // an interface cell stores what the interface kernel computed for it (its
