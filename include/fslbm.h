@@ -155,8 +155,9 @@ typedef struct {
 } fslbm_buffers;
 
 /* Bytes of workspace a context from fslbm_init with these parameters needs
- * (including a cell -> list-entry map and a list-ordered population buffer of
- * N/8 entries, at least 32768, for the interface-first step of fslbm_step). */
+ * (in the FP32 and FP64 forms including a cell -> list-entry map and a
+ * list-ordered population buffer of N/8 entries, at least 32768, for the
+ * interface-first step of fslbm_step). */
 fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes);
 
 /* Validate parameters and buffers, check the cell classes on the device (every
@@ -213,12 +214,13 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
  * when the extent in use is 32 steps old the call waits for the next one
  * (so the device has at most 32 steps queued).  The environment variable
  * FSLBM_EXTENT_EVERY at init sets the 16 (0: every row, never a wait).  In
- * the FP32 and FP16 forms the plain step (no moving wall, surface tension,
- * PLIC, solid cells or prescribed surface) runs the interface kernel before
- * the sweep, which stores the interface populations with its whole rows; the
- * results are the same bits as with the interface kernel after the sweep.
- * The environment variable FSLBM_REORDER at init (0 / 1) selects either
- * order for every form.  The classes change
+ * the FP32 form the plain step (no moving wall, surface tension, PLIC, solid
+ * cells or prescribed surface) runs the interface kernel before the sweep,
+ * which stores the interface populations with its whole rows; the results
+ * are the same bits as with the interface kernel after the sweep.  The
+ * environment variable FSLBM_REORDER at init (0 / 1) selects either order for
+ * the FP32 and FP64 forms; FP16 storage always runs the interface kernel
+ * after the sweep.  The classes change
  * only through the steps: a caller that writes the flags buffer between steps
  * calls fslbm_set_state or fslbm_set_equilibrium afterwards, which also make
  * the next step measure the extent again and rebuild the interface list. */

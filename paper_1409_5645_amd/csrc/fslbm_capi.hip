@@ -257,7 +257,8 @@ fslbm_status fslbm_workspace_size(const fslbm_params* p, size_t* bytes) {
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!bytes) { g_init_error = "bytes is NULL"; return FSLBM_E_INVALID; }
-  *bytes = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2, storage_bytes(p->precision), true).total;
+  *bytes = layout((size_t)p->nx * p->ny * p->nz, p->sigma != 0.0, p->plic == 2, storage_bytes(p->precision),
+                  p->precision != FSLBM_FP16S).total;
   return FSLBM_OK;
 }
 
@@ -313,13 +314,13 @@ fslbm_status init_impl(const fslbm_params* p, const fslbm_buffers* b, void* work
     c->islot = (int32_t*)(w + L.islot);
     c->rbuf = (void*)(w + L.rbuf);
     c->rcap = (int)L.rcap;
-    // On by default in the FP32 and FP16 forms.  In FP64 the 512x320x512
-    // tank's step got 0.9 % slower with it (the sweep lost more than the
-    // interface kernel saved).  FSLBM_REORDER=0 / 1: off / on in every form;
-    // FSLBM_RCAP: fewer list entries in the population buffer (the rest are
-    // written straight into the cells)
-    c->reorder = p->precision != FSLBM_FP64;
-    if (const char* e = std::getenv("FSLBM_REORDER")) c->reorder = std::atoi(e) != 0;
+    // On by default in the FP32 form.  In FP64 the 512x320x512 tank's step
+    // got 0.9 % slower with it (the sweep lost more than the interface kernel
+    // saved); the FP16 sweeps always keep the other order.  FSLBM_REORDER=0 /
+    // 1: off / on in the FP32 and FP64 forms; FSLBM_RCAP: fewer list entries
+    // in the population buffer (the rest are written straight into the cells)
+    c->reorder = p->precision == FSLBM_FP32;
+    if (const char* e = std::getenv("FSLBM_REORDER")) c->reorder = std::atoi(e) != 0 && p->precision != FSLBM_FP16S;
     if (const char* e = std::getenv("FSLBM_RCAP")) c->rcap = std::max(0, std::min(c->rcap, std::atoi(e)));
   }
   {
@@ -377,7 +378,8 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
   fslbm_status s = check_params(p, why);
   if (s != FSLBM_OK) { g_init_error = why; return s; }
   if (!b || !out) { g_init_error = "buffers or out is NULL"; return FSLBM_E_INVALID; }
-  s = init_impl(p, b, b->workspace, b->workspace_bytes, true, out);
+  // the interface-first buffers: FP32 and FP64 forms (FP16 keeps the other order)
+  s = init_impl(p, b, b->workspace, b->workspace_bytes, p->precision != FSLBM_FP16S, out);
   if (s != FSLBM_OK) return s;
   fslbm_ctx* c = *out;
   c->ext_every = 16;

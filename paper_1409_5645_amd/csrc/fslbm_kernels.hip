@@ -7,8 +7,8 @@
 //             step): mass exchange, interface geometry, FSK/FSL
 //             reconstruction, TRT collision, fill update and filled/emptied
 //             classification with list append.
-//   The plain step of the FP32 and FP16 forms runs k_iface4 first, on the
-//   list the step before built, and k_sweep stores its populations (the
+//   The plain step of the FP32 form runs k_iface4 first, on the list the
+//   step before built, and k_sweep stores its populations (the
 //   interface-first order of SweepArgs::order).
 //   k_mark    E' = E minus N(F); new interface cells from gas next to filled
 //             cells (initialised from their interface neighbours) and from

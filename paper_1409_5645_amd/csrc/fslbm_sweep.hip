@@ -20,12 +20,17 @@ constexpr int BLOCK = 256;
 // result (gas populations are never read; a cell that becomes interface is
 // initialised in full).  The interface cells take one of two orders:
 //   - order 0: the interface kernel runs after this one and overwrites them
-//     (the FP64 form, a step with walls, surface tension, PLIC, solids or an
-//     adjoint record, or any step with FSLBM_REORDER=0);
-//   - order 1: the interface kernel ran before this one and left their
-//     populations in a list-ordered buffer; a wavefront with liquid or
+//     (the FP16 and FP64 forms, a step with walls, surface tension, PLIC,
+//     solids or an adjoint record, or any step with FSLBM_REORDER=0);
+//   - order 1 (k_sweep<..., ORDER1>, the plain FP32 step, and FP64 with
+//     FSLBM_REORDER=1): the interface kernel ran before this one and left
+//     their populations in a list-ordered buffer; a wavefront with liquid or
 //     interface cells stores them with its whole row segment, and the list
-//     built here is that of the next step.
+//     built here is that of the next step.  Not in the FP16 forms: there the
+//     compiler fuses the collision's last FMA and the FP16 conversion into
+//     one instruction where it can, and a choice between two values before
+//     the store changes where it can, so the two FP16 sweeps would no longer
+//     give the same bits (rounding explicitly cost the pair sweep 3 %).
 //
 // Pull, Eq. (lbe1): f_q(x) = ft_q(x - c_q).  A source beyond a wall gives
 // halfway bounce-back f_q(x) = ft_qbar(x).  Every load is unconditional with a
@@ -33,13 +38,13 @@ constexpr int BLOCK = 256;
 // loads of a cell are in flight together.  MODEL 1 fixes the incompressible
 // non-Stokes equilibrium at compile time; MODEL 0 reads both switches.
 
-template <class F, int MODEL, bool WITH_U = false>
+template <class F, int MODEL, bool WITH_U = false, bool ORDER1 = false>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
   constexpr bool SH = F::shifted;
   const Grid g = a.c.grid;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && !a.order) {
+  if (!ORDER1 && blockIdx.x == 0 && threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
   }
@@ -51,14 +56,23 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   const int x = chunk * (int)blockDim.x + (int)threadIdx.x;
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint8_t t = x < g.nx ? a.flags[rbase + x] : GAS;
-  const bool it = t == IFACE;
-  // interface cells -> this step's list, wavefront-aggregated append (with
-  // the interface kernel first: the next step's list, after the collision)
-  if (!a.order) wave_append(it, &a.counters[C_I], a.listI, (int)(rbase + x));
-  // a wavefront without liquid cells that holds interface cells (order 1)
-  // pulls nothing: it only stores their populations from the list buffer
+  const int lane = (int)threadIdx.x & 63;
+  if constexpr (!ORDER1) {
+    // interface cells -> list (wavefront-aggregated append)
+    const unsigned long long b = __ballot(t == IFACE);
+    if (b) {
+      const int leader = __ffsll((long long)b) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
+      base = __shfl(base, leader);
+      if (t == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)(rbase + x);
+    }
+  }
+  // with the interface kernel first, a wavefront without liquid cells that
+  // holds interface cells pulls nothing: it only stores their populations
+  // from the list buffer
   const bool wliq = __ballot(t == LIQ) != 0ull;
-  if (!wliq && (!a.order || __ballot(it) == 0ull)) return;
+  if (!wliq && (!ORDER1 || __ballot(t == IFACE) == 0ull)) return;
   if (x >= g.nx || t == SOLID) return;
 
   // source rows (element offsets) of the nine (c_y, c_z) combinations
@@ -81,7 +95,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   // keeps the FP16 form in its storage units (the collision absorbs the scale).
   R f[Q];
   R rho_s = R(0.0), u[3] = {R(0.0), R(0.0), R(0.0)};
-  if (wliq) {
+  if (ORDER1 && !wliq) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = R(0.0);
+  } else {
 #define FSLBM_PULL(q)                                                                               \
   {                                                                                                 \
     const unsigned ro = srow[(CY[q] + 1) + 3 * (CZ[q] + 1)];                                        \
@@ -90,59 +107,59 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
                                                     : (unsigned)q * N + ro + (unsigned)sx;          \
     f[q] = F::load_raw(fin + off);                                                                  \
   }
-    FSLBM_PULL(0)
-    FSLBM_LINKS(FSLBM_PULL)
+  FSLBM_PULL(0)
+  FSLBM_LINKS(FSLBM_PULL)
 #undef FSLBM_PULL
-    if (a.c.moving) {
-      // moving walls (uniform branch): halfway bounce-back gains 2 w_q (c_q . u_w) / c_s^2,
-      // in storage units for the FP16 form
-      const double su = F::scaled ? (double)a.c.scale : 1.0;
+  if (a.c.moving) {
+    // moving walls (uniform branch): halfway bounce-back gains 2 w_q (c_q . u_w) / c_s^2,
+    // in storage units for the FP16 form
+    const double su = F::scaled ? (double)a.c.scale : 1.0;
 #define FSLBM_WALLU(q)                                                         \
   {                                                                            \
     const double t = wall_term<q>(a.wall_t, xm, xp, ym, yp, zm, zp);           \
     if (t != 0.0) f[q] = f[q] + (R)(t * su);                                   \
   }
-      FSLBM_LINKS(FSLBM_WALLU)
+    FSLBM_LINKS(FSLBM_WALLU)
 #undef FSLBM_WALLU
-    }
+  }
 
-    // ---- TRT collision, Eq. (lbe2)
-    const Consts<R>& k = pick_consts<R>(a.c);
-    const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
-    const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
-    if constexpr (sizeof(R) == 4)
-      collide_f32_scaled<SH, F::scaled>(f, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
-    else
-      collide<R, SH>(f, k, incomp, stokes, rho_s, u);
-  } else {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = R(0.0);
+  // ---- TRT collision, Eq. (lbe2)
+  const Consts<R>& k = pick_consts<R>(a.c);
+  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+  if constexpr (sizeof(R) == 4)
+    collide_f32_scaled<SH, F::scaled>(f, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  else
+    collide<R, SH>(f, k, incomp, stokes, rho_s, u);
   }
   S* __restrict__ fout = reinterpret_cast<S*>(a.fout);
-  // With the interface kernel first (a wavefront with interface cells has
-  // come this far, and every lane of the row but none past its end): the list
-  // entry of time t of an interface cell, then its entry in the next list.
-  // The map is read at interface cells only; a wavefront with interface cells
-  // writes its whole segment of it (-1 elsewhere), so no line of it is left
-  // partly written.
-  const bool from_r = a.order && it;
-  int oslot = -1;
-  if (a.order) {
+  if constexpr (!ORDER1) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+  } else {
+    // With the interface kernel first (a wavefront with interface cells has
+    // come this far, and every lane of the row but none past its end): the
+    // list entry of time t of an interface cell, then its entry in the next
+    // list.  The map is read at interface cells only; a wavefront with
+    // interface cells writes its whole segment of it (-1 elsewhere), so no
+    // line of it is left partly written.  An interface cell stores what the
+    // interface kernel computed for it (a list entry beyond rcap: written
+    // there directly, left alone here).
+    const bool it = t == IFACE;
+    int oslot = -1;
     if (it) oslot = a.islot[rbase + x];
     const int pos = wave_append_at(it, &a.counters_next[C_I], a.listI, (int)(rbase + x));
     if (__ballot(it) != 0ull) a.islot[rbase + x] = pos;
-  }
-  // an interface cell stores what the interface kernel computed for it (its
-  // list entry beyond rcap: written there directly, left alone here)
-  const bool keep = from_r && (unsigned)oslot >= (unsigned)a.rcap;
-  if (from_r && !keep) {
-    const S* __restrict__ rb = reinterpret_cast<const S*>(a.rbuf) + oslot;
+    const bool keep = it && (unsigned)oslot >= (unsigned)a.rcap;
+    if (it && !keep) {
+      const S* __restrict__ rb = reinterpret_cast<const S*>(a.rbuf) + oslot;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = F::load_raw(rb + (unsigned)q * (unsigned)a.rcap);
-  }
-  if (!keep) {
+      for (int q = 0; q < Q; ++q) f[q] = F::load_raw(rb + (unsigned)q * (unsigned)a.rcap);
+    }
+    if (!keep) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+      for (int q = 0; q < Q; ++q) F::store_raw(fout + ((unsigned)q * N + rbase + (unsigned)x), f[q]);
+    }
   }
   if constexpr (WITH_U) {
     // collision velocity of the liquid cells, kept for the adjoint of this step
@@ -154,7 +171,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
   }
 }
 
-// FP16-storage sweep with two cells per lane (rows of even length): the 19
+// FP16-storage sweep with two cells per lane (rows of even length; always the
+// order with the interface kernel after the sweep): the 19
 // populations of a pair are 4-byte aligned loads; the x-shifted neighbour comes
 // from the adjacent lane by a wavefront shift (DPP), and the one element beyond
 // the wavefront (or the row end: periodic wrap, or bounce-back at a wall) is a
@@ -239,7 +257,7 @@ __device__ __forceinline__ void pull_pair(float (&f0)[Q], float (&f1)[Q], const 
 template <int MODEL>
 __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   const Grid g = a.c.grid;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && !a.order) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NCOUNT; ++i) a.counters_next[i] = 0;
   }
@@ -254,20 +272,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   const unsigned rbase = (unsigned)row * (unsigned)g.nx;
   const uint16_t fl2 = valid ? *reinterpret_cast<const uint16_t*>(a.flags + rbase + xl) : (uint16_t)0;
   const uint8_t tt[2] = {(uint8_t)(fl2 & 0xffu), (uint8_t)(fl2 >> 8)};
-  // interface cells -> this step's list, wavefront-aggregated append, one
-  // cell of the pair at a time (with the interface kernel first: the next
-  // step's list, after the collision)
-  if (!a.order) {
+  const int lane = (int)threadIdx.x & 63;
+  // interface cells -> list (wavefront-aggregated append, one cell of the pair at a time)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) wave_append(tt[j] == IFACE, &a.counters[C_I], a.listI, (int)rbase + x0 + j);
+  for (int j = 0; j < 2; ++j) {
+    const unsigned long long b = __ballot(tt[j] == IFACE);
+    if (b) {
+      const int leader = __ffsll((long long)b) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&a.counters[C_I], __popcll(b));
+      base = __shfl(base, leader);
+      if (tt[j] == IFACE) a.listI[base + __popcll(b & ((1ull << lane) - 1ull))] = (int)rbase + x0 + j;
+    }
   }
   const bool liq = tt[0] == LIQ || tt[1] == LIQ;
-  const bool from_r0 = a.order && tt[0] == IFACE, from_r1 = a.order && tt[1] == IFACE;
-  // lanes exchange data below: whole wavefronts only.  A wavefront without
-  // liquid cells that holds interface cells (order 1) pulls nothing: it only
-  // stores their populations from the list buffer.
-  const bool wliq = __ballot(liq) != 0ull;
-  if (!wliq && __ballot(from_r0 || from_r1) == 0ull) return;
+  if (__ballot(liq) == 0) return;  // lanes exchange data below: whole wavefronts only
 
   const int ym = step_axis(y, -1, g.ny, g.py), yp = step_axis(y, 1, g.ny, g.py);
   const int zm = step_axis(z, -1, g.nz, g.pz), zp = step_axis(z, 1, g.nz, g.pz);
@@ -288,71 +307,29 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_h2(SweepArgs a) {
   for (int i = 0; i < 9; ++i) srow2[i] = srow[i] == WALL_ROW ? WALL_ROW : 2u * srow[i];
 
   float f0[Q], f1[Q];
-  if (wliq) {
-    // interior blocks (no source row beyond a y/z wall) take a select-only pull;
-    // the few blocks on the y/z faces take the general one
-    bool wall_rows = false;
+  // interior blocks (no source row beyond a y/z wall) take a select-only pull;
+  // the few blocks on the y/z faces take the general one
+  bool wall_rows = false;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
-    const bool ld = tt[0] != GAS || tt[1] != GAS;  // lanes past the row end read as gas
-    if (!wall_rows)
-      pull_pair<false>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
-    else
-      pull_pair<true>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
+  for (int i = 0; i < 9; ++i) wall_rows = wall_rows || srow[i] == WALL_ROW;
+  const bool ld = tt[0] != GAS || tt[1] != GAS;  // lanes past the row end read as gas
+  if (!wall_rows)
+    pull_pair<false>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
+  else
+    pull_pair<true>(f0, f1, fb, g, N2, srow2, 2u * rbase, 2u * (unsigned)xl, wx0, wend, row_end, ld);
 
-    // ---- TRT collision, Eq. (lbe2), in storage units
-    const Consts<float>& k = a.c.kf;
-    const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
-    const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
-    float rho_s, u[3];
-    collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
-    collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
-  } else {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) f0[q] = f1[q] = 0.0f;
-  }
-  // With the interface kernel first (every wavefront with interface cells has
-  // come this far): the list entries of time t of the pair's interface cells,
-  // then their entries in the next list.  The map is read at interface cells
-  // only; a wavefront with interface cells writes its whole segment of it (-1
-  // elsewhere, 8 bytes per pair), so no line of it is left partly written.
-  int oslot[2] = {-1, -1};
-  if (a.order) {
-    int pos[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (tt[j] == IFACE) oslot[j] = a.islot[rbase + (unsigned)(x0 + j)];
-      pos[j] = wave_append_at(tt[j] == IFACE, &a.counters_next[C_I], a.listI, (int)rbase + x0 + j);
-    }
-    if (__ballot(from_r0 || from_r1) != 0ull && valid)
-      *reinterpret_cast<int2*>(a.islot + rbase + (unsigned)x0) = make_int2(pos[0], pos[1]);
-  }
+  // ---- TRT collision, Eq. (lbe2), in storage units
+  const Consts<float>& k = a.c.kf;
+  const bool incomp = MODEL == 1 ? true : (bool)a.c.incomp;
+  const bool stokes = MODEL == 1 ? false : (bool)a.c.stokes;
+  float rho_s, u[3];
+  collide_f32_scaled<true, true>(f0, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
+  collide_f32_scaled<true, true>(f1, k, incomp, stokes, a.c.scale, a.c.inv_scale, rho_s, u);
   if (valid && tt[0] != SOLID && tt[1] != SOLID) {
-    // an interface cell stores what the interface kernel computed for it (its
-    // list entry beyond rcap: written there directly, left alone here)
-    const bool keep0 = from_r0 && (unsigned)oslot[0] >= (unsigned)a.rcap;
-    const bool keep1 = from_r1 && (unsigned)oslot[1] >= (unsigned)a.rcap;
-    const uint16_t* __restrict__ rb = reinterpret_cast<const uint16_t*>(a.rbuf);
-    const unsigned rc = (unsigned)a.rcap;
-    if (from_r0 && !keep0) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) f0[q] = h_one(rb[(unsigned)q * rc + (unsigned)oslot[0]]);
-    }
-    if (from_r1 && !keep1) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) f1[q] = h_one(rb[(unsigned)q * rc + (unsigned)oslot[1]]);
-    }
     char* __restrict__ fo = reinterpret_cast<char*>(a.fout);
     const unsigned o = 2u * (rbase + (unsigned)x0);
-    if (!keep0 && !keep1) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fo + ((unsigned)q * N2 + o)) = h_pack(f0[q], f1[q]);
-    } else {
-      for (int q = 0; q < Q; ++q) {
-        if (!keep0) *reinterpret_cast<_Float16*>(fo + ((unsigned)q * N2 + o)) = (_Float16)f0[q];
-        if (!keep1) *reinterpret_cast<_Float16*>(fo + ((unsigned)q * N2 + o + 2u)) = (_Float16)f1[q];
-      }
-    }
+    for (int q = 0; q < Q; ++q) *reinterpret_cast<uint32_t*>(fo + ((unsigned)q * N2 + o)) = h_pack(f0[q], f1[q]);
   }
 }
 
@@ -482,7 +459,15 @@ static void sweep_form(const StepLaunch& L) {
   const int threads = std::min(BLOCK, 64 * ((g.nx + 63) / 64));
   a.cpr = (g.nx + threads - 1) / threads;
   const unsigned nb = (unsigned)a.cpr * (a.box ? (unsigned)a.bny * (unsigned)a.bnz : (unsigned)g.ny * (unsigned)g.nz);
-  if (a.u_out && a.c.incomp && !a.c.stokes)
+  if (a.order) {
+    // the interface kernel first (FP32 and FP64 forms; never with an adjoint record)
+    if constexpr (!F::scaled) {
+      if (a.c.incomp && !a.c.stokes)
+        k_sweep<F, 1, false, true><<<nb, threads, 0, st>>>(a);
+      else
+        k_sweep<F, 0, false, true><<<nb, threads, 0, st>>>(a);
+    }
+  } else if (a.u_out && a.c.incomp && !a.c.stokes)
     k_sweep<F, 1, true><<<nb, threads, 0, st>>>(a);
   else if (a.c.incomp && !a.c.stokes)
     k_sweep<F, 1><<<nb, threads, 0, st>>>(a);
