@@ -459,15 +459,17 @@ static void sweep_form(const StepLaunch& L) {
   const int threads = std::min(BLOCK, 64 * ((g.nx + 63) / 64));
   a.cpr = (g.nx + threads - 1) / threads;
   const unsigned nb = (unsigned)a.cpr * (a.box ? (unsigned)a.bny * (unsigned)a.bnz : (unsigned)g.ny * (unsigned)g.nz);
-  if (a.order) {
-    // the interface kernel first (FP32 and FP64 forms; never with an adjoint record)
-    if constexpr (!F::scaled) {
+  if constexpr (!F::scaled) {
+    if (a.order) {
+      // the interface kernel first (FP32 and FP64 forms; never with an adjoint record)
       if (a.c.incomp && !a.c.stokes)
         k_sweep<F, 1, false, true><<<nb, threads, 0, st>>>(a);
       else
         k_sweep<F, 0, false, true><<<nb, threads, 0, st>>>(a);
+      return;
     }
-  } else if (a.u_out && a.c.incomp && !a.c.stokes)
+  }
+  if (a.u_out && a.c.incomp && !a.c.stokes)
     k_sweep<F, 1, true><<<nb, threads, 0, st>>>(a);
   else if (a.c.incomp && !a.c.stokes)
     k_sweep<F, 1><<<nb, threads, 0, st>>>(a);
@@ -491,6 +493,7 @@ static void sweep_h2(const StepLaunch& L) {
 
 hipError_t launch_sweep(const StepLaunch& L, int precision, int rule) {
   (void)rule;  // the sweep covers liquid cells only; the rule acts in k_iface
+  if (L.sweep.order && precision == 2) return hipErrorInvalidValue;  // FP16 storage: interface kernel after the sweep
   if (precision == 0) sweep_form<FormF64>(L);
   else if (precision == 1) sweep_form<FormF32>(L);
   else if (L.sweep.c.grid.nx % 2 == 0 && L.sweep.pairs && !L.sweep.c.moving &&
