@@ -104,17 +104,23 @@ def test_sloshing_fp64_parity_with_conversions(fs, oracle_mod, rule):
     assert st["reservoir"] == pytest.approx(o.reservoir(), abs=1e-12)
 
 
-def test_periodic_and_degenerate_extents(fs, oracle_mod):
-    """nx = 1 periodic (a row wraps onto itself) and nz = 1 periodic."""
+@pytest.mark.parametrize("reorder", ["0", "1"])
+def test_periodic_and_degenerate_extents(fs, oracle_mod, monkeypatch, reorder):
+    """nx = 1 periodic (a row wraps onto itself) and nz = 1 periodic, with
+    either order of the interface kernel and the sweep."""
+    monkeypatch.setenv("FSLBM_REORDER", reorder)
     w = W.channel(h=10.83, nx=1, ny=16, nz=1, gx=5e-6)
     _run_pair(fs, oracle_mod, w, 1, 200, 100)
     w = W.sloshing(19, 14, 1, depth=7.0, amp=2.0, seed=3, gy=-3e-4, tau=0.6, periodic=(1, 0, 1))
     _run_pair(fs, oracle_mod, w, 1, 120, 40)
 
 
-def test_all_liquid_and_orphan(fs, oracle_mod):
+@pytest.mark.parametrize("reorder", ["0", "1"])
+def test_all_liquid_and_orphan(fs, oracle_mod, monkeypatch, reorder):
     """No interface cells at all; then one isolated interface cell that fills
-    with no interface neighbour (its excess goes to the reservoir)."""
+    with no interface neighbour (its excess goes to the reservoir).  With
+    either order of the interface kernel and the sweep."""
+    monkeypatch.setenv("FSLBM_REORDER", reorder)
     n = 9
     p = W.Params(nx=n, ny=n, nz=n, periodic=(1, 1, 1), tau=0.7, g=(1e-5, 0, 0))
     flags = np.full(n ** 3, W.LIQUID, np.uint8)
@@ -639,10 +645,13 @@ def test_rotated_film_parity(fs, oracle_mod, rule, plic):
         _compare(o, s, f"rotated film step {50 * (it + 1)}")
 
 
-def test_all_gas_and_enclosed_liquid(fs, oracle_mod):
+@pytest.mark.parametrize("reorder", ["0", "1"])
+def test_all_gas_and_enclosed_liquid(fs, oracle_mod, monkeypatch, reorder):
     """Edge cases: a lattice of gas only (nothing to do, zero mass); a single
     liquid cell enclosed in solid cells (every link a wall link, the wall-cell
-    kernel only) stays at rest, bit-exact against the oracle."""
+    kernel only) stays at rest, bit-exact against the oracle.  With either
+    order of the interface kernel and the sweep."""
+    monkeypatch.setenv("FSLBM_REORDER", reorder)
     p = W.Params(nx=7, ny=5, nz=3, periodic=(1, 1, 1))
     N = p.n_cells
     s = fs.Sim(p, np.zeros(N, dtype=np.uint8))
