@@ -39,9 +39,15 @@ def _state(s):
     return {"f": g["f"], "mass": g["mass"], "phi": g["phi"], "flags": g["flags"], "reservoir": st["reservoir"]}
 
 
-def test_slosh256_fp64_full_lattice_step(fs, oracle_mod):
+@pytest.mark.parametrize("reorder", ["0", "1"])
+def test_slosh256_fp64_full_lattice_step(fs, oracle_mod, monkeypatch, reorder):
+    """The full 256x160x256 tank: 30 GPU steps, then one step on the GPU and in
+    the oracle from the same state, with either order of the interface kernel
+    and the sweep (1: the interface kernel first, its list built by the steps
+    before)."""
+    monkeypatch.setenv("FSLBM_REORDER", reorder)
     w = W.config("slosh256", seed=1)
-    _say("case slosh256 fp64: 30 GPU steps, then one step GPU vs oracle")
+    _say(f"case slosh256 fp64 reorder={reorder}: 30 GPU steps, then one step GPU vs oracle")
     s = fs.Sim.from_workload(w)
     s.step(30, fs.FSL)
     st = _state(s)
