@@ -14,6 +14,8 @@ configuration bench.py times.
   next to gas, mass conserved to the precision of the form, no NaN or
   non-positive density).
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -216,3 +218,87 @@ def test_slosh512_reduced_precision_subbox_step(fs, oracle_mod, precision):
     assert ratio.max() <= 1.0
     it = flo[inner] == W.INTERFACE
     assert np.abs(gm[inner][it] - o.mass().reshape(shp)[inner][it]).max() <= 1e-5
+
+
+# The largest lattices the library addresses.  Population offsets are 32-bit:
+# element offsets reach 19 N - 1 (init refuses 19 N >= 2^32), and the FP16 pair
+# sweep, which reaches its populations by byte offsets, runs while 38 N < 2^32
+# (above that the one-cell FP16 sweep runs).
+MAX_CASES = [
+    ("fp16s", (512, 431, 512)),  # 112,984,064 cells, 38 N = 4,293,394,432: the pair sweep's largest
+    ("fp16s", (640, 551, 640)),  # 225,689,600 cells, 19 N = 4,288,102,400: one-cell FP16 sweep
+    ("fp32", (640, 551, 640)),
+    ("fp64", (640, 551, 640)),
+]
+
+
+@functools.lru_cache(maxsize=1)
+def _max_tank(dims):
+    nx, ny, nz = dims
+    return W.sloshing(nx, ny, nz, depth=0.6 * ny, amp=12.0 * nx / 512, seed=0)
+
+
+@pytest.mark.parametrize("precision,dims", MAX_CASES, ids=[f"{p}-{d[0]}x{d[1]}x{d[2]}" for p, d in MAX_CASES])
+def test_largest_lattice_subbox_step(fs, oracle_mod, precision, dims):
+    """A sloshing tank at the largest sizes above: after 20 GPU steps, one
+    more GPU step against one FP64 oracle step from the same (decoded) state
+    on a sub-box around the surface at the high-z wall, where the offsets are
+    largest (the z = nz - 1 and x = 0 faces are the tank's walls; cells at
+    least MARGIN from the cut faces are compared).  FP64 within 1e-12, the
+    other forms within their rounding (as for the 512 tank); over the whole
+    lattice no NaN or non-positive density, no liquid cell next to gas and
+    mass conserved to the precision of the form."""
+    nx, ny, nz = dims
+    w = _max_tank(dims)
+    p = w.params
+    _say(f"case largest lattice {nx}x{ny}x{nz} {precision}: 20 GPU steps, then one step on a sub-box at z = nz - 1")
+    s = fs.Sim.from_workload(w, precision=precision)
+    st0 = s.stats()
+    s.step(20, fs.FSL)
+    g0 = s.fields(("f", "mass", "phi", "flags"), device=True)
+    d = int(0.6 * ny)
+    box = ((0, 72), (d - 25, d + 25), (nz - 40, nz))
+    sub = {
+        "f": _subbox(g0["f"].reshape(19, nz, ny, nx), box).reshape(19, -1).cpu().numpy(),
+        "mass": _subbox(g0["mass"].reshape(nz, ny, nx), box).reshape(-1).cpu().numpy(),
+        "phi": _subbox(g0["phi"].reshape(nz, ny, nx), box).reshape(-1).cpu().numpy(),
+        "flags": _subbox(g0["flags"].reshape(nz, ny, nx), box).reshape(-1).cpu().numpy(),
+    }
+    del g0
+    (x0, x1), (y0, y1), (z0, z1) = box
+    ps = W.Params(nx=x1 - x0, ny=y1 - y0, nz=z1 - z0, periodic=(0, 0, 0), tau=p.tau, Lambda=p.Lambda,
+                  g=p.g, rho_gas=p.rho_gas, eps=p.eps)
+    o = oracle_mod.Oracle(ps, state=sub)
+    assert (sub["flags"] == W.INTERFACE).sum() > 1000
+    s.step(1, fs.FSL)
+    o.step(1, oracle_mod.FSL)
+    g1 = s.fields(("f", "flags", "mass"), device=True)
+    gf = _subbox(g1["f"].reshape(19, nz, ny, nx), box).cpu().numpy()
+    gfl = _subbox(g1["flags"].reshape(nz, ny, nx), box).cpu().numpy()
+    gm = _subbox(g1["mass"].reshape(nz, ny, nx), box).cpu().numpy()
+    fl = g1["flags"]
+    del g1
+    shp = (ps.nz, ps.ny, ps.nx)
+    inner = (slice(MARGIN, shp[0]), slice(MARGIN, shp[1] - MARGIN), slice(0, shp[2] - MARGIN))
+    flo = o.flags().reshape(shp)
+    np.testing.assert_array_equal(gfl[inner], flo[inner])
+    fo = o.populations().reshape((19,) + shp)
+    act = flo[inner] != W.GAS
+    a, b = gf[(slice(None),) + inner][:, act], fo[(slice(None),) + inner][:, act]
+    it = flo[inner] == W.INTERFACE
+    dm = np.abs(gm[inner][it] - o.mass().reshape(shp)[inner][it]).max()
+    if precision == "fp64":
+        err = np.abs(a - b).max() / np.abs(b).max()
+        _say("population rel err", err, "interface mass err", dm, "active compared", int(act.sum()))
+        assert err <= 1e-12 and dm <= 1e-11
+    else:
+        gq = np.abs(b - WQ[:, None])
+        tol = (2.0 ** -11 * gq + 2e-9) if precision == "fp16s" else np.full(gq.shape, 2e-9)
+        ratio = (np.abs(a - b) / tol).max()
+        _say("max err / bound", ratio, "interface mass err", dm, "active compared", int(act.sum()))
+        assert ratio <= 1.0 and dm <= 1e-5
+    st1 = s.stats()  # raises on NaN / non-positive density
+    rel = abs(st1["total_mass"] - st0["total_mass"]) / st0["total_mass"]
+    _say("mass drift", rel, "interface", st1["interface"])
+    assert rel < {"fp64": 1e-12, "fp32": 1e-6, "fp16s": 1e-4}[precision]
+    assert _layer_ok(fl, (nz, ny, nx))
