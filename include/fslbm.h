@@ -174,8 +174,8 @@ fslbm_status fslbm_init(const fslbm_params* p, const fslbm_buffers* b, fslbm_ctx
  * the sweep). */
 #define FSLBM_STATIC_WORKSPACE_BYTES (64u << 20)
 
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same as
  * fslbm_init, but b->workspace and b->workspace_bytes are ignored -- the
  * context's workspace is an array of FSLBM_STATIC_WORKSPACE_BYTES inside the
  * library on the current device, which each device that uses it holds until
@@ -223,7 +223,11 @@ fslbm_status fslbm_set_state(fslbm_ctx* c, const double* f, const double* mass, 
  * after the sweep.  The classes change
  * only through the steps: a caller that writes the flags buffer between steps
  * calls fslbm_set_state or fslbm_set_equilibrium afterwards, which also make
- * the next step measure the extent again and rebuild the interface list. */
+ * the next step measure the extent again and rebuild the interface list.
+ * Steps are not for HIP graph capture: each call passes host-side state into
+ * its launches (which population buffer is current, the step count that
+ * stamps the conversion marks, and for a context from fslbm_init the row box
+ * and the interface list), so a captured step would replay stale arguments. */
 fslbm_status fslbm_step(fslbm_ctx* c, int32_t n, int32_t rule);
 
 /* Field export into caller device buffers.  mask selects fields by bit; dst[i]
