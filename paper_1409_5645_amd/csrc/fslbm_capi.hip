@@ -1026,6 +1026,7 @@ hipError_t window_step(fslbm_window* w, const fslbm_window::State& A, const fslb
   s.freeze = 1;
   s.cpr = 0;
   s.pairs = c->pairs;
+  s.quad = c->quad;
   s.u_out = R.u;
   s.wall_t = c->wall_t;
   L.stream = (void*)c->stream;

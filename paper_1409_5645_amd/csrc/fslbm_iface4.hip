@@ -193,7 +193,9 @@ __device__ __forceinline__ void rebuild_pair(R& fA, R& fB, R oA, R oB, bool gA, 
   if (gB) fB = vB;
 }
 
-template <class F, int RULE>
+// REC: a step of an adjoint window, which also stores what the reverse step
+// needs at each listed cell, in list order (rules 0 and 1).
+template <class F, int RULE, bool REC = false>
 __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
   using R = typename F::R;
   using S = typename F::S;
@@ -324,6 +326,34 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
         if (L.tB[s] != GAS) L.fB[s] = F::load(fin + offB, isc);
         if (L.tA[s] == IFACE) L.pA[s] = a.phi_in[sa];
         if (L.tB[s] == IFACE) L.pB[s] = a.phi_in[sb];
+      }
+    }
+
+    if constexpr (REC) {
+      // the record: pulled and own populations of time t (each lane its links,
+      // lane 1 the rest link), fill and mass.  A value pulled from a gas source
+      // is not loaded and is recorded as 0: the reverse step reads the pulled
+      // values of liquid and interface sources only.
+      R* __restrict__ rf = reinterpret_cast<R*>(a.rec_f);
+      R* __restrict__ ro = reinterpret_cast<R*>(a.rec_own);
+      const unsigned cap = (unsigned)a.rec_cap, ui = (unsigned)i;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        if (s < nsl) {
+          const unsigned qA = (unsigned)qa[s], qB = qA + 1u;
+          rf[qA * cap + ui] = L.fA[s];
+          rf[qB * cap + ui] = L.fB[s];
+          ro[qA * cap + ui] = L.oA[s];
+          ro[qB * cap + ui] = L.oB[s];
+        }
+      }
+      if (sub == 1) {
+        rf[ui] = L.f0;
+        ro[ui] = L.f0;
+      }
+      if (lead) {
+        a.rec_phi[i] = phix;
+        a.rec_m[i] = m_old;
       }
     }
 
@@ -619,6 +649,13 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
     if (sub == 1) F::store(pb, L.f0, a.c.scale);
     const double rho = SH ? 1.0 + (double)rho_s : (double)rho_s;
     bool filled = false, emptied = false;
+    if (REC && lead) {
+      R* __restrict__ ru = reinterpret_cast<R*>(a.rec_u);
+      const unsigned cap = (unsigned)a.rec_cap;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ru[(unsigned)c * cap + (unsigned)i] = u[c];
+      a.rec_rho[i] = rho;
+    }
     if (lead) {
       a.mass[idx] = a.hold ? m_old : m_new;
       a.phi_out[idx] = a.hold ? phix : m_new / rho;
@@ -636,15 +673,22 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
   }
 }
 
-template <class F, int RULE>
+template <class F, int RULE, bool REC = false>
 static void iface4_go(const StepLaunch& L) {
-  unsigned nb = std::min<unsigned>(IFACE4_GRID, (unsigned)((L.sweep.c.grid.N + QCELLS - 1) / QCELLS));
+  // a window step's list is fixed and its length (rec_cap) known here
+  const size_t cells = REC ? (size_t)L.sweep.rec_cap : (size_t)L.sweep.c.grid.N;
+  unsigned nb = std::min<unsigned>(IFACE4_GRID, (unsigned)std::max<size_t>(1, (cells + QCELLS - 1) / QCELLS));
   nb = (nb + NXCD - 1) / NXCD * NXCD;
-  k_iface4<F, RULE><<<nb, QBLOCK, 0, (hipStream_t)L.stream>>>(L.sweep);
+  k_iface4<F, RULE, REC><<<nb, QBLOCK, 0, (hipStream_t)L.stream>>>(L.sweep);
 }
 
 template <class F>
 static void iface4_form(const StepLaunch& L, int rule) {
+  if (L.sweep.rec_f) {  // a window step (rules 0 and 1)
+    if (rule == 0) iface4_go<F, 0, true>(L);
+    else iface4_go<F, 1, true>(L);
+    return;
+  }
   switch (rule) {
     case 0: iface4_go<F, 0>(L); break;
     case 1: iface4_go<F, 1>(L); break;

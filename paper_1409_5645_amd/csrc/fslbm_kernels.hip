@@ -1015,7 +1015,13 @@ static void iface_form(const StepLaunch& L, int rule) {
   const bool extra =
       L.sweep.c.moving || L.sweep.c.sigma != 0.0 || L.sweep.c.plic || L.sweep.c.solid || L.sweep.c.surface;
   if (L.sweep.rec_f) {
-    // a window step (rules 0 and 1): the list is fixed and its length (rec_cap) known here
+    // a window step (rules 0 and 1): the list is fixed and its length (rec_cap)
+    // known here; the four-lane kernel records as well where the plain step
+    // would take it
+    if (!extra && L.sweep.quad) {
+      (void)launch_iface4(L, std::is_same<F, FormF64>::value ? 0 : (std::is_same<F, FormF32>::value ? 1 : 2), rule);
+      return;
+    }
     const unsigned nbr = std::min<unsigned>(nb, (unsigned)((L.sweep.rec_cap + IBLOCK - 1) / IBLOCK));
     if (rule == 0)
       extra ? iface_go<F, 0, true, true>(L, nbr) : iface_go<F, 0, true, false>(L, nbr);

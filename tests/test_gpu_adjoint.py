@@ -220,6 +220,34 @@ def test_checkpoint_spacing_does_not_change_the_gradient(fs, case):
     sim.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("rule", [0, 1])
+def test_window_interface_kernels_agree(fs, case, monkeypatch, precision, rule):
+    """The window's forward steps record their interface cells with the
+    four-lanes-per-cell kernel (the default) or with the one-lane kernel
+    (FSLBM_IFACE_QUAD=0).  FP64: the same gradient bit for bit (the two
+    kernels compute the same bits, and the recorded value pulled from a gas
+    source, which only the one-lane kernel loads, is never read by the
+    reverse step).  FP32: the two kernels sum in different orders, so the
+    gradients agree to the FP32 rounding, well inside 1e-3."""
+    _say(f"case adjoint window interface kernels {precision} rule {rule}")
+    monkeypatch.setenv("FSLBM_IFACE_QUAD", "0")
+    g1 = _gpu_grad(fs, case, rule, precision=precision)
+    monkeypatch.delenv("FSLBM_IFACE_QUAD")
+    g4 = _gpu_grad(fs, case, rule, precision=precision)
+    for k in ("f", "m", "phi", "g"):
+        if precision == "fp64":
+            np.testing.assert_array_equal(g4[k], g1[k], err_msg=k)
+        else:
+            rel = np.linalg.norm(g4[k] - g1[k]) / np.linalg.norm(g1[k])
+            _say(f"  {k} relative difference {rel:.2e}")
+            assert rel <= 1e-3, k
+    if precision == "fp64":
+        assert g4["P_b"] == g1["P_b"] and g4["L"] == g1["L"]
+    else:
+        assert abs(g4["P_b"] - g1["P_b"]) <= 1e-3 * abs(g1["P_b"])
+
+
 def test_fp32_gradient_error_stated(fs, case):
     _say("case adjoint fp32 vs fp64 gradient")
     g64 = _gpu_grad(fs, case, 1)
