@@ -225,10 +225,11 @@ def test_slosh512_reduced_precision_subbox_step(fs, oracle_mod, precision):
 # sweep, which reaches its populations by byte offsets, runs while 38 N < 2^32
 # (above that the one-cell FP16 sweep runs).
 MAX_CASES = [
-    ("fp16s", (512, 431, 512)),  # 112,984,064 cells, 38 N = 4,293,394,432: the pair sweep's largest
-    ("fp16s", (640, 551, 640)),  # 225,689,600 cells, 19 N = 4,288,102,400: one-cell FP16 sweep
-    ("fp32", (640, 551, 640)),
-    ("fp64", (640, 551, 640)),
+    ("fp16s", (512, 431, 512), "0"),  # 112,984,064 cells, 38 N = 4,293,394,432: the pair sweep's largest
+    ("fp16s", (640, 551, 640), "0"),  # 225,689,600 cells, 19 N = 4,288,102,400: one-cell FP16 sweep
+    ("fp32", (640, 551, 640), "1"),   # interface kernel first (the FP32 default)
+    ("fp64", (640, 551, 640), "0"),
+    ("fp64", (640, 551, 640), "1"),   # interface kernel first: a list buffer of N / 8 entries
 ]
 
 
@@ -238,8 +239,9 @@ def _max_tank(dims):
     return W.sloshing(nx, ny, nz, depth=0.6 * ny, amp=12.0 * nx / 512, seed=0)
 
 
-@pytest.mark.parametrize("precision,dims", MAX_CASES, ids=[f"{p}-{d[0]}x{d[1]}x{d[2]}" for p, d in MAX_CASES])
-def test_largest_lattice_subbox_step(fs, oracle_mod, precision, dims):
+@pytest.mark.parametrize("precision,dims,reorder", MAX_CASES,
+                         ids=[f"{p}-{d[0]}x{d[1]}x{d[2]}-order{r}" for p, d, r in MAX_CASES])
+def test_largest_lattice_subbox_step(fs, oracle_mod, monkeypatch, precision, dims, reorder):
     """A sloshing tank at the largest sizes above: after 20 GPU steps, one
     more GPU step against one FP64 oracle step from the same (decoded) state
     on a sub-box around the surface at the high-z wall, where the offsets are
@@ -248,10 +250,12 @@ def test_largest_lattice_subbox_step(fs, oracle_mod, precision, dims):
     other forms within their rounding (as for the 512 tank); over the whole
     lattice no NaN or non-positive density, no liquid cell next to gas and
     mass conserved to the precision of the form."""
+    monkeypatch.setenv("FSLBM_REORDER", reorder)
     nx, ny, nz = dims
     w = _max_tank(dims)
     p = w.params
-    _say(f"case largest lattice {nx}x{ny}x{nz} {precision}: 20 GPU steps, then one step on a sub-box at z = nz - 1")
+    _say(f"case largest lattice {nx}x{ny}x{nz} {precision} order {reorder}: 20 GPU steps, "
+         "then one step on a sub-box at z = nz - 1")
     s = fs.Sim.from_workload(w, precision=precision)
     st0 = s.stats()
     s.step(20, fs.FSL)
