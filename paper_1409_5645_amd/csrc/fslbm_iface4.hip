@@ -333,7 +333,8 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
       // the record: pulled and own populations of time t (each lane its links,
       // lane 1 the rest link), fill and mass.  A value pulled from a gas source
       // is not loaded and is recorded as 0: the reverse step reads the pulled
-      // values of liquid and interface sources only.
+      // values of liquid and interface sources only.  Non-temporal stores: the
+      // record is read once, in the reverse pass.
       R* __restrict__ rf = reinterpret_cast<R*>(a.rec_f);
       R* __restrict__ ro = reinterpret_cast<R*>(a.rec_own);
       const unsigned cap = (unsigned)a.rec_cap, ui = (unsigned)i;
@@ -341,19 +342,19 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
       for (int s = 0; s < 3; ++s) {
         if (s < nsl) {
           const unsigned qA = (unsigned)qa[s], qB = qA + 1u;
-          rf[qA * cap + ui] = L.fA[s];
-          rf[qB * cap + ui] = L.fB[s];
-          ro[qA * cap + ui] = L.oA[s];
-          ro[qB * cap + ui] = L.oB[s];
+          __builtin_nontemporal_store(L.fA[s], &rf[qA * cap + ui]);
+          __builtin_nontemporal_store(L.fB[s], &rf[qB * cap + ui]);
+          __builtin_nontemporal_store(L.oA[s], &ro[qA * cap + ui]);
+          __builtin_nontemporal_store(L.oB[s], &ro[qB * cap + ui]);
         }
       }
       if (sub == 1) {
-        rf[ui] = L.f0;
-        ro[ui] = L.f0;
+        __builtin_nontemporal_store(L.f0, &rf[ui]);
+        __builtin_nontemporal_store(L.f0, &ro[ui]);
       }
       if (lead) {
-        a.rec_phi[i] = phix;
-        a.rec_m[i] = m_old;
+        __builtin_nontemporal_store(phix, &a.rec_phi[i]);
+        __builtin_nontemporal_store(m_old, &a.rec_m[i]);
       }
     }
 
@@ -653,8 +654,8 @@ __global__ __launch_bounds__(QBLOCK) void k_iface4(SweepArgs a) {
       R* __restrict__ ru = reinterpret_cast<R*>(a.rec_u);
       const unsigned cap = (unsigned)a.rec_cap;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ru[(unsigned)c * cap + (unsigned)i] = u[c];
-      a.rec_rho[i] = rho;
+      for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(u[c], &ru[(unsigned)c * cap + (unsigned)i]);
+      __builtin_nontemporal_store(rho, &a.rec_rho[i]);
     }
     if (lead) {
       a.mass[idx] = a.hold ? m_old : m_new;

@@ -162,11 +162,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a) {
     }
   }
   if constexpr (WITH_U) {
-    // collision velocity of the liquid cells, kept for the adjoint of this step
-    if (t == LIQ) {
+    // collision velocity of the row segment, kept for the adjoint of this step,
+    // which reads it at liquid cells only: whole lines, and non-temporal
+    // stores, as it is read once, in the reverse pass, long after (cached
+    // stores would evict the window's hot state)
+    {
       R* __restrict__ uo = reinterpret_cast<R*>(a.u_out);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) uo[(unsigned)c * N + rbase + (unsigned)x] = u[c];
+      for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(u[c], &uo[(unsigned)c * N + rbase + (unsigned)x]);
     }
   }
 }
