@@ -335,17 +335,18 @@ __global__ __launch_bounds__(IBLOCK, (iface_waves<F, RULE, EXTRA>())) void k_ifa
     }
     if constexpr (REC) {
       // what the adjoint of this step needs at this cell, in list order
+      // (non-temporal stores: read once, in the reverse pass)
       using RR = typename F::R;
       RR* rf = reinterpret_cast<RR*>(a.rec_f);
       RR* ro = reinterpret_cast<RR*>(a.rec_own);
       const unsigned cap = (unsigned)a.rec_cap;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        rf[(unsigned)q * cap + (unsigned)i] = d.f[q];
-        ro[(unsigned)q * cap + (unsigned)i] = d.own[q];
+        __builtin_nontemporal_store(d.f[q], &rf[(unsigned)q * cap + (unsigned)i]);
+        __builtin_nontemporal_store(d.own[q], &ro[(unsigned)q * cap + (unsigned)i]);
       }
-      a.rec_phi[i] = d.phix;
-      a.rec_m[i] = d.m;
+      __builtin_nontemporal_store(d.phix, &a.rec_phi[i]);
+      __builtin_nontemporal_store(d.m, &a.rec_m[i]);
     }
     // ---- phase 2: interface treatment and collision
     R rho_s, u[3];
@@ -360,8 +361,8 @@ __global__ __launch_bounds__(IBLOCK, (iface_waves<F, RULE, EXTRA>())) void k_ifa
       typename F::R* ru = reinterpret_cast<typename F::R*>(a.rec_u);
       const unsigned cap = (unsigned)a.rec_cap;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ru[(unsigned)c * cap + (unsigned)i] = u[c];
-      a.rec_rho[i] = rho;
+      for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(u[c], &ru[(unsigned)c * cap + (unsigned)i]);
+      __builtin_nontemporal_store(rho, &a.rec_rho[i]);
     }
     a.mass[idx] = a.hold ? d.m : m_new;
     a.phi_out[idx] = a.hold ? d.phix : m_new / rho;
