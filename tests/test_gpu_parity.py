@@ -115,6 +115,29 @@ def test_periodic_and_degenerate_extents(fs, oracle_mod, monkeypatch, reorder):
     _run_pair(fs, oracle_mod, w, 1, 120, 40)
 
 
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1)])
+def test_single_cell_lattice(fs, oracle_mod, periodic):
+    """The smallest lattice, one liquid cell: walled on every side (every link
+    bounces back) or periodic on every axis (every link pulls from the cell
+    itself).  A count of 0 steps leaves the state as it is and a negative
+    count is refused; then 50 steps with gravity against the oracle."""
+    _say(f"case single cell, periodic {periodic}")
+    p = W.Params(nx=1, ny=1, nz=1, periodic=periodic, tau=0.7, g=(1e-5, -2e-5, 3e-6))
+    flags = np.full(1, W.LIQUID, np.uint8)
+    rho, u = np.array([1.001]), np.array([[1e-3], [-2e-3], [5e-4]])
+    o = oracle_mod.Oracle(p, flags, rho, u, np.ones(1))
+    s = fs.Sim(p, flags)
+    s.set_equilibrium(rho, u, np.ones(1))
+    f0 = s.fields(("f",))["f"]
+    s.step(0, fs.FSL)
+    assert np.array_equal(s.fields(("f",))["f"], f0) and s.stats()["steps"] == 0
+    with pytest.raises(fs.FslbmError, match="n must be"):
+        s.step(-1, fs.FSL)
+    o.step(50, oracle_mod.FSL)
+    s.step(50, fs.FSL)
+    _compare(o, s, f"single cell {periodic}")
+
+
 @pytest.mark.parametrize("reorder", ["0", "1"])
 def test_all_liquid_and_orphan(fs, oracle_mod, monkeypatch, reorder):
     """No interface cells at all; then one isolated interface cell that fills
